@@ -1,0 +1,272 @@
+"""Benchmark: batched HMult + relinearise + rescale on one MI355X.
+
+Workload (one "step"): a batch of 256 ciphertext pairs at N = 2^15 with 16
+data primes of 50 bits and 2 special primes of 60 bits (hybrid key
+switching with dnum = 4), residues uniform in [0, q): one fused, batched
+ckks_hmult_relin_rescale call. value = pairs / second over the timed steps.
+
+Also reported (under "extra"): the ragged batch (4..16 limbs), the plain
+one-op-per-launch path (multiply, relinearize, rescale per pair), a batched
+NTT microbench, the per-kernel breakdown from HIP events, and the roofline
+of the dominant kernel. The oracle (plain C, CPU) is timed on a bounded
+sample of the same workload for "cpu_baseline".
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch B]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LOG_N = 15
+Q_BITS = [50] * 16
+P_BITS = [60, 60]
+DNUM = 4
+HBM_PEAK_GBS = 8000.0
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit lane-ops/s.
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def limb_bytes(n):
+    return 8 * n
+
+
+def kernel_model(name, items, ctx, level):
+    """Algorithmic HBM bytes of one launch of a kernel family in the fused
+    HMult pipeline at one level (every item of the launch at that level)."""
+    N, k, A = ctx.N, len(ctx.p), -(-len(ctx.q) // ctx.dnum)
+    L = level + 1
+    E = L + k
+    beta = -(-L // A)
+    lb = limb_bytes(N)
+    fam = name.split("/")[0]
+    if fam == "ntt_fwd_modup":
+        # per ciphertext: every digit's source limbs read once, every
+        # extended limb written once
+        per_ct_items = sum(E - min(A, L - j * A) for j in range(beta))
+        cts = items / per_ct_items
+        return cts * (L + per_ct_items) * lb
+    if fam == "keyswitch_inner_product":
+        cts = items / E
+        # ModUp'd limbs (or the two source limbs of d2), key limbs, 2 outputs
+        per = 0
+        for t in range(E):
+            per += beta * 1 + 2 * beta + 2
+        return cts * per * lb
+    if fam in ("ntt_inv_mul",):
+        return items * 3 * lb
+    if fam == "ntt_fwd_hmult_tail":
+        # reads k special limbs + top limb (shared per poly), acc limb, 4 input limbs; writes 1
+        return items * 6 * lb
+    return items * 2 * lb
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--plain-pairs", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requests are independent; see DESIGN.md for how the work would shard)")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2110_13638_amd import _native as nat
+    from paper_2110_13638_amd import ckks
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    primes = nat.ckks_find_primes(LOG_N, Q_BITS + P_BITS)
+    q, p = primes[: len(Q_BITS)], primes[len(Q_BITS):]
+    ctx = ckks.Context(LOG_N, q, p, DNUM, device=dev).keygen(1)
+    N = ctx.N
+    top = len(q) - 1
+    B = args.batch
+    log("setup: N=2^%d, %d data + %d special primes, dnum=%d, batch %d" % (LOG_N, len(q), len(p), DNUM, B))
+
+    # ---- inputs: B pairs at 16 limbs, uniform residues (seeded, on device)
+    res = S.residues_device(0, q, N, 4 * B, dev).view(B, 2, 2, len(q), N)
+    A = [ckks.Ciphertext(ctx, res[i, 0], 2, top, 1.0) for i in range(B)]
+    Bc = [ckks.Ciphertext(ctx, res[i, 1], 2, top, 1.0) for i in range(B)]
+    outs = [ctx.new_ct(2, top - 1, 1.0) for _ in range(B)]
+    ws, wb = ctx.ws_for(nat.CKKS_OP_HMULT, B, [top] * B)
+    sa, sb, so = ctx._structs(A), ctx._structs(Bc), ctx._structs(outs)
+    rk = ctx.rk.data_ptr()
+
+    def step():
+        nat.ckks_hmult_relin_rescale(ctx.h, rk, sa, sb, so, ws, wb, ctx.stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nat.ckks_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nat.ckks_profile_enable(False)
+    recs = nat.ckks_profile_collect()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
+
+    # per-kernel breakdown
+    fam = {}
+    for name, items, ms in recs:
+        f = fam.setdefault(name, [0, 0.0, 0])
+        f[0] += 1
+        f[1] += ms
+        f[2] = items
+    breakdown = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "items": v[2]} for k, v in fam.items()}
+    dom = max(fam, key=lambda k: fam[k][1])
+    d = breakdown[dom]
+    alg_bytes = kernel_model(dom, d["items"], ctx, top)
+    achieved = alg_bytes / (d["avg_ms"] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": d["avg_ms"]}
+
+    # ---- ragged batch (limbs 4..16)
+    levels = [l - 1 for l in S.ragged_limbs(B)]
+    RA = [ckks.Ciphertext(ctx, res[i, 0], 2, levels[i], 1.0) for i in range(B)]
+    RB = [ckks.Ciphertext(ctx, res[i, 1], 2, levels[i], 1.0) for i in range(B)]
+    rws, rwb = ctx.ws_for(nat.CKKS_OP_HMULT, B, levels)
+    ro = ctx._structs([ctx.new_ct(2, max(l - 1, 0), 1.0, stride=top) for l in levels])
+    ra, rb = ctx._structs(RA), ctx._structs(RB)
+    nat.ckks_hmult_relin_rescale(ctx.h, rk, ra, rb, ro, rws, rwb, ctx.stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rsteps = max(1, args.steps // 2)
+    for _ in range(rsteps):
+        nat.ckks_hmult_relin_rescale(ctx.h, rk, ra, rb, ro, rws, rwb, ctx.stream)
+    torch.cuda.synchronize()
+    ragged_rate = B * rsteps / (time.perf_counter() - t0)
+    log("ragged 4..16 limbs: %.1f HMult/s" % ragged_rate)
+
+    # ---- plain path: one op per launch, B = 1, unfused
+    npl = min(args.plain_pairs, B)
+    t3 = [ctx.new_ct(3, top, 1.0) for _ in range(npl)]
+    r2 = [ctx.new_ct(2, top, 1.0) for _ in range(npl)]
+    o2 = [ctx.new_ct(2, top - 1, 1.0) for _ in range(npl)]
+    ews, ewb = ctx.ws_for(nat.CKKS_OP_ELEMENTWISE, 1, [top])
+    kws, kwb = ctx.ws_for(nat.CKKS_OP_KEYSWITCH, 1, [top])
+    ws_plain = torch.empty(max(ewb, kwb) + 512, dtype=torch.uint8, device=dev)
+    wp = ckks._align(ws_plain.data_ptr())
+    wpb = ws_plain.numel() - 256
+
+    def plain(i):
+        a1, b1 = ctx._structs([A[i]]), ctx._structs([Bc[i]])
+        s3 = ctx._structs([t3[i]])
+        nat.ckks_multiply(ctx.h, a1, b1, s3, wp, wpb, ctx.stream)
+        s2 = ctx._structs([r2[i]])
+        nat.ckks_relinearize(ctx.h, rk, s3, s2, wp, wpb, ctx.stream)
+        so2 = ctx._structs([o2[i]])
+        nat.ckks_rescale(ctx.h, s2, so2, wp, wpb, ctx.stream)
+
+    plain(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(npl):
+        plain(i)
+    torch.cuda.synchronize()
+    plain_rate = npl / (time.perf_counter() - t0)
+    same = bool(torch.equal(o2[0].buf[:, :top], outs[0].buf[:, :top]))
+    log("plain path: %.1f HMult/s (batched/plain %.1fx), plain==fused: %s" % (plain_rate, value / plain_rate, same))
+
+    # ---- NTT microbench: every limb of the ragged batch (2 polys each)
+    limbs = []
+    for i in range(B):
+        for t in range(2):
+            for j in range(levels[i] + 1):
+                limbs.append((res[i, 0, t, j].data_ptr(), j))
+    ptrs = [x[0] for x in limbs]
+    pidx = [x[1] for x in limbs]
+    nws, nwb = ctx.ws_for(nat.CKKS_OP_NTT, len(limbs))
+    nat.ckks_ntt(ctx.h, ptrs, pidx, nws, nwb, ctx.stream)
+    nat.ckks_intt(ctx.h, ptrs, pidx, nws, nwb, ctx.stream)
+    torch.cuda.synchronize()
+    nat.ckks_profile_enable(True)
+    for _ in range(3):
+        nat.ckks_ntt(ctx.h, ptrs, pidx, nws, nwb, ctx.stream)
+        nat.ckks_intt(ctx.h, ptrs, pidx, nws, nwb, ctx.stream)
+    torch.cuda.synchronize()
+    nat.ckks_profile_enable(False)
+    nrec = nat.ckks_profile_collect()
+    fwd_ms = np.mean([r[2] for r in nrec if r[0].startswith("ntt_fwd/")])
+    inv_ms = np.mean([r[2] for r in nrec if r[0].startswith("ntt_inv/")])
+    ntt_bytes = len(limbs) * 2 * limb_bytes(N)
+    ntt = {"limbs": len(limbs), "fwd_ms": fwd_ms, "inv_ms": inv_ms,
+           "fwd_limb_ntt_per_s": len(limbs) / (fwd_ms * 1e-3),
+           "fwd_hbm_GBs": ntt_bytes / (fwd_ms * 1e-3) / 1e9,
+           "fwd_hbm_frac": ntt_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "inv_hbm_frac": ntt_bytes / (inv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "butterflies_per_s": len(limbs) * (N // 2) * LOG_N / (fwd_ms * 1e-3)}
+    log("NTT: %d limbs fwd %.3f ms (%.0f GB/s, %.1f%% HBM) inv %.3f ms" %
+        (len(limbs), fwd_ms, ntt["fwd_hbm_GBs"], 100 * ntt["fwd_hbm_frac"], inv_ms))
+
+    # ---- oracle on the host cores, bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        from concurrent.futures import ThreadPoolExecutor
+        orc = O.Oracle(LOG_N, q, p, DNUM)
+        _, sn = orc.keygen_secret(1)
+        rk_o = orc.keygen_relin(sn, 3)
+        cores = min(16, os.cpu_count() or 1)
+        host = [(A[i].residues().copy(), Bc[i].residues().copy()) for i in range(cores)]
+        t0 = time.perf_counter()
+        done = 0
+        with ThreadPoolExecutor(cores) as ex:
+            while time.perf_counter() - t0 < args.cpu_seconds or done == 0:
+                list(ex.map(lambda ab: orc.mul_relin_rescale(ab[0], ab[1], rk_o), host))
+                done += len(host)
+        cpu_el = time.perf_counter() - t0
+        want = orc.mul_relin_rescale(host[0][0], host[0][1], rk_o)
+        got = outs[0].residues()
+        cpu = {"value": done / cpu_el, "unit": "HMult+relin+rescale/s", "cores": cores, "kind": "oracle",
+               "sample": "%d HMult+relin+rescale at N=2^15, 16 limbs, dnum=4 on %d threads (%.1f s)"
+                         % (done, cores, cpu_el),
+               "gpu_matches_oracle": bool(np.array_equal(got, want))}
+        log("oracle: %.3f HMult/s on %d threads; GPU ciphertext == oracle: %s" %
+            (cpu["value"], cores, cpu["gpu_matches_oracle"]))
+
+    line = {
+        "metric": "HMult+relin+rescale/s at N=2^15,L=16; encrypted infer/s + p50/p99 latency",
+        "value": round(value, 2), "unit": "HMult+relin+rescale/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched HMult+relin+rescale, N=2^15, 16 x 50-bit data primes + 2 x 60-bit "
+                               "special primes, dnum=4, %d ciphertext pairs at 16 limbs per launch" % B,
+                   "log_n": LOG_N, "limbs": 16, "special_primes": 2, "dnum": DNUM, "batch": B},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": {"ragged_4_16_hmult_per_s": round(ragged_rate, 2),
+                  "plain_one_op_per_launch_hmult_per_s": round(plain_rate, 2),
+                  "batched_over_plain": round(value / plain_rate, 2),
+                  "plain_equals_fused": same,
+                  "ntt": ntt, "kernels": breakdown},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

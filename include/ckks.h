@@ -1,0 +1,382 @@
+/*
+ * ckks.h -- C ABI of libckks_hip.so: RNS-CKKS ciphertext arithmetic for
+ * encrypted neural-network inference on AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those the paper relies on for encrypted inference
+ * (Onoufriou, Hanheide, Leontidis, "EDLaaS: Fully Homomorphic Encryption
+ * Over Neural Network Graphs", arXiv 2110.13638):
+ *   - Sections 2.1 and 3 (FHE background; FHE and deep learning): CKKS
+ *     packs N/2 values into one polynomial; ciphertexts that interact must
+ *     share parameters and key; every multiplication consumes one prime of
+ *     the modulus chain;
+ *   - Section 4.1 (FHE parameterisation): the ciphertext container
+ *     relinearises after a ciphertext product, rescales, and switches the
+ *     higher operand down the modulus chain before a binary op;
+ *   - Sections 4.2.2-4.2.3 (CNN, Dense/ANN): conv and dense nodes are sums of
+ *     ciphertext-times-weight products plus a bias; activations are
+ *     polynomials (the square x^2 is the degree-2 case);
+ *   - Algorithms 1-5 (neuronal firing): forward traversal of a
+ *     multi-directed graph of such nodes.
+ * The integer-level conventions (NTT order, key switching, rounding,
+ * randomness) are not fixed by the paper; the ones used here are stated
+ * next to each call.
+ *
+ * Conventions
+ *   - Every call returns a status (CKKS_OK = 0 or a negative CKKS_E*).
+ *     ckks_last_error() returns a thread-local message for the last
+ *     failure. No C++ exception crosses this boundary.
+ *   - The library never allocates device memory. Every device buffer
+ *     (context tables, keys, ciphertexts, plaintexts, workspace) is owned
+ *     by the caller and sized with the *_bytes queries. Host handles
+ *     (ckks_ctx, ckks_graph) are created and destroyed by the library.
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *     Device calls are asynchronous on that stream; argument checks run
+ *     on the host before any launch, and a failing check launches nothing.
+ *   - Residues are uint64 in [0, q). A polynomial at level l has l+1 limbs
+ *     (limb i modulo data prime q_i), each N = 2^log_n residues, contiguous.
+ *     Ciphertexts and plaintexts are kept in NTT form: slot k of a limb
+ *     holds a(psi^(2 brv(k) + 1)) with psi the smallest primitive 2N-th
+ *     root of unity mod q_i (brv = log_n-bit reversal).
+ *   - Batched calls take arrays of B descriptors; B = 1 is the plain path.
+ *     Unless stated otherwise out may alias the input (in-place).
+ *   - The secret key appears only in client-side calls (keygen, decrypt),
+ *     matching the semi-honest server of the paper's threat model
+ *     (Section 2.3): the server side needs pk, relinearisation and Galois
+ *     keys only.
+ */
+#ifndef CKKS_H
+#define CKKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CKKS_OK 0
+#define CKKS_EINVAL (-1)  /* bad argument (null pointer, size, range)     */
+#define CKKS_ELEVEL (-2)  /* operands at different levels                */
+#define CKKS_ESCALE (-3)  /* operands at different scales                */
+#define CKKS_EDEPTH (-4)  /* no prime left to rescale / out of levels    */
+#define CKKS_ENOKEY (-5)  /* Galois key for the requested step missing   */
+#define CKKS_EPARAMS (-6) /* parameters invalid (prime, N, dnum)         */
+#define CKKS_ENOMEM (-7)  /* caller buffer (workspace) too small         */
+#define CKKS_EDEVICE (-8) /* HIP runtime error                           */
+
+/* thread-local text for the last failing call on this thread */
+const char *ckks_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* parameters and context                                               */
+/* ------------------------------------------------------------------ */
+/* Parameters (the paper's parameter dictionary, Section 4.1 and Algorithm 8: scale,
+ * polynomial modulus degree, coefficient modulus chain). q[0] is the base
+ * prime that holds the final result, q[1..n_q-1] the primes consumed by
+ * rescaling, p[] the key-switching special primes (the last, "special"
+ * entry of Algorithm 8's chain). dnum = number of key-switching digits at
+ * the top level; each digit is alpha = ceil(n_q / dnum) consecutive data
+ * primes (hybrid key switching). Every prime must be 1 mod 2N, distinct,
+ * and below 2^61. log_n in [10, 15]. */
+typedef struct {
+    uint32_t log_n;
+    uint32_t n_q;
+    const uint64_t *q;
+    uint32_t n_p;
+    const uint64_t *p;
+    uint32_t dnum;
+} ckks_params;
+
+typedef struct ckks_ctx ckks_ctx;
+
+/* Prime chain rule used for every configuration: for each requested bit
+ * size, in list order, the largest prime below 2^bits that is 1 mod 2N
+ * and not already chosen. out[n]. */
+int ckks_find_primes(uint32_t log_n, const uint32_t *bits, uint32_t n, uint64_t *out);
+
+/* Algorithm 8 (heuristic parameterisation): maximal group cost c, scale
+ * power s, special-prime multiplier p -> bit sizes [s*p, s x c, s*p]
+ * (c+2 entries, written to bits_out) and N = 1024 * b / 27 where b
+ * doubles from 27 until it covers the bit sum. */
+int ckks_parameterise(uint32_t cost, uint32_t scale_bits, double special_mult,
+                      uint32_t *bits_out, uint32_t bits_cap, uint32_t *n_bits, uint32_t *log_n);
+
+/* Builds host-side tables (twiddles with Shoup companions, basis
+ * conversion constants). No device work. */
+int ckks_ctx_create(const ckks_params *params, ckks_ctx **out);
+void ckks_ctx_destroy(ckks_ctx *ctx);
+
+/* Device bytes for the context tables, and their upload into a caller
+ * buffer of at least that size (256-byte aligned). Must precede every
+ * device call. The host copy stays alive until ckks_ctx_destroy. */
+size_t ckks_ctx_device_bytes(const ckks_ctx *ctx);
+int ckks_ctx_upload(ckks_ctx *ctx, void *dev, void *stream);
+
+uint32_t ckks_ctx_log_n(const ckks_ctx *ctx);
+uint32_t ckks_ctx_max_level(const ckks_ctx *ctx);       /* n_q - 1 */
+uint32_t ckks_ctx_digits(const ckks_ctx *ctx, uint32_t level); /* ceil((l+1)/alpha) */
+/* prime by index: 0..n_q-1 data, n_q.. special. 0 if out of range */
+uint64_t ckks_ctx_prime(const ckks_ctx *ctx, uint32_t index);
+
+/* ------------------------------------------------------------------ */
+/* objects                                                              */
+/* ------------------------------------------------------------------ */
+/* Ciphertext: device buffer, poly t limb i at data + (t*limb_stride+i)*N.
+ * limb_stride >= level + 1 is the number of limbs allocated per poly, so
+ * that switching down the modulus chain (the level matching of Section 4.1)
+ * is a change of 'level' only. n_poly is 2, or 3 straight after a
+ * tensor product. */
+typedef struct {
+    uint64_t *data;
+    uint32_t n_poly;
+    uint32_t level;
+    uint32_t limb_stride;
+    uint32_t reserved;
+    double scale;
+} ckks_ct;
+
+/* Plaintext: device buffer [level+1][N] in NTT form. */
+typedef struct {
+    uint64_t *data;
+    uint32_t level;
+    uint32_t reserved;
+    double scale;
+} ckks_pt;
+
+size_t ckks_ct_bytes(const ckks_ctx *ctx, uint32_t n_poly, uint32_t level);
+size_t ckks_pt_bytes(const ckks_ctx *ctx, uint32_t level);
+
+#define CKKS_KEY_SECRET 0 /* [n_q+n_p][N], NTT form over every prime     */
+#define CKKS_KEY_PUBLIC 1 /* [2][n_q][N]: (b = -a s + e, a)               */
+#define CKKS_KEY_SWITCH 2 /* [digits][2][n_q+n_p][N]: relin or one Galois */
+size_t ckks_key_bytes(const ckks_ctx *ctx, int kind);
+
+/* ------------------------------------------------------------------ */
+/* workspace                                                            */
+/* ------------------------------------------------------------------ */
+#define CKKS_OP_NTT 0        /* count = number of limbs                  */
+#define CKKS_OP_ELEMENTWISE 1 /* add, sub, plain and scalar ops, tensor   */
+#define CKKS_OP_KEYSWITCH 2  /* relinearize / rotate                     */
+#define CKKS_OP_RESCALE 3
+#define CKKS_OP_HMULT 4      /* hmult_relin_rescale                      */
+#define CKKS_OP_KEYGEN 5
+#define CKKS_OP_ENCRYPT 6
+#define CKKS_OP_LINEAR 7     /* count = n_out, levels[0] = level, levels[1] = n_in */
+/* Workspace bytes for B operations at the given levels (levels[b] for
+ * b < B; NULL = every operand at the top level). */
+size_t ckks_workspace_bytes(const ckks_ctx *ctx, int op, uint32_t B, const uint32_t *levels);
+
+/* ------------------------------------------------------------------ */
+/* NTT primitives (batched over limbs of any prime)                     */
+/* ------------------------------------------------------------------ */
+/* In place forward / inverse negacyclic NTT of n limbs; limbs[i] points
+ * at N residues modulo prime index prime_idx[i]. Output fully reduced. */
+int ckks_ntt(const ckks_ctx *ctx, uint64_t *const *limbs, const uint32_t *prime_idx, uint32_t n,
+             void *ws, size_t ws_bytes, void *stream);
+int ckks_intt(const ckks_ctx *ctx, uint64_t *const *limbs, const uint32_t *prime_idx, uint32_t n,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* client side: keys, encoding, encryption, decryption                  */
+/* ------------------------------------------------------------------ */
+/* Randomness: Philox4x32-10 keyed by the 64-bit seed, counter =
+ * (coefficient index, limb index or 0xFFFFFFFF, object id, domain tag).
+ * Ternary = ((w0 * 3) >> 32) - 1; error = centred binomial
+ * popcount(w0 & 0x1FFFFF) - popcount(w1 & 0x1FFFFF); uniform = the
+ * 128-bit word mod q, drawn directly in the NTT domain. */
+
+/* secret s (ternary, tag 1), written in NTT form over every prime */
+int ckks_keygen_secret(const ckks_ctx *ctx, uint64_t seed, uint64_t *sk, void *ws, size_t ws_bytes,
+                       void *stream);
+/* pk = (-a s + e, a) over the data primes: a tag 2, e tag 3, object 0 */
+int ckks_keygen_public(const ckks_ctx *ctx, const uint64_t *sk, uint64_t seed, uint64_t *pk,
+                       void *ws, size_t ws_bytes, void *stream);
+/* Switching key s^2 -> s (key id 0). For every top-level digit j:
+ * a_j uniform (tag 4), e_j error (tag 5), object (key_id << 8) | j,
+ * b_j = -a_j s + e_j + [i in digit j] (P mod q_i) s' mod each prime,
+ * with P the product of the special primes. */
+int ckks_keygen_relin(const ckks_ctx *ctx, const uint64_t *sk, uint64_t seed, uint64_t *rk,
+                      void *ws, size_t ws_bytes, void *stream);
+/* Switching key sigma_g(s) -> s for Galois element g (odd, < 2N), key id g. */
+int ckks_keygen_galois(const ckks_ctx *ctx, const uint64_t *sk, uint32_t galois_elt, uint64_t seed,
+                       uint64_t *gk, void *ws, size_t ws_bytes, void *stream);
+/* Galois element for a left rotation of the N/2 slots by step (negative
+ * = right): 5^(step mod N/2) mod 2N. Conjugation is 2N - 1. */
+uint32_t ckks_galois_elt(const ckks_ctx *ctx, int32_t step);
+
+/* Host FP64 encoder (canonical embedding; slot j <-> zeta^(5^j),
+ * zeta = exp(i pi / N)): n <= N/2 values (im may be NULL), zero padded,
+ * coefficients round_half_away(scale * sigma^-1(z)) into coeffs[N].
+ * CKKS_EINVAL when a coefficient would reach 2^62. */
+int ckks_encode(const ckks_ctx *ctx, const double *re, const double *im, size_t n, double scale,
+                int64_t *coeffs);
+/* Host decoder from decrypted residues in coefficient form
+ * ([level+1][N], host memory): exact centred CRT lift, then
+ * slots = m(zeta^(5^j)) / scale for j < n. im may be NULL. */
+int ckks_decode(const ckks_ctx *ctx, const uint64_t *residues, uint32_t level, double scale,
+                double *re, double *im, size_t n);
+/* Integer polynomial (device int64[N]) -> device plaintext in NTT form
+ * at out->level; out->scale is left as set by the caller. */
+int ckks_pt_load(const ckks_ctx *ctx, const int64_t *coeffs, ckks_pt *out, void *ws,
+                 size_t ws_bytes, void *stream);
+/* Public-key encryption at pt->level: v ternary (tag 6), e0, e1 errors
+ * (tags 7, 8), object obj: ct = (v b + e0 + m, v a + e1). out->scale =
+ * pt->scale, out->level = pt->level. */
+int ckks_encrypt(const ckks_ctx *ctx, const uint64_t *pk, const ckks_pt *pt, uint64_t seed,
+                 uint32_t obj, ckks_ct *out, void *ws, size_t ws_bytes, void *stream);
+/* m = c0 + c1 s (+ c2 s^2) in coefficient form into m[level+1][N]
+ * (device). */
+int ckks_decrypt(const ckks_ctx *ctx, const uint64_t *sk, const ckks_ct *ct, uint64_t *m, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* server side: evaluation (batched, B >= 1)                            */
+/* ------------------------------------------------------------------ */
+/* Binary ops need equal levels (CKKS_ELEVEL) and bit-equal scales
+ * (CKKS_ESCALE); ckks_mod_switch_to lowers the higher operand first. */
+int ckks_add(const ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, uint32_t B,
+             void *ws, size_t ws_bytes, void *stream);
+int ckks_sub(const ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, uint32_t B,
+             void *ws, size_t ws_bytes, void *stream);
+int ckks_add_plain(const ckks_ctx *ctx, const ckks_ct *a, const ckks_pt *p, ckks_ct *out,
+                   uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* ct x pt (Hadamard product of slots); out scale = a.scale * p.scale */
+int ckks_multiply_plain(const ckks_ctx *ctx, const ckks_ct *a, const ckks_pt *p, ckks_ct *out,
+                        uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* ct x constant: v[b] is the integer constant polynomial round(c * s_c);
+ * out scale = a.scale * v_scale[b] */
+int ckks_multiply_scalar(const ckks_ctx *ctx, const ckks_ct *a, const int64_t *v,
+                         const double *v_scale, ckks_ct *out, uint32_t B, void *ws,
+                         size_t ws_bytes, void *stream);
+/* ct + constant polynomial v[b] (already at the ciphertext's scale) */
+int ckks_add_scalar(const ckks_ctx *ctx, const ckks_ct *a, const int64_t *v, ckks_ct *out,
+                    uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* tensor: out (n_poly 3) = (a0 b0, a0 b1 + a1 b0, a1 b1), scale product */
+int ckks_multiply(const ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_ct *out3,
+                  uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* hybrid key switch of c2 with the relinearisation key:
+ * out = (c0 + ks0, c1 + ks1). ModUp is the approximate basis conversion
+ * of each digit; ModDown subtracts the conversion of the special-prime
+ * part and multiplies by P^-1. out must not alias in3. */
+int ckks_relinearize(const ckks_ctx *ctx, const uint64_t *rk, const ckks_ct *in3, ckks_ct *out,
+                     uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* rescale by the top prime q_l: c' = floor((c + floor(q_l/2)) / q_l)
+ * coefficient-wise, scale / q_l, level - 1. out may alias in. */
+int ckks_rescale(const ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws,
+                 size_t ws_bytes, void *stream);
+/* modulus-chain level match: a view change (no device work) */
+int ckks_mod_switch_to(const ckks_ctx *ctx, ckks_ct *inout, uint32_t level);
+/* slot rotation: X -> X^g on both polys, then key switch of the second
+ * with the Galois key for g: out = (sigma(c0) + ks0, ks1). All B use
+ * the same key. out must not alias in. */
+int ckks_rotate(const ckks_ctx *ctx, const uint64_t *gk, uint32_t galois_elt, const ckks_ct *in,
+                ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream);
+/* Fused, batched HMult + relinearise + rescale (the ciphertext product as
+ * the container performs it): out[b] = rescale(relin(a[b] x b[b])),
+ * ragged levels allowed. Bit-identical to the three calls in sequence. */
+int ckks_hmult_relin_rescale(const ckks_ctx *ctx, const uint64_t *rk, const ckks_ct *a,
+                             const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws,
+                             size_t ws_bytes, void *stream);
+/* Encrypted linear layer with integer weights (conv and dense of the
+ * paper's Sections 4.2.2-4.2.3, weights encoded as constant polynomials):
+ * out[j] = sum_i W[j * n_in + i] * in[i]  for j < n_out, W device int64.
+ * All inputs at one level and scale; out scale = in.scale * w_scale. */
+int ckks_linear(const ckks_ctx *ctx, const ckks_ct *in, uint32_t n_in, const int64_t *W,
+                double w_scale, ckks_ct *out, uint32_t n_out, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* Sparse form of the same layer (the strided cross-correlation of
+ * Section 4.2.2 touches at most k x k inputs per output): row j is
+ * sum_{e in [row_ptr[j], row_ptr[j+1])} w[e] * in[col[e]]. Host arrays;
+ * consecutive rows with identical column lists are evaluated together so
+ * each input residue is loaded once per group. */
+size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *ctx, uint32_t n_in, uint32_t n_out, size_t nnz,
+                                       uint32_t level);
+int ckks_linear_csr(const ckks_ctx *ctx, const ckks_ct *in, uint32_t n_in, uint32_t n_out,
+                    const uint32_t *row_ptr, const uint32_t *col, const int64_t *w, double w_scale,
+                    ckks_ct *out, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* graph traversal (Algorithms 1-5, forward receptor only)              */
+/* ------------------------------------------------------------------ */
+/* A multi-directed graph of encrypted layers (Section 4): every edge
+ * carries a signal (a list of ciphertexts); a node fires once every
+ * in-edge carries one, its inputs are the in-edge signals stacked in edge
+ * insertion order (levels matched by switching down to the lowest), and
+ * its result is broadcast to all out-edges. Parallel edges are separate
+ * edges. Receptors:
+ *   INPUT       the run's input ciphertexts (attrs: ckks_input_attrs);
+ *   LINEAR      conv / dense: row j = sum_e round(w[e] w_scale) in[col[e]],
+ *               rescale, + round(bias[j] * scale) (ckks_linear_attrs);
+ *   DIAG_DENSE  rotation-based matvec on each input ciphertext:
+ *               sum_i diag_i (x) rot(x, in_steps[i]), rescale, then
+ *               x += rot(x, r) for every post step, + bias plaintext;
+ *               steps without their own Galois key are composed from
+ *               power-of-two keys in non-adjacent form (ckks_diag_attrs);
+ *   SQUARE      x^2: ckks_hmult_relin_rescale(x, x) on each ciphertext;
+ *   OUTPUT      collects its signal as run outputs (node order). */
+typedef struct ckks_graph ckks_graph;
+#define CKKS_NODE_INPUT 0
+#define CKKS_NODE_LINEAR 1
+#define CKKS_NODE_DIAG_DENSE 2
+#define CKKS_NODE_SQUARE 3
+#define CKKS_NODE_OUTPUT 4
+typedef struct {
+    uint32_t n_ct;
+    uint32_t level;
+    double scale;
+} ckks_input_attrs;
+typedef struct {
+    uint32_t n_out;
+    const uint32_t *row_ptr; /* [n_out + 1] */
+    const uint32_t *col;     /* [nnz], index into the node's stacked inputs */
+    const double *w;         /* [nnz] */
+    double w_scale;          /* weights become round(w * w_scale) */
+    const double *bias;      /* [n_out] or NULL */
+} ckks_linear_attrs;
+typedef struct {
+    uint32_t n_diag;
+    const int32_t *in_steps;     /* [n_diag], 0 = no rotation */
+    const int64_t *diag_coeffs;  /* [n_diag][N] integer plaintexts at pt_scale */
+    double pt_scale;
+    uint32_t n_post;
+    const int32_t *post_steps;   /* [n_post] rotate-and-sum steps */
+    const double *bias_slots;    /* [n_bias_slots] or NULL: encoded at plan */
+    uint32_t n_bias_slots;
+    const int64_t *bias_coeffs;  /* [N] integer plaintext at the output scale, or NULL */
+} ckks_diag_attrs;
+int ckks_graph_create(const ckks_ctx *ctx, ckks_graph **out);
+void ckks_graph_destroy(ckks_graph *g);
+/* attributes are copied */
+int ckks_graph_add_node(ckks_graph *g, int kind, const void *attrs, uint32_t *id);
+int ckks_graph_add_edge(ckks_graph *g, uint32_t from, uint32_t to);
+/* Dry traversal: output count, levels and scales of every node, and the
+ * workspace the run needs (all node outputs plus scratch). */
+int ckks_graph_plan(ckks_graph *g, size_t *ws_bytes, uint32_t *n_outputs);
+/* inputs: the ciphertexts of every INPUT node in node order, at the
+ * planned level and scale; outputs receive views into the workspace
+ * (valid until the workspace is reused). Galois keys by element. */
+int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_inputs, ckks_ct *outputs, uint32_t n_outputs,
+                   const uint64_t *rk, const uint32_t *galois_elts, const uint64_t *const *galois_keys,
+                   uint32_t n_galois, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* measurement                                                          */
+/* ------------------------------------------------------------------ */
+/* Per-launch timing: while enabled, every kernel launch of every call is
+ * bracketed by two HIP events recorded on that call's stream (process
+ * wide; not thread safe; off by default). */
+typedef struct {
+    char name[56];   /* kernel family and ring degree, e.g. "ntt_fwd/N=2^15" */
+    uint32_t items;  /* work items (workgroups or limbs) in the launch */
+    float ms;        /* event-measured duration */
+} ckks_launch_record;
+int ckks_profile_enable(int on);
+/* Waits for the recorded events, writes up to cap records (out may be
+ * NULL), the total count to *n, and clears the record list. */
+int ckks_profile_collect(ckks_launch_record *out, uint32_t cap, uint32_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKKS_H */

@@ -77,6 +77,7 @@ def lib():
             "orc_relinearize": (None, [vp, _U64P, u32, _U64P, _U64P]),
             "orc_apply_galois": (None, [vp, _U64P, u32, u64, _U64P, _U64P]),
             "orc_mul_relin_rescale": (None, [vp, _U64P, _U64P, u32, _U64P, _U64P]),
+            "orc_lincomb": (None, [vp, ctypes.POINTER(_U64P), _I64P, u32, u32, u32, _U64P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -346,6 +347,15 @@ class Oracle:
         a = _u64(a)
         out = np.zeros_like(a)
         lib().orc_automorph_ntt(self._h, prime_idx, g, _p64(a), _p64(out))
+        return out
+
+    def lincomb(self, cts, weights):
+        """sum_k weights[k] * cts[k] (integer weights, one level)"""
+        cts = [_u64(c) for c in cts]
+        arr = (_U64P * len(cts))(*[_p64(c) for c in cts])
+        w = np.ascontiguousarray(weights, dtype=np.int64)
+        out = np.zeros_like(cts[0])
+        lib().orc_lincomb(self._h, arr, _pi64(w), len(cts), cts[0].shape[0], cts[0].shape[1] - 1, _p64(out))
         return out
 
     def mul_relin_rescale(self, a, b, rk):

@@ -780,3 +780,23 @@ void orc_mul_relin_rescale(const orc_ctx *c, const u64 *a, const u64 *b, u32 lev
     orc_rescale(c, t2, 2, level, out);
     free(t3); free(t2);
 }
+
+/* sum_k w_k * ct_k over n ciphertexts (same level, n_poly polys each):
+ * the definition of a linear layer with integer weights (each weight a
+ * constant polynomial), evaluated residue by residue. */
+void orc_lincomb(const orc_ctx *c, const u64 *const *cts, const i64 *w, u32 n, u32 n_poly, u32 level,
+                 u64 *out)
+{
+    u32 nn_ = nn(c), L = level + 1;
+    for (u32 p = 0; p < n_poly; p++)
+        for (u32 i = 0; i < L; i++) {
+            u64 q = c->q[i];
+            u64 *o = out + ((size_t)p * L + i) * nn_;
+            for (u32 j = 0; j < nn_; j++) o[j] = 0;
+            for (u32 k = 0; k < n; k++) {
+                u64 wk = reduce_signed(w[k], q);
+                const u64 *x = cts[k] + ((size_t)p * L + i) * nn_;
+                for (u32 j = 0; j < nn_; j++) o[j] = addmod(o[j], mulmod(x[j], wk, q), q);
+            }
+        }
+}

@@ -1,0 +1,121 @@
+"""Encrypted lowerings of the benchmark networks, on the oracle's
+primitives.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+The paper builds conv and dense nodes as sums of ciphertext x weight
+products plus a bias (Sections 4.2.2-4.2.3; its Equation for the biased
+cross-correlation), uses a polynomial activation, and lets the ciphertext
+container rescale after every product (Section 4.1). The op sequence of
+each layer below is fixed so that the GPU path can reproduce it bit for
+bit:
+
+  linear layer (integer weights round(w * 2^40)):
+      acc = sum_k w_k ct_k ; acc = rescale(acc) ; acc = acc + round(b * scale)
+  diagonal (rotation-based) dense layer:
+      acc = sum_i diag_i (x) rot(x, in_steps[i]) ; acc = rescale(acc) ;
+      for r in post_steps: acc = acc + rot(acc, r) ; acc = acc + bias_pt
+  square activation: rescale(relinearise(x (x) x))
+
+Rotations by a step that has its own Galois key use it directly;
+otherwise the step is composed from power-of-two keys in non-adjacent form,
+least significant digit first.
+"""
+import numpy as np
+
+from . import plainnet as PN
+
+
+def galois_seed(base, g):
+    """seed of the Galois key for element g (both sides derive it so)"""
+    return base + g
+
+
+class Keys:
+    """Oracle keys derived from one seed: secret (seed), public (seed + 1),
+    relinearisation (seed + 2), Galois for element g (seed + 3 + g)."""
+
+    def __init__(self, orc, seed, galois_elts=()):
+        self.orc = orc
+        self.s, self.sn = orc.keygen_secret(seed)
+        self.pk = orc.keygen_public(self.sn, seed + 1)
+        self.rk = orc.keygen_relin(self.sn, seed + 2)
+        self.seed = seed
+        self.gk = {}
+        for g in galois_elts:
+            self.add_galois(g)
+
+    def add_galois(self, g):
+        if g not in self.gk:
+            self.gk[g] = self.orc.keygen_galois(self.s, self.sn, g, galois_seed(self.seed + 3, g))
+        return self.gk[g]
+
+
+def rotate(orc, keys, ct, step):
+    half = orc.N // 2
+    step %= half
+    if step == 0:
+        return ct
+    g = orc.galois_elt(step)
+    if g in keys.gk:
+        return orc.apply_galois(ct, g, keys.gk[g])
+    # signed step in (-N/4, N/4], composed in non-adjacent form
+    s = step if step <= half // 2 else step - half
+    for k, d in PN.naf(s):
+        gk = orc.galois_elt(d * (1 << k))
+        ct = orc.apply_galois(ct, gk, keys.gk[gk])
+    return ct
+
+
+def naf_elements(orc, steps):
+    """Galois elements needed to compose the given steps from powers of two"""
+    half = orc.N // 2
+    out = set()
+    for st in steps:
+        st %= half
+        if st == 0:
+            continue
+        s = st if st <= half // 2 else st - half
+        for k, d in PN.naf(s):
+            out.add(orc.galois_elt(d * (1 << k)))
+    return sorted(out)
+
+
+def linear(orc, cts, scale, rows, w_scale, biases):
+    """rows[j] = [(input index, weight)], biases[j] float or None.
+    Returns (output cts, output scale)."""
+    level = cts[0].shape[1] - 1
+    q_top = orc.q[level]
+    out_scale = scale * w_scale / q_top
+    outs = []
+    for j, row in enumerate(rows):
+        idx = [i for i, _ in row]
+        w = [int(np.sign(x * w_scale) * np.floor(abs(x * w_scale) + 0.5)) for _, x in row]
+        acc = orc.lincomb([cts[i] for i in idx], w)
+        acc = orc.rescale(acc)
+        if biases is not None and biases[j] is not None:
+            acc = orc.add_const(acc, int(np.sign(biases[j] * out_scale) * np.floor(abs(biases[j] * out_scale) + 0.5)))
+        outs.append(acc)
+    return outs, out_scale
+
+
+def square(orc, keys, ct, scale):
+    return orc.mul_relin_rescale(ct, ct, keys.rk), scale * scale / orc.q[ct.shape[1] - 1]
+
+
+def diag_dense(orc, keys, ct, scale, diag_pts, pt_scale, in_steps, post_steps, bias_pt=None):
+    """diag_pts: NTT-form plaintexts at the ciphertext's level (integer
+    encodings at pt_scale); bias_pt: NTT-form plaintext at the level and
+    scale after the rescale, or None."""
+    acc = None
+    for pt, st in zip(diag_pts, in_steps):
+        t = orc.mul_plain(rotate(orc, keys, ct, st), pt)
+        acc = t if acc is None else orc.add(acc, t)
+    level = ct.shape[1] - 1
+    acc = orc.rescale(acc)
+    out_scale = scale * pt_scale / orc.q[level]
+    for st in post_steps:
+        acc = orc.add(acc, rotate(orc, keys, acc, st))
+    if bias_pt is not None:
+        acc = orc.add_plain(acc, bias_pt)
+    return acc, out_scale

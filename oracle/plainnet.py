@@ -1,0 +1,214 @@
+"""FP64 plaintext networks: the paper's validation method (Section 5:
+the same graph is run on plain arrays and on ciphertexts and the results
+are compared).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+Each network exists twice:
+  * ``*_math``: the plain network as written (matrix products, x^2);
+  * ``*_packed``: the same computation on one FP64 slot vector laid out as
+    the encrypted lowering lays it out, with np.roll for slot rotations
+    (left rotation by r: slot j <- slot j + r). Agreement of the two to
+    1e-12 pins the packing algebra (diagonals, rotate-and-sum) before any
+    encryption is involved.
+"""
+import numpy as np
+
+
+def naf(n):
+    """Non-adjacent form of a signed integer, least significant digit
+    first: list of (position, +1 / -1)."""
+    out = []
+    k = 0
+    while n != 0:
+        if n & 1:
+            d = 2 - (n & 3)  # +1 or -1
+            out.append((k, d))
+            n -= d
+        n >>= 1
+        k += 1
+    return out
+
+
+# ---------------------------------------------------------------------------
+# tiny dense: 16 features x 256 samples in 4096 slots, dense 16->8, x^2
+# ---------------------------------------------------------------------------
+def tiny_dense_math(x, W):
+    """x [16][256], W [8][16] -> (W x)^2 [8][256]"""
+    return (W @ x) ** 2
+
+
+def tiny_dense_layout(n_in=16, n_samples=256):
+    """feature-major: slot f * n_samples + w"""
+    return n_in * n_samples
+
+
+def tiny_dense_diagonals(W, n_samples=256):
+    """d_i[f * S + w] = W[f mod n_out][(f + i) mod n_in] for i < n_out"""
+    n_out, n_in = W.shape
+    d = np.zeros((n_out, n_in * n_samples))
+    for i in range(n_out):
+        for f in range(n_in):
+            d[i, f * n_samples:(f + 1) * n_samples] = W[f % n_out, (f + i) % n_in]
+    return d
+
+
+def tiny_dense_steps(n_in=16, n_out=8, n_samples=256):
+    """input rotations (i * S for i < n_out) and the rotate-and-sum steps"""
+    in_steps = [i * n_samples for i in range(n_out)]
+    post = []
+    span = n_out
+    while span < n_in:
+        post.append(span * n_samples)
+        span *= 2
+    return in_steps, post
+
+
+def tiny_dense_packed(x, W):
+    n_out, n_in = W.shape
+    S = x.shape[1]
+    v = x.reshape(-1)
+    d = tiny_dense_diagonals(W, S)
+    in_steps, post = tiny_dense_steps(n_in, n_out, S)
+    y = sum(d[i] * np.roll(v, -in_steps[i]) for i in range(n_out))
+    for r in post:
+        y = y + np.roll(y, -r)
+    y = y * y
+    return y[: n_out * S].reshape(n_out, S)
+
+
+# ---------------------------------------------------------------------------
+# vision: slot-batched, one ciphertext per pixel
+# ---------------------------------------------------------------------------
+def vision_conv_rows(conv_w, side=28, stride=2):
+    """Output (o, y, x) of the strided cross-correlation as a sparse row:
+    [(pixel index, weight)], pixels outside the image (the zero padding of
+    one bottom row and one right column) contribute nothing."""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    rows = []
+    for o in range(F):
+        for y in range(out_side):
+            for xx in range(out_side):
+                row = []
+                for dy in range(k):
+                    for dx in range(k):
+                        r, c = stride * y + dy, stride * xx + dx
+                        if r < side and c < side:
+                            row.append((r * side + c, conv_w[o, dy, dx]))
+                rows.append(row)
+    return rows, out_side
+
+
+def vision_math(x, P):
+    """x [n][28][28] -> logits [n][10]"""
+    n, side, _ = x.shape
+    F, k, _ = P["conv_w"].shape
+    pad = np.zeros((n, side + 1, side + 1))
+    pad[:, :side, :side] = x
+    out_side = (side + 1 - k) // 2 + 1
+    conv = np.zeros((n, F, out_side, out_side))
+    for o in range(F):
+        for y in range(out_side):
+            for xx in range(out_side):
+                patch = pad[:, 2 * y:2 * y + k, 2 * xx:2 * xx + k]
+                conv[:, o, y, xx] = np.tensordot(patch, P["conv_w"][o], axes=([1, 2], [0, 1])) + P["conv_b"][o]
+    h = (conv ** 2).reshape(n, -1)
+    h = (h @ P["w1"].T + P["b1"]) ** 2
+    return h @ P["w2"].T + P["b2"]
+
+
+def vision_packed(x, P):
+    """Same network on the per-pixel slot vectors (slot s = image s)."""
+    n, side, _ = x.shape
+    pix = x.reshape(n, -1).T  # [784][n]
+    rows, _ = vision_conv_rows(P["conv_w"], side)
+    F = P["conv_w"].shape[0]
+    per = len(rows) // F
+    conv = np.stack([sum(w * pix[i] for i, w in row) + P["conv_b"][j // per] for j, row in enumerate(rows)])
+    h = conv ** 2
+    h = np.stack([P["w1"][j] @ h + P["b1"][j] for j in range(P["w1"].shape[0])]) ** 2
+    out = np.stack([P["w2"][j] @ h + P["b2"][j] for j in range(P["w2"].shape[0])])
+    return out.T
+
+
+# ---------------------------------------------------------------------------
+# yield regressor: feature-major packing, rotation-based matvec
+# ---------------------------------------------------------------------------
+def yield_math(x, ws, bs):
+    h = (x @ ws[0].T + bs[0]) ** 2
+    h = (h @ ws[1].T + bs[1]) ** 2
+    return h @ ws[2].T + bs[2]
+
+
+def yield_layout(slots, n_feat=256):
+    """windows per ciphertext W = slots / 256; slot f * W + w"""
+    return slots // n_feat
+
+
+def yield_pack(x, slots, n_feat=256):
+    """x [n][147] -> slot vectors [n_ct][slots] (zero padded features)"""
+    W = yield_layout(slots, n_feat)
+    n = x.shape[0]
+    n_ct = -(-n // W)
+    v = np.zeros((n_ct, n_feat, W))
+    for c in range(n_ct):
+        blk = x[c * W:(c + 1) * W]
+        v[c, : blk.shape[1], : blk.shape[0]] = blk.T
+    return v.reshape(n_ct, -1)
+
+
+def yield_layer_plan(n_in, n_out, period, W):
+    """Hybrid diagonal layer on an input that is `period`-periodic in the
+    feature index (period = 256 for the first layer): diagonals i < n_out
+    with d_i[f] = M[f mod n_out][(f + i) mod period] (zero beyond n_in),
+    input rotations i * W, then rotate-and-sum by n_out * W, 2 n_out W, ...
+    until the span reaches the period."""
+    in_steps = [i * W for i in range(n_out)]
+    post = []
+    span = n_out
+    while span < period:
+        post.append(span * W)
+        span *= 2
+    return in_steps, post
+
+
+def yield_diagonals(M, period, W, n_feat=256):
+    n_out, n_in = M.shape
+    d = np.zeros((n_out, n_feat, W))
+    for i in range(n_out):
+        for f in range(n_feat):
+            col = (f + i) % period
+            if col < n_in:
+                d[i, f, :] = M[f % n_out, col]
+    return d.reshape(n_out, -1)
+
+
+def yield_bias_vector(b, W, n_feat=256):
+    """bias of output j at every feature block f with f mod n_out = j"""
+    n_out = len(b)
+    v = np.zeros((n_feat, W))
+    for f in range(n_feat):
+        v[f] = b[f % n_out]
+    return v.reshape(-1)
+
+
+def yield_packed(x, ws, bs, slots):
+    W = yield_layout(slots)
+    v = yield_pack(x, slots)
+    periods = [256, 64, 16]
+    outs = []
+    for c in range(v.shape[0]):
+        y = v[c]
+        for layer in range(3):
+            M, b = ws[layer], bs[layer]
+            n_out = M.shape[0]
+            in_steps, post = yield_layer_plan(M.shape[1], n_out, periods[layer], W)
+            d = yield_diagonals(M, periods[layer], W)
+            z = sum(d[i] * np.roll(y, -in_steps[i]) for i in range(n_out))
+            for r in post:
+                z = z + np.roll(z, -r)
+            z = z + yield_bias_vector(b, W)
+            y = z ** 2 if layer < 2 else z
+        outs.append(y[:W])
+    return np.concatenate(outs)[: x.shape[0]]

@@ -1,0 +1,389 @@
+"""ctypes binding of libckks_hip.so: the C ABI declared in include/ckks.h.
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls and does no arithmetic. Loading fails loudly when the HIP
+library has not been built: there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckks_hip.so")
+
+CKKS_OK = 0
+CKKS_EINVAL, CKKS_ELEVEL, CKKS_ESCALE, CKKS_EDEPTH = -1, -2, -3, -4
+CKKS_ENOKEY, CKKS_EPARAMS, CKKS_ENOMEM, CKKS_EDEVICE = -5, -6, -7, -8
+ERROR_NAMES = {-1: "EINVAL", -2: "ELEVEL", -3: "ESCALE", -4: "EDEPTH", -5: "ENOKEY", -6: "EPARAMS",
+               -7: "ENOMEM", -8: "EDEVICE"}
+
+CKKS_KEY_SECRET, CKKS_KEY_PUBLIC, CKKS_KEY_SWITCH = 0, 1, 2
+(CKKS_OP_NTT, CKKS_OP_ELEMENTWISE, CKKS_OP_KEYSWITCH, CKKS_OP_RESCALE, CKKS_OP_HMULT, CKKS_OP_KEYGEN,
+ CKKS_OP_ENCRYPT, CKKS_OP_LINEAR) = range(8)
+
+
+class CkksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERROR_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class ckks_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q", ctypes.POINTER(ctypes.c_uint64)),
+                ("n_p", ctypes.c_uint32), ("p", ctypes.POINTER(ctypes.c_uint64)), ("dnum", ctypes.c_uint32)]
+
+
+class ckks_ct(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n_poly", ctypes.c_uint32), ("level", ctypes.c_uint32),
+                ("limb_stride", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
+class ckks_pt(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("level", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("scale", ctypes.c_double)]
+
+
+class ckks_launch_record(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 56), ("items", ctypes.c_uint32), ("ms", ctypes.c_float)]
+
+
+class ckks_input_attrs(ctypes.Structure):
+    _fields_ = [("n_ct", ctypes.c_uint32), ("level", ctypes.c_uint32), ("scale", ctypes.c_double)]
+
+
+class ckks_linear_attrs(ctypes.Structure):
+    _fields_ = [("n_out", ctypes.c_uint32), ("row_ptr", ctypes.POINTER(ctypes.c_uint32)),
+                ("col", ctypes.POINTER(ctypes.c_uint32)), ("w", ctypes.POINTER(ctypes.c_double)),
+                ("w_scale", ctypes.c_double), ("bias", ctypes.POINTER(ctypes.c_double))]
+
+
+class ckks_diag_attrs(ctypes.Structure):
+    _fields_ = [("n_diag", ctypes.c_uint32), ("in_steps", ctypes.POINTER(ctypes.c_int32)),
+                ("diag_coeffs", ctypes.POINTER(ctypes.c_int64)), ("pt_scale", ctypes.c_double),
+                ("n_post", ctypes.c_uint32), ("post_steps", ctypes.POINTER(ctypes.c_int32)),
+                ("bias_slots", ctypes.POINTER(ctypes.c_double)), ("n_bias_slots", ctypes.c_uint32),
+                ("bias_coeffs", ctypes.POINTER(ctypes.c_int64))]
+
+
+CKKS_NODE_INPUT, CKKS_NODE_LINEAR, CKKS_NODE_DIAG_DENSE, CKKS_NODE_SQUARE, CKKS_NODE_OUTPUT = range(5)
+
+_u32, _u64, _i32, _sz, _vp, _dbl = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t,
+                                    ctypes.c_void_p, ctypes.c_double)
+_P = ctypes.POINTER
+_SIGS = {
+    "ckks_last_error": (ctypes.c_char_p, []),
+    "ckks_find_primes": (ctypes.c_int, [_u32, _P(_u32), _u32, _P(_u64)]),
+    "ckks_parameterise": (ctypes.c_int, [_u32, _u32, _dbl, _P(_u32), _u32, _P(_u32), _P(_u32)]),
+    "ckks_ctx_create": (ctypes.c_int, [_P(ckks_params), _P(_vp)]),
+    "ckks_ctx_destroy": (None, [_vp]),
+    "ckks_ctx_device_bytes": (_sz, [_vp]),
+    "ckks_ctx_upload": (ctypes.c_int, [_vp, _vp, _vp]),
+    "ckks_ctx_log_n": (_u32, [_vp]),
+    "ckks_ctx_max_level": (_u32, [_vp]),
+    "ckks_ctx_digits": (_u32, [_vp, _u32]),
+    "ckks_ctx_prime": (_u64, [_vp, _u32]),
+    "ckks_ct_bytes": (_sz, [_vp, _u32, _u32]),
+    "ckks_pt_bytes": (_sz, [_vp, _u32]),
+    "ckks_key_bytes": (_sz, [_vp, ctypes.c_int]),
+    "ckks_workspace_bytes": (_sz, [_vp, ctypes.c_int, _u32, _P(_u32)]),
+    "ckks_ntt": (ctypes.c_int, [_vp, _P(_vp), _P(_u32), _u32, _vp, _sz, _vp]),
+    "ckks_intt": (ctypes.c_int, [_vp, _P(_vp), _P(_u32), _u32, _vp, _sz, _vp]),
+    "ckks_keygen_secret": (ctypes.c_int, [_vp, _u64, _vp, _vp, _sz, _vp]),
+    "ckks_keygen_public": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "ckks_keygen_relin": (ctypes.c_int, [_vp, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "ckks_keygen_galois": (ctypes.c_int, [_vp, _vp, _u32, _u64, _vp, _vp, _sz, _vp]),
+    "ckks_galois_elt": (_u32, [_vp, _i32]),
+    "ckks_encode": (ctypes.c_int, [_vp, _P(_dbl), _P(_dbl), _sz, _dbl, _P(ctypes.c_int64)]),
+    "ckks_decode": (ctypes.c_int, [_vp, _P(_u64), _u32, _dbl, _P(_dbl), _P(_dbl), _sz]),
+    "ckks_pt_load": (ctypes.c_int, [_vp, _vp, _P(ckks_pt), _vp, _sz, _vp]),
+    "ckks_encrypt": (ctypes.c_int, [_vp, _vp, _P(ckks_pt), _u64, _u32, _P(ckks_ct), _vp, _sz, _vp]),
+    "ckks_decrypt": (ctypes.c_int, [_vp, _vp, _P(ckks_ct), _vp, _vp, _sz, _vp]),
+    "ckks_add": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_sub": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_add_plain": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_pt), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_multiply_plain": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_pt), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_multiply_scalar": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ctypes.c_int64), _P(_dbl), _P(ckks_ct), _u32,
+                                            _vp, _sz, _vp]),
+    "ckks_add_scalar": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ctypes.c_int64), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_multiply": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_relinearize": (ctypes.c_int, [_vp, _vp, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_rescale": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_mod_switch_to": (ctypes.c_int, [_vp, _P(ckks_ct), _u32]),
+    "ckks_rotate": (ctypes.c_int, [_vp, _vp, _u32, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_hmult_relin_rescale": (ctypes.c_int, [_vp, _vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz,
+                                                _vp]),
+    "ckks_linear": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _vp, _dbl, _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_linear_csr_workspace_bytes": (_sz, [_vp, _u32, _u32, _sz, _u32]),
+    "ckks_linear_csr": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _u32, _P(_u32), _P(_u32), _P(ctypes.c_int64), _dbl,
+                                       _P(ckks_ct), _vp, _sz, _vp]),
+    "ckks_graph_create": (ctypes.c_int, [_vp, _P(_vp)]),
+    "ckks_graph_destroy": (None, [_vp]),
+    "ckks_graph_add_node": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _P(_u32)]),
+    "ckks_graph_add_edge": (ctypes.c_int, [_vp, _u32, _u32]),
+    "ckks_graph_plan": (ctypes.c_int, [_vp, _P(_sz), _P(_u32)]),
+    "ckks_graph_run": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _P(ckks_ct), _u32, _vp, _P(_u32), _P(_vp), _u32,
+                                      _vp, _sz, _vp]),
+    "ckks_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "ckks_profile_collect": (ctypes.c_int, [_P(ckks_launch_record), _u32, _P(_u32)]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libckks_hip.so is not built (run paper_2110_13638_amd/build.py); "
+                              "there is no fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def check(rc):
+    if rc != CKKS_OK:
+        raise CkksError(rc, lib().ckks_last_error().decode())
+    return rc
+
+
+def _call(name, *args):
+    return check(getattr(lib(), name)(*args))
+
+
+# one wrapper per entry point, same names as the C ABI ------------------------
+def ckks_last_error():
+    return lib().ckks_last_error().decode()
+
+
+def ckks_find_primes(log_n, bits):
+    b = (ctypes.c_uint32 * len(bits))(*bits)
+    out = (ctypes.c_uint64 * len(bits))()
+    _call("ckks_find_primes", log_n, b, len(bits), out)
+    return [int(x) for x in out]
+
+
+def ckks_parameterise(cost, scale_bits=40, special_mult=1.5):
+    cap = cost + 2
+    bits = (ctypes.c_uint32 * cap)()
+    nb, ln = ctypes.c_uint32(), ctypes.c_uint32()
+    _call("ckks_parameterise", cost, scale_bits, special_mult, bits, cap, ctypes.byref(nb), ctypes.byref(ln))
+    return [int(bits[i]) for i in range(nb.value)], 1 << ln.value
+
+
+def ckks_ctx_create(log_n, q, p, dnum):
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pa = (ctypes.c_uint64 * len(p))(*p)
+    prm = ckks_params(log_n, len(q), qa, len(p), pa, dnum)
+    h = ctypes.c_void_p()
+    _call("ckks_ctx_create", ctypes.byref(prm), ctypes.byref(h))
+    return h
+
+
+def ckks_ctx_destroy(h):
+    lib().ckks_ctx_destroy(h)
+
+
+def ckks_ctx_device_bytes(h):
+    return int(lib().ckks_ctx_device_bytes(h))
+
+
+def ckks_ctx_upload(h, dev_ptr, stream=None):
+    _call("ckks_ctx_upload", h, dev_ptr, stream)
+
+
+def ckks_ctx_digits(h, level):
+    return int(lib().ckks_ctx_digits(h, level))
+
+
+def ckks_ctx_prime(h, i):
+    return int(lib().ckks_ctx_prime(h, i))
+
+
+def ckks_ct_bytes(h, n_poly, level):
+    return int(lib().ckks_ct_bytes(h, n_poly, level))
+
+
+def ckks_key_bytes(h, kind):
+    return int(lib().ckks_key_bytes(h, kind))
+
+
+def ckks_workspace_bytes(h, op, B, levels=None):
+    lv = (ctypes.c_uint32 * len(levels))(*levels) if levels is not None else None
+    return int(lib().ckks_workspace_bytes(h, op, B, lv))
+
+
+def _ptr_arrays(limb_ptrs, prime_idx):
+    n = len(limb_ptrs)
+    return (ctypes.c_void_p * n)(*limb_ptrs), (ctypes.c_uint32 * n)(*prime_idx), n
+
+
+def ckks_ntt(h, limb_ptrs, prime_idx, ws, ws_bytes, stream=None):
+    lp, pi, n = _ptr_arrays(limb_ptrs, prime_idx)
+    _call("ckks_ntt", h, lp, pi, n, ws, ws_bytes, stream)
+
+
+def ckks_intt(h, limb_ptrs, prime_idx, ws, ws_bytes, stream=None):
+    lp, pi, n = _ptr_arrays(limb_ptrs, prime_idx)
+    _call("ckks_intt", h, lp, pi, n, ws, ws_bytes, stream)
+
+
+def ckks_keygen_secret(h, seed, sk, ws, ws_bytes, stream=None):
+    _call("ckks_keygen_secret", h, seed, sk, ws, ws_bytes, stream)
+
+
+def ckks_keygen_public(h, sk, seed, pk, ws, ws_bytes, stream=None):
+    _call("ckks_keygen_public", h, sk, seed, pk, ws, ws_bytes, stream)
+
+
+def ckks_keygen_relin(h, sk, seed, rk, ws, ws_bytes, stream=None):
+    _call("ckks_keygen_relin", h, sk, seed, rk, ws, ws_bytes, stream)
+
+
+def ckks_keygen_galois(h, sk, galois_elt, seed, gk, ws, ws_bytes, stream=None):
+    _call("ckks_keygen_galois", h, sk, galois_elt, seed, gk, ws, ws_bytes, stream)
+
+
+def ckks_galois_elt(h, step):
+    return int(lib().ckks_galois_elt(h, step))
+
+
+def ckks_encode(h, re, im, n, scale, coeffs_out):
+    """re/im: pointers to n doubles (im may be None); coeffs_out: int64[N]"""
+    _call("ckks_encode", h, re, im, n, scale, coeffs_out)
+
+
+def ckks_decode(h, residues, level, scale, re_out, im_out):
+    _call("ckks_decode", h, residues, level, scale, re_out, im_out, len(re_out))
+
+
+def ckks_pt_load(h, coeffs_dev, pt, ws, ws_bytes, stream=None):
+    _call("ckks_pt_load", h, coeffs_dev, ctypes.byref(pt), ws, ws_bytes, stream)
+
+
+def ckks_encrypt(h, pk, pt, seed, obj, ct, ws, ws_bytes, stream=None):
+    _call("ckks_encrypt", h, pk, ctypes.byref(pt), seed, obj, ctypes.byref(ct), ws, ws_bytes, stream)
+
+
+def ckks_decrypt(h, sk, ct, m_dev, ws, ws_bytes, stream=None):
+    _call("ckks_decrypt", h, sk, ctypes.byref(ct), m_dev, ws, ws_bytes, stream)
+
+
+def _arr(T, xs):
+    return (T * len(xs))(*xs)
+
+
+def ckks_add(h, a, b, out, ws, ws_bytes, stream=None):
+    _call("ckks_add", h, a, b, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_sub(h, a, b, out, ws, ws_bytes, stream=None):
+    _call("ckks_sub", h, a, b, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_add_plain(h, a, p, out, ws, ws_bytes, stream=None):
+    _call("ckks_add_plain", h, a, p, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_multiply_plain(h, a, p, out, ws, ws_bytes, stream=None):
+    _call("ckks_multiply_plain", h, a, p, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_multiply_scalar(h, a, v, v_scale, out, ws, ws_bytes, stream=None):
+    _call("ckks_multiply_scalar", h, a, _arr(ctypes.c_int64, v), _arr(ctypes.c_double, v_scale), out, len(out),
+          ws, ws_bytes, stream)
+
+
+def ckks_add_scalar(h, a, v, out, ws, ws_bytes, stream=None):
+    _call("ckks_add_scalar", h, a, _arr(ctypes.c_int64, v), out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_multiply(h, a, b, out3, ws, ws_bytes, stream=None):
+    _call("ckks_multiply", h, a, b, out3, len(out3), ws, ws_bytes, stream)
+
+
+def ckks_relinearize(h, rk, in3, out, ws, ws_bytes, stream=None):
+    _call("ckks_relinearize", h, rk, in3, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_rescale(h, a, out, ws, ws_bytes, stream=None):
+    _call("ckks_rescale", h, a, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_mod_switch_to(h, ct, level):
+    _call("ckks_mod_switch_to", h, ctypes.byref(ct), level)
+
+
+def ckks_rotate(h, gk, galois_elt, a, out, ws, ws_bytes, stream=None):
+    _call("ckks_rotate", h, gk, galois_elt, a, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_hmult_relin_rescale(h, rk, a, b, out, ws, ws_bytes, stream=None):
+    _call("ckks_hmult_relin_rescale", h, rk, a, b, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_linear(h, inp, W_dev, w_scale, out, ws, ws_bytes, stream=None):
+    _call("ckks_linear", h, inp, len(inp), W_dev, w_scale, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_linear_csr_workspace_bytes(h, n_in, n_out, nnz, level):
+    return int(lib().ckks_linear_csr_workspace_bytes(h, n_in, n_out, nnz, level))
+
+
+def ckks_linear_csr(h, inp, n_out, row_ptr, col, w, w_scale, out, ws, ws_bytes, stream=None):
+    """row_ptr/col: uint32 numpy arrays, w: int64 numpy array (host)"""
+    _call("ckks_linear_csr", h, inp, len(inp), n_out, row_ptr.ctypes.data_as(_P(_u32)),
+          col.ctypes.data_as(_P(_u32)), w.ctypes.data_as(_P(ctypes.c_int64)), w_scale, out, ws, ws_bytes, stream)
+
+
+def ckks_profile_enable(on):
+    _call("ckks_profile_enable", 1 if on else 0)
+
+
+def ckks_profile_collect(cap=1 << 16):
+    recs = (ckks_launch_record * cap)()
+    n = ctypes.c_uint32()
+    _call("ckks_profile_collect", recs, cap, ctypes.byref(n))
+    return [(recs[i].name.decode(), int(recs[i].items), float(recs[i].ms)) for i in range(min(n.value, cap))]
+
+
+def ckks_graph_create(h):
+    g = ctypes.c_void_p()
+    _call("ckks_graph_create", h, ctypes.byref(g))
+    return g
+
+
+def ckks_graph_destroy(g):
+    lib().ckks_graph_destroy(g)
+
+
+def ckks_graph_add_node(g, kind, attrs=None):
+    nid = ctypes.c_uint32()
+    _call("ckks_graph_add_node", g, kind, ctypes.byref(attrs) if attrs is not None else None, ctypes.byref(nid))
+    return nid.value
+
+
+def ckks_graph_add_edge(g, src, dst):
+    _call("ckks_graph_add_edge", g, src, dst)
+
+
+def ckks_graph_plan(g):
+    ws = ctypes.c_size_t()
+    nout = ctypes.c_uint32()
+    _call("ckks_graph_plan", g, ctypes.byref(ws), ctypes.byref(nout))
+    return ws.value, nout.value
+
+
+def ckks_graph_run(g, inputs, outputs, rk, galois_elts, galois_keys, ws, ws_bytes, stream=None):
+    n = len(galois_elts)
+    ge = (ctypes.c_uint32 * max(n, 1))(*galois_elts)
+    gk = (ctypes.c_void_p * max(n, 1))(*galois_keys)
+    _call("ckks_graph_run", g, inputs, len(inputs), outputs, len(outputs), rk, ge, gk, n, ws, ws_bytes, stream)

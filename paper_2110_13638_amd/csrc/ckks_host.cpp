@@ -1,0 +1,1663 @@
+// Host runtime behind the C ABI of libckks_hip.so: parameter checks, prime
+// and root search, device table image, FP64 canonical-embedding encoder,
+// exact CRT decoder, and the per-op planners that turn ciphertext
+// descriptors into flat work-item tables for the gfx950 kernels.
+//
+// The library never allocates device memory: every call receives a caller
+// workspace, carves scratch limbs from its front and places the work-item
+// tables at its end, uploads the tables with one asynchronous copy and
+// launches the kernels on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/ckks.h"
+#include "ckks_internal.h"
+
+namespace ckks {
+hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s);
+hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
+hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s);
+hipError_t launch_ip(const DevTables &tb, const Item *items, int n, hipStream_t s);
+hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,
+                         u64 *const *out_ptrs, u32 n_in, u32 n_out, u32 limbs, u32 in_stride,
+                         u32 out_stride, hipStream_t s);
+hipError_t launch_reduce_weights(const DevTables &tb, const i64 *W, u64 *wt, u32 count, u32 limbs,
+                                 hipStream_t s);
+hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
+                                 const u64 *wt, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
+                                 u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
+
+// kernel op codes (mirrors of the enums in the kernel file)
+enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_HMULT = 4, F_SAMPLE = 5, F_INT = 6 };
+enum { I_COPY = 0, I_MUL = 1, I_HMULT = 2, I_DECRYPT = 3 };
+enum {
+    EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_MUL_CONST = 3, EW_ADD_CONST = 4, EW_TENSOR = 5,
+    EW_COPY = 6, EW_AUTOMORPH = 7, EW_NEG = 8, EW_KEYGEN = 9, EW_ENCRYPT = 10, EW_SQUARE_S = 11,
+    EW_HMULT_FIN = 12
+};
+enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_SWK_A = 4, TAG_SWK_E = 5, TAG_ENC_V = 6,
+       TAG_ENC_E0 = 7, TAG_ENC_E1 = 8 };
+enum { S_TERNARY = 0, S_CBD = 1 };
+
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------
+static thread_local std::string g_err;
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) return fail(CKKS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------
+// integer helpers
+// ---------------------------------------------------------------------
+static u64 mulmod(u64 a, u64 b, u64 q) { return (u64)((u128)a * b % q); }
+static u64 powmod(u64 a, u64 e, u64 q) {
+    u64 r = 1 % q;
+    a %= q;
+    for (; e; e >>= 1) {
+        if (e & 1) r = mulmod(r, a, q);
+        a = mulmod(a, a, q);
+    }
+    return r;
+}
+static u64 invmod(u64 a, u64 q) { return powmod(a, q - 2, q); }
+static u64 shoup_companion(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+static bool is_prime(u64 n) {
+    static const u64 bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    if (n < 2) return false;
+    for (u64 b : bases) {
+        if (n == b) return true;
+        if (n % b == 0) return false;
+    }
+    u64 d = n - 1;
+    int r = 0;
+    while (!(d & 1)) d >>= 1, r++;
+    for (u64 b : bases) {
+        u64 x = powmod(b, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int k = 1; k < r && comp; k++) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) comp = false;
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+static u32 bitrev(u32 x, u32 bits) {
+    u32 r = 0;
+    for (u32 i = 0; i < bits; i++) r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+// smallest primitive 2N-th root of unity mod q
+static u64 smallest_psi(u64 q, u32 log_n) {
+    const u64 n = 1ull << log_n, two_n = n << 1;
+    u64 g = 0;
+    for (u64 x = 2; x < q && !g; x++) {
+        u64 c = powmod(x, (q - 1) / two_n, q);
+        if (powmod(c, n, q) == q - 1) g = c;
+    }
+    if (!g) return 0;
+    u64 best = g, g2 = mulmod(g, g, q), cur = g;
+    for (u64 k = 1; k < n; k++) {
+        cur = mulmod(cur, g2, q);
+        best = std::min(best, cur);
+    }
+    return best;
+}
+
+// little multiword unsigned integers for the CRT lift
+typedef std::vector<u64> Big;
+static void big_mul_small(Big &a, u64 m) {
+    u64 carry = 0;
+    for (auto &w : a) {
+        u128 t = (u128)w * m + carry;
+        w = (u64)t;
+        carry = (u64)(t >> 64);
+    }
+    if (carry) a.push_back(carry);
+}
+static int big_cmp(const Big &a, const Big &b) {
+    size_t n = std::max(a.size(), b.size());
+    for (size_t i = n; i-- > 0;) {
+        u64 x = i < a.size() ? a[i] : 0, y = i < b.size() ? b[i] : 0;
+        if (x != y) return x < y ? -1 : 1;
+    }
+    return 0;
+}
+static void big_sub(Big &a, const Big &b) {  // a -= b, a >= b
+    u64 borrow = 0;
+    for (size_t i = 0; i < a.size(); i++) {
+        u64 y = i < b.size() ? b[i] : 0;
+        u128 t = (u128)a[i] - y - borrow;
+        a[i] = (u64)t;
+        borrow = (u64)(t >> 64) ? 1 : 0;
+    }
+}
+static void big_addmul(Big &acc, const Big &b, u64 m) {  // acc += b * m
+    if (acc.size() < b.size() + 2) acc.resize(b.size() + 2, 0);
+    u64 carry = 0;
+    size_t i = 0;
+    for (; i < b.size(); i++) {
+        u128 t = (u128)b[i] * m + acc[i] + carry;
+        acc[i] = (u64)t;
+        carry = (u64)(t >> 64);
+    }
+    for (; carry && i < acc.size(); i++) {
+        u128 t = (u128)acc[i] + carry;
+        acc[i] = (u64)t;
+        carry = (u64)(t >> 64);
+    }
+}
+static double big_to_double(const Big &a) {
+    double d = 0;
+    for (size_t i = a.size(); i-- > 0;) d = d * 18446744073709551616.0 + (double)a[i];
+    return d;
+}
+
+}  // namespace ckks
+
+using namespace ckks;
+
+// ---------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------
+struct ckks_ctx {
+    u32 log_n, N, n_q, n_p, n_prim, dnum, alpha, digits_top;
+    std::vector<u64> primes;
+    std::vector<u64> image;  // device table image (u64 words)
+    size_t off_pc, off_tw, off_itw, off_modup, off_moddown, off_rescale;
+    DevTables tb{};
+    bool uploaded = false;
+    // encoder
+    std::vector<std::complex<double>> fft_roots;  // e^{2 pi i k / M}, k < M
+    std::vector<std::complex<double>> twist;      // zeta^i, i < M
+    std::vector<u32> slot_index;                  // k_j = (5^j mod 2N - 1) / 4
+    // CRT per level
+    std::vector<std::vector<Big>> qhat;    // [level][i]
+    std::vector<std::vector<u64>> qhat_inv;
+    std::vector<Big> Q, Qhalf;
+};
+
+static size_t align_words(size_t w) { return (w + 31) & ~(size_t)31; }  // 256 bytes
+
+extern "C" const char *ckks_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ckks_find_primes(uint32_t log_n, const uint32_t *bits, uint32_t n, uint64_t *out) {
+    if (!bits || !out || log_n < 1 || log_n > 20) return fail(CKKS_EINVAL, "find_primes: bad args");
+    const u64 two_n = 2ull << log_n;
+    for (u32 i = 0; i < n; i++) {
+        if (bits[i] < 2 || bits[i] > 62) return fail(CKKS_EINVAL, "find_primes: bits out of range");
+        u64 top = (bits[i] == 64) ? ~0ull : ((1ull << bits[i]) - 1);
+        u64 c = (top / two_n) * two_n + 1;
+        if (c > top) c -= two_n;
+        for (;;) {
+            if (c < two_n) return fail(CKKS_EPARAMS, "find_primes: exhausted");
+            bool used = false;
+            for (u32 k = 0; k < i; k++) used |= out[k] == c;
+            if (!used && is_prime(c)) break;
+            c -= two_n;
+        }
+        out[i] = c;
+    }
+    return CKKS_OK;
+}
+
+extern "C" int ckks_parameterise(uint32_t cost, uint32_t scale_bits, double special_mult,
+                                 uint32_t *bits_out, uint32_t bits_cap, uint32_t *n_bits, uint32_t *log_n) {
+    if (!bits_out || !n_bits || !log_n || bits_cap < cost + 2) return fail(CKKS_EINVAL, "parameterise: bad args");
+    u32 count = cost + 2, sum = 0;
+    for (u32 i = 0; i < count; i++) bits_out[i] = scale_bits;
+    bits_out[0] = (u32)(bits_out[0] * special_mult);
+    bits_out[count - 1] = (u32)(bits_out[count - 1] * special_mult);
+    for (u32 i = 0; i < count; i++) sum += bits_out[i];
+    u64 b = 27;
+    while (b < sum) b *= 2;
+    u64 n = 1024 * (b / 27);
+    u32 ln = 0;
+    while ((1ull << ln) < n) ln++;
+    *n_bits = count;
+    *log_n = ln;
+    return CKKS_OK;
+}
+
+extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
+    if (!p || !out || !p->q || (p->n_p && !p->p)) return fail(CKKS_EINVAL, "ctx_create: null argument");
+    if (p->log_n < kMinLogN || p->log_n > kMaxLogN)
+        return fail(CKKS_EPARAMS, "ctx_create: log_n %u outside [%d, %d]", p->log_n, kMinLogN, kMaxLogN);
+    if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > (u32)kMaxPrimes || p->dnum < 1 || p->dnum > p->n_q)
+        return fail(CKKS_EPARAMS, "ctx_create: bad prime counts / dnum");
+    ckks_ctx *c = new ckks_ctx();
+    c->log_n = p->log_n;
+    c->N = 1u << p->log_n;
+    c->n_q = p->n_q;
+    c->n_p = p->n_p;
+    c->n_prim = p->n_q + p->n_p;
+    c->dnum = p->dnum;
+    c->alpha = (p->n_q + p->dnum - 1) / p->dnum;
+    c->digits_top = (p->n_q + c->alpha - 1) / c->alpha;
+    for (u32 i = 0; i < p->n_q; i++) c->primes.push_back(p->q[i]);
+    for (u32 i = 0; i < p->n_p; i++) c->primes.push_back(p->p[i]);
+    const u64 two_n = 2ull * c->N;
+    for (u32 i = 0; i < c->n_prim; i++) {
+        u64 q = c->primes[i];
+        if (q >= (1ull << 61) || q % two_n != 1 || !is_prime(q)) {
+            delete c;
+            return fail(CKKS_EPARAMS, "ctx_create: prime %u (%llu) must be a prime < 2^61, 1 mod 2N", i,
+                        (unsigned long long)q);
+        }
+        for (u32 k = 0; k < i; k++)
+            if (c->primes[k] == q) {
+                delete c;
+                return fail(CKKS_EPARAMS, "ctx_create: duplicate prime");
+            }
+    }
+    const u32 N = c->N, np = c->n_prim, nq = c->n_q, npp = c->n_p, A = c->alpha;
+    // ---- device image layout
+    size_t w = 0;
+    c->off_pc = w;
+    w = align_words(w + np * (sizeof(PrimeConst) / 8));
+    c->off_tw = w;
+    w = align_words(w + (size_t)np * N * 2);
+    c->off_itw = w;
+    w = align_words(w + (size_t)np * N * 2);
+    c->off_modup = w;
+    const u32 blockw = modup_block_words(A, np);
+    w = align_words(w + (size_t)c->digits_top * A * blockw);
+    c->off_moddown = w;
+    w = align_words(w + 2 * npp + (size_t)npp * nq);
+    c->off_rescale = w;
+    w = align_words(w + (size_t)nq * nq * 2);
+    c->image.assign(w, 0);
+    u64 *img = c->image.data();
+    // ---- per prime
+    u64 Pmod[kMaxPrimes];
+    for (u32 i = 0; i < np; i++) {
+        const u64 q = c->primes[i];
+        PrimeConst pc{};
+        pc.q = q;
+        pc.two_q = 2 * q;
+        u128 r = (~(u128)0) / q;  // floor((2^128 - 1) / q) == floor(2^128 / q) for odd q
+        pc.br_hi = (u64)(r >> 64);
+        pc.br_lo = (u64)r;
+        pc.mu = (u64)((~(u64)0) / q);
+        const u64 psi = smallest_psi(q, c->log_n);
+        if (!psi) {
+            delete c;
+            return fail(CKKS_EPARAMS, "ctx_create: no 2N-th root for prime %u", i);
+        }
+        // forward twiddle table tw[k] = psi^brv(k), inverse itw[k] = tw[k]^-1
+        ulonglong2 *tw = reinterpret_cast<ulonglong2 *>(img + c->off_tw) + (size_t)i * N;
+        ulonglong2 *itw = reinterpret_cast<ulonglong2 *>(img + c->off_itw) + (size_t)i * N;
+        std::vector<u64> pw(N);
+        u64 x = 1;
+        for (u32 k = 0; k < N; k++) pw[k] = x, x = mulmod(x, psi, q);
+        for (u32 k = 0; k < N; k++) {
+            const u64 v = pw[bitrev(k, c->log_n)];
+            const u64 iv = invmod(v, q);
+            tw[k].x = v;
+            tw[k].y = shoup_companion(v, q);
+            itw[k].x = iv;
+            itw[k].y = shoup_companion(iv, q);
+        }
+        pc.ninv = invmod(N % q, q);
+        pc.ninv_sh = shoup_companion(pc.ninv, q);
+        pc.last_w = mulmod(itw[1].x, pc.ninv, q);
+        pc.last_w_sh = shoup_companion(pc.last_w, q);
+        u64 P = 1;
+        for (u32 m = 0; m < npp; m++) P = mulmod(P, c->primes[nq + m] % q, q);
+        Pmod[i] = P;
+        pc.pmod = P;
+        pc.pmod_sh = shoup_companion(P, q);
+        if (i < nq) {
+            pc.pinv = invmod(P, q);
+            pc.pinv_sh = shoup_companion(pc.pinv, q);
+        }
+        memcpy(img + c->off_pc + i * (sizeof(PrimeConst) / 8), &pc, sizeof pc);
+    }
+    (void)Pmod;
+    // ---- ModUp blocks: digit j truncated to s primes
+    for (u32 j = 0; j < c->digits_top; j++)
+        for (u32 s = 1; s <= A; s++) {
+            u64 *blk = img + c->off_modup + (size_t)(j * A + s - 1) * blockw;
+            const u32 lo = j * A;
+            if (lo + s > nq) continue;
+            for (u32 i = 0; i < s; i++) {
+                const u64 qi = c->primes[lo + i];
+                u64 hat = 1;
+                for (u32 m = 0; m < s; m++)
+                    if (m != i) hat = mulmod(hat, c->primes[lo + m] % qi, qi);
+                const u64 inv = invmod(hat, qi);
+                blk[2 * i] = inv;
+                blk[2 * i + 1] = shoup_companion(inv, qi);
+                for (u32 t = 0; t < np; t++) {
+                    const u64 qt = c->primes[t];
+                    u64 h = 1;
+                    for (u32 m = 0; m < s; m++)
+                        if (m != i) h = mulmod(h, c->primes[lo + m] % qt, qt);
+                    blk[2 * A + (size_t)i * np + t] = h;
+                }
+            }
+        }
+    // ---- ModDown block
+    {
+        u64 *blk = img + c->off_moddown;
+        for (u32 m = 0; m < npp; m++) {
+            const u64 pm = c->primes[nq + m];
+            u64 hat = 1;
+            for (u32 k = 0; k < npp; k++)
+                if (k != m) hat = mulmod(hat, c->primes[nq + k] % pm, pm);
+            const u64 inv = invmod(hat, pm);
+            blk[2 * m] = inv;
+            blk[2 * m + 1] = shoup_companion(inv, pm);
+            for (u32 t = 0; t < nq; t++) {
+                const u64 qt = c->primes[t];
+                u64 h = 1;
+                for (u32 k = 0; k < npp; k++)
+                    if (k != m) h = mulmod(h, c->primes[nq + k] % qt, qt);
+                blk[2 * npp + (size_t)m * nq + t] = h;
+            }
+        }
+    }
+    // ---- rescale: q_l^-1 mod q_i
+    for (u32 l = 1; l < nq; l++)
+        for (u32 i = 0; i < l; i++) {
+            const u64 qi = c->primes[i];
+            const u64 inv = invmod(c->primes[l] % qi, qi);
+            u64 *e = img + c->off_rescale + ((size_t)l * nq + i) * 2;
+            e[0] = inv;
+            e[1] = shoup_companion(inv, qi);
+        }
+    // ---- encoder tables
+    const u32 M = N / 2;
+    c->fft_roots.resize(M);
+    for (u32 k = 0; k < M; k++) c->fft_roots[k] = std::polar(1.0, 2.0 * M_PI * (double)k / (double)M);
+    c->twist.resize(M);
+    for (u32 i = 0; i < M; i++) c->twist[i] = std::polar(1.0, M_PI * (double)i / (double)N);
+    c->slot_index.resize(M);
+    u64 e = 1;
+    for (u32 j = 0; j < M; j++) {
+        c->slot_index[j] = (u32)((e - 1) / 4);
+        e = e * 5 % two_n;
+    }
+    // ---- CRT tables per level
+    c->qhat.resize(nq);
+    c->qhat_inv.resize(nq);
+    c->Q.resize(nq);
+    c->Qhalf.resize(nq);
+    for (u32 l = 0; l < nq; l++) {
+        Big Q{1};
+        for (u32 i = 0; i <= l; i++) big_mul_small(Q, c->primes[i]);
+        c->Q[l] = Q;
+        Big h = Q;  // Q >> 1
+        for (size_t k = 0; k < h.size(); k++) h[k] = (h[k] >> 1) | (k + 1 < h.size() ? (h[k + 1] << 63) : 0);
+        c->Qhalf[l] = h;
+        for (u32 i = 0; i <= l; i++) {
+            Big qh{1};
+            u64 hm = 1;
+            for (u32 m = 0; m <= l; m++)
+                if (m != i) big_mul_small(qh, c->primes[m]), hm = mulmod(hm, c->primes[m] % c->primes[i], c->primes[i]);
+            c->qhat[l].push_back(qh);
+            c->qhat_inv[l].push_back(invmod(hm, c->primes[i]));
+        }
+    }
+    *out = c;
+    return CKKS_OK;
+}
+
+extern "C" void ckks_ctx_destroy(ckks_ctx *ctx) { delete ctx; }
+extern "C" size_t ckks_ctx_device_bytes(const ckks_ctx *c) { return c ? c->image.size() * 8 : 0; }
+extern "C" uint32_t ckks_ctx_log_n(const ckks_ctx *c) { return c ? c->log_n : 0; }
+extern "C" uint32_t ckks_ctx_max_level(const ckks_ctx *c) { return c ? c->n_q - 1 : 0; }
+extern "C" uint32_t ckks_ctx_digits(const ckks_ctx *c, uint32_t level) {
+    return c ? (level + 1 + c->alpha - 1) / c->alpha : 0;
+}
+extern "C" uint64_t ckks_ctx_prime(const ckks_ctx *c, uint32_t i) {
+    return (c && i < c->n_prim) ? c->primes[i] : 0;
+}
+
+extern "C" int ckks_ctx_upload(ckks_ctx *c, void *dev, void *stream) {
+    if (!c || !dev) return fail(CKKS_EINVAL, "ctx_upload: null argument");
+    if (((uintptr_t)dev) & 255) return fail(CKKS_EINVAL, "ctx_upload: device buffer not 256-byte aligned");
+    HIP_TRY(hipMemcpyAsync(dev, c->image.data(), c->image.size() * 8, hipMemcpyHostToDevice, (hipStream_t)stream));
+    const u64 *base = (const u64 *)dev;
+    DevTables &t = c->tb;
+    t.pc = reinterpret_cast<const PrimeConst *>(base + c->off_pc);
+    t.tw = reinterpret_cast<const ulonglong2 *>(base + c->off_tw);
+    t.itw = reinterpret_cast<const ulonglong2 *>(base + c->off_itw);
+    t.modup = base + c->off_modup;
+    t.moddown = base + c->off_moddown;
+    t.rescale = reinterpret_cast<const ulonglong2 *>(base + c->off_rescale);
+    t.log_n = c->log_n;
+    t.n_q = c->n_q;
+    t.n_p = c->n_p;
+    t.n_prim = c->n_prim;
+    t.alpha = c->alpha;
+    t.n_digits_top = c->digits_top;
+    c->uploaded = true;
+    return CKKS_OK;
+}
+
+extern "C" size_t ckks_ct_bytes(const ckks_ctx *c, uint32_t n_poly, uint32_t level) {
+    return c ? (size_t)n_poly * (level + 1) * c->N * 8 : 0;
+}
+extern "C" size_t ckks_pt_bytes(const ckks_ctx *c, uint32_t level) { return c ? (size_t)(level + 1) * c->N * 8 : 0; }
+extern "C" size_t ckks_key_bytes(const ckks_ctx *c, int kind) {
+    if (!c) return 0;
+    const size_t limb = (size_t)c->N * 8;
+    switch (kind) {
+        case CKKS_KEY_SECRET: return c->n_prim * limb;
+        case CKKS_KEY_PUBLIC: return 2 * c->n_q * limb;
+        case CKKS_KEY_SWITCH: return (size_t)c->digits_top * 2 * c->n_prim * limb;
+    }
+    return 0;
+}
+extern "C" uint32_t ckks_galois_elt(const ckks_ctx *c, int32_t step) {
+    if (!c) return 0;
+    const i64 half = c->N / 2;
+    i64 r = ((i64)step % half + half) % half;
+    return (u32)powmod(5, (u64)r, 2ull * c->N);
+}
+
+// ---------------------------------------------------------------------
+// encoder / decoder (host FP64)
+// ---------------------------------------------------------------------
+// in-place iterative radix-2 DFT of size M: X_k = sum_i x_i e^{sign 2 pi i k i / M}
+static void host_fft(const ckks_ctx *c, std::vector<std::complex<double>> &x, int sign) {
+    const u32 M = (u32)x.size();
+    u32 lg = 0;
+    while ((1u << lg) < M) lg++;
+    for (u32 i = 0; i < M; i++) {
+        u32 r = bitrev(i, lg);
+        if (r > i) std::swap(x[i], x[r]);
+    }
+    for (u32 len = 2; len <= M; len <<= 1) {
+        const u32 half = len >> 1, step = M / len;
+        for (u32 s = 0; s < M; s += len)
+            for (u32 j = 0; j < half; j++) {
+                std::complex<double> w = c->fft_roots[(size_t)j * step];
+                if (sign < 0) w = std::conj(w);
+                const std::complex<double> u = x[s + j], v = x[s + j + half] * w;
+                x[s + j] = u + v;
+                x[s + j + half] = u - v;
+            }
+    }
+}
+
+extern "C" int ckks_encode(const ckks_ctx *c, const double *re, const double *im, size_t n, double scale,
+                           int64_t *coeffs) {
+    if (!c || (!re && n) || !coeffs) return fail(CKKS_EINVAL, "encode: null argument");
+    const u32 M = c->N / 2;
+    if (n > M) return fail(CKKS_EINVAL, "encode: %zu values exceed %u slots", n, M);
+    std::vector<std::complex<double>> Z(M, 0.0);
+    for (size_t j = 0; j < n; j++) Z[c->slot_index[j]] = std::complex<double>(re[j], im ? im[j] : 0.0) * scale;
+    host_fft(c, Z, -1);  // sum_k Z_k e^{-2 pi i k i / M}
+    for (u32 i = 0; i < M; i++) {
+        const std::complex<double> wv = Z[i] / (double)M * std::conj(c->twist[i]);
+        const double a = wv.real(), b = wv.imag();
+        const double ra = a < 0 ? -floor(-a + 0.5) : floor(a + 0.5);
+        const double rb = b < 0 ? -floor(-b + 0.5) : floor(b + 0.5);
+        if (fabs(ra) >= 4611686018427387904.0 || fabs(rb) >= 4611686018427387904.0)
+            return fail(CKKS_EINVAL, "encode: coefficient reaches 2^62 (scale too large)");
+        coeffs[i] = (int64_t)ra;
+        coeffs[i + M] = (int64_t)rb;
+    }
+    return CKKS_OK;
+}
+
+extern "C" int ckks_decode(const ckks_ctx *c, const uint64_t *res, uint32_t level, double scale, double *re,
+                           double *im, size_t n) {
+    if (!c || !res || (!re && n)) return fail(CKKS_EINVAL, "decode: null argument");
+    if (level >= c->n_q) return fail(CKKS_ELEVEL, "decode: level %u out of range", level);
+    const u32 N = c->N, M = N / 2;
+    if (n > M) return fail(CKKS_EINVAL, "decode: too many slots");
+    std::vector<double> m(N);
+    const Big &Q = c->Q[level], &Qh = c->Qhalf[level];
+    for (u32 j = 0; j < N; j++) {
+        Big acc(Q.size() + 2, 0);
+        for (u32 i = 0; i <= level; i++) {
+            const u64 qi = c->primes[i];
+            const u64 y = mulmod(res[(size_t)i * N + j] % qi, c->qhat_inv[level][i], qi);
+            big_addmul(acc, c->qhat[level][i], y);
+        }
+        while (big_cmp(acc, Q) >= 0) big_sub(acc, Q);
+        if (big_cmp(acc, Qh) > 0) {
+            Big neg = Q;
+            neg.resize(acc.size(), 0);
+            big_sub(neg, acc);
+            m[j] = -big_to_double(neg);
+        } else {
+            m[j] = big_to_double(acc);
+        }
+    }
+    std::vector<std::complex<double>> w(M);
+    for (u32 i = 0; i < M; i++) w[i] = std::complex<double>(m[i], m[i + M]) * c->twist[i];
+    host_fft(c, w, +1);
+    for (size_t j = 0; j < n; j++) {
+        const std::complex<double> z = w[c->slot_index[j]] / scale;
+        re[j] = z.real();
+        if (im) im[j] = z.imag();
+    }
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// optional per-launch timing with HIP events on the launch stream
+// ---------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    std::string name;
+    u32 items;
+    hipEvent_t e0, e1;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+const char *fwd_names[] = {"ntt_fwd", "ntt_fwd_modup", "ntt_fwd_rescale", "ntt_fwd_moddown",
+                           "ntt_fwd_hmult_tail", "ntt_fwd_sample", "ntt_fwd_int"};
+const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_hmult_top", "ntt_inv_decrypt"};
+std::string launch_name(int kind, int op, u32 log_n) {
+    char b[64];
+    switch (kind) {
+        case 0: snprintf(b, sizeof b, "%s/N=2^%u", fwd_names[op], log_n); break;
+        case 1: snprintf(b, sizeof b, "%s/N=2^%u", inv_names[op], log_n); break;
+        case 2: snprintf(b, sizeof b, "elementwise/N=2^%u", log_n); break;
+        case 3: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
+        default: snprintf(b, sizeof b, "linear/N=2^%u", log_n); break;
+    }
+    return b;
+}
+}  // namespace
+
+extern "C" int ckks_profile_enable(int on) {
+    g_prof_on = on != 0;
+    return CKKS_OK;
+}
+
+extern "C" int ckks_profile_collect(ckks_launch_record *out, uint32_t cap, uint32_t *n) {
+    if (!n) return fail(CKKS_EINVAL, "profile_collect: null count");
+    u32 k = 0;
+    for (auto &r : g_prof) {
+        if (hipEventSynchronize(r.e1) != hipSuccess) return fail(CKKS_EDEVICE, "profile_collect: event sync");
+        float ms = 0;
+        hipEventElapsedTime(&ms, r.e0, r.e1);
+        if (out && k < cap) {
+            memset(&out[k], 0, sizeof out[k]);
+            snprintf(out[k].name, sizeof out[k].name, "%s", r.name.c_str());
+            out[k].items = r.items;
+            out[k].ms = ms;
+        }
+        k++;
+        hipEventDestroy(r.e0);
+        hipEventDestroy(r.e1);
+    }
+    g_prof.clear();
+    *n = k;
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// planning: scratch carving + work-item tables
+// ---------------------------------------------------------------------
+namespace {
+struct Launch {
+    int kind;  // 0 fwd, 1 inv, 2 ew, 3 ip
+    int op;
+    size_t off;
+    int n;
+    u64 seed;
+};
+struct Plan {
+    const ckks_ctx *c;
+    uint8_t *ws;          // device base (may be null when sizing)
+    size_t scratch = 0;   // bytes of scratch carved so far
+    std::vector<uint8_t> desc;
+    std::vector<Launch> launches;
+    explicit Plan(const ckks_ctx *cc, void *w) : c(cc), ws((uint8_t *)w) {}
+    u64 *limbs(size_t count) {
+        const size_t bytes = count * c->N * 8;
+        u64 *p = ws ? (u64 *)(ws + scratch) : (u64 *)(uintptr_t)(0x1000 + scratch);
+        scratch += (bytes + 255) & ~(size_t)255;
+        return p;
+    }
+    template <class T>
+    void add(int kind, int op, const std::vector<T> &v, u64 seed = 0) {
+        if (v.empty()) return;
+        size_t off = (desc.size() + 255) & ~(size_t)255;
+        desc.resize(off + v.size() * sizeof(T));
+        memcpy(desc.data() + off, v.data(), v.size() * sizeof(T));
+        launches.push_back({kind, op, off, (int)v.size(), seed});
+    }
+    size_t total() const { return ((scratch + 255) & ~(size_t)255) + desc.size(); }
+    int run(size_t ws_bytes, hipStream_t s) {
+        if (total() > ws_bytes)
+            return fail(CKKS_ENOMEM, "workspace too small: need %zu bytes, got %zu", total(), ws_bytes);
+        if (!ws && total()) return fail(CKKS_EINVAL, "null workspace");
+        if (((uintptr_t)ws) & 255) return fail(CKKS_EINVAL, "workspace not 256-byte aligned");
+        const size_t doff = (scratch + 255) & ~(size_t)255;
+        if (!desc.empty()) HIP_TRY(hipMemcpyAsync(ws + doff, desc.data(), desc.size(), hipMemcpyHostToDevice, s));
+        for (const Launch &L : launches) {
+            const uint8_t *p = ws + doff + L.off;
+            hipError_t e = hipSuccess;
+            ProfRec rec;
+            if (g_prof_on) {
+                rec.name = launch_name(L.kind, L.op, c->log_n);
+                rec.items = (u32)L.n;
+                HIP_TRY(hipEventCreate(&rec.e0));
+                HIP_TRY(hipEventCreate(&rec.e1));
+                HIP_TRY(hipEventRecord(rec.e0, s));
+            }
+            switch (L.kind) {
+                case 0: e = launch_fwd(c->tb, L.op, (const Item *)p, L.n, L.seed, s); break;
+                case 1: e = launch_inv(c->tb, L.op, (const Item *)p, L.n, s); break;
+                case 2: e = launch_ew(c->tb, (const EwItem *)p, L.n, L.seed, s); break;
+                case 3: e = launch_ip(c->tb, (const Item *)p, L.n, s); break;
+            }
+            if (e != hipSuccess) return fail(CKKS_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
+            if (g_prof_on) {
+                HIP_TRY(hipEventRecord(rec.e1, s));
+                g_prof.push_back(rec);
+            }
+        }
+        return CKKS_OK;
+    }
+};
+
+inline u64 *limb(const ckks_ctx *c, const ckks_ct &ct, u32 poly, u32 i) {
+    return ct.data + ((size_t)poly * ct.limb_stride + i) * c->N;
+}
+inline Item item0() {
+    Item it;
+    memset(&it, 0, sizeof it);
+    return it;
+}
+inline EwItem ew0() {
+    EwItem it;
+    memset(&it, 0, sizeof it);
+    return it;
+}
+
+int check_ctx(const ckks_ctx *c) {
+    if (!c) return fail(CKKS_EINVAL, "null context");
+    if (!c->uploaded) return fail(CKKS_EINVAL, "context tables not uploaded (ckks_ctx_upload)");
+    return CKKS_OK;
+}
+int check_ct(const ckks_ctx *c, const ckks_ct &ct, const char *what) {
+    if (!ct.data) return fail(CKKS_EINVAL, "%s: null data", what);
+    if (ct.level >= c->n_q) return fail(CKKS_ELEVEL, "%s: level %u beyond top %u", what, ct.level, c->n_q - 1);
+    if (ct.limb_stride < ct.level + 1) return fail(CKKS_EINVAL, "%s: limb_stride < level + 1", what);
+    if (ct.n_poly < 2 || ct.n_poly > 3) return fail(CKKS_EINVAL, "%s: n_poly must be 2 or 3", what);
+    return CKKS_OK;
+}
+#define CK(x)                  \
+    do {                       \
+        int r_ = (x);          \
+        if (r_ != CKKS_OK) return r_; \
+    } while (0)
+
+// ---------------------------------------------------------------------
+// key switching core: for each b, d_b (NTT form, L_b limbs) ->
+// out_c = addend_c + ModDown(acc_c) for c = 0, 1.
+// ---------------------------------------------------------------------
+struct KsJob {
+    u32 level;
+    std::vector<const u64 *> dl;  // limbs of the polynomial to switch (NTT form)
+    const u64 *addend[2];         // limb 0 of the poly added to each output, or null
+    u64 *out[2];                  // limb 0 of each output poly (limbs contiguous)
+};
+
+void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
+    const ckks_ctx *c = P.c;
+    const u32 N = c->N, k = c->n_p, A = c->alpha;
+    std::vector<Item> icopy, modup, ip, ipP, mdown;
+    for (const KsJob &J : jobs) {
+        const u32 L = J.level + 1, E = L + k, beta = (L + A - 1) / A;
+        u64 *dcoef = P.limbs(L);
+        u64 *ext = P.limbs((size_t)beta * E);
+        u64 *acc = P.limbs((size_t)2 * E);
+        for (u32 i = 0; i < L; i++) {
+            Item it = item0();
+            it.in[0] = J.dl[i];
+            it.out = dcoef + (size_t)i * N;
+            it.prime = i;
+            icopy.push_back(it);
+        }
+        for (u32 j = 0; j < beta; j++) {
+            const u32 lo = j * A, s = std::min(A, L - lo);
+            for (u32 t = 0; t < E; t++) {
+                if (t >= lo && t < lo + s) continue;
+                Item it = item0();
+                it.in[0] = dcoef + (size_t)lo * N;
+                it.a = lo;
+                it.b = s;
+                it.c = j;
+                it.prime = t < L ? t : c->n_q + (t - L);
+                it.out = ext + ((size_t)j * E + t) * N;
+                modup.push_back(it);
+            }
+        }
+        for (u32 t = 0; t < E; t++) {
+            Item it = item0();
+            it.in[0] = ext;
+            it.in[1] = key;
+            it.in[2] = t < L ? J.dl[t] : nullptr;
+            it.a = beta;
+            it.b = t < L ? t / A : 0xFFFFFFFFu;
+            it.c = E;
+            it.v = t;
+            it.prime = t < L ? t : c->n_q + (t - L);
+            it.out = acc + (size_t)t * N;
+            it.out2 = acc + ((size_t)E + t) * N;
+            ip.push_back(it);
+        }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 m = 0; m < k; m++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L + m) * N;
+                it.out = (u64 *)it.in[0];
+                it.prime = c->n_q + m;
+                ipP.push_back(it);
+            }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 i = 0; i < L; i++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L) * N;
+                it.a = c->n_q;
+                it.b = k;
+                it.in[1] = acc + ((size_t)cc * E + i) * N;
+                it.in[2] = J.addend[cc] ? J.addend[cc] + (size_t)i * N : nullptr;
+                it.prime = i;
+                it.out = J.out[cc] + (size_t)i * N;
+                mdown.push_back(it);
+            }
+    }
+    P.add(1, I_COPY, icopy);
+    P.add(0, F_MODUP, modup);
+    P.add(3, 0, ip);
+    P.add(1, I_COPY, ipP);
+    P.add(0, F_MODDOWN, mdown);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------
+// workspace sizing: run the planner on placeholder objects
+// ---------------------------------------------------------------------
+static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B);
+
+extern "C" size_t ckks_workspace_bytes(const ckks_ctx *c, int op, uint32_t B, const uint32_t *levels) {
+    if (!c) return 0;
+    const size_t limb = (size_t)c->N * 8;
+    const size_t desc_pad = 4096;
+    auto lev = [&](u32 b) { return levels ? levels[b] : c->n_q - 1; };
+    size_t items = 0, scratch = 0;
+    switch (op) {
+        case CKKS_OP_NTT: return (size_t)B * sizeof(Item) + desc_pad;
+        case CKKS_OP_ELEMENTWISE: {
+            for (u32 b = 0; b < B; b++) items += 3 * (lev(b) + 1);
+            return items * sizeof(EwItem) + desc_pad;
+        }
+        case CKKS_OP_RESCALE: {
+            for (u32 b = 0; b < B; b++) items += 3 * (lev(b) + 1), scratch += 3 * limb + 768;
+            return scratch + items * sizeof(Item) + 2 * desc_pad;
+        }
+        case CKKS_OP_KEYSWITCH:
+        case CKKS_OP_HMULT: {
+            std::vector<ckks_ct> x(B);
+            for (u32 b = 0; b < B; b++) {
+                x[b] = ckks_ct{(u64 *)(uintptr_t)0x100000, 2, lev(b), lev(b) + 1, 0, 1.0};
+            }
+            Plan P(c, nullptr);
+            if (op == CKKS_OP_HMULT) {
+                std::vector<ckks_ct> o = x;
+                plan_hmult(P, (const u64 *)(uintptr_t)0x100000, x.data(), x.data(), o.data(), B);
+            } else {
+                std::vector<KsJob> jobs(B);
+                for (u32 b = 0; b < B; b++) {
+                    jobs[b].level = lev(b);
+                    jobs[b].dl.assign(lev(b) + 1, (const u64 *)(uintptr_t)0x100000);
+                    jobs[b].addend[0] = jobs[b].addend[1] = nullptr;
+                    jobs[b].out[0] = jobs[b].out[1] = (u64 *)(uintptr_t)0x100000;
+                    P.limbs(2 * (lev(b) + 1));  // rotate: automorphism staging
+                }
+                plan_keyswitch(P, jobs, (const u64 *)(uintptr_t)0x100000);
+                std::vector<EwItem> ew(B * 2 * (c->n_q));
+                P.add(2, 0, ew);
+            }
+            return P.total() + 2 * desc_pad;
+        }
+        case CKKS_OP_KEYGEN: {
+            // switching key: digits x n_prim error limbs + n_prim staging for s'
+            scratch = ((size_t)c->digits_top * c->n_prim + c->n_prim) * (limb + 256);
+            items = (size_t)c->digits_top * c->n_prim * 2 + c->n_prim;
+            return scratch + items * (sizeof(Item) + sizeof(EwItem)) + 2 * desc_pad;
+        }
+        case CKKS_OP_ENCRYPT: {
+            u32 L = lev(0) + 1;
+            return 3 * (size_t)L * (limb + 256) + 4 * L * (sizeof(Item) + sizeof(EwItem)) + 2 * desc_pad;
+        }
+        case CKKS_OP_LINEAR: {
+            const u32 n_out = B, L = levels ? levels[0] + 1 : c->n_q, n_in = levels ? levels[1] : 1;
+            return (size_t)L * n_out * n_in * 8 + (size_t)(n_in + n_out) * 8 + 3 * desc_pad;
+        }
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------
+// NTT primitives
+// ---------------------------------------------------------------------
+static int ntt_common(const ckks_ctx *c, uint64_t *const *limbs, const uint32_t *pidx, uint32_t n, void *ws,
+                      size_t ws_bytes, void *stream, bool inverse) {
+    CK(check_ctx(c));
+    if ((!limbs || !pidx) && n) return fail(CKKS_EINVAL, "ntt: null argument");
+    Plan P(c, ws);
+    std::vector<Item> v;
+    for (u32 i = 0; i < n; i++) {
+        if (pidx[i] >= c->n_prim) return fail(CKKS_EINVAL, "ntt: prime index %u out of range", pidx[i]);
+        if (!limbs[i]) return fail(CKKS_EINVAL, "ntt: null limb");
+        Item it = item0();
+        it.in[0] = limbs[i];
+        it.out = limbs[i];
+        it.prime = pidx[i];
+        v.push_back(it);
+    }
+    if (inverse)
+        P.add(1, I_COPY, v);
+    else
+        P.add(0, F_COPY, v);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+extern "C" int ckks_ntt(const ckks_ctx *c, uint64_t *const *limbs, const uint32_t *pidx, uint32_t n, void *ws,
+                        size_t ws_bytes, void *stream) {
+    return ntt_common(c, limbs, pidx, n, ws, ws_bytes, stream, false);
+}
+extern "C" int ckks_intt(const ckks_ctx *c, uint64_t *const *limbs, const uint32_t *pidx, uint32_t n, void *ws,
+                         size_t ws_bytes, void *stream) {
+    return ntt_common(c, limbs, pidx, n, ws, ws_bytes, stream, true);
+}
+
+// ---------------------------------------------------------------------
+// client side
+// ---------------------------------------------------------------------
+static void add_sample(std::vector<Item> &v, u64 *out, u32 prime, u32 kind, u32 obj, u32 tag) {
+    Item it = item0();
+    it.out = out;
+    it.prime = prime;
+    it.a = kind;
+    it.b = obj;
+    it.c = tag;
+    v.push_back(it);
+}
+
+extern "C" int ckks_keygen_secret(const ckks_ctx *c, uint64_t seed, uint64_t *sk, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    CK(check_ctx(c));
+    if (!sk) return fail(CKKS_EINVAL, "keygen_secret: null key");
+    Plan P(c, ws);
+    std::vector<Item> v;
+    for (u32 i = 0; i < c->n_prim; i++) add_sample(v, sk + (size_t)i * c->N, i, S_TERNARY, 0, TAG_SK);
+    P.add(0, F_SAMPLE, v, seed);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ckks_keygen_public(const ckks_ctx *c, const uint64_t *sk, uint64_t seed, uint64_t *pk, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!sk || !pk) return fail(CKKS_EINVAL, "keygen_public: null argument");
+    Plan P(c, ws);
+    const u32 N = c->N;
+    u64 *eh = P.limbs(c->n_q);
+    std::vector<Item> smp;
+    std::vector<EwItem> ew;
+    for (u32 i = 0; i < c->n_q; i++) {
+        add_sample(smp, eh + (size_t)i * N, i, S_CBD, 0, TAG_PK_E);
+        EwItem e = ew0();
+        e.op = EW_KEYGEN;
+        e.prime = i;
+        e.x[0] = eh + (size_t)i * N;
+        e.x[1] = sk + (size_t)i * N;
+        e.x[2] = nullptr;
+        e.y[0] = pk + (size_t)i * N;
+        e.y[1] = pk + ((size_t)c->n_q + i) * N;
+        e.v = (i64)(((u64)TAG_PK_A << 32) | 0u);
+        ew.push_back(e);
+    }
+    P.add(0, F_SAMPLE, smp, seed);
+    P.add(2, 0, ew, seed);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+// switching key from s' (NTT form over all primes, device) to s
+static int keygen_switch(const ckks_ctx *c, Plan &P, const u64 *sk, const u64 *sprime, u64 seed, u32 key_id,
+                         u64 *key) {
+    const u32 N = c->N, np = c->n_prim, A = c->alpha;
+    u64 *eh = P.limbs((size_t)c->digits_top * np);
+    std::vector<Item> smp;
+    std::vector<EwItem> ew;
+    for (u32 j = 0; j < c->digits_top; j++) {
+        const u32 obj = (key_id << 8) | j, lo = j * A, hi = std::min(lo + A, c->n_q);
+        for (u32 i = 0; i < np; i++) {
+            u64 *e = eh + ((size_t)j * np + i) * N;
+            add_sample(smp, e, i, S_CBD, obj, TAG_SWK_E);
+            EwItem w = ew0();
+            w.op = EW_KEYGEN;
+            w.prime = i;
+            w.x[0] = e;
+            w.x[1] = sk + (size_t)i * N;
+            w.x[2] = (i >= lo && i < hi) ? sprime + (size_t)i * N : nullptr;
+            w.y[0] = key + (((size_t)j * 2 + 0) * np + i) * N;
+            w.y[1] = key + (((size_t)j * 2 + 1) * np + i) * N;
+            w.v = (i64)(((u64)TAG_SWK_A << 32) | obj);
+            ew.push_back(w);
+        }
+    }
+    P.add(0, F_SAMPLE, smp, seed);
+    P.add(2, 0, ew, seed);
+    return CKKS_OK;
+}
+
+extern "C" int ckks_keygen_relin(const ckks_ctx *c, const uint64_t *sk, uint64_t seed, uint64_t *rk, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!sk || !rk) return fail(CKKS_EINVAL, "keygen_relin: null argument");
+    Plan P(c, ws);
+    u64 *s2 = P.limbs(c->n_prim);
+    std::vector<EwItem> sq;
+    for (u32 i = 0; i < c->n_prim; i++) {
+        EwItem w = ew0();
+        w.op = EW_SQUARE_S;
+        w.prime = i;
+        w.x[0] = sk + (size_t)i * c->N;
+        w.y[0] = s2 + (size_t)i * c->N;
+        sq.push_back(w);
+    }
+    P.add(2, 0, sq);
+    CK(keygen_switch(c, P, sk, s2, seed, 0, rk));
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ckks_keygen_galois(const ckks_ctx *c, const uint64_t *sk, uint32_t g, uint64_t seed, uint64_t *gk,
+                                  void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!sk || !gk) return fail(CKKS_EINVAL, "keygen_galois: null argument");
+    if (!(g & 1) || g >= 2 * c->N) return fail(CKKS_EINVAL, "keygen_galois: element %u not odd / < 2N", g);
+    if (g >= (1u << 24)) return fail(CKKS_EINVAL, "keygen_galois: element too large for the object id");
+    Plan P(c, ws);
+    u64 *sg = P.limbs(c->n_prim);
+    std::vector<EwItem> am;
+    for (u32 i = 0; i < c->n_prim; i++) {
+        EwItem w = ew0();
+        w.op = EW_AUTOMORPH;
+        w.prime = i;
+        w.v = g;
+        w.x[0] = sk + (size_t)i * c->N;
+        w.y[0] = sg + (size_t)i * c->N;
+        am.push_back(w);
+    }
+    P.add(2, 0, am);
+    CK(keygen_switch(c, P, sk, sg, seed, g, gk));
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ckks_pt_load(const ckks_ctx *c, const int64_t *coeffs, ckks_pt *out, void *ws, size_t ws_bytes,
+                            void *stream) {
+    CK(check_ctx(c));
+    if (!coeffs || !out || !out->data) return fail(CKKS_EINVAL, "pt_load: null argument");
+    if (out->level >= c->n_q) return fail(CKKS_ELEVEL, "pt_load: level out of range");
+    Plan P(c, ws);
+    std::vector<Item> v;
+    for (u32 i = 0; i <= out->level; i++) {
+        Item it = item0();
+        it.in[0] = (const u64 *)coeffs;
+        it.out = out->data + (size_t)i * c->N;
+        it.prime = i;
+        v.push_back(it);
+    }
+    P.add(0, F_INT, v);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ckks_encrypt(const ckks_ctx *c, const uint64_t *pk, const ckks_pt *pt, uint64_t seed, uint32_t obj,
+                            ckks_ct *out, void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!pk || !pt || !pt->data || !out || !out->data) return fail(CKKS_EINVAL, "encrypt: null argument");
+    if (pt->level >= c->n_q) return fail(CKKS_ELEVEL, "encrypt: level out of range");
+    const u32 L = pt->level + 1, N = c->N;
+    if (out->limb_stride < L) out->limb_stride = L;
+    Plan P(c, ws);
+    u64 *vh = P.limbs(L), *e0 = P.limbs(L), *e1 = P.limbs(L);
+    std::vector<Item> smp;
+    std::vector<EwItem> ew;
+    for (u32 i = 0; i < L; i++) {
+        add_sample(smp, vh + (size_t)i * N, i, S_TERNARY, obj, TAG_ENC_V);
+        add_sample(smp, e0 + (size_t)i * N, i, S_CBD, obj, TAG_ENC_E0);
+        add_sample(smp, e1 + (size_t)i * N, i, S_CBD, obj, TAG_ENC_E1);
+        EwItem w = ew0();
+        w.op = EW_ENCRYPT;
+        w.prime = i;
+        w.x[0] = vh + (size_t)i * N;
+        w.x[1] = e0 + (size_t)i * N;
+        w.x[2] = e1 + (size_t)i * N;
+        w.x[3] = pk + (size_t)i * N;
+        w.x[4] = pk + ((size_t)c->n_q + i) * N;
+        w.x[5] = pt->data + (size_t)i * N;
+        w.y[0] = out->data + (size_t)i * N;
+        w.y[1] = out->data + ((size_t)out->limb_stride + i) * N;
+        ew.push_back(w);
+    }
+    P.add(0, F_SAMPLE, smp, seed);
+    P.add(2, 0, ew, seed);
+    CK(P.run(ws_bytes, (hipStream_t)stream));
+    out->n_poly = 2;
+    out->level = pt->level;
+    out->scale = pt->scale;
+    return CKKS_OK;
+}
+
+extern "C" int ckks_decrypt(const ckks_ctx *c, const uint64_t *sk, const ckks_ct *ct, uint64_t *m, void *ws,
+                            size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!sk || !ct || !m) return fail(CKKS_EINVAL, "decrypt: null argument");
+    CK(check_ct(c, *ct, "decrypt"));
+    Plan P(c, ws);
+    std::vector<Item> v;
+    for (u32 i = 0; i <= ct->level; i++) {
+        Item it = item0();
+        it.in[0] = limb(c, *ct, 0, i);
+        it.in[1] = limb(c, *ct, 1, i);
+        it.in[2] = ct->n_poly == 3 ? limb(c, *ct, 2, i) : nullptr;
+        it.in[3] = sk + (size_t)i * c->N;
+        it.a = ct->n_poly;
+        it.prime = i;
+        it.out = m + (size_t)i * c->N;
+        v.push_back(it);
+    }
+    P.add(1, I_DECRYPT, v);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------
+// server side: elementwise ops
+// ---------------------------------------------------------------------
+static int ew_binary(const ckks_ctx *c, u32 op, const ckks_ct *a, const ckks_ct *b, const ckks_pt *p,
+                     const int64_t *v, const double *vs, ckks_ct *out, u32 B, void *ws, size_t ws_bytes,
+                     void *stream, const char *name) {
+    CK(check_ctx(c));
+    if (!a || !out || (B && !out)) return fail(CKKS_EINVAL, "%s: null argument", name);
+    Plan P(c, ws);
+    std::vector<EwItem> items;
+    for (u32 k = 0; k < B; k++) {
+        CK(check_ct(c, a[k], name));
+        if (!out[k].data) return fail(CKKS_EINVAL, "%s: null output", name);
+        const u32 L = a[k].level + 1;
+        u32 n_poly_out = a[k].n_poly;
+        double scale = a[k].scale;
+        if (b) {
+            CK(check_ct(c, b[k], name));
+            if (b[k].level != a[k].level)
+                return fail(CKKS_ELEVEL, "%s: level %u vs %u (mod-switch the higher one first)", name, a[k].level,
+                            b[k].level);
+            if (op == EW_TENSOR) {
+                if (a[k].n_poly != 2 || b[k].n_poly != 2) return fail(CKKS_EINVAL, "%s: inputs must have 2 polys", name);
+                n_poly_out = 3;
+                scale = a[k].scale * b[k].scale;
+            } else {
+                if (a[k].scale != b[k].scale)
+                    return fail(CKKS_ESCALE, "%s: scales %.17g vs %.17g differ", name, a[k].scale, b[k].scale);
+                if (a[k].n_poly != b[k].n_poly) return fail(CKKS_EINVAL, "%s: poly counts differ", name);
+            }
+        }
+        if (p) {
+            if (!p[k].data) return fail(CKKS_EINVAL, "%s: null plaintext", name);
+            if (p[k].level < a[k].level) return fail(CKKS_ELEVEL, "%s: plaintext level below ciphertext", name);
+            if (op == EW_ADD && a[k].scale != p[k].scale)
+                return fail(CKKS_ESCALE, "%s: scales %.17g vs %.17g differ", name, a[k].scale, p[k].scale);
+            if (op == EW_MUL) scale = a[k].scale * p[k].scale;
+        }
+        if (op == EW_MUL_CONST) scale = a[k].scale * vs[k];
+        ckks_ct o = out[k];
+        if (o.limb_stride < L) o.limb_stride = L;
+        for (u32 i = 0; i < L; i++) {
+            if (op == EW_TENSOR) {
+                EwItem w = ew0();
+                w.op = EW_TENSOR;
+                w.prime = i;
+                w.x[0] = limb(c, a[k], 0, i);
+                w.x[1] = limb(c, a[k], 1, i);
+                w.x[2] = limb(c, b[k], 0, i);
+                w.x[3] = limb(c, b[k], 1, i);
+                w.y[0] = limb(c, o, 0, i);
+                w.y[1] = limb(c, o, 1, i);
+                w.y[2] = limb(c, o, 2, i);
+                items.push_back(w);
+                continue;
+            }
+            for (u32 t = 0; t < a[k].n_poly; t++) {
+                EwItem w = ew0();
+                w.prime = i;
+                w.x[0] = limb(c, a[k], t, i);
+                w.y[0] = limb(c, o, t, i);
+                if (b) {
+                    w.op = op;
+                    w.x[1] = limb(c, b[k], t, i);
+                } else if (p) {
+                    if (op == EW_ADD && t > 0) {
+                        w.op = EW_COPY;
+                    } else {
+                        w.op = op;
+                        w.x[1] = p[k].data + (size_t)i * c->N;
+                    }
+                } else {
+                    if (op == EW_ADD_CONST && t > 0)
+                        w.op = EW_COPY;
+                    else
+                        w.op = op, w.v = v[k];
+                }
+                if (w.op == EW_COPY && w.x[0] == w.y[0]) continue;
+                items.push_back(w);
+            }
+        }
+        out[k].n_poly = n_poly_out;
+        out[k].level = a[k].level;
+        out[k].limb_stride = o.limb_stride;
+        out[k].scale = scale;
+    }
+    P.add(2, 0, items);
+    return P.run(ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ckks_add(const ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws,
+                        size_t ws_bytes, void *stream) {
+    if (!b) return fail(CKKS_EINVAL, "add: null argument");
+    return ew_binary(c, EW_ADD, a, b, nullptr, nullptr, nullptr, out, B, ws, ws_bytes, stream, "add");
+}
+extern "C" int ckks_sub(const ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws,
+                        size_t ws_bytes, void *stream) {
+    if (!b) return fail(CKKS_EINVAL, "sub: null argument");
+    return ew_binary(c, EW_SUB, a, b, nullptr, nullptr, nullptr, out, B, ws, ws_bytes, stream, "sub");
+}
+extern "C" int ckks_add_plain(const ckks_ctx *c, const ckks_ct *a, const ckks_pt *p, ckks_ct *out, uint32_t B,
+                              void *ws, size_t ws_bytes, void *stream) {
+    if (!p) return fail(CKKS_EINVAL, "add_plain: null argument");
+    return ew_binary(c, EW_ADD, a, nullptr, p, nullptr, nullptr, out, B, ws, ws_bytes, stream, "add_plain");
+}
+extern "C" int ckks_multiply_plain(const ckks_ctx *c, const ckks_ct *a, const ckks_pt *p, ckks_ct *out,
+                                   uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+    if (!p) return fail(CKKS_EINVAL, "multiply_plain: null argument");
+    return ew_binary(c, EW_MUL, a, nullptr, p, nullptr, nullptr, out, B, ws, ws_bytes, stream, "multiply_plain");
+}
+extern "C" int ckks_multiply_scalar(const ckks_ctx *c, const ckks_ct *a, const int64_t *v, const double *vs,
+                                    ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+    if (!v || !vs) return fail(CKKS_EINVAL, "multiply_scalar: null argument");
+    return ew_binary(c, EW_MUL_CONST, a, nullptr, nullptr, v, vs, out, B, ws, ws_bytes, stream, "multiply_scalar");
+}
+extern "C" int ckks_add_scalar(const ckks_ctx *c, const ckks_ct *a, const int64_t *v, ckks_ct *out, uint32_t B,
+                               void *ws, size_t ws_bytes, void *stream) {
+    if (!v) return fail(CKKS_EINVAL, "add_scalar: null argument");
+    return ew_binary(c, EW_ADD_CONST, a, nullptr, nullptr, v, nullptr, out, B, ws, ws_bytes, stream, "add_scalar");
+}
+extern "C" int ckks_multiply(const ckks_ctx *c, const ckks_ct *a, const ckks_ct *b, ckks_ct *out3, uint32_t B,
+                             void *ws, size_t ws_bytes, void *stream) {
+    if (!b) return fail(CKKS_EINVAL, "multiply: null argument");
+    return ew_binary(c, EW_TENSOR, a, b, nullptr, nullptr, nullptr, out3, B, ws, ws_bytes, stream, "multiply");
+}
+
+extern "C" int ckks_mod_switch_to(const ckks_ctx *c, ckks_ct *ct, uint32_t level) {
+    if (!c || !ct) return fail(CKKS_EINVAL, "mod_switch_to: null argument");
+    if (level > ct->level) return fail(CKKS_ELEVEL, "mod_switch_to: cannot raise level %u to %u", ct->level, level);
+    ct->level = level;
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// server side: key switching, rescale, rotation, fused HMult
+// ---------------------------------------------------------------------
+extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *rk, const ckks_ct *in3, ckks_ct *out, uint32_t B,
+                                void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!rk || !in3 || !out) return fail(CKKS_EINVAL, "relinearize: null argument");
+    Plan P(c, ws);
+    std::vector<KsJob> jobs(B);
+    for (u32 k = 0; k < B; k++) {
+        CK(check_ct(c, in3[k], "relinearize"));
+        if (in3[k].n_poly != 3) return fail(CKKS_EINVAL, "relinearize: input must have 3 polys");
+        if (!out[k].data) return fail(CKKS_EINVAL, "relinearize: null output");
+        if (out[k].data == in3[k].data) return fail(CKKS_EINVAL, "relinearize: out must not alias in");
+        const u32 L = in3[k].level + 1;
+        if (out[k].limb_stride < L) out[k].limb_stride = L;
+        KsJob &J = jobs[k];
+        J.level = in3[k].level;
+        for (u32 i = 0; i < L; i++) J.dl.push_back(limb(c, in3[k], 2, i));
+        for (u32 cc = 0; cc < 2; cc++) {
+            J.addend[cc] = limb(c, in3[k], cc, 0);
+            J.out[cc] = limb(c, out[k], cc, 0);
+        }
+    }
+    plan_keyswitch(P, jobs, rk);
+    CK(P.run(ws_bytes, (hipStream_t)stream));
+    for (u32 k = 0; k < B; k++) {
+        out[k].n_poly = 2;
+        out[k].level = in3[k].level;
+        out[k].scale = in3[k].scale;
+    }
+    return CKKS_OK;
+}
+
+extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *gk, uint32_t g, const ckks_ct *in, ckks_ct *out,
+                           uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!gk || !in || !out) return fail(CKKS_EINVAL, "rotate: null argument");
+    if (!(g & 1) || g >= 2 * c->N) return fail(CKKS_EINVAL, "rotate: Galois element %u not odd / < 2N", g);
+    Plan P(c, ws);
+    std::vector<EwItem> am;
+    std::vector<KsJob> jobs(B);
+    for (u32 k = 0; k < B; k++) {
+        CK(check_ct(c, in[k], "rotate"));
+        if (in[k].n_poly != 2) return fail(CKKS_EINVAL, "rotate: input must have 2 polys");
+        if (!out[k].data || out[k].data == in[k].data) return fail(CKKS_EINVAL, "rotate: out null or aliasing in");
+        const u32 L = in[k].level + 1, N = c->N;
+        if (out[k].limb_stride < L) out[k].limb_stride = L;
+        u64 *rot = P.limbs(2 * L);
+        for (u32 t = 0; t < 2; t++)
+            for (u32 i = 0; i < L; i++) {
+                EwItem w = ew0();
+                w.op = EW_AUTOMORPH;
+                w.prime = i;
+                w.v = g;
+                w.x[0] = limb(c, in[k], t, i);
+                w.y[0] = rot + ((size_t)t * L + i) * N;
+                am.push_back(w);
+            }
+        KsJob &J = jobs[k];
+        J.level = in[k].level;
+        for (u32 i = 0; i < L; i++) J.dl.push_back(rot + ((size_t)L + i) * N);
+        J.addend[0] = rot;
+        J.addend[1] = nullptr;
+        J.out[0] = limb(c, out[k], 0, 0);
+        J.out[1] = limb(c, out[k], 1, 0);
+    }
+    P.add(2, 0, am);
+    plan_keyswitch(P, jobs, gk);
+    CK(P.run(ws_bytes, (hipStream_t)stream));
+    for (u32 k = 0; k < B; k++) {
+        out[k].n_poly = 2;
+        out[k].level = in[k].level;
+        out[k].scale = in[k].scale;
+    }
+    return CKKS_OK;
+}
+
+extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws,
+                            size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!in || !out) return fail(CKKS_EINVAL, "rescale: null argument");
+    Plan P(c, ws);
+    std::vector<Item> top, res;
+    for (u32 k = 0; k < B; k++) {
+        CK(check_ct(c, in[k], "rescale"));
+        if (in[k].level == 0) return fail(CKKS_EDEPTH, "rescale: no prime left (level 0)");
+        if (!out[k].data) return fail(CKKS_EINVAL, "rescale: null output");
+        const u32 l = in[k].level;
+        ckks_ct o = out[k];
+        if (o.data == in[k].data) o.limb_stride = in[k].limb_stride;
+        else if (o.limb_stride < l) o.limb_stride = l;
+        u64 *tp = P.limbs(in[k].n_poly);
+        for (u32 t = 0; t < in[k].n_poly; t++) {
+            Item it = item0();
+            it.in[0] = limb(c, in[k], t, l);
+            it.out = tp + (size_t)t * c->N;
+            it.prime = l;
+            top.push_back(it);
+            for (u32 i = 0; i < l; i++) {
+                Item r = item0();
+                r.in[0] = tp + (size_t)t * c->N;
+                r.in[1] = limb(c, in[k], t, i);
+                r.a = l;
+                r.prime = i;
+                r.out = limb(c, o, t, i);
+                res.push_back(r);
+            }
+        }
+        out[k].limb_stride = o.limb_stride;
+    }
+    P.add(1, I_COPY, top);
+    P.add(0, F_RESCALE, res);
+    CK(P.run(ws_bytes, (hipStream_t)stream));
+    for (u32 k = 0; k < B; k++) {
+        out[k].n_poly = in[k].n_poly;
+        out[k].level = in[k].level - 1;
+        out[k].scale = in[k].scale / (double)c->primes[in[k].level];
+    }
+    return CKKS_OK;
+}
+
+// Fused HMult + relinearise + rescale over a ragged batch:
+//   1. INTT(a1 b1) per limb, stored pre-multiplied by its digit's hat^-1;
+//   2. ModUp of every digit to every other prime, NTT;
+//   3. key-switch inner product (the digit's own limbs use a1 b1 directly);
+//   4. INTT of the special-prime part of both accumulators;
+//   5. top limb: INTT(acc_l P^-1 + d_c);
+//   6. per limb i < l: z = conv_i(acc_P) P^-1 + rescale correction of the
+//      relinearised top limb, NTT;
+//   7. elementwise: out_c = (acc_c P^-1 + d_c - z_c) q_l^-1 for both polys.
+// By linearity this equals relinearise (ModDown) followed by rescale.
+static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B) {
+    const ckks_ctx *c = P.c;
+    const u32 N = c->N, k = c->n_p, A = c->alpha;
+    std::vector<Item> mul, modup, ip, ipP, last, fin;
+    std::vector<EwItem> tail;
+    for (u32 x = 0; x < B; x++) {
+        const u32 l = a[x].level, L = l + 1, E = L + k, beta = (L + A - 1) / A;
+        u64 *dcoef = P.limbs(L);
+        u64 *ext = P.limbs((size_t)beta * E);
+        u64 *acc = P.limbs((size_t)2 * E);
+        u64 *top = P.limbs(2);
+        u64 *zh = P.limbs((size_t)2 * L);
+        for (u32 i = 0; i < L; i++) {
+            const u32 j = i / A, lo = j * A, s = std::min(A, L - lo);
+            Item it = item0();
+            it.in[0] = limb(c, a[x], 1, i);
+            it.in[1] = limb(c, b[x], 1, i);
+            it.out = dcoef + (size_t)i * N;
+            it.prime = i;
+            it.v = 1;
+            it.c = j * A + s - 1;
+            it.a = i - lo;
+            mul.push_back(it);
+        }
+        for (u32 j = 0; j < beta; j++) {
+            const u32 lo = j * A, s = std::min(A, L - lo);
+            for (u32 t = 0; t < E; t++) {
+                if (t >= lo && t < lo + s) continue;
+                Item it = item0();
+                it.in[0] = dcoef + (size_t)lo * N;
+                it.a = lo;
+                it.b = s;
+                it.c = j;
+                it.v = 1;
+                it.prime = t < L ? t : c->n_q + (t - L);
+                it.out = ext + ((size_t)j * E + t) * N;
+                modup.push_back(it);
+            }
+        }
+        for (u32 t = 0; t < E; t++) {
+            Item it = item0();
+            it.in[0] = ext;
+            it.in[1] = rk;
+            it.in[3] = t < L ? limb(c, a[x], 1, t) : nullptr;
+            it.in[4] = t < L ? limb(c, b[x], 1, t) : nullptr;
+            it.a = beta;
+            it.b = t < L ? t / A : 0xFFFFFFFFu;
+            it.c = E;
+            it.v = t;
+            it.prime = t < L ? t : c->n_q + (t - L);
+            it.out = acc + (size_t)t * N;
+            it.out2 = acc + ((size_t)E + t) * N;
+            ip.push_back(it);
+        }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 m = 0; m < k; m++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L + m) * N;
+                it.out = (u64 *)it.in[0];
+                it.prime = c->n_q + m;
+                ipP.push_back(it);
+            }
+        for (u32 cc = 0; cc < 2; cc++) {
+            Item it = item0();
+            it.in[0] = acc + ((size_t)cc * E + l) * N;
+            it.in[1] = limb(c, a[x], 0, l);
+            it.in[2] = limb(c, a[x], 1, l);
+            it.in[3] = limb(c, b[x], 0, l);
+            it.in[4] = limb(c, b[x], 1, l);
+            it.b = cc;
+            it.prime = l;
+            it.out = top + (size_t)cc * N;
+            last.push_back(it);
+        }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 i = 0; i < l; i++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L) * N;
+                it.in[1] = top + (size_t)cc * N;
+                it.a = c->n_q;
+                it.b = k;
+                it.c = l;
+                it.prime = i;
+                it.out = zh + ((size_t)cc * L + i) * N;
+                fin.push_back(it);
+            }
+        for (u32 i = 0; i < l; i++) {
+            EwItem w = ew0();
+            w.op = EW_HMULT_FIN;
+            w.prime = i;
+            w.v = l;
+            w.x[0] = zh + (size_t)i * N;
+            w.x[1] = zh + ((size_t)L + i) * N;
+            w.x[2] = acc + (size_t)i * N;
+            w.x[3] = acc + ((size_t)E + i) * N;
+            w.x[4] = limb(c, a[x], 0, i);
+            w.x[5] = limb(c, a[x], 1, i);
+            w.x[6] = limb(c, b[x], 0, i);
+            w.x[7] = limb(c, b[x], 1, i);
+            w.y[0] = limb(c, out[x], 0, i);
+            w.y[1] = limb(c, out[x], 1, i);
+            tail.push_back(w);
+        }
+    }
+    P.add(1, I_MUL, mul);
+    P.add(0, F_MODUP, modup);
+    P.add(3, 0, ip);
+    P.add(1, I_COPY, ipP);
+    P.add(1, I_HMULT, last);
+    P.add(0, F_HMULT, fin);
+    P.add(2, 0, tail);
+    return CKKS_OK;
+}
+
+extern "C" int ckks_hmult_relin_rescale(const ckks_ctx *c, const uint64_t *rk, const ckks_ct *a, const ckks_ct *b,
+                                        ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!rk || !a || !b || !out) return fail(CKKS_EINVAL, "hmult: null argument");
+    for (u32 x = 0; x < B; x++) {
+        CK(check_ct(c, a[x], "hmult a"));
+        CK(check_ct(c, b[x], "hmult b"));
+        if (a[x].n_poly != 2 || b[x].n_poly != 2) return fail(CKKS_EINVAL, "hmult: inputs must have 2 polys");
+        if (a[x].level != b[x].level) return fail(CKKS_ELEVEL, "hmult: levels %u vs %u", a[x].level, b[x].level);
+        if (a[x].level == 0) return fail(CKKS_EDEPTH, "hmult: no prime left to rescale");
+        if (!out[x].data) return fail(CKKS_EINVAL, "hmult: null output");
+        if (out[x].data == a[x].data || out[x].data == b[x].data)
+            return fail(CKKS_EINVAL, "hmult: out must not alias an input");
+        if (out[x].limb_stride < a[x].level) out[x].limb_stride = a[x].level;
+    }
+    Plan P(c, ws);
+    CK(plan_hmult(P, rk, a, b, out, B));
+    CK(P.run(ws_bytes, (hipStream_t)stream));
+    for (u32 x = 0; x < B; x++) {
+        out[x].n_poly = 2;
+        out[x].level = a[x].level - 1;
+        out[x].scale = a[x].scale * b[x].scale / (double)c->primes[a[x].level];
+    }
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// encrypted linear layer
+// ---------------------------------------------------------------------
+extern "C" int ckks_linear(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, const int64_t *W, double w_scale,
+                           ckks_ct *out, uint32_t n_out, void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!in || !W || !out || !n_in || !n_out) return fail(CKKS_EINVAL, "linear: bad argument");
+    const u32 l = in[0].level, L = l + 1, stride = in[0].limb_stride;
+    for (u32 i = 0; i < n_in; i++) {
+        CK(check_ct(c, in[i], "linear"));
+        if (in[i].n_poly != 2) return fail(CKKS_EINVAL, "linear: inputs must have 2 polys");
+        if (in[i].level != l) return fail(CKKS_ELEVEL, "linear: input levels differ");
+        if (in[i].scale != in[0].scale) return fail(CKKS_ESCALE, "linear: input scales differ");
+        if (in[i].limb_stride != stride) return fail(CKKS_EINVAL, "linear: input limb strides differ");
+    }
+    const u32 ostride = std::max(out[0].limb_stride, L);
+    for (u32 j = 0; j < n_out; j++)
+        if (!out[j].data || std::max(out[j].limb_stride, L) != ostride)
+            return fail(CKKS_EINVAL, "linear: outputs need data and one limb stride");
+    const size_t wt_bytes = (size_t)L * n_out * n_in * 8;
+    const size_t ptr_off = (wt_bytes + 255) & ~(size_t)255;
+    const size_t need = ptr_off + (size_t)(n_in + n_out) * 8;
+    if (need > ws_bytes) return fail(CKKS_ENOMEM, "linear: workspace too small: need %zu", need);
+    if (!ws || (((uintptr_t)ws) & 255)) return fail(CKKS_EINVAL, "linear: null or unaligned workspace");
+    uint8_t *w8 = (uint8_t *)ws;
+    u64 *wt = (u64 *)w8;
+    std::vector<const u64 *> ptrs(n_in + n_out);
+    for (u32 i = 0; i < n_in; i++) ptrs[i] = in[i].data;
+    for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(w8 + ptr_off, ptrs.data(), ptrs.size() * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_reduce_weights(c->tb, W, wt, n_out * n_in, L, s));
+    ProfRec rec;
+    if (g_prof_on) {
+        rec.name = launch_name(4, 0, c->log_n);
+        rec.items = n_out;
+        HIP_TRY(hipEventCreate(&rec.e0));
+        HIP_TRY(hipEventCreate(&rec.e1));
+        HIP_TRY(hipEventRecord(rec.e0, s));
+    }
+    HIP_TRY(launch_linear(c->tb, (const u64 *const *)(w8 + ptr_off), wt, (u64 *const *)(w8 + ptr_off + n_in * 8),
+                          n_in, n_out, L, stride, ostride, s));
+    if (g_prof_on) {
+        HIP_TRY(hipEventRecord(rec.e1, s));
+        g_prof.push_back(rec);
+    }
+    for (u32 j = 0; j < n_out; j++) {
+        out[j].n_poly = 2;
+        out[j].level = l;
+        out[j].limb_stride = ostride;
+        out[j].scale = in[0].scale * w_scale;
+    }
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// encrypted linear layer, sparse rows (CSR)
+// ---------------------------------------------------------------------
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_in, uint32_t n_out, size_t nnz,
+                                                  uint32_t level) {
+    if (!c) return 0;
+    const size_t L = level + 1;
+    return al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8) + al256((size_t)(n_in + n_out) * 8) +
+           1024;
+}
+
+extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, uint32_t n_out,
+                               const uint32_t *row_ptr, const uint32_t *col, const int64_t *w, double w_scale,
+                               ckks_ct *out, void *ws, size_t ws_bytes, void *stream) {
+    CK(check_ctx(c));
+    if (!in || !out || !row_ptr || !col || !w || !n_in || !n_out) return fail(CKKS_EINVAL, "linear_csr: bad argument");
+    const u32 l = in[0].level, L = l + 1, stride = in[0].limb_stride;
+    for (u32 i = 0; i < n_in; i++) {
+        CK(check_ct(c, in[i], "linear_csr"));
+        if (in[i].n_poly != 2) return fail(CKKS_EINVAL, "linear_csr: inputs must have 2 polys");
+        if (in[i].level != l) return fail(CKKS_ELEVEL, "linear_csr: input levels differ");
+        if (in[i].scale != in[0].scale) return fail(CKKS_ESCALE, "linear_csr: input scales differ");
+        if (in[i].limb_stride != stride) return fail(CKKS_EINVAL, "linear_csr: input limb strides differ");
+    }
+    const u32 ostride = std::max(out[0].limb_stride, L);
+    for (u32 j = 0; j < n_out; j++)
+        if (!out[j].data || std::max(out[j].limb_stride, L) != ostride)
+            return fail(CKKS_EINVAL, "linear_csr: outputs need data and one limb stride");
+    const size_t nnz = row_ptr[n_out];
+    for (u32 j = 0; j < n_out; j++)
+        if (row_ptr[j + 1] < row_ptr[j]) return fail(CKKS_EINVAL, "linear_csr: row_ptr not monotone");
+    for (size_t e = 0; e < nnz; e++)
+        if (col[e] >= n_in) return fail(CKKS_EINVAL, "linear_csr: column %u out of range", col[e]);
+    // groups of consecutive rows with identical column lists
+    std::vector<LinGroup> groups;
+    std::vector<u32> cols;
+    std::vector<i64> wv;
+    for (u32 j = 0; j < n_out;) {
+        const u32 b = row_ptr[j], n = row_ptr[j + 1] - b;
+        u32 r = 1;
+        while (j + r < n_out && r < (u32)kLinRows) {
+            const u32 b2 = row_ptr[j + r], n2 = row_ptr[j + r + 1] - b2;
+            if (n2 != n || memcmp(col + b, col + b2, n * 4) != 0) break;
+            r++;
+        }
+        LinGroup g{j, r, (u32)cols.size(), n, (u32)wv.size(), 0};
+        cols.insert(cols.end(), col + b, col + b + n);
+        for (u32 k = 0; k < r; k++) wv.insert(wv.end(), w + row_ptr[j + k], w + row_ptr[j + k] + n);
+        groups.push_back(g);
+        j += r;
+    }
+    const size_t W = wv.size();
+    std::vector<u64> wt((size_t)L * W);
+    for (u32 t = 0; t < L; t++) {
+        const u64 q = c->primes[t];
+        for (size_t e = 0; e < W; e++) {
+            const i64 v = wv[e];
+            u64 m = v >= 0 ? (u64)v % q : (q - ((u64)(-(v + 1)) + 1) % q) % q;
+            wt[(size_t)t * W + e] = m;
+        }
+    }
+    const size_t o_groups = 0, o_cols = al256(groups.size() * sizeof(LinGroup)), o_wt = o_cols + al256(cols.size() * 4),
+                 o_ptr = o_wt + al256(wt.size() * 8), need = o_ptr + al256((size_t)(n_in + n_out) * 8);
+    if (need > ws_bytes) return fail(CKKS_ENOMEM, "linear_csr: workspace too small: need %zu", need);
+    if (!ws || (((uintptr_t)ws) & 255)) return fail(CKKS_EINVAL, "linear_csr: null or unaligned workspace");
+    std::vector<uint8_t> img(need, 0);
+    memcpy(img.data() + o_groups, groups.data(), groups.size() * sizeof(LinGroup));
+    memcpy(img.data() + o_cols, cols.data(), cols.size() * 4);
+    memcpy(img.data() + o_wt, wt.data(), wt.size() * 8);
+    std::vector<const u64 *> ptrs(n_in + n_out);
+    for (u32 i = 0; i < n_in; i++) ptrs[i] = in[i].data;
+    for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
+    memcpy(img.data() + o_ptr, ptrs.data(), ptrs.size() * 8);
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *w8 = (uint8_t *)ws;
+    HIP_TRY(hipMemcpyAsync(w8, img.data(), need, hipMemcpyHostToDevice, s));
+    ProfRec rec;
+    if (g_prof_on) {
+        rec.name = launch_name(4, 0, c->log_n);
+        rec.items = (u32)groups.size();
+        HIP_TRY(hipEventCreate(&rec.e0));
+        HIP_TRY(hipEventCreate(&rec.e1));
+        HIP_TRY(hipEventRecord(rec.e0, s));
+    }
+    HIP_TRY(launch_linear_grouped(c->tb, (const LinGroup *)(w8 + o_groups), (u32)groups.size(),
+                                  (const u32 *)(w8 + o_cols), (const u64 *)(w8 + o_wt), (u32)W,
+                                  (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L,
+                                  stride, ostride, s));
+    if (g_prof_on) {
+        HIP_TRY(hipEventRecord(rec.e1, s));
+        g_prof.push_back(rec);
+    }
+    for (u32 j = 0; j < n_out; j++) {
+        out[j].n_poly = 2;
+        out[j].level = l;
+        out[j].limb_stride = ostride;
+        out[j].scale = in[0].scale * w_scale;
+    }
+    return CKKS_OK;
+}

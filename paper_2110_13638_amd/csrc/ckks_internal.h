@@ -1,0 +1,85 @@
+// Internal definitions shared by the host runtime (ckks_host.cpp) and the
+// gfx950 kernels (ckks_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ckks {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+constexpr int kMaxPrimes = 64;
+constexpr int kMinLogN = 10;
+constexpr int kMaxLogN = 15;
+
+// Per-prime constants (one entry per prime index: data primes, then the
+// special primes).
+struct PrimeConst {
+    u64 q;
+    u64 two_q;
+    u64 br_hi, br_lo;  // floor(2^128 / q) as two words (128-bit Barrett)
+    u64 mu;            // floor(2^64 / q) (64-bit Barrett)
+    u64 ninv, ninv_sh;     // N^-1 mod q with its Shoup companion
+    u64 last_w, last_w_sh; // (psi^-1 table entry 1) * N^-1: merged last inverse stage
+    u64 pinv, pinv_sh;     // P^-1 mod q (data primes; P = product of special primes)
+    u64 pmod, pmod_sh;     // P mod q
+};
+
+// Device view of the uploaded context tables. Built by the host from the
+// device base address; passed by value to every kernel.
+struct DevTables {
+    const PrimeConst *pc;        // [n_prim]
+    const ulonglong2 *tw;        // [n_prim][N] (w, w') forward psi^brv(k)
+    const ulonglong2 *itw;       // [n_prim][N] (w, w') inverse: (psi^brv(k))^-1
+    const u64 *modup;            // ModUp blocks, see modup_block()
+    const u64 *moddown;          // ModDown block
+    const ulonglong2 *rescale;   // [n_q][n_q] (q_l^-1 mod q_i, Shoup)
+    u32 log_n, n_q, n_p, n_prim, alpha, n_digits_top;
+};
+
+// ModUp constants for digit j truncated to s primes (1 <= s <= alpha):
+// block (j * alpha + s - 1) of size modup_block_words(): first 2*alpha
+// words are (inv, inv_sh) pairs for (Q_D / q_i)^-1 mod q_i, then
+// alpha x n_prim words of (Q_D / q_i) mod t.
+__host__ __device__ inline u32 modup_block_words(u32 alpha, u32 n_prim) {
+    return 2 * alpha + alpha * n_prim;
+}
+// ModDown block: n_p pairs (inv, inv_sh) of (P / p_m)^-1 mod p_m, then
+// n_p x n_q words (P / p_m) mod q_i.
+
+// ---------------------------------------------------------------------
+// Work-item descriptors (one per workgroup of an NTT-shaped kernel, or a
+// unit of an elementwise kernel). Their meaning is per kernel and
+// documented next to each kernel.
+// ---------------------------------------------------------------------
+struct Item {
+    const u64 *in[8];
+    u64 *out;
+    u64 *out2;
+    u32 prime;  // prime index of the limb this item produces
+    u32 a, b, c;  // small kernel-specific integers
+    i64 v;      // kernel-specific signed constant
+};
+
+// Elementwise descriptors: one per output limb (or limb pair).
+struct EwItem {
+    const u64 *x[8];
+    u64 *y[3];
+    u32 prime;
+    u32 op;
+    i64 v;
+};
+
+// Grouped sparse linear layer: rows that share one column list are one
+// group; weights of a group are dense [nrows][ncols] at w_off.
+struct LinGroup {
+    u32 row0, nrows;   // output rows row0 .. row0 + nrows - 1
+    u32 col_off, ncols;  // columns col[col_off .. col_off + ncols - 1]
+    u32 w_off, pad;
+};
+constexpr int kLinRows = 8;  // rows per group (accumulators per thread)
+
+}  // namespace ckks

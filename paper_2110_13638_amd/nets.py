@@ -1,0 +1,217 @@
+"""Encrypted lowerings of the paper's network shapes onto the graph runtime.
+
+Layer semantics follow the paper: conv ("biased cross-correlation",
+Section 4.2.2) and dense (Section 4.2.3) are sums of ciphertext x weight
+products plus a bias, the activation is a polynomial (x^2), and the
+container rescales after every product (Section 4.1). Three packings:
+
+  * tiny dense: features x samples in one ciphertext (feature-major),
+    dense layer by the hybrid diagonal method (rotations + plaintext
+    diagonals), then rotate-and-sum, then x^2;
+  * vision: slot-batched, one ciphertext per pixel, image s in slot s;
+    conv = sparse linear layer over pixels (stride 2, one zero row and
+    column of padding), dense layers = linear layers over ciphertexts;
+  * yield regressor: windows x 256 padded features per ciphertext,
+    three hybrid-diagonal dense layers with power-of-two Galois keys.
+"""
+import numpy as np
+
+from .graph import Graph
+
+
+def naf_digits(n):
+    """signed binary digits of n, least significant first: [(position, +-1)]"""
+    out, k = [], 0
+    while n:
+        if n & 1:
+            d = 2 - (n & 3)
+            out.append((k, d))
+            n -= d
+        n >>= 1
+        k += 1
+    return out
+
+
+def galois_for_steps(ctx, steps, direct=False):
+    """Galois elements needed for the steps: each step itself when
+    direct, else the power-of-two factors of its non-adjacent form."""
+    half = ctx.N // 2
+    out = set()
+    for s in steps:
+        s %= half
+        if s == 0:
+            continue
+        if direct:
+            out.add(ctx.galois_elt(s))
+            continue
+        v = s if s <= half // 2 else s - half
+        for k, d in naf_digits(v):
+            out.add(ctx.galois_elt(d * (1 << k)))
+    return sorted(out)
+
+
+def galois_key_seed(base, g):
+    return base + g
+
+
+# ---------------------------------------------------------------------------
+# tiny dense: dense n_in -> n_out by diagonals on n_in x S slots, then x^2
+# ---------------------------------------------------------------------------
+def diag_plan(n_in, n_out, block):
+    """in_steps i * block (i < n_out), then rotate-and-sum by n_out * block,
+    2 n_out block, ... while the span stays below n_in"""
+    in_steps = [i * block for i in range(n_out)]
+    post, span = [], n_out
+    while span < n_in:
+        post.append(span * block)
+        span *= 2
+    return in_steps, post
+
+
+def tiny_dense_diagonals(W, block):
+    """diag_i[f * block + w] = W[f mod n_out][(f + i) mod n_in]"""
+    n_out, n_in = W.shape
+    d = np.empty((n_out, n_in, block))
+    for i in range(n_out):
+        for f in range(n_in):
+            d[i, f, :] = W[f % n_out, (f + i) % n_in]
+    return d.reshape(n_out, n_in * block)
+
+
+def build_tiny_dense(ctx, W, block, in_level, scale, diag_coeffs=None):
+    n_out, n_in = W.shape
+    in_steps, post = diag_plan(n_in, n_out, block)
+    if diag_coeffs is None:
+        diag_coeffs = np.stack([ctx.encode_coeffs(d, scale) for d in tiny_dense_diagonals(W, block)])
+    g = Graph(ctx)
+    x = g.input(1, in_level, scale)
+    d = g.diag_dense(diag_coeffs, in_steps, scale, post)
+    g.chain(x, d, g.square(), g.output())
+    g.plan()
+    return g, in_steps + post
+
+
+# ---------------------------------------------------------------------------
+# vision: slot-batched conv -> x^2 -> dense -> x^2 -> dense
+# ---------------------------------------------------------------------------
+def conv_rows(conv_w, side, stride=2):
+    """rows of the strided cross-correlation over the pixel ciphertexts:
+    output (o, y, x) = sum w_o[dy, dx] pix(2y + dy, 2x + dx); pixels in the
+    zero padding (one bottom row, one right column) are dropped"""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    rows = []
+    for o in range(F):
+        for y in range(out_side):
+            for xx in range(out_side):
+                r = []
+                for dy in range(k):
+                    for dx in range(k):
+                        pr, pc = stride * y + dy, stride * xx + dx
+                        if pr < side and pc < side:
+                            r.append((pr * side + pc, conv_w[o, dy, dx]))
+                rows.append(r)
+    return rows, out_side
+
+
+def reorder_conv_rows(rows, filters):
+    """Group the filters of one output position next to each other (they
+    share their pixel list, so the linear kernel loads it once): new row
+    order is position-major; returns rows and the permutation back."""
+    per = len(rows) // filters
+    order = [o * per + p for p in range(per) for o in range(filters)]
+    return [rows[i] for i in order], order
+
+
+def build_vision(ctx, P, side, in_level, scale, w_scale=None):
+    w_scale = w_scale or scale
+    F = P["conv_w"].shape[0]
+    rows, out_side = conv_rows(P["conv_w"], side)
+    rows_g, order = reorder_conv_rows(rows, F)
+    per = out_side * out_side
+    conv_bias = [P["conv_b"][i // per] for i in order]
+    # dense 1 consumes the conv outputs in their grouped order
+    W1 = P["w1"][:, order]
+    g = Graph(ctx)
+    x = g.input(side * side, in_level, scale)
+    c = g.linear(rows_g, w_scale, conv_bias)
+    s1 = g.square()
+    d1 = g.dense(W1, w_scale, P["b1"])
+    s2 = g.square()
+    d2 = g.dense(P["w2"], w_scale, P["b2"])
+    g.chain(x, c, s1, d1, s2, d2, g.output())
+    g.plan()
+    return g
+
+
+# ---------------------------------------------------------------------------
+# yield regressor: 256 padded features x W windows per ciphertext
+# ---------------------------------------------------------------------------
+def yield_windows(slots, n_feat=256):
+    return slots // n_feat
+
+
+def yield_pack(x, slots, n_feat=256):
+    """x [n][features] -> [n_ct][slots], slot f * W + w holds window w's
+    feature f (zero padded to 256 features)"""
+    W = yield_windows(slots, n_feat)
+    n, f = x.shape
+    n_ct = -(-n // W)
+    v = np.zeros((n_ct, n_feat, W))
+    for c in range(n_ct):
+        blk = x[c * W:(c + 1) * W]
+        v[c, :f, : blk.shape[0]] = blk.T
+    return v.reshape(n_ct, n_feat * W)
+
+
+def yield_diagonals(M, period, W, n_feat=256):
+    """d_i[f * W + w] = M[f mod n_out][(f + i) mod period] (0 beyond n_in)"""
+    n_out, n_in = M.shape
+    d = np.zeros((n_out, n_feat, W))
+    for i in range(n_out):
+        for f in range(n_feat):
+            c = (f + i) % period
+            if c < n_in:
+                d[i, f, :] = M[f % n_out, c]
+    return d.reshape(n_out, n_feat * W)
+
+
+def yield_bias(b, W, n_feat=256):
+    n_out = len(b)
+    return np.repeat(np.array([b[f % n_out] for f in range(n_feat)]), W)
+
+
+YIELD_PERIODS = (256, 64, 16)
+
+
+def yield_steps(ws, W):
+    steps = []
+    for l, M in enumerate(ws):
+        a, b = diag_plan(YIELD_PERIODS[l], M.shape[0], W)
+        steps += a + b
+    return steps
+
+
+def build_yield(ctx, ws, bs, n_ct, in_level, scale, diag_coeffs=None, bias_coeffs=None):
+    """diag_coeffs / bias_coeffs: optional pre-encoded integer plaintexts
+    per layer (otherwise encoded here with the library's encoder)."""
+    W = yield_windows(ctx.N // 2)
+    g = Graph(ctx)
+    prev = g.input(n_ct, in_level, scale)
+    for l, (M, b) in enumerate(zip(ws, bs)):
+        in_steps, post = diag_plan(YIELD_PERIODS[l], M.shape[0], W)
+        if diag_coeffs is None:
+            dc = np.stack([ctx.encode_coeffs(d, scale) for d in yield_diagonals(M, YIELD_PERIODS[l], W)])
+        else:
+            dc = diag_coeffs[l]
+        if bias_coeffs is None:
+            node = g.diag_dense(dc, in_steps, scale, post, bias_slots=yield_bias(b, W))
+        else:
+            node = g.diag_dense(dc, in_steps, scale, post, bias_coeffs=bias_coeffs[l])
+        g.edge(prev, node)
+        prev = node
+        if l < len(ws) - 1:
+            prev = g.edge(prev, g.square())
+    g.edge(prev, g.output())
+    g.plan()
+    return g

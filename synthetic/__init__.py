@@ -21,6 +21,19 @@ def residues(seed, primes, n, count=1):
     return out
 
 
+def residues_device(seed, primes, n, count, device):
+    """Same role as ``residues`` for large batches, drawn on the device with
+    a seeded torch generator: tensor [count][limbs][n] int64 holding values
+    uniform in [0, q_i)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    out = torch.empty(count, len(primes), n, dtype=torch.int64, device=device)
+    for i, q in enumerate(primes):
+        out[:, i] = torch.randint(0, int(q), (count, n), generator=g, device=device, dtype=torch.int64)
+    return out
+
+
 def ragged_limbs(batch, lo=4, hi=16):
     """Limb counts lo + (i mod (hi - lo + 1)) for a ragged batch."""
     span = hi - lo + 1

@@ -1,0 +1,89 @@
+"""The C ABI library loads and exports every symbol include/ckks.h declares
+(no device calls), and the host-only entry points behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ckks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ckks_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2110_13638_amd import _native as nat
+    lib = ctypes.CDLL(nat.LIB_PATH)
+    names = _declared()
+    assert len(names) > 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared entry points
+    assert sorted(nat.exported_symbols()) == names
+
+
+def test_host_only_calls():
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    assert nat.ckks_find_primes(13, [60, 40, 40, 60]) == O.find_primes(13, [60, 40, 40, 60])
+    primes = O.find_primes(13, [60, 40, 40, 60])
+    h = nat.ckks_ctx_create(13, primes[:3], primes[3:], 3)
+    try:
+        assert nat.ckks_ctx_digits(h, 2) == 3
+        assert nat.ckks_ct_bytes(h, 2, 2) == 2 * 3 * 8192 * 8
+        assert nat.ckks_workspace_bytes(h, nat.CKKS_OP_HMULT, 4, [2, 2, 1, 1]) > 0
+        assert nat.ckks_galois_elt(h, 1) == 5 and nat.ckks_galois_elt(h, -1) == pow(5, 4095, 16384)
+        # device calls before ckks_ctx_upload are rejected on the host
+        with pytest.raises(nat.CkksError):
+            nat.ckks_keygen_secret(h, 1, 0, None, 0)
+    finally:
+        nat.ckks_ctx_destroy(h)
+
+
+def test_bad_parameters_rejected():
+    from paper_2110_13638_amd import _native as nat
+    with pytest.raises(nat.CkksError) as e:
+        nat.ckks_ctx_create(13, [97], [193], 1)  # not 1 mod 2N
+    assert e.value.code == nat.CKKS_EPARAMS
+
+
+def test_parameterise_matches_algorithm8_closed_form():
+    from paper_2110_13638_amd import _native as nat
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "alg8_parameterise.txt"))
+            if l.strip() and not l.startswith("#")]
+    for r in rows:
+        c, n, bits = int(r[0]), int(r[1]), [int(x) for x in r[2:]]
+        assert nat.ckks_parameterise(c) == (bits, n)
+
+
+def test_host_encoder_roundtrip():
+    import numpy as np
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    from oracle import encoding as OE
+    logn = 10
+    primes = O.find_primes(logn, [60, 40, 60])
+    h = nat.ckks_ctx_create(logn, primes[:2], primes[2:], 2)
+    try:
+        n = 1 << logn
+        rng = np.random.default_rng(0)
+        z = rng.uniform(-1, 1, n // 2)
+        re_ = (ctypes.c_double * len(z))(*z)
+        coeffs = (ctypes.c_int64 * n)()
+        nat.ckks_encode(h, re_, None, len(z), 2.0 ** 40, coeffs)
+        m = np.array(coeffs[:], dtype=np.int64)
+        mo = OE.encode(z, 2.0 ** 40, n)
+        assert np.abs(m - mo).max() <= 1
+        res = np.stack([np.array([int(c) % q for c in m], dtype=np.uint64) for q in primes[:2]])
+        out_re = (ctypes.c_double * (n // 2))()
+        out_im = (ctypes.c_double * (n // 2))()
+        nat._call("ckks_decode", h, res.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), 1, 2.0 ** 40,
+                  out_re, out_im, n // 2)
+        assert np.max(np.abs(np.array(out_re[:]) - z)) < 1e-9
+        assert np.allclose(np.array(out_re[:]), OE.decode_residues(res, primes, 2.0 ** 40, n).real, atol=1e-12)
+    finally:
+        nat.ckks_ctx_destroy(h)

@@ -1,0 +1,164 @@
+"""GPU graph runtime on the three network shapes: ciphertexts bit-exact
+against the oracle's lowering from the same integer plaintexts and seeds,
+decoded outputs within 2^-18 * max(1, |y|) of the FP64 network."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from oracle import encoding as E
+from oracle import nets as ON
+from oracle import plainnet as PN
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 2.0 ** -18
+SCALE = 2.0 ** 40
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_13638_amd import ckks, nets
+    return ckks, nets
+
+
+def _setup(ckks, logn, q_bits, p_bits, dnum, seed):
+    primes = O.find_primes(logn, list(q_bits) + list(p_bits))
+    q, p = primes[: len(q_bits)], primes[len(q_bits):]
+    ctx = ckks.Context(logn, q, p, dnum).keygen(seed)
+    orc = O.Oracle(logn, q, p, dnum)
+    return ctx, orc
+
+
+def _enc_both(ctx, orc, keys, z, level, seed, obj):
+    m = E.encode(z, SCALE, ctx.N)
+    ct = ctx.encrypt(ctx.pt_from_coeffs(m, level, SCALE), seed=seed, obj=obj)
+    cto = orc.encrypt(keys.pk, orc.reduce_int(m, level), level, seed, obj)
+    assert np.array_equal(ct.residues(), cto)
+    return ct, cto
+
+
+def _rel_err(got, want):
+    return np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+
+
+def test_tiny_dense_full_size(mods):
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 13, [60, 40, 40], [60], 3, 1)
+    x, W = S.tiny_dense_inputs()
+    in_steps, post = PN.tiny_dense_steps()
+    steps = in_steps[1:] + post
+    elts = [orc.galois_elt(s) for s in steps]
+    keys = ON.Keys(orc, 1, elts)
+    assert sorted(elts) == nets.galois_for_steps(ctx, steps, direct=True)
+    for g in elts:
+        ctx.add_galois_key(g, nets.galois_key_seed(1 + 3, g))
+    ct, cto = _enc_both(ctx, orc, keys, x.reshape(-1), 2, 7, 0)
+    # the product computes the same diagonals as the oracle's plain network
+    assert np.array_equal(nets.tiny_dense_diagonals(W, 256), PN.tiny_dense_diagonals(W))
+    coeffs = np.stack([E.encode(d, SCALE, ctx.N) for d in PN.tiny_dense_diagonals(W)])
+    g, _ = nets.build_tiny_dense(ctx, W, 256, 2, SCALE, diag_coeffs=coeffs)
+    out = g.run([ct])[0]
+    pts = [orc.reduce_int(c, 2) for c in coeffs]
+    y, s1 = ON.diag_dense(orc, keys, cto, SCALE, pts, SCALE, in_steps, post)
+    z, s2 = ON.square(orc, keys, y, s1)
+    assert out.level == 0 and out.scale == s2
+    assert np.array_equal(out.residues(), z)
+    got = ctx.decrypt(out, 4096).real[: 8 * 256].reshape(8, 256)
+    err = _rel_err(got, PN.tiny_dense_math(x, W))
+    print("tiny dense: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL
+
+
+def test_yield_small_ring(mods):
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 12, [60] + [40] * 5, [60], 6, 2)
+    x, ws, bs = S.yield_inputs(n_windows=16)
+    slots = ctx.N // 2
+    Wn = nets.yield_windows(slots)
+    steps = nets.yield_steps(ws, Wn)
+    elts = nets.galois_for_steps(ctx, steps)
+    assert elts == ON.naf_elements(orc, steps)
+    keys = ON.Keys(orc, 2, elts)
+    for g in elts:
+        ctx.add_galois_key(g, nets.galois_key_seed(2 + 3, g))
+    packed = PN.yield_pack(x, slots)
+    assert np.array_equal(nets.yield_pack(x, slots), packed)
+    n_ct = packed.shape[0]
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, packed[c], 5, 9, c) for c in range(n_ct)])
+    # integer plaintexts of every layer, encoded by the oracle
+    dcs, bcs = [], []
+    s, lvl = SCALE, 5
+    periods = [256, 64, 16]
+    for l in range(3):
+        d = PN.yield_diagonals(ws[l], periods[l], Wn)
+        assert np.array_equal(nets.yield_diagonals(ws[l], periods[l], Wn), d)
+        dcs.append(np.stack([E.encode(di, SCALE, ctx.N) for di in d]))
+        out_scale = s * SCALE / orc.q[lvl]
+        bcs.append(E.encode(PN.yield_bias_vector(bs[l], Wn), out_scale, ctx.N))
+        s, lvl = out_scale, lvl - 1
+        if l < 2:
+            s, lvl = s * s / orc.q[lvl], lvl - 1
+    g = nets.build_yield(ctx, ws, bs, n_ct, 5, SCALE, diag_coeffs=dcs, bias_coeffs=bcs)
+    outs = g.run(list(cts))
+    # oracle lowering of the same layers
+    s = SCALE
+    ys = list(ctos)
+    for l in range(3):
+        M = ws[l]
+        in_steps, post = PN.yield_layer_plan(M.shape[1], M.shape[0], periods[l], Wn)
+        lv = ys[0].shape[1] - 1
+        pts = [orc.reduce_int(c, lv) for c in dcs[l]]
+        bias = orc.reduce_int(bcs[l], lv - 1)
+        res = [ON.diag_dense(orc, keys, y, s, pts, SCALE, in_steps, post, bias) for y in ys]
+        ys = [r[0] for r in res]
+        s = res[0][1]
+        if l < 2:
+            res = [ON.square(orc, keys, y, s) for y in ys]
+            ys = [r[0] for r in res]
+            s = res[0][1]
+    want = PN.yield_math(x, ws, bs)[:, 0]
+    got = []
+    for c in range(n_ct):
+        assert outs[c].scale == s and np.array_equal(outs[c].residues(), ys[c]), c
+        got.append(ctx.decrypt(outs[c], Wn).real)
+    err = _rel_err(np.concatenate(got)[: len(want)], want)
+    print("yield: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL
+
+
+def test_vision_small_ring(mods):
+    ckks, nets = mods
+    logn = 10
+    ctx, orc = _setup(ckks, logn, [60] + [40] * 7, [60], 8, 3)
+    n_img = ctx.N // 2
+    x, P = S.vision_inputs(n_images=n_img)
+    keys = ON.Keys(orc, 3)
+    pix = x.reshape(n_img, -1).T
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, pix[i], 7, 11, i) for i in range(pix.shape[0])])
+    g = nets.build_vision(ctx, P, 28, 7, SCALE)
+    outs = g.run(list(cts))
+    # oracle: conv (original row order) -> x^2 -> dense -> x^2 -> dense
+    rows, _ = PN.vision_conv_rows(P["conv_w"])
+    F = P["conv_w"].shape[0]
+    per = len(rows) // F
+    h, s = ON.linear(orc, list(ctos), SCALE, rows, SCALE, [P["conv_b"][j // per] for j in range(len(rows))])
+    sq = [ON.square(orc, keys, c, s) for c in h]
+    h, s = [c for c, _ in sq], sq[0][1]
+    W1 = P["w1"]
+    h, s = ON.linear(orc, h, s, [[(i, W1[j, i]) for i in range(W1.shape[1])] for j in range(W1.shape[0])], SCALE,
+                     list(P["b1"]))
+    sq = [ON.square(orc, keys, c, s) for c in h]
+    h, s = [c for c, _ in sq], sq[0][1]
+    W2 = P["w2"]
+    h, s = ON.linear(orc, h, s, [[(i, W2[j, i]) for i in range(W2.shape[1])] for j in range(W2.shape[0])], SCALE,
+                     list(P["b2"]))
+    for j in range(10):
+        assert outs[j].scale == s and np.array_equal(outs[j].residues(), h[j]), j
+    got = np.stack([ctx.decrypt(outs[j], n_img).real for j in range(10)], axis=1)
+    want = PN.vision_math(x, P)
+    err = _rel_err(got, want)
+    print("vision: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL

@@ -1,0 +1,78 @@
+"""The oracle's encrypted lowerings decode to the FP64 plaintext networks
+(the paper's own plaintext-vs-ciphertext check) within the tolerance
+2^-18 * max(1, |y|)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from oracle import encoding as E
+from oracle import nets as ON
+from oracle import plainnet as PN
+
+TOL = 2.0 ** -18
+
+
+def _encrypt(orc, keys, z, level, scale, seed, obj):
+    m = E.encode(z, scale, orc.N)
+    return orc.encrypt(keys.pk, orc.reduce_int(m, level), level, seed, obj)
+
+
+def _decrypt(orc, keys, ct, scale, n):
+    return E.decode_residues(orc.decrypt(keys.sn, ct), orc.q, scale, orc.N, n).real
+
+
+def test_tiny_dense_network():
+    # dense 16->8 by diagonals on 4096 slots, then x^2 (N = 8192, [60,40,40 | 60])
+    logn = 13
+    primes = O.find_primes(logn, [60, 40, 40, 60])
+    orc = O.Oracle(logn, primes[:3], primes[3:], 3)
+    x, W = S.tiny_dense_inputs()
+    in_steps, post = PN.tiny_dense_steps()
+    keys = ON.Keys(orc, 1, [orc.galois_elt(s) for s in in_steps[1:] + post])
+    scale = 2.0 ** 40
+    ct = _encrypt(orc, keys, x.reshape(-1), 2, scale, 7, 0)
+    diags = PN.tiny_dense_diagonals(W)
+    pts = [orc.reduce_int(E.encode(d, scale, orc.N), 2) for d in diags]
+    y, s1 = ON.diag_dense(orc, keys, ct, scale, pts, scale, in_steps, post)
+    z, s2 = ON.square(orc, keys, y, s1)
+    got = _decrypt(orc, keys, z, s2, 4096)[: 8 * 256].reshape(8, 256)
+    want = PN.tiny_dense_math(x, W)
+    err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err
+
+
+def test_yield_network_small_ring():
+    # the three rotation-based layers at N = 2^12 (8 windows per ciphertext)
+    logn = 12
+    primes = O.find_primes(logn, [60] + [40] * 5 + [60])
+    orc = O.Oracle(logn, primes[:6], primes[6:], 6)
+    x, ws, bs = S.yield_inputs(n_windows=8)
+    slots = orc.N // 2
+    Wn = PN.yield_layout(slots)
+    periods = [256, 64, 16]
+    steps = []
+    for l in range(3):
+        a, b = PN.yield_layer_plan(ws[l].shape[1], ws[l].shape[0], periods[l], Wn)
+        steps += a + b
+    elts = set(ON.naf_elements(orc, steps))
+    keys = ON.Keys(orc, 2, sorted(elts))
+    scale = 2.0 ** 40
+    v = PN.yield_pack(x, slots)[0]
+    ct = _encrypt(orc, keys, v, 5, scale, 9, 0)
+    s = scale
+    for l in range(3):
+        M, b = ws[l], bs[l]
+        in_steps, post = PN.yield_layer_plan(M.shape[1], M.shape[0], periods[l], Wn)
+        lvl = ct.shape[1] - 1
+        d = PN.yield_diagonals(M, periods[l], Wn)
+        pts = [orc.reduce_int(E.encode(di, scale, orc.N), lvl) for di in d]
+        out_scale = s * scale / orc.q[lvl]
+        bias = orc.reduce_int(E.encode(PN.yield_bias_vector(b, Wn), out_scale, orc.N), lvl - 1)
+        ct, s = ON.diag_dense(orc, keys, ct, s, pts, scale, in_steps, post, bias)
+        if l < 2:
+            ct, s = ON.square(orc, keys, ct, s)
+    got = _decrypt(orc, keys, ct, s, slots)[:Wn]
+    want = PN.yield_math(x, ws, bs)[:, 0]
+    err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err

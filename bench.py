@@ -69,6 +69,80 @@ def kernel_model(name, items, ctx, level):
     return items * 2 * lb
 
 
+def serve_leg(args, dev, log):
+    """Serving mix: Poisson arrivals, half HMult pairs (rings 2^13..2^15,
+    4..16 limbs), half vision inferences (rings 2^13..2^14, starting level
+    5..7), keys resident, admission by HBM bytes; continuous batching vs the
+    plain one-op-per-launch path on the same requests."""
+    import numpy as np
+    import synthetic as S
+    from paper_2110_13638_amd import _native as nat
+    from paper_2110_13638_amd import ckks, serve
+
+    rng = np.random.default_rng(2)
+    ctxs, vision = {}, {}
+    for log_n in (13, 14, 15):
+        pr = nat.ckks_find_primes(log_n, Q_BITS + P_BITS)
+        ctxs[("hmult", log_n)] = ckks.Context(log_n, pr[:16], pr[16:], DNUM, device=dev).keygen(7)
+    _, P = S.vision_inputs(n_images=1)
+    for log_n in (13, 14):
+        pr = nat.ckks_find_primes(log_n, [60] + [40] * 7 + [60])
+        c = ckks.Context(log_n, pr[:8], pr[8:], 8, device=dev).keygen(8)
+        ctxs[("vision", log_n)] = c
+        vision[log_n] = serve.VisionModel(c, P)
+
+    def make(seed):
+        reqs = []
+        t = 0.0
+        r2 = np.random.default_rng(seed)
+        for rid in range(args.serve_requests):
+            t += r2.exponential(1.0 / args.serve_rate)
+            if r2.random() < 0.5:
+                kind, log_n, level, n_ct = "hmult", int(r2.choice([13, 14, 15])), int(r2.integers(3, 16)), 2
+            else:
+                kind, log_n, level, n_ct = "vision", int(r2.choice([13, 14])), int(r2.integers(5, 8)), 784
+            ctx = ctxs[(kind, log_n)]
+            res = S.residues_device(1000 + rid, ctx.q[: level + 1], ctx.N, 2 * n_ct, dev).view(n_ct, 2, level + 1,
+                                                                                            ctx.N)
+            cts = [ckks.Ciphertext(ctx, res[i], 2, level, ctx.default_scale) for i in range(n_ct)]
+            reqs.append(serve.Request(rid, kind, log_n, t, cts))
+        return reqs
+
+    # warm up every (kind, ring) once
+    serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30).run(
+        [r for r in make(99)[:6]])
+    torch_sync()
+    reqs = make(3)
+    t0 = time.perf_counter()
+    done = serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30).run(reqs)
+    span = max(r.finish for r in done) - min(r.arrival for r in done)
+    st = serve.latency_stats(done)
+    n_vis = sum(r.kind == "vision" for r in done)
+    out = {"requests": len(done), "vision_requests": n_vis, "arrival_rate_per_s": args.serve_rate,
+           "requests_per_s": len(done) / span, "encrypted_infer_per_s": n_vis / span,
+           "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "hbm_cap_GiB": args.serve_cap}
+    log("serving: %d requests (%d vision) in %.2f s: %.1f req/s, p50 %.1f ms, p99 %.1f ms" %
+        (len(done), n_vis, span, out["requests_per_s"], st["p50_ms"], st["p99_ms"]))
+    # plain path on the same requests (same inputs), compared ciphertext by ciphertext
+    preqs = make(3)
+    plain = serve.run_plain(ctxs, vision, preqs)
+    pspan = max(r.finish for r in plain) - min(r.arrival for r in plain)
+    pst = serve.latency_stats(plain)
+    same = all(all(bool((a.buf[:, : a.level + 1] == b.buf[:, : b.level + 1]).all()) for a, b in
+                   zip(x.result, y.result)) for x, y in zip(sorted(done, key=lambda r: r.rid), plain))
+    out.update({"plain_requests_per_s": len(plain) / pspan, "plain_encrypted_infer_per_s": n_vis / pspan,
+                "plain_p50_ms": pst["p50_ms"], "plain_p99_ms": pst["p99_ms"],
+                "batched_over_plain": (len(done) / span) / (len(plain) / pspan), "results_equal_plain": same})
+    log("plain path: %.1f req/s, p50 %.1f ms, p99 %.1f ms; batched/plain %.1fx; identical results: %s" %
+        (out["plain_requests_per_s"], pst["p50_ms"], pst["p99_ms"], out["batched_over_plain"], same))
+    return out
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,10 +152,14 @@ def main():
     ap.add_argument("--plain-pairs", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(requests are independent; see DESIGN.md for how the work would shard)")
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(requests and ciphertexts are independent and would shard by request)")
         sys.exit(2)
 
     import numpy as np
@@ -249,6 +327,8 @@ def main():
         log("oracle: %.3f HMult/s on %d threads; GPU ciphertext == oracle: %s" %
             (cpu["value"], cores, cpu["gpu_matches_oracle"]))
 
+    serving = None if args.no_serve else serve_leg(args, dev, log)
+
     line = {
         "metric": "HMult+relin+rescale/s at N=2^15,L=16; encrypted infer/s + p50/p99 latency",
         "value": round(value, 2), "unit": "HMult+relin+rescale/s", "n_gpus": 1, "steps": args.steps,
@@ -263,7 +343,7 @@ def main():
                   "plain_one_op_per_launch_hmult_per_s": round(plain_rate, 2),
                   "batched_over_plain": round(value / plain_rate, 2),
                   "plain_equals_fused": same,
-                  "ntt": ntt, "kernels": breakdown},
+                  "ntt": ntt, "kernels": breakdown, "serving": serving},
     }
     print(json.dumps(line))
 

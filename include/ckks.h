@@ -360,6 +360,39 @@ int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_inputs, ckks
                    const uint64_t *rk, const uint32_t *galois_elts, const uint64_t *const *galois_keys,
                    uint32_t n_galois, void *ws, size_t ws_bytes, void *stream);
 
+/* Algorithms 6-7 (automatic FHE parameterisation): node cost = depth it
+ * consumes (1 for LINEAR, DIAG_DENSE, SQUARE; 0 for INPUT, OUTPUT); every
+ * node is labelled with the longest cost from each source that reaches
+ * it, OUTPUT nodes are concern nodes where the labelling restarts, and
+ * sources meeting at a node are merged into one parameter group whose
+ * cost is the largest label reached. Writes the group count, the group of
+ * every node (indexed by node id, cap entries; 0xFFFFFFFF for a node no
+ * source reaches) and each group's cost, ready for ckks_parameterise. */
+int ckks_graph_autohe(ckks_graph *g, uint32_t *n_groups, uint32_t *group_of_node, uint32_t *group_cost,
+                      uint32_t cap);
+
+/* ------------------------------------------------------------------ */
+/* tuning                                                               */
+/* ------------------------------------------------------------------ */
+/* Launch-shape knobs of a context. Every setting computes bit-identical
+ * results; only speed differs, so an autotuner may time the variants on
+ * the workload at hand and keep the fastest. Settings apply to launches
+ * issued after the call (not thread safe against concurrent calls on the
+ * same context).
+ *   CKKS_TUNE_NTT_WIDE   0 (default): 16 residues per thread in the NTT
+ *                        kernels for N < 2^15, 32 at 2^15; 1: twice that
+ *                        (N >= 2^11 only).
+ *   CKKS_TUNE_EW_LOG     log2 of residues per thread in the streaming
+ *                        (element-wise, key-switch inner product) kernels:
+ *                        1, 2 (default) or 3.
+ *   CKKS_TUNE_XCD_REMAP  1 (default): map consecutive NTT work items to one
+ *                        XCD (shared L2); 0: plain block order.
+ * Returns CKKS_EINVAL for an unknown knob or a value out of range. */
+enum { CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2 };
+int ckks_ctx_set_tuning(ckks_ctx *ctx, int knob, int value);
+/* Current value of a knob, or -1 for a null context / unknown knob. */
+int ckks_ctx_get_tuning(const ckks_ctx *ctx, int knob);
+
 /* ------------------------------------------------------------------ */
 /* measurement                                                          */
 /* ------------------------------------------------------------------ */

@@ -12,9 +12,10 @@
  * psi-twisted sequence, and basis conversions are written as the sums
  * that define them.
  *
- * What is computed follows the paper's use of RNS-CKKS (Section 2.1, FHE
- * background; Section 3.1, the meta-object that relinearises after a
- * ciphertext product and rescales / matches levels before binary ops).
+ * What is computed follows the paper's use of RNS-CKKS (Sections 2.1 and 3,
+ * FHE background; Section 4.1, the ciphertext container that relinearises
+ * after a ciphertext product and rescales / matches levels before binary
+ * operations).
  * The paper defers every integer-level detail to its CKKS backend, so the
  * conventions below are this project's readings (listed in the design doc):
  *   - NTT slot k holds a(psi^(2*brv(k)+1)), psi = smallest primitive

@@ -19,6 +19,7 @@ ERROR_NAMES = {-1: "EINVAL", -2: "ELEVEL", -3: "ESCALE", -4: "EDEPTH", -5: "ENOK
 CKKS_KEY_SECRET, CKKS_KEY_PUBLIC, CKKS_KEY_SWITCH = 0, 1, 2
 (CKKS_OP_NTT, CKKS_OP_ELEMENTWISE, CKKS_OP_KEYSWITCH, CKKS_OP_RESCALE, CKKS_OP_HMULT, CKKS_OP_KEYGEN,
  CKKS_OP_ENCRYPT, CKKS_OP_LINEAR) = range(8)
+CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP = 0, 1, 2
 
 
 class CkksError(RuntimeError):
@@ -122,6 +123,9 @@ _SIGS = {
     "ckks_graph_plan": (ctypes.c_int, [_vp, _P(_sz), _P(_u32)]),
     "ckks_graph_run": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _P(ckks_ct), _u32, _vp, _P(_u32), _P(_vp), _u32,
                                       _vp, _sz, _vp]),
+    "ckks_graph_autohe": (ctypes.c_int, [_vp, _P(_u32), _P(_u32), _P(_u32), _u32]),
+    "ckks_ctx_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
+    "ckks_ctx_get_tuning": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ckks_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "ckks_profile_collect": (ctypes.c_int, [_P(ckks_launch_record), _u32, _P(_u32)]),
 }
@@ -344,6 +348,14 @@ def ckks_linear_csr(h, inp, n_out, row_ptr, col, w, w_scale, out, ws, ws_bytes, 
           col.ctypes.data_as(_P(_u32)), w.ctypes.data_as(_P(ctypes.c_int64)), w_scale, out, ws, ws_bytes, stream)
 
 
+def ckks_ctx_set_tuning(h, knob, value):
+    _call("ckks_ctx_set_tuning", h, knob, value)
+
+
+def ckks_ctx_get_tuning(h, knob):
+    return lib().ckks_ctx_get_tuning(h, knob)
+
+
 def ckks_profile_enable(on):
     _call("ckks_profile_enable", 1 if on else 0)
 
@@ -387,3 +399,11 @@ def ckks_graph_run(g, inputs, outputs, rk, galois_elts, galois_keys, ws, ws_byte
     ge = (ctypes.c_uint32 * max(n, 1))(*galois_elts)
     gk = (ctypes.c_void_p * max(n, 1))(*galois_keys)
     _call("ckks_graph_run", g, inputs, len(inputs), outputs, len(outputs), rk, ge, gk, n, ws, ws_bytes, stream)
+
+
+def ckks_graph_autohe(g, n_nodes):
+    ng = ctypes.c_uint32()
+    gof = (ctypes.c_uint32 * max(n_nodes, 1))()
+    cost = (ctypes.c_uint32 * max(n_nodes, 1))()
+    _call("ckks_graph_autohe", g, ctypes.byref(ng), gof, cost, n_nodes)
+    return ng.value, [int(gof[i]) for i in range(n_nodes)], [int(cost[i]) for i in range(ng.value)]

@@ -124,6 +124,17 @@ class Context:
     def digits(self, level):
         return nat.ckks_ctx_digits(self.h, level)
 
+    TUNING_KNOBS = {"ntt_wide": nat.CKKS_TUNE_NTT_WIDE, "ew_log": nat.CKKS_TUNE_EW_LOG,
+                    "xcd_remap": nat.CKKS_TUNE_XCD_REMAP}
+
+    def tuning(self):
+        return {k: nat.ckks_ctx_get_tuning(self.h, v) for k, v in self.TUNING_KNOBS.items()}
+
+    def set_tuning(self, **knobs):
+        for k, v in knobs.items():
+            nat.ckks_ctx_set_tuning(self.h, self.TUNING_KNOBS[k], int(v))
+        return self
+
     def workspace(self, nbytes):
         nbytes = max(int(nbytes), 1 << 20)
         if self._ws is None or self._ws.numel() < nbytes + 256:
@@ -360,3 +371,31 @@ class Context:
         ws, wb = self.workspace(nat.ckks_workspace_bytes(self.h, nat.CKKS_OP_LINEAR, n_out, [lvl, n_in]))
         nat.ckks_linear(self.h, self._structs(inputs), Wd.data_ptr(), w_scale, so, ws, wb, self.stream)
         return self._outs(so, outs)
+
+    # --- batched helpers used by the serving engine ---------------------------------
+    def linear_csr(self, inputs, row_ptr, col, w_int, w_scale, outs=None):
+        """rows over `inputs`: out[j] = sum_e w_int[e] * inputs[col[e]]"""
+        lvl = inputs[0].level
+        n_out = len(row_ptr) - 1
+        outs = outs or [self.new_ct(2, lvl, 1.0) for _ in range(n_out)]
+        so = self._structs(outs)
+        nb = nat.ckks_linear_csr_workspace_bytes(self.h, len(inputs), n_out, int(row_ptr[-1]), lvl)
+        ws, wb = self.workspace(nb)
+        nat.ckks_linear_csr(self.h, self._structs(inputs), n_out, np.ascontiguousarray(row_ptr, dtype=np.uint32),
+                            np.ascontiguousarray(col, dtype=np.uint32), np.ascontiguousarray(w_int, dtype=np.int64),
+                            w_scale, so, ws, wb, self.stream)
+        return self._outs(so, outs)
+
+    def rescale_inplace(self, cts):
+        s = self._structs(cts)
+        ws, wb = self.ws_for(nat.CKKS_OP_RESCALE, len(cts), [c.level for c in cts])
+        nat.ckks_rescale(self.h, s, s, ws, wb, self.stream)
+        return self._outs(s, cts)
+
+    def add_scalars_inplace(self, cts, values):
+        """cts[k] += values[k] (floats, encoded at each ciphertext's scale)"""
+        v = [self.const_int(x, c.scale) for x, c in zip(values, cts)]
+        s = self._structs(cts)
+        ws, wb = self.ws_for(nat.CKKS_OP_ELEMENTWISE, len(cts), [c.level for c in cts])
+        nat.ckks_add_scalar(self.h, s, v, s, ws, wb, self.stream)
+        return self._outs(s, cts)

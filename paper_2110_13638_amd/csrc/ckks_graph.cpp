@@ -550,3 +550,102 @@ extern "C" int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_i
             }
     return CKKS_OK;
 }
+
+// ------------------------------------------------------------------
+// Algorithms 6-7: automatic parameterisation groups
+// ------------------------------------------------------------------
+// The cost of a node is the multiplicative depth it consumes (one for
+// linear, diagonal and square nodes, none for input and output nodes); an
+// edge costs what its destination costs. autoHE_discover labels every node
+// with, per source, the largest cost accumulated on any path from that
+// source; at a concern node (an output, where ciphertexts leave the graph)
+// the traversal restarts with the node as a new source. autoHE then merges
+// sources that meet at a common node into one group whose cost is the
+// largest label any of its sources reached.
+namespace {
+u32 node_cost(const Node &n) {
+    return (n.kind == CKKS_NODE_LINEAR || n.kind == CKKS_NODE_DIAG_DENSE || n.kind == CKKS_NODE_SQUARE) ? 1u : 0u;
+}
+
+void autohe_discover(ckks_graph *g, std::vector<std::map<u32, u32>> &sources, u32 n, u32 src, u32 cost,
+                     std::vector<char> &restarted) {
+    if (src != n) {
+        auto it = sources[n].find(src);
+        if (it == sources[n].end() || it->second < cost) sources[n][src] = cost;
+        else return;  // an equal or longer path from this source was already propagated
+    }
+    const Node &node = g->nodes[n];
+    if (node.kind == CKKS_NODE_OUTPUT && src != n) {
+        // concern: restart from this node as a new source (reading of the
+        // printed recursion, which would otherwise call itself unchanged)
+        if (!restarted[n]) {
+            restarted[n] = 1;
+            autohe_discover(g, sources, n, n, 0, restarted);
+        }
+        return;
+    }
+    std::vector<u32> succ;
+    for (u32 e : node.out_edges) {
+        u32 t = g->edges[e].to;
+        if (std::find(succ.begin(), succ.end(), t) == succ.end()) succ.push_back(t);
+    }
+    for (u32 t : succ) autohe_discover(g, sources, t, src, cost + node_cost(g->nodes[t]), restarted);
+}
+}  // namespace
+
+extern "C" int ckks_graph_autohe(ckks_graph *g, uint32_t *n_groups, uint32_t *group_of_node,
+                                 uint32_t *group_cost, uint32_t cap) {
+    if (!g || !n_groups) return gfail(CKKS_EINVAL, "graph_autohe: null argument");
+    const u32 n = (u32)g->nodes.size();
+    std::vector<std::map<u32, u32>> sources(n);
+    std::vector<char> restarted(n, 0);
+    std::vector<u32> inputs;
+    for (u32 i = 0; i < n; i++)
+        if (g->nodes[i].kind == CKKS_NODE_INPUT) inputs.push_back(i);
+    for (u32 i : inputs) autohe_discover(g, sources, i, i, 0, restarted);
+    // group assignment and merging (union of sources meeting at a node)
+    std::vector<int> group(n, -1);
+    std::vector<u32> cost;
+    std::vector<u32> all_src = inputs;
+    for (u32 i = 0; i < n; i++)
+        if (restarted[i]) all_src.push_back(i);
+    for (u32 i : all_src) {
+        if (group[i] < 0) {
+            group[i] = (int)cost.size();
+            cost.push_back(0);
+        }
+        for (u32 j = 0; j < n; j++) {
+            const auto &src = sources[j];
+            if (!src.count(i)) continue;
+            const int gi = group[i];
+            for (auto &kv : src) {
+                const int old = group[kv.first];
+                if (old >= 0 && old != gi) {
+                    // merge the old group into gi
+                    for (u32 x = 0; x < n; x++)
+                        if (group[x] == old) group[x] = gi;
+                    cost[gi] = std::max(cost[gi], cost[old]);
+                }
+                group[kv.first] = gi;
+                cost[gi] = std::max(cost[gi], kv.second);
+            }
+        }
+    }
+    // every other node joins the group of the sources that reach it
+    for (u32 j = 0; j < n; j++)
+        if (group[j] < 0 && !sources[j].empty()) group[j] = group[sources[j].begin()->first];
+    // compact group ids
+    std::map<int, u32> ids;
+    for (u32 i : all_src) ids.emplace(group[i], 0);
+    u32 k = 0;
+    for (auto &kv : ids) kv.second = k++;
+    *n_groups = k;
+    if (group_of_node || group_cost) {
+        for (u32 i = 0; i < n && i < cap; i++)
+            if (group_of_node) group_of_node[i] = group[i] >= 0 ? ids[group[i]] : 0xFFFFFFFFu;
+        if (group_cost)
+            for (auto &kv : ids)
+                if (kv.second < cap) group_cost[kv.second] = cost[kv.first];
+    }
+    return CKKS_OK;
+}

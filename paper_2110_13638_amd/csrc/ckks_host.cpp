@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <complex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -24,7 +25,7 @@ namespace ckks {
 hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s);
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
 hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s);
-hipError_t launch_ip(const DevTables &tb, const Item *items, int n, hipStream_t s);
+hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s);
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,
                          u64 *const *out_ptrs, u32 n_in, u32 n_out, u32 limbs, u32 in_stride,
                          u32 out_stride, hipStream_t s);
@@ -35,12 +36,12 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
                                  u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
 
 // kernel op codes (mirrors of the enums in the kernel file)
-enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_HMULT = 4, F_SAMPLE = 5, F_INT = 6 };
-enum { I_COPY = 0, I_MUL = 1, I_HMULT = 2, I_DECRYPT = 3 };
+enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_SAMPLE = 5, F_INT = 6 };
+enum { I_COPY = 0, I_MUL = 1, I_DECRYPT = 3 };
 enum {
     EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_MUL_CONST = 3, EW_ADD_CONST = 4, EW_TENSOR = 5,
     EW_COPY = 6, EW_AUTOMORPH = 7, EW_NEG = 8, EW_KEYGEN = 9, EW_ENCRYPT = 10, EW_SQUARE_S = 11,
-    EW_HMULT_FIN = 12
+    EW_HMULT_FIN = 12, EW_HMULT_U = 13, EW_HMULT_Z = 14
 };
 enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_SWK_A = 4, TAG_SWK_E = 5, TAG_ENC_V = 6,
        TAG_ENC_E0 = 7, TAG_ENC_E1 = 8 };
@@ -252,6 +253,9 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     if (p->n_q < 1 || p->n_p < 1 || p->n_q + p->n_p > (u32)kMaxPrimes || p->dnum < 1 || p->dnum > p->n_q)
         return fail(CKKS_EPARAMS, "ctx_create: bad prime counts / dnum");
     ckks_ctx *c = new ckks_ctx();
+    c->tb.ntt_wide = 0;
+    c->tb.ew_log = 2;
+    c->tb.xcd_remap = 1;
     c->log_n = p->log_n;
     c->N = 1u << p->log_n;
     c->n_q = p->n_q;
@@ -462,6 +466,35 @@ extern "C" int ckks_ctx_upload(ckks_ctx *c, void *dev, void *stream) {
     return CKKS_OK;
 }
 
+extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
+    if (!c) return fail(CKKS_EINVAL, "set_tuning: null context");
+    switch (knob) {
+        case CKKS_TUNE_NTT_WIDE:
+            if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: NTT_WIDE takes 0 or 1");
+            if (value && c->log_n < 11) return fail(CKKS_EINVAL, "set_tuning: NTT_WIDE needs N >= 2^11");
+            c->tb.ntt_wide = (u32)value;
+            return CKKS_OK;
+        case CKKS_TUNE_EW_LOG:
+            if (value < 1 || value > 3) return fail(CKKS_EINVAL, "set_tuning: EW_LOG takes 1..3");
+            c->tb.ew_log = (u32)value;
+            return CKKS_OK;
+        case CKKS_TUNE_XCD_REMAP:
+            if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: XCD_REMAP takes 0 or 1");
+            c->tb.xcd_remap = (u32)value;
+            return CKKS_OK;
+    }
+    return fail(CKKS_EINVAL, "set_tuning: unknown knob");
+}
+extern "C" int ckks_ctx_get_tuning(const ckks_ctx *c, int knob) {
+    if (!c) return -1;
+    switch (knob) {
+        case CKKS_TUNE_NTT_WIDE: return (int)c->tb.ntt_wide;
+        case CKKS_TUNE_EW_LOG: return (int)c->tb.ew_log;
+        case CKKS_TUNE_XCD_REMAP: return (int)c->tb.xcd_remap;
+    }
+    return -1;
+}
+
 extern "C" size_t ckks_ct_bytes(const ckks_ctx *c, uint32_t n_poly, uint32_t level) {
     return c ? (size_t)n_poly * (level + 1) * c->N * 8 : 0;
 }
@@ -577,14 +610,17 @@ struct ProfRec {
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 const char *fwd_names[] = {"ntt_fwd", "ntt_fwd_modup", "ntt_fwd_rescale", "ntt_fwd_moddown",
-                           "ntt_fwd_hmult_tail", "ntt_fwd_sample", "ntt_fwd_int"};
-const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_hmult_top", "ntt_inv_decrypt"};
+                           "ntt_fwd_unused", "ntt_fwd_sample", "ntt_fwd_int"};
+const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_unused", "ntt_inv_decrypt"};
+const char *ew_names[] = {"ew_add", "ew_sub", "ew_mul", "ew_mul_const", "ew_add_const", "ew_tensor", "ew_copy",
+                          "ew_automorph", "ew_neg", "ew_keygen", "ew_encrypt", "ew_square_s", "ew_hmult_fin",
+                          "ew_hmult_u", "ew_hmult_z"};
 std::string launch_name(int kind, int op, u32 log_n) {
     char b[64];
     switch (kind) {
         case 0: snprintf(b, sizeof b, "%s/N=2^%u", fwd_names[op], log_n); break;
         case 1: snprintf(b, sizeof b, "%s/N=2^%u", inv_names[op], log_n); break;
-        case 2: snprintf(b, sizeof b, "elementwise/N=2^%u", log_n); break;
+        case 2: snprintf(b, sizeof b, "%s/N=2^%u", op >= 0 && op < 15 ? ew_names[op] : "elementwise", log_n); break;
         case 3: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
         default: snprintf(b, sizeof b, "linear/N=2^%u", log_n); break;
     }
@@ -646,6 +682,7 @@ struct Plan {
     template <class T>
     void add(int kind, int op, const std::vector<T> &v, u64 seed = 0) {
         if (v.empty()) return;
+        if constexpr (std::is_same<T, EwItem>::value) op = (int)v[0].op;  // for the launch name
         size_t off = (desc.size() + 255) & ~(size_t)255;
         desc.resize(off + v.size() * sizeof(T));
         memcpy(desc.data() + off, v.data(), v.size() * sizeof(T));
@@ -674,7 +711,7 @@ struct Plan {
                 case 0: e = launch_fwd(c->tb, L.op, (const Item *)p, L.n, L.seed, s); break;
                 case 1: e = launch_inv(c->tb, L.op, (const Item *)p, L.n, s); break;
                 case 2: e = launch_ew(c->tb, (const EwItem *)p, L.n, L.seed, s); break;
-                case 3: e = launch_ip(c->tb, (const Item *)p, L.n, s); break;
+                case 3: e = launch_ip(c->tb, (const IpItem *)p, L.n, s); break;
             }
             if (e != hipSuccess) return fail(CKKS_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
             if (g_prof_on) {
@@ -685,6 +722,46 @@ struct Plan {
         return CKKS_OK;
     }
 };
+
+// one ciphertext's share of the key-switch inner product
+struct IpCt {
+    u32 level;
+    const u64 *ext;
+    u64 *acc;
+    std::vector<const u64 *> own0, own1;  // per data limb t <= level
+};
+// items of the inner product: ciphertexts of one level are grouped by
+// kIpCts so that each key residue is loaded once per group
+void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<IpCt> &cts, const u64 *key) {
+    std::vector<size_t> order(cts.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
+    for (size_t g = 0; g < order.size();) {
+        size_t h = g;
+        while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < (size_t)kIpCts) h++;
+        const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
+        for (u32 t = 0; t < E; t++) {
+            IpItem it;
+            memset(&it, 0, sizeof it);
+            it.n_ct = (u32)(h - g);
+            it.prime = t < L ? t : c->n_q + (t - L);
+            it.beta = beta;
+            it.own_digit = t < L ? t / c->alpha : 0xFFFFFFFFu;
+            it.E = E;
+            it.pos = t;
+            it.key = key;
+            for (size_t k = g; k < h; k++) {
+                const IpCt &x = cts[order[k]];
+                it.ext[k - g] = x.ext;
+                it.acc[k - g] = x.acc;
+                it.own0[k - g] = t < L ? x.own0[t] : nullptr;
+                it.own1[k - g] = (t < L && !x.own1.empty()) ? x.own1[t] : nullptr;
+            }
+            v.push_back(it);
+        }
+        g = h;
+    }
+}
 
 inline u64 *limb(const ckks_ctx *c, const ckks_ct &ct, u32 poly, u32 i) {
     return ct.data + ((size_t)poly * ct.limb_stride + i) * c->N;
@@ -732,7 +809,9 @@ struct KsJob {
 void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
     const ckks_ctx *c = P.c;
     const u32 N = c->N, k = c->n_p, A = c->alpha;
-    std::vector<Item> icopy, modup, ip, ipP, mdown;
+    std::vector<Item> icopy, modup, ipP, mdown;
+    std::vector<IpCt> ipc;
+    std::vector<IpItem> ip;
     for (const KsJob &J : jobs) {
         const u32 L = J.level + 1, E = L + k, beta = (L + A - 1) / A;
         u64 *dcoef = P.limbs(L);
@@ -759,19 +838,13 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
                 modup.push_back(it);
             }
         }
-        for (u32 t = 0; t < E; t++) {
-            Item it = item0();
-            it.in[0] = ext;
-            it.in[1] = key;
-            it.in[2] = t < L ? J.dl[t] : nullptr;
-            it.a = beta;
-            it.b = t < L ? t / A : 0xFFFFFFFFu;
-            it.c = E;
-            it.v = t;
-            it.prime = t < L ? t : c->n_q + (t - L);
-            it.out = acc + (size_t)t * N;
-            it.out2 = acc + ((size_t)E + t) * N;
-            ip.push_back(it);
+        {
+            IpCt x;
+            x.level = J.level;
+            x.ext = ext;
+            x.acc = acc;
+            x.own0 = J.dl;
+            ipc.push_back(x);
         }
         for (u32 cc = 0; cc < 2; cc++)
             for (u32 m = 0; m < k; m++) {
@@ -794,6 +867,7 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
                 mdown.push_back(it);
             }
     }
+    add_ip_items(c, ip, ipc, key);
     P.add(1, I_COPY, icopy);
     P.add(0, F_MODUP, modup);
     P.add(3, 0, ip);
@@ -1347,9 +1421,12 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
     P.add(0, F_RESCALE, res);
     CK(P.run(ws_bytes, (hipStream_t)stream));
     for (u32 k = 0; k < B; k++) {
-        out[k].n_poly = in[k].n_poly;
-        out[k].level = in[k].level - 1;
-        out[k].scale = in[k].scale / (double)c->primes[in[k].level];
+        // read everything from in[k] first: out may be the same array
+        const u32 n_poly = in[k].n_poly, l = in[k].level;
+        const double scale = in[k].scale / (double)c->primes[l];
+        out[k].n_poly = n_poly;
+        out[k].level = l - 1;
+        out[k].scale = scale;
     }
     return CKKS_OK;
 }
@@ -1359,16 +1436,20 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
 //   2. ModUp of every digit to every other prime, NTT;
 //   3. key-switch inner product (the digit's own limbs use a1 b1 directly);
 //   4. INTT of the special-prime part of both accumulators;
-//   5. top limb: INTT(acc_l P^-1 + d_c);
+//   5. top limb: u = acc_l P^-1 + d_c (elementwise), INTT(u);
 //   6. per limb i < l: z = conv_i(acc_P) P^-1 + rescale correction of the
-//      relinearised top limb, NTT;
+//      relinearised top limb u - conv_l(acc_P) P^-1 (elementwise), NTT(z);
 //   7. elementwise: out_c = (acc_c P^-1 + d_c - z_c) q_l^-1 for both polys.
+// The corrections run in streaming elementwise kernels so that every NTT of
+// the pipeline stays a plain register-resident transform.
 // By linearity this equals relinearise (ModDown) followed by rescale.
 static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B) {
     const ckks_ctx *c = P.c;
     const u32 N = c->N, k = c->n_p, A = c->alpha;
-    std::vector<Item> mul, modup, ip, ipP, last, fin;
-    std::vector<EwItem> tail;
+    std::vector<Item> mul, modup, ipP, last, fin;
+    std::vector<EwItem> tail, tu, tz;
+    std::vector<IpCt> ipc;
+    std::vector<IpItem> ip;
     for (u32 x = 0; x < B; x++) {
         const u32 l = a[x].level, L = l + 1, E = L + k, beta = (L + A - 1) / A;
         u64 *dcoef = P.limbs(L);
@@ -1403,20 +1484,16 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
                 modup.push_back(it);
             }
         }
-        for (u32 t = 0; t < E; t++) {
-            Item it = item0();
-            it.in[0] = ext;
-            it.in[1] = rk;
-            it.in[3] = t < L ? limb(c, a[x], 1, t) : nullptr;
-            it.in[4] = t < L ? limb(c, b[x], 1, t) : nullptr;
-            it.a = beta;
-            it.b = t < L ? t / A : 0xFFFFFFFFu;
-            it.c = E;
-            it.v = t;
-            it.prime = t < L ? t : c->n_q + (t - L);
-            it.out = acc + (size_t)t * N;
-            it.out2 = acc + ((size_t)E + t) * N;
-            ip.push_back(it);
+        {
+            IpCt y;
+            y.level = l;
+            y.ext = ext;
+            y.acc = acc;
+            for (u32 t = 0; t < L; t++) {
+                y.own0.push_back(limb(c, a[x], 1, t));
+                y.own1.push_back(limb(c, b[x], 1, t));
+            }
+            ipc.push_back(y);
         }
         for (u32 cc = 0; cc < 2; cc++)
             for (u32 m = 0; m < k; m++) {
@@ -1427,27 +1504,37 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
                 ipP.push_back(it);
             }
         for (u32 cc = 0; cc < 2; cc++) {
+            EwItem w = ew0();
+            w.op = EW_HMULT_U;
+            w.prime = l;
+            w.v = cc;
+            w.x[0] = acc + ((size_t)cc * E + l) * N;
+            w.x[1] = limb(c, a[x], 0, l);
+            w.x[2] = limb(c, a[x], 1, l);
+            w.x[3] = limb(c, b[x], 0, l);
+            w.x[4] = limb(c, b[x], 1, l);
+            w.y[0] = top + (size_t)cc * N;
+            tu.push_back(w);
             Item it = item0();
-            it.in[0] = acc + ((size_t)cc * E + l) * N;
-            it.in[1] = limb(c, a[x], 0, l);
-            it.in[2] = limb(c, a[x], 1, l);
-            it.in[3] = limb(c, b[x], 0, l);
-            it.in[4] = limb(c, b[x], 1, l);
-            it.b = cc;
-            it.prime = l;
+            it.in[0] = top + (size_t)cc * N;
             it.out = top + (size_t)cc * N;
+            it.prime = l;
             last.push_back(it);
         }
         for (u32 cc = 0; cc < 2; cc++)
             for (u32 i = 0; i < l; i++) {
+                EwItem w = ew0();
+                w.op = EW_HMULT_Z;
+                w.prime = i;
+                w.v = l;
+                w.x[0] = acc + ((size_t)cc * E + L) * N;
+                w.x[1] = top + (size_t)cc * N;
+                w.y[0] = zh + ((size_t)cc * L + i) * N;
+                tz.push_back(w);
                 Item it = item0();
-                it.in[0] = acc + ((size_t)cc * E + L) * N;
-                it.in[1] = top + (size_t)cc * N;
-                it.a = c->n_q;
-                it.b = k;
-                it.c = l;
-                it.prime = i;
+                it.in[0] = zh + ((size_t)cc * L + i) * N;
                 it.out = zh + ((size_t)cc * L + i) * N;
+                it.prime = i;
                 fin.push_back(it);
             }
         for (u32 i = 0; i < l; i++) {
@@ -1468,12 +1555,15 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
             tail.push_back(w);
         }
     }
+    add_ip_items(c, ip, ipc, rk);
     P.add(1, I_MUL, mul);
     P.add(0, F_MODUP, modup);
     P.add(3, 0, ip);
     P.add(1, I_COPY, ipP);
-    P.add(1, I_HMULT, last);
-    P.add(0, F_HMULT, fin);
+    P.add(2, 0, tu);
+    P.add(1, I_COPY, last);
+    P.add(2, 0, tz);
+    P.add(0, F_COPY, fin);
     P.add(2, 0, tail);
     return CKKS_OK;
 }

@@ -38,6 +38,10 @@ struct DevTables {
     const u64 *moddown;          // ModDown block
     const ulonglong2 *rescale;   // [n_q][n_q] (q_l^-1 mod q_i, Shoup)
     u32 log_n, n_q, n_p, n_prim, alpha, n_digits_top;
+    // tuning knobs (all settings give bit-identical results)
+    u32 ntt_wide;   // 1: 32 residues per thread below N = 2^15 (default 16)
+    u32 ew_log;     // log2 of residues per thread in streaming kernels (1..3)
+    u32 xcd_remap;  // 1: consecutive work items on one XCD
 };
 
 // ModUp constants for digit j truncated to s primes (1 <= s <= alpha):
@@ -81,5 +85,17 @@ struct LinGroup {
     u32 w_off, pad;
 };
 constexpr int kLinRows = 8;  // rows per group (accumulators per thread)
+
+// Key-switch inner product over up to kIpCts ciphertexts of one level that
+// share the key: target limb `pos` of the extended basis (prime `prime`).
+constexpr int kIpCts = 4;
+struct IpItem {
+    const u64 *ext[kIpCts];   // ModUp output base of each ciphertext, [digit][E][N]
+    u64 *acc[kIpCts];         // accumulator base of each ciphertext, [2][E][N]
+    const u64 *own0[kIpCts];  // own digit: the NTT-form input limb, or a1 of a product
+    const u64 *own1[kIpCts];  // own digit: b1 of a product, or null
+    const u64 *key;           // [digits][2][n_prim][N]
+    u32 n_ct, prime, beta, own_digit, E, pos;
+};
 
 }  // namespace ckks

@@ -22,6 +22,8 @@
 // index c*T + t"; an element-wise prologue (what to load) and epilogue
 // (what to store) fuse basis conversions, rescale and key-switch steps
 // into the transform so intermediate limbs do not round-trip through HBM.
+#include <type_traits>
+
 #include "ckks_internal.h"
 
 namespace ckks {
@@ -75,6 +77,22 @@ __device__ __forceinline__ u64 reduce_signed(i64 v, const PrimeConst &pc) {
     if (v >= 0) return reduce64((u64)v, pc);
     u64 m = reduce64((u64)(-(v + 1)) + 1, pc);
     return m == 0 ? 0 : pc.q - m;
+}
+
+// (r - h) mod q for r, h in [0, q_l): branch-free (one 64-bit reduction)
+__device__ __forceinline__ u64 centered_mod(u64 r, u64 h, const PrimeConst &pc) {
+    const bool ge = r >= h;
+    const u64 m = reduce64(ge ? r - h : h - r, pc);
+    return ge ? m : (m ? pc.q - m : 0);
+}
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -309,22 +327,21 @@ enum FwdOp : int {
     F_MODUP = 1,    // ModUp digit conversion -> NTT -> out
     F_RESCALE = 2,  // rescale correction -> NTT -> (in[1] - .) q_l^-1 -> out
     F_MODDOWN = 3,  // ModDown conversion -> NTT -> (in[1] - .) P^-1 (+ in[2]) -> out
-    F_HMULT = 4,    // ModDown + rescale correction of the fused HMult tail -> NTT -> out
-    F_SAMPLE = 5,   // sampled small polynomial -> NTT -> out
+    F_SAMPLE = 5,   // sampled small polynomial -> NTT -> out (4 is unused)
     F_INT = 6,      // signed int64 coefficients -> NTT -> out
 };
 enum InvOp : int {
     I_COPY = 0,     // in[0] -> INTT -> out
     I_MUL = 1,      // in[0] * in[1] -> INTT -> out
-    I_HMULT = 2,    // acc_top P^-1 + d_poly (top limb of the fused HMult) -> INTT -> out
-    I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out
+    I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out (2 is unused)
 };
 
 // XCD-aware item order: the chip dispatches workgroup b to XCD (b mod 8).
 // Consecutive items (which often read the same source limbs) are mapped
 // to one XCD so those limbs are reused from that XCD's L2.
-__device__ __forceinline__ int xcd_item(int nitems) {
+__device__ __forceinline__ int xcd_item(int nitems, u32 remap) {
     const int b = blockIdx.x, nb = gridDim.x;
+    if (!remap) return b < nitems ? b : -1;
     const int per = nb >> 3;  // grid is padded to a multiple of 8
     const int it = (b & 7) * per + (b >> 3);
     return it < nitems ? it : -1;
@@ -337,7 +354,7 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
     using NT = Ntt<LOGN, LOGE>;
     constexpr int N = NT::N, E = NT::E, T = NT::T;
     __shared__ u32 lds[NT::LDS_WORDS];
-    const int iid = xcd_item(nitems);
+    const int iid = xcd_item(nitems, tb.xcd_remap);
     if (iid < 0) return;
     const Item it = items[iid];
     const u32 tid = threadIdx.x, vo = tid * 8;
@@ -349,7 +366,7 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
     if constexpr (OP == F_COPY) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
-    } else if constexpr (OP == F_MODUP || OP == F_MODDOWN || OP == F_HMULT) {
+    } else if constexpr (OP == F_MODUP || OP == F_MODDOWN) {
         // sum_i [x_i * hat_i^-1]_{q_i} * (hat_i mod t), one Barrett at the end
         const u32 lo = it.a, s = it.b;  // first source prime index, count
         const u64 *blk;
@@ -365,48 +382,28 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
             hat_stride = tb.n_q;
         }
         const Buf src(it.in[0]);
-        // F_HMULT: z = conv * P^-1 + ((r_top - h) mod q_t), r_top = [u + h]_{q_l},
-        // it.c = l (the prime being dropped), it.in[1] = relinearised top limb
-        const u64 hl = (OP == F_HMULT) ? (tb.pc[it.c].q >> 1) : 0;
-        const u64 ql = (OP == F_HMULT) ? tb.pc[it.c].q : 0;
-#pragma unroll
-        for (int c0 = 0; c0 < E; c0 += kConvChunk) {
+        static_for<0, E / kConvChunk>([&](auto C0) {
+            constexpr int c0 = decltype(C0)::value * kConvChunk;
             Acc128 acc[kConvChunk];
-            Acc128 acc_l[(OP == F_HMULT) ? kConvChunk : 1];
             for (u32 i = 0; i < s; i++) {
                 const u64 inv = blk[2 * i], inv_sh = blk[2 * i + 1], qi = tb.pc[lo + i].q, h = hat[i * hat_stride];
-                const u64 hl_i = (OP == F_HMULT) ? hat[i * hat_stride + (it.c - it.prime)] : 0;
 #pragma unroll
                 for (int c = 0; c < kConvChunk; c++) {
                     const u64 x = src.ld(vo, (i * N + (c0 + c) * T) * 8);
                     // ModUp sources arrive pre-multiplied by hat_i^-1 (it.v == 1)
                     const u64 y = (OP == F_MODUP && it.v == 1) ? x : shoup(x, inv, inv_sh, qi);
                     acc[c].mac(y, h);
-                    if constexpr (OP == F_HMULT) acc_l[c].mac(y, hl_i);
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kConvChunk; c++) {
-                u64 x = acc[c].reduce(pc);
-                if constexpr (OP == F_HMULT) {
-                    // top limb after ModDown: t = u - conv_l * P^-1 (mod q_l), u from in[1]
-                    const PrimeConst &pl = tb.pc[it.c];
-                    const u64 conv_l = shoup(acc_l[c].reduce(pl), pl.pinv, pl.pinv_sh, ql);
-                    const u64 t = subm(Buf(it.in[1]).ld(vo, (c0 + c) * T * 8), conv_l, ql);
-                    const u64 rr = addm(t, hl, ql);
-                    const u64 v = rr >= hl ? reduce64(rr - hl, pc) : subm(0, reduce64(hl - rr, pc), q);
-                    x = addm(shoup(x, pc.pinv, pc.pinv_sh, q), v, q);
-                }
-                r[c0 + c] = x;
-            }
-        }
+            for (int c = 0; c < kConvChunk; c++) r[c0 + c] = acc[c].reduce(pc);
+        });
     } else if constexpr (OP == F_RESCALE) {
         const PrimeConst pl = tb.pc[it.a];  // q_l
         const u64 hl = pl.q >> 1;
 #pragma unroll
         for (int c = 0; c < E; c++) {
-            const u64 rr = addm(Buf(it.in[0]).ld(vo, c * T * 8), hl, pl.q);
-            r[c] = rr >= hl ? reduce64(rr - hl, pc) : subm(0, reduce64(hl - rr, pc), q);
+            r[c] = centered_mod(addm(Buf(it.in[0]).ld(vo, c * T * 8), hl, pl.q), hl, pc);
         }
     } else if constexpr (OP == F_SAMPLE) {
         // it.a = kind, it.b = object id, it.c = domain tag
@@ -421,7 +418,7 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
     NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
 
     // ---- epilogue
-    if constexpr (OP == F_COPY || OP == F_MODUP || OP == F_SAMPLE || OP == F_INT || OP == F_HMULT) {
+    if constexpr (OP == F_COPY || OP == F_MODUP || OP == F_SAMPLE || OP == F_INT) {
 #pragma unroll
         for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
     } else if constexpr (OP == F_RESCALE) {
@@ -462,7 +459,7 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
     using NT = Ntt<LOGN, LOGE>;
     constexpr int N = NT::N, E = NT::E, T = NT::T;
     __shared__ u32 lds[NT::LDS_WORDS];
-    const int iid = xcd_item(nitems);
+    const int iid = xcd_item(nitems, tb.xcd_remap);
     if (iid < 0) return;
     const Item it = items[iid];
     const u32 tid = threadIdx.x, vo = tid * 8;
@@ -476,23 +473,6 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
     } else if constexpr (OP == I_MUL) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = mulm(Buf(it.in[0]).ld(vo, c * T * 8), Buf(it.in[1]).ld(vo, c * T * 8), pc);
-    } else if constexpr (OP == I_HMULT) {
-        // u = acc_top * P^-1 + d_poly (NTT domain)
-        const u64 *accl = it.in[0], *a0 = it.in[1], *a1 = it.in[2], *b0 = it.in[3], *b1 = it.in[4];
-#pragma unroll
-        for (int c = 0; c < E; c++) {
-            const u32 so = c * T * 8;
-            u64 d;
-            if (it.b == 0) {
-                d = mulm(Buf(a0).ld(vo, so), Buf(b0).ld(vo, so), pc);
-            } else {
-                Acc128 t;
-                t.mac(Buf(a0).ld(vo, so), Buf(b1).ld(vo, so));
-                t.mac(Buf(a1).ld(vo, so), Buf(b0).ld(vo, so));
-                d = t.reduce(pc);
-            }
-            r[c] = addm(shoup(Buf(accl).ld(vo, so), pc.pinv, pc.pinv_sh, q), d, q);
-        }
     } else if constexpr (OP == I_DECRYPT) {
         const u64 *s = it.in[3];
 #pragma unroll
@@ -540,20 +520,35 @@ enum EwOp : u32 {
     // limbs (x2, x3), a0 a1 b0 b1 (x4..x7): y_c = (acc_c P^-1 + d_c - z_c) q_l^-1,
     // d_0 = a0 b0, d_1 = a0 b1 + a1 b0, l = v
     EW_HMULT_FIN = 12,
+    // top limb of the fused HMult, before its INTT: y0 = acc P^-1 + d_v with
+    // acc (x0), a0 a1 b0 b1 (x1..x4), poly v
+    EW_HMULT_U = 13,
+    // per remaining limb i, before its NTT (coefficient domain): with the
+    // special-prime part of acc (x0, n_p limbs) and the INTT'd top limb u (x1):
+    // t = u - conv_l(acc_P) P^-1 mod q_l (relinearised top limb),
+    // y0 = conv_i(acc_P) P^-1 + ((t + h - h) centred) mod q_i, l = v
+    EW_HMULT_Z = 14,
 };
 
 __device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
 
+// One workgroup serves one descriptor over kEwPer * 256 consecutive residues,
+// so the descriptor is read once per thread through wave-uniform loads.
+template <int kEwPer>
 __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restrict__ items, int nitems,
                                             u64 seed) {
     const u32 N = 1u << tb.log_n;
-    const size_t total = (size_t)nitems * N;
-    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (size_t)gridDim.x * blockDim.x) {
-        const u32 iid = (u32)(g >> tb.log_n), j = (u32)(g & (N - 1));
-        const EwItem &it = items[iid];
-        const PrimeConst pc = tb.pc[it.prime];
-        const u64 q = pc.q;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const EwItem it = items[iid];
+    const PrimeConst pc = tb.pc[it.prime];
+    const u64 q = pc.q;
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 j = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (j >= N) break;
         switch (it.op) {
             case EW_ADD: it.y[0][j] = addm(it.x[0][j], it.x[1][j], q); break;
             case EW_SUB: it.y[0][j] = subm(it.x[0][j], it.x[1][j], q); break;
@@ -598,6 +593,37 @@ __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restri
                 break;
             }
             case EW_SQUARE_S: it.y[0][j] = mulm(it.x[0][j], it.x[0][j], pc); break;
+            case EW_HMULT_U: {
+                const u64 a0 = it.x[1][j], a1 = it.x[2][j], b0 = it.x[3][j], b1 = it.x[4][j];
+                u64 d;
+                if (it.v == 0) {
+                    d = mulm(a0, b0, pc);
+                } else {
+                    Acc128 t;
+                    t.mac(a0, b1);
+                    t.mac(a1, b0);
+                    d = t.reduce(pc);
+                }
+                it.y[0][j] = addm(shoup(it.x[0][j], pc.pinv, pc.pinv_sh, q), d, q);
+                break;
+            }
+            case EW_HMULT_Z: {
+                const u32 l = (u32)it.v;
+                const PrimeConst pl = tb.pc[l];
+                const u64 *md = tb.moddown;
+                Acc128 ai, al;
+                for (u32 m = 0; m < tb.n_p; m++) {
+                    const u64 y = shoup(it.x[0][(size_t)m * N + j], md[2 * m], md[2 * m + 1], tb.pc[tb.n_q + m].q);
+                    ai.mac(y, md[2 * tb.n_p + (size_t)m * tb.n_q + it.prime]);
+                    al.mac(y, md[2 * tb.n_p + (size_t)m * tb.n_q + l]);
+                }
+                const u64 conv_l = shoup(al.reduce(pl), pl.pinv, pl.pinv_sh, pl.q);
+                const u64 t = subm(it.x[1][j], conv_l, pl.q);
+                const u64 hl = pl.q >> 1;
+                const u64 v = centered_mod(addm(t, hl, pl.q), hl, pc);
+                it.y[0][j] = addm(shoup(ai.reduce(pc), pc.pinv, pc.pinv_sh, q), v, q);
+                break;
+            }
             case EW_HMULT_FIN: {
                 const u64 a0 = it.x[4][j], a1 = it.x[5][j], b0 = it.x[6][j], b1 = it.x[7][j];
                 const u64 z0 = it.x[0][j], z1 = it.x[1][j], c0 = it.x[2][j], c1 = it.x[3][j];
@@ -617,36 +643,49 @@ __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restri
 }
 
 // Key-switch inner product over the extended basis: one item per target
-// limb t. For each digit j < a: the ModUp'd limb (ext + (j*c + t')*N, or,
-// for the digit that owns t, the input limb in[2] / the product
-// in[3]*in[4]) times the key limbs (b_j, a_j) of prime `prime`,
-// accumulated in 128 bits and reduced once. out = sum for b_j, out2 for a_j.
-// it.b = digit that owns t (0xFFFFFFFF for special primes), it.c = ext
-// limbs per digit, it.v = position of t in the ext layout.
-__global__ void __launch_bounds__(256) k_ip(DevTables tb, const Item *__restrict__ items, int nitems) {
+// limb `pos` (prime `prime`) and up to kIpCts ciphertexts of one level. For
+// each digit j < beta the ModUp'd limb (ext + (j E + pos) N), or for the digit
+// that owns the target the input limb own0 (times own1 when given), is
+// multiplied by the key limbs (b_j, a_j) of that prime; sums are 128-bit and
+// reduced once. Each key residue is loaded once for all the item's
+// ciphertexts. acc + pos N receives the b-sum, acc + (E + pos) N the a-sum.
+template <int kEwPer>
+__global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restrict__ items, int nitems) {
     const u32 N = 1u << tb.log_n;
-    const size_t total = (size_t)nitems * N;
-    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (size_t)gridDim.x * blockDim.x) {
-        const u32 iid = (u32)(g >> tb.log_n), x = (u32)(g & (N - 1));
-        const Item &it = items[iid];
-        const PrimeConst pc = tb.pc[it.prime];
-        const u64 *key = it.in[1];
-        const size_t kstride = (size_t)tb.n_prim * N;  // one component
-        Acc128 s0, s1;
-        for (u32 j = 0; j < it.a; j++) {
-            u64 e;
-            if (j == it.b) {
-                e = it.in[3] ? mulm(it.in[3][x], it.in[4][x], pc) : it.in[2][x];
-            } else {
-                e = it.in[0][((size_t)j * it.c + (u32)it.v) * N + x];
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const IpItem it = items[iid];
+    const PrimeConst pc = tb.pc[it.prime];
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (x >= N) break;
+        Acc128 s0[kIpCts], s1[kIpCts];
+        for (u32 j = 0; j < it.beta; j++) {
+            const u64 *kb = it.key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
+            const u64 k0 = kb[x], k1 = kb[kstride + x];
+#pragma unroll
+            for (int c = 0; c < kIpCts; c++) {
+                if ((u32)c >= it.n_ct) break;
+                u64 v;
+                if (j == it.own_digit) {
+                    v = it.own1[c] ? mulm(it.own0[c][x], it.own1[c][x], pc) : it.own0[c][x];
+                } else {
+                    v = it.ext[c][((size_t)j * it.E + it.pos) * N + x];
+                }
+                s0[c].mac(v, k0);
+                s1[c].mac(v, k1);
             }
-            const u64 *kb = key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
-            s0.mac(e, kb[x]);
-            s1.mac(e, kb[kstride + x]);
         }
-        it.out[x] = s0.reduce(pc);
-        it.out2[x] = s1.reduce(pc);
+#pragma unroll
+        for (int c = 0; c < kIpCts; c++) {
+            if ((u32)c >= it.n_ct) break;
+            it.acc[c][(size_t)it.pos * N + x] = s0[c].reduce(pc);
+            it.acc[c][((size_t)it.E + it.pos) * N + x] = s1[c].reduce(pc);
+        }
     }
 }
 
@@ -763,7 +802,6 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
             case F_MODUP: return launch_fwd_t<LN, LE, F_MODUP>(tb, items, n, seed, s);     \
             case F_RESCALE: return launch_fwd_t<LN, LE, F_RESCALE>(tb, items, n, seed, s); \
             case F_MODDOWN: return launch_fwd_t<LN, LE, F_MODDOWN>(tb, items, n, seed, s); \
-            case F_HMULT: return launch_fwd_t<LN, LE, F_HMULT>(tb, items, n, seed, s);     \
             case F_SAMPLE: return launch_fwd_t<LN, LE, F_SAMPLE>(tb, items, n, seed, s);   \
             case F_INT: return launch_fwd_t<LN, LE, F_INT>(tb, items, n, seed, s);         \
         }                                                                            \
@@ -773,13 +811,24 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
         switch (op) {                                                                \
             case I_COPY: return launch_inv_t<LN, LE, I_COPY>(tb, items, n, s);             \
             case I_MUL: return launch_inv_t<LN, LE, I_MUL>(tb, items, n, s);               \
-            case I_HMULT: return launch_inv_t<LN, LE, I_HMULT>(tb, items, n, s);           \
             case I_DECRYPT: return launch_inv_t<LN, LE, I_DECRYPT>(tb, items, n, s);       \
         }                                                                            \
         break;
 
+// Residues per thread: 16 below N = 2^15 and 32 at 2^15 by default; the
+// wide variant doubles that (32 for 2^11..2^14, 64 at 2^15) and is a
+// tuning choice.
 hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (tb.ntt_wide) {
+        switch (tb.log_n) {
+            CKKS_FWD_CASE(11, 5)
+            CKKS_FWD_CASE(12, 5)
+            CKKS_FWD_CASE(13, 5)
+            CKKS_FWD_CASE(14, 5)
+            CKKS_FWD_CASE(15, 6)
+        }
+    }
     switch (tb.log_n) {
         CKKS_FWD_CASE(10, 4)
         CKKS_FWD_CASE(11, 4)
@@ -792,6 +841,15 @@ hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64
 }
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (tb.ntt_wide) {
+        switch (tb.log_n) {
+            CKKS_INV_CASE(11, 5)
+            CKKS_INV_CASE(12, 5)
+            CKKS_INV_CASE(13, 5)
+            CKKS_INV_CASE(14, 5)
+            CKKS_INV_CASE(15, 6)
+        }
+    }
     switch (tb.log_n) {
         CKKS_INV_CASE(10, 4)
         CKKS_INV_CASE(11, 4)
@@ -809,16 +867,26 @@ static int ew_grid(size_t work) {
     return (int)(blocks < cap ? (blocks ? blocks : 1) : cap);
 }
 
+static u32 ew_blocks(const DevTables &tb, int n, int per) {
+    const u32 N = 1u << tb.log_n;
+    return (u32)n * ((N + 256 * per - 1) / (256 * per));
+}
 hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const size_t work = (size_t)n << tb.log_n;
-    hipLaunchKernelGGL(k_ew, dim3(ew_grid(work)), dim3(256), 0, s, tb, items, n, seed);
+    switch (tb.ew_log) {
+        case 1: hipLaunchKernelGGL(k_ew<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n, seed); break;
+        case 3: hipLaunchKernelGGL(k_ew<8>, dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n, seed); break;
+        default: hipLaunchKernelGGL(k_ew<4>, dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n, seed);
+    }
     return hipGetLastError();
 }
-hipError_t launch_ip(const DevTables &tb, const Item *items, int n, hipStream_t s) {
+hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const size_t work = (size_t)n << tb.log_n;
-    hipLaunchKernelGGL(k_ip, dim3(ew_grid(work)), dim3(256), 0, s, tb, items, n);
+    switch (tb.ew_log) {
+        case 1: hipLaunchKernelGGL(k_ip<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
+        case 3: hipLaunchKernelGGL(k_ip<8>, dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
+        default: hipLaunchKernelGGL(k_ip<4>, dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
+    }
     return hipGetLastError();
 }
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,

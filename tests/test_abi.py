@@ -87,3 +87,35 @@ def test_host_encoder_roundtrip():
         assert np.allclose(np.array(out_re[:]), OE.decode_residues(res, primes, 2.0 ** 40, n).real, atol=1e-12)
     finally:
         nat.ckks_ctx_destroy(h)
+
+
+def test_tuning_knobs_host():
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    primes = O.find_primes(12, [50, 50, 60])
+    h = nat.ckks_ctx_create(12, primes[:2], primes[2:], 2)
+    try:
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_NTT_WIDE) == 0
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_EW_LOG) == 2
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_XCD_REMAP) == 1
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_WIDE, 1)
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_EW_LOG, 3)
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_XCD_REMAP, 0)
+        assert [nat.ckks_ctx_get_tuning(h, k) for k in range(3)] == [1, 3, 0]
+        for knob, bad in [(nat.CKKS_TUNE_EW_LOG, 0), (nat.CKKS_TUNE_EW_LOG, 4), (nat.CKKS_TUNE_NTT_WIDE, 2),
+                          (nat.CKKS_TUNE_XCD_REMAP, -1), (7, 0)]:
+            with pytest.raises(nat.CkksError) as e:
+                nat.ckks_ctx_set_tuning(h, knob, bad)
+            assert e.value.code == nat.CKKS_EINVAL
+        # a rejected value leaves the knob as it was
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_EW_LOG) == 3
+        assert nat.ckks_ctx_get_tuning(h, 7) == -1
+    finally:
+        nat.ckks_ctx_destroy(h)
+    small = O.find_primes(10, [50, 60])
+    h = nat.ckks_ctx_create(10, small[:1], small[1:], 1)
+    try:
+        with pytest.raises(nat.CkksError):
+            nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_WIDE, 1)  # no wide variant at N = 2^10
+    finally:
+        nat.ckks_ctx_destroy(h)

@@ -1,0 +1,101 @@
+"""Every launch-shape setting the autotuner may pick computes the same
+residues: NTT / INTT against the oracle for each ring degree, and the
+batched HMult + relinearise + rescale against the oracle under every
+setting; the autotuner's pick and its cache round-trip."""
+import itertools
+import json
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ck():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_13638_amd import ckks
+    return ckks
+
+
+def _u(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x) for w, e, x in itertools.product((0, 1), (1, 2, 3), (0, 1))]
+
+
+@pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15])
+def test_ntt_variants_bit_exact(ck, log_n):
+    from paper_2110_13638_amd import _native as nat
+    primes = O.find_primes(log_n, [60, 50, 40, 36])
+    orc = O.Oracle(log_n, primes[:3], primes[3:], 1)
+    ctx = ck.Context(log_n, primes[:3], primes[3:], 1)
+    x = S.residues(9 + log_n, primes, 1 << log_n)[0]
+    want = [orc.ntt(x[i], i) for i in range(len(primes))]
+    for wide, remap in itertools.product((0, 1), (0, 1)):
+        print("ntt variant log_n=%d wide=%d remap=%d" % (log_n, wide, remap), flush=True)
+        ctx.set_tuning(ntt_wide=wide, xcd_remap=remap)
+        dev = torch.from_numpy(x.view(np.int64)).cuda()
+        ptrs = [dev[i].data_ptr() for i in range(len(primes))]
+        ws, wb = ctx.ws_for(nat.CKKS_OP_NTT, len(primes))
+        nat.ckks_ntt(ctx.h, ptrs, list(range(len(primes))), ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        got = _u(dev)
+        for i in range(len(primes)):
+            assert np.array_equal(got[i], want[i]), (wide, remap, i)
+        nat.ckks_intt(ctx.h, ptrs, list(range(len(primes))), ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(_u(dev), x)
+
+
+@pytest.fixture(scope="module")
+def hm(ck):
+    primes = O.find_primes(12, [50] * 16 + [60, 60])
+    ctx = ck.Context(12, primes[:16], primes[16:], 4).keygen(3)
+    orc = O.Oracle(12, primes[:16], primes[16:], 4)
+    _, sn = orc.keygen_secret(3)
+    rk = orc.keygen_relin(sn, 3 + 2)
+    levels = [l - 1 for l in S.ragged_limbs(6)]
+    ins, want = [], []
+    for i, lv in enumerate(levels):
+        res = S.residues(300 + i, ctx.q[: lv + 1], ctx.N, 4)
+        ins.append((ctx.ct_from_residues(res[:2]), ctx.ct_from_residues(res[2:])))
+        want.append(orc.mul_relin_rescale(res[:2], res[2:], rk))
+    return ctx, ins, want
+
+
+@pytest.mark.parametrize("st", SETTINGS, ids=lambda d: "w%d_e%d_x%d" % (d["ntt_wide"], d["ew_log"], d["xcd_remap"]))
+def test_hmult_variants_bit_exact(hm, st):
+    ctx, ins, want = hm
+    print("hmult variant", st, flush=True)
+    ctx.set_tuning(**st)
+    outs = ctx.hmult_relin_rescale([a for a, _ in ins], [b for _, b in ins])
+    for o, w in zip(outs, want):
+        assert np.array_equal(o.residues(), w)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1)
+
+
+def test_autotune_pick_and_cache(hm, tmp_path):
+    from paper_2110_13638_amd import tune
+    ctx, ins, want = hm
+    A, B = [a for a, _ in ins], [b for _, b in ins]
+    cache = str(tmp_path / "tune.json")
+    best, times = tune.autotune(ctx, lambda: ctx.hmult_relin_rescale(A, B), "hmult-ragged", cache=cache,
+                                space={"ntt_wide": (0, 1), "ew_log": (2, 3), "xcd_remap": (1,)}, reps=2)
+    assert len(times) == 4 and all(t > 0 for t in times.values())
+    assert ctx.tuning() == best
+    # the cached pick is applied without timing again
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1)
+    again, times2 = tune.autotune(ctx, None, "hmult-ragged", cache=cache)
+    assert again == best and times2 == {} and ctx.tuning() == best
+    assert json.load(open(cache))
+    outs = ctx.hmult_relin_rescale(A, B)
+    for o, w in zip(outs, want):
+        assert np.array_equal(o.residues(), w)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1)

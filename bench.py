@@ -27,8 +27,8 @@ Q_BITS = [50] * 16
 P_BITS = [60, 60]
 DNUM = 4
 HBM_PEAK_GBS = 8000.0
-# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit lane-ops/s.
-VALU_LANE_OPS = 256 * 64 * 2.4e9
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit lane-slots/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -39,34 +39,62 @@ def limb_bytes(n):
     return 8 * n
 
 
+# Minimal 32-bit VALU issue slots of the exact 64-bit modular primitives on
+# gfx950 (the instruction-level derivation is in the design notes):
+#   BF   Harvey butterfly with a Shoup twiddle, lazy range [0, 4q)
+#   MAC  64x64 -> 128-bit product accumulated into a 128-bit sum
+#   RED  Barrett reduction of a 128-bit sum to [0, q)
+#   MULM Shoup multiplication by a precomputed constant
+OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23}
+
+
 def kernel_model(name, items, ctx, level):
-    """Algorithmic HBM bytes of one launch of a kernel family in the fused
-    HMult pipeline at one level (every item of the launch at that level)."""
-    N, k, A = ctx.N, len(ctx.p), -(-len(ctx.q) // ctx.dnum)
+    """Algorithmic work of one launch of a kernel family in the fused HMult
+    pipeline, every item of the launch at ``level``: (HBM bytes, 32-bit
+    VALU slots). Bytes count each operand that must cross HBM once per
+    launch (a key limb shared by all ciphertexts of the batch once)."""
+    N, logN, k, A = ctx.N, ctx.log_n, len(ctx.p), -(-len(ctx.q) // ctx.dnum)
     L = level + 1
     E = L + k
     beta = -(-L // A)
+    digit = [min(A, L - j * A) for j in range(beta)]
     lb = limb_bytes(N)
+    ntt = (N // 2) * logN * OPS["BF"]
     fam = name.split("/")[0]
     if fam == "ntt_fwd_modup":
-        # per ciphertext: every digit's source limbs read once, every
-        # extended limb written once
-        per_ct_items = sum(E - min(A, L - j * A) for j in range(beta))
+        # per ciphertext: each digit's coefficient limbs read once, every
+        # extended limb outside the digit converted (s MACs + 1 reduction
+        # per coefficient), transformed and written once
+        per_ct_items = sum(E - s for s in digit)
         cts = items / per_ct_items
-        return cts * (L + per_ct_items) * lb
+        ops = cts * sum((E - s) * (N * (s * OPS["MAC"] + OPS["RED"]) + ntt) for s in digit)
+        return cts * (L + per_ct_items) * lb, ops
     if fam == "keyswitch_inner_product":
         cts = items / E
-        # ModUp'd limbs (or the two source limbs of d2), key limbs, 2 outputs
-        per = 0
-        for t in range(E):
-            per += beta * 1 + 2 * beta + 2
-        return cts * per * lb
-    if fam in ("ntt_inv_mul",):
-        return items * 3 * lb
-    if fam == "ntt_fwd_hmult_tail":
-        # reads k special limbs + top limb (shared per poly), acc limb, 4 input limbs; writes 1
-        return items * 6 * lb
-    return items * 2 * lb
+        # extended limbs (own-digit limbs come from the input limbs a1, b1),
+        # a0, b0 for the folded P d term, key limbs once per launch, two
+        # accumulators out; beta MACs + 1 reduction per coefficient of each
+        # output limb, plus the P d term on data limbs
+        per_ct = (beta * E - L) + 4 * L + 2 * E
+        ops = cts * (2 * E * N * (beta * OPS["MAC"] + OPS["RED"])
+                     + L * N * (3 * OPS["MAC"] + 2 * OPS["RED"] + 2 * OPS["MULM"]))
+        return (cts * per_ct + 2 * beta * E) * lb, ops
+    if fam == "ntt_inv_mul":
+        # product of two limbs, inverse transform, scaling by the CRT constant
+        return items * 3 * lb, items * (N * (OPS["MAC"] + OPS["RED"] + OPS["MULM"]) + ntt)
+    if fam in ("ntt_fwd_moddown_z", "ntt_fwd_relin_rescale"):
+        # per ciphertext (2 l items): both polys' n_p converted limbs and top
+        # limb read once, one limb out per item; the fused variant also reads
+        # the accumulator limb and rescales
+        l = level
+        cts = items / (2 * l)
+        conv = N * (k * OPS["MAC"] + OPS["RED"] + OPS["MULM"] + OPS["RED"])
+        if fam == "ntt_fwd_moddown_z":
+            return cts * (2 * (k + 1) + 2 * l) * lb, items * (conv + ntt)
+        return cts * (2 * (k + 1) + 4 * l) * lb, items * (conv + ntt + 2 * N * OPS["MULM"])
+    if fam in ("ntt_fwd", "ntt_inv"):
+        return items * 2 * lb, items * ntt
+    return items * 2 * lb, 0.0
 
 
 def serve_leg(args, dev, log):
@@ -138,91 +166,14 @@ def serve_leg(args, dev, log):
     return out
 
 
-def torch_sync():
-    import torch
-    torch.cuda.synchronize()
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=256)
-    ap.add_argument("--plain-pairs", type=int, default=32)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
-    ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
-    ap.add_argument("--no-serve", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: there is no multi-GPU path "
-              "(requests and ciphertexts are independent and would shard by request)")
-        sys.exit(2)
-
+def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
+    """Ragged batch, plain one-op-per-launch path and NTT microbench."""
     import numpy as np
     import torch
     import synthetic as S
     from paper_2110_13638_amd import _native as nat
     from paper_2110_13638_amd import ckks
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    primes = nat.ckks_find_primes(LOG_N, Q_BITS + P_BITS)
-    q, p = primes[: len(Q_BITS)], primes[len(Q_BITS):]
-    ctx = ckks.Context(LOG_N, q, p, DNUM, device=dev).keygen(1)
-    N = ctx.N
-    top = len(q) - 1
-    B = args.batch
-    log("setup: N=2^%d, %d data + %d special primes, dnum=%d, batch %d" % (LOG_N, len(q), len(p), DNUM, B))
-
-    # ---- inputs: B pairs at 16 limbs, uniform residues (seeded, on device)
-    res = S.residues_device(0, q, N, 4 * B, dev).view(B, 2, 2, len(q), N)
-    A = [ckks.Ciphertext(ctx, res[i, 0], 2, top, 1.0) for i in range(B)]
-    Bc = [ckks.Ciphertext(ctx, res[i, 1], 2, top, 1.0) for i in range(B)]
-    outs = [ctx.new_ct(2, top - 1, 1.0) for _ in range(B)]
-    ws, wb = ctx.ws_for(nat.CKKS_OP_HMULT, B, [top] * B)
-    sa, sb, so = ctx._structs(A), ctx._structs(Bc), ctx._structs(outs)
-    rk = ctx.rk.data_ptr()
-
-    def step():
-        nat.ckks_hmult_relin_rescale(ctx.h, rk, sa, sb, so, ws, wb, ctx.stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    nat.ckks_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nat.ckks_profile_enable(False)
-    recs = nat.ckks_profile_collect()
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = B * args.steps / elapsed
-    log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
-
-    # per-kernel breakdown
-    fam = {}
-    for name, items, ms in recs:
-        f = fam.setdefault(name, [0, 0.0, 0])
-        f[0] += 1
-        f[1] += ms
-        f[2] = items
-    breakdown = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "items": v[2]} for k, v in fam.items()}
-    dom = max(fam, key=lambda k: fam[k][1])
-    d = breakdown[dom]
-    alg_bytes = kernel_model(dom, d["items"], ctx, top)
-    achieved = alg_bytes / (d["avg_ms"] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": d["avg_ms"]}
-
+    N, dev, rk = ctx.N, ctx.device, ctx.rk.data_ptr()
     # ---- ragged batch (limbs 4..16)
     levels = [l - 1 for l in S.ragged_limbs(B)]
     RA = [ckks.Ciphertext(ctx, res[i, 0], 2, levels[i], 1.0) for i in range(B)]
@@ -301,6 +252,130 @@ def main():
     log("NTT: %d limbs fwd %.3f ms (%.0f GB/s, %.1f%% HBM) inv %.3f ms" %
         (len(limbs), fwd_ms, ntt["fwd_hbm_GBs"], 100 * ntt["fwd_hbm_frac"], inv_ms))
 
+    return ragged_rate, plain_rate, same, ntt
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--plain-pairs", type=int, default=32)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="time only the batched HMult step (ragged, plain, NTT and serving legs skipped)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tune-cache", default=None, help="JSON file that keeps the autotuned launch shapes")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(requests and ciphertexts are independent and would shard by request)")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2110_13638_amd import _native as nat
+    from paper_2110_13638_amd import ckks
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        x = torch.ones(n, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "copies": 3}))
+        return
+    primes = nat.ckks_find_primes(LOG_N, Q_BITS + P_BITS)
+    q, p = primes[: len(Q_BITS)], primes[len(Q_BITS):]
+    ctx = ckks.Context(LOG_N, q, p, DNUM, device=dev).keygen(1)
+    N = ctx.N
+    top = len(q) - 1
+    B = args.batch
+    log("setup: N=2^%d, %d data + %d special primes, dnum=%d, batch %d" % (LOG_N, len(q), len(p), DNUM, B))
+
+    # ---- inputs: B pairs at 16 limbs, uniform residues (seeded, on device)
+    res = S.residues_device(0, q, N, 4 * B, dev).view(B, 2, 2, len(q), N)
+    A = [ckks.Ciphertext(ctx, res[i, 0], 2, top, 1.0) for i in range(B)]
+    Bc = [ckks.Ciphertext(ctx, res[i, 1], 2, top, 1.0) for i in range(B)]
+    outs = [ctx.new_ct(2, top - 1, 1.0) for _ in range(B)]
+    ws, wb = ctx.ws_for(nat.CKKS_OP_HMULT, B, [top] * B)
+    sa, sb, so = ctx._structs(A), ctx._structs(Bc), ctx._structs(outs)
+    rk = ctx.rk.data_ptr()
+
+    def step():
+        nat.ckks_hmult_relin_rescale(ctx.h, rk, sa, sb, so, ws, wb, ctx.stream)
+
+    tuning = {"setting": ctx.tuning(), "candidates_ms": {}}
+    if not args.no_tune:
+        from paper_2110_13638_amd import tune
+        best, times = tune.autotune(ctx, step, "hmult-batch-%d" % B, cache=args.tune_cache, reps=3)
+        tuning = {"setting": best, "candidates_ms": {k: round(v, 3) for k, v in times.items()}}
+        log("autotuned launch shapes: %s%s" % (best, " (%.2f ms)" % min(times.values()) if times else " (cached)"))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    nat.ckks_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nat.ckks_profile_enable(False)
+    recs = nat.ckks_profile_collect()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
+
+    # per-kernel breakdown
+    fam = {}
+    for name, items, ms in recs:
+        f = fam.setdefault(name, [0, 0.0, 0])
+        f[0] += 1
+        f[1] += ms
+        f[2] = items
+    breakdown = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "items": v[2]} for k, v in fam.items()}
+    dom = max(fam, key=lambda k: fam[k][1])
+    d = breakdown[dom]
+    alg_bytes, alg_ops = kernel_model(dom, d["items"], ctx, top)
+    sec = d["avg_ms"] * 1e-3
+    hbm = {"achieved": round(alg_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    hbm["frac"] = round(hbm["achieved"] / HBM_PEAK_GBS, 4)
+    alu = {"achieved": round(alg_ops / sec / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s"}
+    alu["frac"] = round(alu["achieved"] / alu["peak"], 4)
+    bound, prim, other = ("alu", alu, hbm) if alu["frac"] >= hbm["frac"] else ("hbm", hbm, alu)
+    roofline = {"kernel": dom, "bound": bound, "achieved": prim["achieved"], "peak": prim["peak"],
+                "unit": prim["unit"], "frac": prim["frac"], "traffic": None,
+                "other": dict(other, bound="hbm" if bound == "alu" else "alu"),
+                "alg_bytes_per_launch": alg_bytes, "alg_ops_per_launch": alg_ops, "avg_launch_ms": d["avg_ms"],
+                "launches": d["launches"]}
+    log("dominant kernel %s: %.3f ms/launch, %s %.1f %s (%.1f%% of peak); %s %.1f%%" %
+        (dom, d["avg_ms"], bound, prim["achieved"], prim["unit"], 100 * prim["frac"],
+         other["unit"], 100 * other["frac"]))
+
+    ragged_rate = plain_rate = same = ntt = None
+    if not args.no_extra:
+        ragged_rate, plain_rate, same, ntt = extra_legs(args, ctx, res, A, Bc, outs, B, top, value)
+
     # ---- oracle on the host cores, bounded sample of the same workload
     cpu = None
     if not args.no_cpu:
@@ -327,7 +402,7 @@ def main():
         log("oracle: %.3f HMult/s on %d threads; GPU ciphertext == oracle: %s" %
             (cpu["value"], cores, cpu["gpu_matches_oracle"]))
 
-    serving = None if args.no_serve else serve_leg(args, dev, log)
+    serving = None if (args.no_serve or args.no_extra) else serve_leg(args, dev, log)
 
     line = {
         "metric": "HMult+relin+rescale/s at N=2^15,L=16; encrypted infer/s + p50/p99 latency",
@@ -339,10 +414,10 @@ def main():
                    "log_n": LOG_N, "limbs": 16, "special_primes": 2, "dnum": DNUM, "batch": B},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "extra": {"ragged_4_16_hmult_per_s": round(ragged_rate, 2),
-                  "plain_one_op_per_launch_hmult_per_s": round(plain_rate, 2),
-                  "batched_over_plain": round(value / plain_rate, 2),
-                  "plain_equals_fused": same,
+        "extra": {"ragged_4_16_hmult_per_s": ragged_rate and round(ragged_rate, 2),
+                  "plain_one_op_per_launch_hmult_per_s": plain_rate and round(plain_rate, 2),
+                  "batched_over_plain": plain_rate and round(value / plain_rate, 2),
+                  "plain_equals_fused": same, "tuning": tuning,
                   "ntt": ntt, "kernels": breakdown, "serving": serving},
     }
     print(json.dumps(line))

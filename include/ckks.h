@@ -387,8 +387,11 @@ int ckks_graph_autohe(ckks_graph *g, uint32_t *n_groups, uint32_t *group_of_node
  *                        1, 2 (default) or 3.
  *   CKKS_TUNE_XCD_REMAP  1 (default): map consecutive NTT work items to one
  *                        XCD (shared L2); 0: plain block order.
+ *   CKKS_TUNE_FUSE_TAIL  0 (default): the rescale step of
+ *                        ckks_hmult_relin_rescale runs as its own
+ *                        element-wise pass; 1: inside the last NTT.
  * Returns CKKS_EINVAL for an unknown knob or a value out of range. */
-enum { CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2 };
+enum { CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2, CKKS_TUNE_FUSE_TAIL = 3 };
 int ckks_ctx_set_tuning(ckks_ctx *ctx, int knob, int value);
 /* Current value of a knob, or -1 for a null context / unknown knob. */
 int ckks_ctx_get_tuning(const ckks_ctx *ctx, int knob);

@@ -19,7 +19,7 @@ ERROR_NAMES = {-1: "EINVAL", -2: "ELEVEL", -3: "ESCALE", -4: "EDEPTH", -5: "ENOK
 CKKS_KEY_SECRET, CKKS_KEY_PUBLIC, CKKS_KEY_SWITCH = 0, 1, 2
 (CKKS_OP_NTT, CKKS_OP_ELEMENTWISE, CKKS_OP_KEYSWITCH, CKKS_OP_RESCALE, CKKS_OP_HMULT, CKKS_OP_KEYGEN,
  CKKS_OP_ENCRYPT, CKKS_OP_LINEAR) = range(8)
-CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP = 0, 1, 2
+CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP, CKKS_TUNE_FUSE_TAIL = 0, 1, 2, 3
 
 
 class CkksError(RuntimeError):

@@ -36,12 +36,12 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
                                  u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
 
 // kernel op codes (mirrors of the enums in the kernel file)
-enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_SAMPLE = 5, F_INT = 6 };
-enum { I_COPY = 0, I_MUL = 1, I_DECRYPT = 3 };
+enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_RELIN = 4, F_SAMPLE = 5, F_INT = 6, F_RELIN_RS = 7 };
+enum { I_COPY = 0, I_MUL = 1, I_SCALE = 2, I_DECRYPT = 3 };
 enum {
     EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_MUL_CONST = 3, EW_ADD_CONST = 4, EW_TENSOR = 5,
     EW_COPY = 6, EW_AUTOMORPH = 7, EW_NEG = 8, EW_KEYGEN = 9, EW_ENCRYPT = 10, EW_SQUARE_S = 11,
-    EW_HMULT_FIN = 12, EW_HMULT_U = 13, EW_HMULT_Z = 14
+    EW_HMULT_FIN = 12, EW_HMULT_T = 14
 };
 enum { TAG_SK = 1, TAG_PK_A = 2, TAG_PK_E = 3, TAG_SWK_A = 4, TAG_SWK_E = 5, TAG_ENC_V = 6,
        TAG_ENC_E0 = 7, TAG_ENC_E1 = 8 };
@@ -256,6 +256,7 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     c->tb.ntt_wide = 0;
     c->tb.ew_log = 2;
     c->tb.xcd_remap = 1;
+    c->tb.fuse_tail = 0;
     c->log_n = p->log_n;
     c->N = 1u << p->log_n;
     c->n_q = p->n_q;
@@ -482,6 +483,10 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
             if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: XCD_REMAP takes 0 or 1");
             c->tb.xcd_remap = (u32)value;
             return CKKS_OK;
+        case CKKS_TUNE_FUSE_TAIL:
+            if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: FUSE_TAIL takes 0 or 1");
+            c->tb.fuse_tail = (u32)value;
+            return CKKS_OK;
     }
     return fail(CKKS_EINVAL, "set_tuning: unknown knob");
 }
@@ -491,6 +496,7 @@ extern "C" int ckks_ctx_get_tuning(const ckks_ctx *c, int knob) {
         case CKKS_TUNE_NTT_WIDE: return (int)c->tb.ntt_wide;
         case CKKS_TUNE_EW_LOG: return (int)c->tb.ew_log;
         case CKKS_TUNE_XCD_REMAP: return (int)c->tb.xcd_remap;
+        case CKKS_TUNE_FUSE_TAIL: return (int)c->tb.fuse_tail;
     }
     return -1;
 }
@@ -610,11 +616,11 @@ struct ProfRec {
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 const char *fwd_names[] = {"ntt_fwd", "ntt_fwd_modup", "ntt_fwd_rescale", "ntt_fwd_moddown",
-                           "ntt_fwd_unused", "ntt_fwd_sample", "ntt_fwd_int"};
-const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_unused", "ntt_inv_decrypt"};
+                           "ntt_fwd_moddown_z", "ntt_fwd_sample", "ntt_fwd_int", "ntt_fwd_relin_rescale"};
+const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_scale", "ntt_inv_decrypt"};
 const char *ew_names[] = {"ew_add", "ew_sub", "ew_mul", "ew_mul_const", "ew_add_const", "ew_tensor", "ew_copy",
                           "ew_automorph", "ew_neg", "ew_keygen", "ew_encrypt", "ew_square_s", "ew_hmult_fin",
-                          "ew_hmult_u", "ew_hmult_z"};
+                          "ew_unused", "ew_hmult_t"};
 std::string launch_name(int kind, int op, u32 log_n) {
     char b[64];
     switch (kind) {
@@ -729,6 +735,7 @@ struct IpCt {
     const u64 *ext;
     u64 *acc;
     std::vector<const u64 *> own0, own1;  // per data limb t <= level
+    std::vector<const u64 *> own2, own3;  // a0, b0 of a product (P d folded into the sums)
 };
 // items of the inner product: ciphertexts of one level are grouped by
 // kIpCts so that each key residue is loaded once per group
@@ -756,6 +763,8 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
                 it.acc[k - g] = x.acc;
                 it.own0[k - g] = t < L ? x.own0[t] : nullptr;
                 it.own1[k - g] = (t < L && !x.own1.empty()) ? x.own1[t] : nullptr;
+                it.own2[k - g] = (t < L && !x.own2.empty()) ? x.own2[t] : nullptr;
+                it.own3[k - g] = (t < L && !x.own3.empty()) ? x.own3[t] : nullptr;
             }
             v.push_back(it);
         }
@@ -1446,8 +1455,9 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
 static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B) {
     const ckks_ctx *c = P.c;
     const u32 N = c->N, k = c->n_p, A = c->alpha;
-    std::vector<Item> mul, modup, ipP, last, fin;
-    std::vector<EwItem> tail, tu, tz;
+    const bool fuse = c->tb.fuse_tail != 0;
+    std::vector<Item> mul, modup, scale, fin;
+    std::vector<EwItem> tt, tail;
     std::vector<IpCt> ipc;
     std::vector<IpItem> ip;
     for (u32 x = 0; x < B; x++) {
@@ -1456,7 +1466,8 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
         u64 *ext = P.limbs((size_t)beta * E);
         u64 *acc = P.limbs((size_t)2 * E);
         u64 *top = P.limbs(2);
-        u64 *zh = P.limbs((size_t)2 * L);
+        u64 *zh = fuse ? nullptr : P.limbs((size_t)2 * l);
+        // d2 = a1 b1 -> INTT -> times hat_i^-1 (the ModUp input of its digit)
         for (u32 i = 0; i < L; i++) {
             const u32 j = i / A, lo = j * A, s = std::min(A, L - lo);
             Item it = item0();
@@ -1469,6 +1480,7 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
             it.a = i - lo;
             mul.push_back(it);
         }
+        // ModUp of every digit to the primes outside it, then NTT
         for (u32 j = 0; j < beta; j++) {
             const u32 lo = j * A, s = std::min(A, L - lo);
             for (u32 t = 0; t < E; t++) {
@@ -1484,6 +1496,7 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
                 modup.push_back(it);
             }
         }
+        // key-switch inner product; data limbs also take P d_0, P d_1
         {
             IpCt y;
             y.level = l;
@@ -1492,79 +1505,71 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
             for (u32 t = 0; t < L; t++) {
                 y.own0.push_back(limb(c, a[x], 1, t));
                 y.own1.push_back(limb(c, b[x], 1, t));
+                y.own2.push_back(limb(c, a[x], 0, t));
+                y.own3.push_back(limb(c, b[x], 0, t));
             }
             ipc.push_back(y);
         }
-        for (u32 cc = 0; cc < 2; cc++)
+        for (u32 cc = 0; cc < 2; cc++) {
+            // special-prime part: INTT, times hat_m^-1 (in place)
             for (u32 m = 0; m < k; m++) {
                 Item it = item0();
                 it.in[0] = acc + ((size_t)cc * E + L + m) * N;
                 it.out = (u64 *)it.in[0];
                 it.prime = c->n_q + m;
-                ipP.push_back(it);
+                it.a = m;
+                scale.push_back(it);
             }
-        for (u32 cc = 0; cc < 2; cc++) {
-            EwItem w = ew0();
-            w.op = EW_HMULT_U;
-            w.prime = l;
-            w.v = cc;
-            w.x[0] = acc + ((size_t)cc * E + l) * N;
-            w.x[1] = limb(c, a[x], 0, l);
-            w.x[2] = limb(c, a[x], 1, l);
-            w.x[3] = limb(c, b[x], 0, l);
-            w.x[4] = limb(c, b[x], 1, l);
-            w.y[0] = top + (size_t)cc * N;
-            tu.push_back(w);
+            // top limb: INTT, times P^-1; then minus conv_l(y) P^-1
             Item it = item0();
-            it.in[0] = top + (size_t)cc * N;
+            it.in[0] = acc + ((size_t)cc * E + l) * N;
             it.out = top + (size_t)cc * N;
             it.prime = l;
-            last.push_back(it);
+            it.b = 1;
+            scale.push_back(it);
+            EwItem v = ew0();
+            v.op = EW_HMULT_T;
+            v.prime = l;
+            v.x[0] = top + (size_t)cc * N;
+            v.x[1] = acc + ((size_t)cc * E + L) * N;
+            v.y[0] = top + (size_t)cc * N;
+            tt.push_back(v);
         }
+        // remaining limbs: ModDown correction, NTT, rescale
         for (u32 cc = 0; cc < 2; cc++)
             for (u32 i = 0; i < l; i++) {
-                EwItem w = ew0();
-                w.op = EW_HMULT_Z;
-                w.prime = i;
-                w.v = l;
-                w.x[0] = acc + ((size_t)cc * E + L) * N;
-                w.x[1] = top + (size_t)cc * N;
-                w.y[0] = zh + ((size_t)cc * L + i) * N;
-                tz.push_back(w);
                 Item it = item0();
-                it.in[0] = zh + ((size_t)cc * L + i) * N;
-                it.out = zh + ((size_t)cc * L + i) * N;
+                it.in[0] = acc + ((size_t)cc * E + L) * N;
+                it.in[1] = top + (size_t)cc * N;
+                it.in[2] = acc + ((size_t)cc * E + i) * N;
+                it.out = fuse ? limb(c, out[x], cc, i) : zh + ((size_t)cc * l + i) * N;
                 it.prime = i;
+                it.a = l;
                 fin.push_back(it);
             }
-        for (u32 i = 0; i < l; i++) {
-            EwItem w = ew0();
-            w.op = EW_HMULT_FIN;
-            w.prime = i;
-            w.v = l;
-            w.x[0] = zh + (size_t)i * N;
-            w.x[1] = zh + ((size_t)L + i) * N;
-            w.x[2] = acc + (size_t)i * N;
-            w.x[3] = acc + ((size_t)E + i) * N;
-            w.x[4] = limb(c, a[x], 0, i);
-            w.x[5] = limb(c, a[x], 1, i);
-            w.x[6] = limb(c, b[x], 0, i);
-            w.x[7] = limb(c, b[x], 1, i);
-            w.y[0] = limb(c, out[x], 0, i);
-            w.y[1] = limb(c, out[x], 1, i);
-            tail.push_back(w);
-        }
+        if (!fuse)
+            for (u32 i = 0; i < l; i++) {
+                EwItem w = ew0();
+                w.op = EW_HMULT_FIN;
+                w.prime = i;
+                w.v = l;
+                w.x[0] = zh + (size_t)i * N;
+                w.x[1] = zh + ((size_t)l + i) * N;
+                w.x[2] = acc + (size_t)i * N;
+                w.x[3] = acc + ((size_t)E + i) * N;
+                w.y[0] = limb(c, out[x], 0, i);
+                w.y[1] = limb(c, out[x], 1, i);
+                tail.push_back(w);
+            }
     }
     add_ip_items(c, ip, ipc, rk);
     P.add(1, I_MUL, mul);
     P.add(0, F_MODUP, modup);
     P.add(3, 0, ip);
-    P.add(1, I_COPY, ipP);
-    P.add(2, 0, tu);
-    P.add(1, I_COPY, last);
-    P.add(2, 0, tz);
-    P.add(0, F_COPY, fin);
-    P.add(2, 0, tail);
+    P.add(1, I_SCALE, scale);
+    P.add(2, 0, tt);
+    P.add(0, fuse ? F_RELIN_RS : F_RELIN, fin);
+    if (!fuse) P.add(2, 0, tail);
     return CKKS_OK;
 }
 

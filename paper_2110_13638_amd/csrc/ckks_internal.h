@@ -42,6 +42,7 @@ struct DevTables {
     u32 ntt_wide;   // 1: 32 residues per thread below N = 2^15 (default 16)
     u32 ew_log;     // log2 of residues per thread in streaming kernels (1..3)
     u32 xcd_remap;  // 1: consecutive work items on one XCD
+    u32 fuse_tail;  // 1: HMult's rescale epilogue inside the last NTT
 };
 
 // ModUp constants for digit j truncated to s primes (1 <= s <= alpha):
@@ -94,6 +95,11 @@ struct IpItem {
     u64 *acc[kIpCts];         // accumulator base of each ciphertext, [2][E][N]
     const u64 *own0[kIpCts];  // own digit: the NTT-form input limb, or a1 of a product
     const u64 *own1[kIpCts];  // own digit: b1 of a product, or null
+    // a0, b0 of a product (or null): the accumulators of data limbs also
+    // receive P (a0 b0) and P (a0 b1 + a1 b0), so that ModDown returns
+    // the relinearised product d + floor(acc / P) in one pass
+    const u64 *own2[kIpCts];
+    const u64 *own3[kIpCts];
     const u64 *key;           // [digits][2][n_prim][N]
     u32 n_ct, prime, beta, own_digit, E, pos;
 };

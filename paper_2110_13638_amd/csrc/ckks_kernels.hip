@@ -66,6 +66,10 @@ struct Acc128 {
         lo += l;
         hi += h + (lo < l);
     }
+    __device__ __forceinline__ void add(u64 a) {
+        lo += a;
+        hi += (lo < a);
+    }
     __device__ __forceinline__ u64 reduce(const PrimeConst &pc) const { return barrett128(lo, hi, pc); }
 };
 // x < 2^64 reduced mod q with floor(2^64/q): quotient estimate off by at most one
@@ -327,13 +331,20 @@ enum FwdOp : int {
     F_MODUP = 1,    // ModUp digit conversion -> NTT -> out
     F_RESCALE = 2,  // rescale correction -> NTT -> (in[1] - .) q_l^-1 -> out
     F_MODDOWN = 3,  // ModDown conversion -> NTT -> (in[1] - .) P^-1 (+ in[2]) -> out
-    F_SAMPLE = 5,   // sampled small polynomial -> NTT -> out (4 is unused)
+    // ModDown + rescale of one limb i < l of an HMult accumulator:
+    // z = conv_i(y) P^-1 + [t]_centred -> NTT, with y (in[0], n_p limbs) =
+    // INTT(acc_P) hat_m^-1 and t (in[1]) the relinearised top limb in the
+    // coefficient domain; l = a; out = z
+    F_RELIN = 4,
+    F_SAMPLE = 5,   // sampled small polynomial -> NTT -> out
     F_INT = 6,      // signed int64 coefficients -> NTT -> out
+    F_RELIN_RS = 7, // F_RELIN, then out = (acc' P^-1 - z) q_l^-1, acc' (in[2]) the accumulator limb
 };
 enum InvOp : int {
     I_COPY = 0,     // in[0] -> INTT -> out
     I_MUL = 1,      // in[0] * in[1] -> INTT -> out
-    I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out (2 is unused)
+    I_SCALE = 2,    // in[0] -> INTT -> * (hat_m^-1 mod p_m, m = a | P^-1 mod q when b = 1) -> out
+    I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out
 };
 
 // XCD-aware item order: the chip dispatches workgroup b to XCD (b mod 8).
@@ -382,13 +393,14 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
             hat_stride = tb.n_q;
         }
         const Buf src(it.in[0]);
-        static_for<0, E / kConvChunk>([&](auto C0) {
-            constexpr int c0 = decltype(C0)::value * kConvChunk;
-            Acc128 acc[kConvChunk];
+        constexpr int kCC = E >= 32 ? 4 : kConvChunk;
+        static_for<0, E / kCC>([&](auto C0) {
+            constexpr int c0 = decltype(C0)::value * kCC;
+            Acc128 acc[kCC];
             for (u32 i = 0; i < s; i++) {
                 const u64 inv = blk[2 * i], inv_sh = blk[2 * i + 1], qi = tb.pc[lo + i].q, h = hat[i * hat_stride];
 #pragma unroll
-                for (int c = 0; c < kConvChunk; c++) {
+                for (int c = 0; c < kCC; c++) {
                     const u64 x = src.ld(vo, (i * N + (c0 + c) * T) * 8);
                     // ModUp sources arrive pre-multiplied by hat_i^-1 (it.v == 1)
                     const u64 y = (OP == F_MODUP && it.v == 1) ? x : shoup(x, inv, inv_sh, qi);
@@ -396,7 +408,27 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kConvChunk; c++) r[c0 + c] = acc[c].reduce(pc);
+            for (int c = 0; c < kCC; c++) r[c0 + c] = acc[c].reduce(pc);
+        });
+    } else if constexpr (OP == F_RELIN || OP == F_RELIN_RS) {
+        const PrimeConst pl = tb.pc[it.a];  // q_l
+        const u64 hl = pl.q >> 1;
+        const u64 *hat = tb.moddown + 2 * tb.n_p + it.prime;  // hat[m * n_q]: P/p_m mod q_i
+        const Buf ys(it.in[0]), ts(it.in[1]);
+        constexpr int kCC = E >= 32 ? 4 : kConvChunk;
+        static_for<0, E / kCC>([&](auto C0) {
+            constexpr int c0 = decltype(C0)::value * kCC;
+            Acc128 acc[kCC];
+            for (u32 m = 0; m < tb.n_p; m++) {
+                const u64 h = hat[(size_t)m * tb.n_q];
+#pragma unroll
+                for (int c = 0; c < kCC; c++) acc[c].mac(ys.ld(vo, (m * N + (c0 + c) * T) * 8), h);
+            }
+#pragma unroll
+            for (int c = 0; c < kCC; c++) {
+                const u64 tc = centered_mod(addm(ts.ld(vo, (c0 + c) * T * 8), hl, pl.q), hl, pc);
+                r[c0 + c] = addm(shoup(acc[c].reduce(pc), pc.pinv, pc.pinv_sh, q), tc, q);
+            }
         });
     } else if constexpr (OP == F_RESCALE) {
         const PrimeConst pl = tb.pc[it.a];  // q_l
@@ -418,7 +450,7 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
     NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
 
     // ---- epilogue
-    if constexpr (OP == F_COPY || OP == F_MODUP || OP == F_SAMPLE || OP == F_INT) {
+    if constexpr (OP == F_COPY || OP == F_MODUP || OP == F_SAMPLE || OP == F_INT || OP == F_RELIN) {
 #pragma unroll
         for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
     } else if constexpr (OP == F_RESCALE) {
@@ -432,6 +464,22 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
 #pragma unroll
             for (int c = 0; c < kEpiChunk; c++)
                 dst.st(vo, (c0 + c) * T * 8, shoup(subm(x[c], r[c0 + c], q), qi.x, qi.y, q));
+        }
+    } else if constexpr (OP == F_RELIN_RS) {
+        // y = (acc' P^-1 - z) q_l^-1 with acc' (in[2]) the accumulator limb
+        const ulonglong2 qi = tb.rescale[(size_t)it.a * tb.n_q + it.prime];
+        const Buf accb(it.in[2]), dst(it.out);
+        constexpr int kRC = 4;
+#pragma unroll
+        for (int c0 = 0; c0 < E; c0 += kRC) {
+            u64 x[kRC];
+#pragma unroll
+            for (int c = 0; c < kRC; c++) x[c] = accb.ld(vo, (c0 + c) * T * 8);
+#pragma unroll
+            for (int c = 0; c < kRC; c++) {
+                const u64 u = shoup(x[c], pc.pinv, pc.pinv_sh, q);
+                dst.st(vo, (c0 + c) * T * 8, shoup(subm(u, r[c0 + c], q), qi.x, qi.y, q));
+            }
         }
     } else if constexpr (OP == F_MODDOWN) {
         const Buf in1(it.in[1]), in2(it.in[2] ? it.in[2] : it.in[1]), dst(it.out);
@@ -467,7 +515,7 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
     const u64 q = pc.q;
     u64 r[E];
 
-    if constexpr (OP == I_COPY) {
+    if constexpr (OP == I_COPY || OP == I_SCALE) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
     } else if constexpr (OP == I_MUL) {
@@ -495,6 +543,11 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
 #pragma unroll
             for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
         }
+    } else if constexpr (OP == I_SCALE) {
+        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q
+        const u64 inv = it.b ? pc.pinv : tb.moddown[2 * it.a], inv_sh = it.b ? pc.pinv_sh : tb.moddown[2 * it.a + 1];
+#pragma unroll
+        for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
     }
 #pragma unroll
     for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
@@ -516,18 +569,13 @@ enum EwOp : u32 {
     EW_KEYGEN = 9,     // y0 = -a s + x0 (+ P s' when x2), y1 = a; a sampled uniform
     EW_ENCRYPT = 10,   // y0 = x0 x3 + x1 + x5, y1 = x0 x4 + x2 (v, e0, e1, b, a, m)
     EW_SQUARE_S = 11,  // y0 = x0^2
-    // fused HMult tail, both polys of one limb: with z0, z1 (x0, x1), acc
-    // limbs (x2, x3), a0 a1 b0 b1 (x4..x7): y_c = (acc_c P^-1 + d_c - z_c) q_l^-1,
-    // d_0 = a0 b0, d_1 = a0 b1 + a1 b0, l = v
+    // HMult rescale of limb i < l = v, both polys: y_c = (x_{2+c} P^-1 -
+    // x_c) q_l^-1 with z_c (x0, x1) and the accumulators acc'_c (x2, x3)
     EW_HMULT_FIN = 12,
-    // top limb of the fused HMult, before its INTT: y0 = acc P^-1 + d_v with
-    // acc (x0), a0 a1 b0 b1 (x1..x4), poly v
-    EW_HMULT_U = 13,
-    // per remaining limb i, before its NTT (coefficient domain): with the
-    // special-prime part of acc (x0, n_p limbs) and the INTT'd top limb u (x1):
-    // t = u - conv_l(acc_P) P^-1 mod q_l (relinearised top limb),
-    // y0 = conv_i(acc_P) P^-1 + ((t + h - h) centred) mod q_i, l = v
-    EW_HMULT_Z = 14,
+    // relinearised top limb in the coefficient domain: y0 = u - conv_l(y) P^-1
+    // with u (x0) the INTT'd top limb and y (x1, n_p limbs) the INTT'd
+    // special-prime accumulator times hat_m^-1
+    EW_HMULT_T = 14,
 };
 
 __device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
@@ -593,49 +641,20 @@ __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restri
                 break;
             }
             case EW_SQUARE_S: it.y[0][j] = mulm(it.x[0][j], it.x[0][j], pc); break;
-            case EW_HMULT_U: {
-                const u64 a0 = it.x[1][j], a1 = it.x[2][j], b0 = it.x[3][j], b1 = it.x[4][j];
-                u64 d;
-                if (it.v == 0) {
-                    d = mulm(a0, b0, pc);
-                } else {
-                    Acc128 t;
-                    t.mac(a0, b1);
-                    t.mac(a1, b0);
-                    d = t.reduce(pc);
-                }
-                it.y[0][j] = addm(shoup(it.x[0][j], pc.pinv, pc.pinv_sh, q), d, q);
-                break;
-            }
-            case EW_HMULT_Z: {
-                const u32 l = (u32)it.v;
-                const PrimeConst pl = tb.pc[l];
-                const u64 *md = tb.moddown;
-                Acc128 ai, al;
-                for (u32 m = 0; m < tb.n_p; m++) {
-                    const u64 y = shoup(it.x[0][(size_t)m * N + j], md[2 * m], md[2 * m + 1], tb.pc[tb.n_q + m].q);
-                    ai.mac(y, md[2 * tb.n_p + (size_t)m * tb.n_q + it.prime]);
-                    al.mac(y, md[2 * tb.n_p + (size_t)m * tb.n_q + l]);
-                }
-                const u64 conv_l = shoup(al.reduce(pl), pl.pinv, pl.pinv_sh, pl.q);
-                const u64 t = subm(it.x[1][j], conv_l, pl.q);
-                const u64 hl = pl.q >> 1;
-                const u64 v = centered_mod(addm(t, hl, pl.q), hl, pc);
-                it.y[0][j] = addm(shoup(ai.reduce(pc), pc.pinv, pc.pinv_sh, q), v, q);
-                break;
-            }
             case EW_HMULT_FIN: {
-                const u64 a0 = it.x[4][j], a1 = it.x[5][j], b0 = it.x[6][j], b1 = it.x[7][j];
-                const u64 z0 = it.x[0][j], z1 = it.x[1][j], c0 = it.x[2][j], c1 = it.x[3][j];
                 const ulonglong2 qi = tb.rescale[(size_t)it.v * tb.n_q + it.prime];
-                Acc128 t;
-                t.mac(a0, b1);
-                t.mac(a1, b0);
-                const u64 d0 = mulm(a0, b0, pc), d1 = t.reduce(pc);
-                const u64 u0 = addm(shoup(c0, pc.pinv, pc.pinv_sh, q), d0, q);
-                const u64 u1 = addm(shoup(c1, pc.pinv, pc.pinv_sh, q), d1, q);
-                it.y[0][j] = shoup(subm(u0, z0, q), qi.x, qi.y, q);
-                it.y[1][j] = shoup(subm(u1, z1, q), qi.x, qi.y, q);
+                const u64 u0 = shoup(it.x[2][j], pc.pinv, pc.pinv_sh, q);
+                const u64 u1 = shoup(it.x[3][j], pc.pinv, pc.pinv_sh, q);
+                it.y[0][j] = shoup(subm(u0, it.x[0][j], q), qi.x, qi.y, q);
+                it.y[1][j] = shoup(subm(u1, it.x[1][j], q), qi.x, qi.y, q);
+                break;
+            }
+            case EW_HMULT_T: {
+                // x0: INTT'd top limb u; x1: y = INTT(acc_P) hat_m^-1 (n_p limbs)
+                const u64 *hat = tb.moddown + 2 * tb.n_p + it.prime;
+                Acc128 a;
+                for (u32 m = 0; m < tb.n_p; m++) a.mac(it.x[1][(size_t)m * N + j], hat[(size_t)m * tb.n_q]);
+                it.y[0][j] = subm(it.x[0][j], shoup(a.reduce(pc), pc.pinv, pc.pinv_sh, q), q);
                 break;
             }
         }
@@ -683,6 +702,14 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
 #pragma unroll
         for (int c = 0; c < kIpCts; c++) {
             if ((u32)c >= it.n_ct) break;
+            if (it.own2[c]) {
+                const u64 a0 = it.own2[c][x], b0 = it.own3[c][x], a1 = it.own0[c][x], b1 = it.own1[c][x];
+                Acc128 t;
+                t.mac(a0, b1);
+                t.mac(a1, b0);
+                s0[c].add(shoup(mulm(a0, b0, pc), pc.pmod, pc.pmod_sh, pc.q));
+                s1[c].add(shoup(t.reduce(pc), pc.pmod, pc.pmod_sh, pc.q));
+            }
             it.acc[c][(size_t)it.pos * N + x] = s0[c].reduce(pc);
             it.acc[c][((size_t)it.E + it.pos) * N + x] = s1[c].reduce(pc);
         }
@@ -802,6 +829,8 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
             case F_MODUP: return launch_fwd_t<LN, LE, F_MODUP>(tb, items, n, seed, s);     \
             case F_RESCALE: return launch_fwd_t<LN, LE, F_RESCALE>(tb, items, n, seed, s); \
             case F_MODDOWN: return launch_fwd_t<LN, LE, F_MODDOWN>(tb, items, n, seed, s); \
+            case F_RELIN: return launch_fwd_t<LN, LE, F_RELIN>(tb, items, n, seed, s);     \
+            case F_RELIN_RS: return launch_fwd_t<LN, LE, F_RELIN_RS>(tb, items, n, seed, s); \
             case F_SAMPLE: return launch_fwd_t<LN, LE, F_SAMPLE>(tb, items, n, seed, s);   \
             case F_INT: return launch_fwd_t<LN, LE, F_INT>(tb, items, n, seed, s);         \
         }                                                                            \
@@ -811,6 +840,7 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
         switch (op) {                                                                \
             case I_COPY: return launch_inv_t<LN, LE, I_COPY>(tb, items, n, s);             \
             case I_MUL: return launch_inv_t<LN, LE, I_MUL>(tb, items, n, s);               \
+            case I_SCALE: return launch_inv_t<LN, LE, I_SCALE>(tb, items, n, s);           \
             case I_DECRYPT: return launch_inv_t<LN, LE, I_DECRYPT>(tb, items, n, s);       \
         }                                                                            \
         break;

@@ -102,6 +102,9 @@ def test_tuning_knobs_host():
         nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_EW_LOG, 3)
         nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_XCD_REMAP, 0)
         assert [nat.ckks_ctx_get_tuning(h, k) for k in range(3)] == [1, 3, 0]
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_FUSE_TAIL) == 0
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_FUSE_TAIL, 1)
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_FUSE_TAIL) == 1
         for knob, bad in [(nat.CKKS_TUNE_EW_LOG, 0), (nat.CKKS_TUNE_EW_LOG, 4), (nat.CKKS_TUNE_NTT_WIDE, 2),
                           (nat.CKKS_TUNE_XCD_REMAP, -1), (7, 0)]:
             with pytest.raises(nat.CkksError) as e:

@@ -48,6 +48,27 @@ def limb_bytes(n):
 OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hmult_b256_n32768_hbm_traffic.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_2110_13638_amd", "csrc", f), "rb").read()
+                   for f in ("ckks_kernels.hip", "ckks_internal.h"))
+    text = open(TRAFFIC_FILE).read()
+    if hashlib.sha256(src).hexdigest() not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch %s:" % kernel):
+            return int(line.split(":")[1])
+    return None
+
+
 def kernel_model(name, items, ctx, level):
     """Algorithmic work of one launch of a kernel family in the fused HMult
     pipeline, every item of the launch at ``level``: (HBM bytes, 32-bit
@@ -277,6 +298,7 @@ def main():
                     help="time only the batched HMult step (ragged, plain, NTT and serving legs skipped)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--tune-cache", default=None, help="JSON file that keeps the autotuned launch shapes")
+    ap.add_argument("--tuning", default=None, help='fixed launch shapes as JSON, e.g. \'{"fuse_tail": 1}\' (no search)')
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -323,7 +345,10 @@ def main():
         nat.ckks_hmult_relin_rescale(ctx.h, rk, sa, sb, so, ws, wb, ctx.stream)
 
     tuning = {"setting": ctx.tuning(), "candidates_ms": {}}
-    if not args.no_tune:
+    if args.tuning:
+        ctx.set_tuning(**json.loads(args.tuning))
+        tuning = {"setting": ctx.tuning(), "candidates_ms": {}, "fixed": True}
+    elif not args.no_tune:
         from paper_2110_13638_amd import tune
         best, times = tune.autotune(ctx, step, "hmult-batch-%d" % B, cache=args.tune_cache, reps=3)
         tuning = {"setting": best, "candidates_ms": {k: round(v, 3) for k, v in times.items()}}
@@ -363,8 +388,9 @@ def main():
     alu = {"achieved": round(alg_ops / sec / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s"}
     alu["frac"] = round(alu["achieved"] / alu["peak"], 4)
     bound, prim, other = ("alu", alu, hbm) if alu["frac"] >= hbm["frac"] else ("hbm", hbm, alu)
+    traffic = measured_traffic(dom) if B == 256 else None
     roofline = {"kernel": dom, "bound": bound, "achieved": prim["achieved"], "peak": prim["peak"],
-                "unit": prim["unit"], "frac": prim["frac"], "traffic": None,
+                "unit": prim["unit"], "frac": prim["frac"], "traffic": traffic,
                 "other": dict(other, bound="hbm" if bound == "alu" else "alu"),
                 "alg_bytes_per_launch": alg_bytes, "alg_ops_per_launch": alg_ops, "avg_launch_ms": d["avg_ms"],
                 "launches": d["launches"]}

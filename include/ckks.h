@@ -152,6 +152,34 @@ size_t ckks_pt_bytes(const ckks_ctx *ctx, uint32_t level);
 size_t ckks_key_bytes(const ckks_ctx *ctx, int kind);
 
 /* ------------------------------------------------------------------ */
+/* serialisation (client <-> server transfer, Section 4: ciphertexts are */
+/* encrypted by the client, evaluated by the server, sent back)          */
+/* ------------------------------------------------------------------ */
+/* Byte format: a 64-byte little-endian header (magic "CKKS", version 1,
+ * object kind, log2 N, n_q, n_p, dnum, n_poly, level, key kind, scale as
+ * an IEEE double, FNV-1a hash of the prime chain, payload bytes) followed
+ * by the residues as u64 [n_poly][level+1][N] (the limb stride of a device
+ * ciphertext is not kept). Objects: a ciphertext (obj = ckks_ct *), a
+ * plaintext (ckks_pt *), or a key (obj = device pointer to the key, kind
+ * given by key_kind; n_poly / level are implied by the kind).
+ * ckks_serialize: with host_bytes == NULL stores the size in *n and returns;
+ * otherwise copies device -> host on `stream` and waits for it; ENOMEM if
+ * *n is smaller than the size (the size is stored in *n).
+ * ckks_deserialize: checks the header against ctx (ring, chain hash, dnum:
+ * EPARAMS on mismatch; EINVAL for a bad magic, kind or length), copies the
+ * residues host -> device into the object's buffer (a ct / pt needs data
+ * with room for the stored level: limb_stride >= level + 1, which is
+ * checked; level, n_poly and scale are set from the header) and waits. Not
+ * allowed while recording (EINVAL). */
+#define CKKS_OBJ_CT 0
+#define CKKS_OBJ_PT 1
+#define CKKS_OBJ_KEY 2
+int ckks_serialize(const ckks_ctx *ctx, int obj_kind, const void *obj, int key_kind, void *host_bytes, size_t *n,
+                   void *stream);
+int ckks_deserialize(const ckks_ctx *ctx, int obj_kind, const void *host_bytes, size_t n, void *obj, int key_kind,
+                     void *stream);
+
+/* ------------------------------------------------------------------ */
 /* workspace                                                            */
 /* ------------------------------------------------------------------ */
 #define CKKS_OP_NTT 0        /* count = number of limbs                  */
@@ -314,6 +342,14 @@ int ckks_linear_csr(const ckks_ctx *ctx, const ckks_ct *in, uint32_t n_in, uint3
  *               steps without their own Galois key are composed from
  *               power-of-two keys in non-adjacent form (ckks_diag_attrs);
  *   SQUARE      x^2: ckks_hmult_relin_rescale(x, x) on each ciphertext;
+ *   POLY        polynomial activation p(x) = sum_k c_k x^k of degree
+ *               d >= 1 (Section 4.4: the ReLU approximation
+ *               4/(3 pi q) x^2 + x/2 + q/(3 pi), the sigmoid approximation
+ *               0.5 + 0.197 x - 0.004 x^3) by Horner's rule on each
+ *               ciphertext: h = rescale(x * round(c_d w_scale)); for k =
+ *               d-1..1: h += round(c_k scale_h), h = x' (x) h relinearised
+ *               and rescaled with x' = x switched down to h's level; then
+ *               h += round(c_0 scale_h). Uses d levels (ckks_poly_attrs);
  *   OUTPUT      collects its signal as run outputs (node order). */
 typedef struct ckks_graph ckks_graph;
 #define CKKS_NODE_INPUT 0
@@ -321,6 +357,7 @@ typedef struct ckks_graph ckks_graph;
 #define CKKS_NODE_DIAG_DENSE 2
 #define CKKS_NODE_SQUARE 3
 #define CKKS_NODE_OUTPUT 4
+#define CKKS_NODE_POLY 5
 typedef struct {
     uint32_t n_ct;
     uint32_t level;
@@ -345,6 +382,11 @@ typedef struct {
     uint32_t n_bias_slots;
     const int64_t *bias_coeffs;  /* [N] integer plaintext at the output scale, or NULL */
 } ckks_diag_attrs;
+typedef struct {
+    uint32_t degree;      /* d >= 1 */
+    const double *coeffs; /* [d + 1], c_0 first */
+    double w_scale;       /* scale of the constant in the first product */
+} ckks_poly_attrs;
 int ckks_graph_create(const ckks_ctx *ctx, ckks_graph **out);
 void ckks_graph_destroy(ckks_graph *g);
 /* attributes are copied */
@@ -370,6 +412,37 @@ int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_inputs, ckks
  * source reaches) and each group's cost, ready for ckks_parameterise. */
 int ckks_graph_autohe(ckks_graph *g, uint32_t *n_groups, uint32_t *group_of_node, uint32_t *group_cost,
                       uint32_t cap);
+
+/* ------------------------------------------------------------------ */
+/* launch recording (HIP graph capture)                                 */
+/* ------------------------------------------------------------------ */
+/* Between ckks_record_begin and ckks_record_end, every device call made
+ * with ctx still runs as usual, and in addition its kernel launches are
+ * recorded. The launch data such calls upload (work descriptors, pointer
+ * tables, weight images) goes to the caller's `arena` (device memory,
+ * 256-byte aligned) instead of the workspace, so that it outlives the call.
+ * ckks_plan_launch re-issues exactly the recorded launches on a stream,
+ * with no copy, allocation, memset or host synchronisation, so it can be
+ * captured into a HIP graph (stream capture) and replayed: a layer
+ * sequence or a batched HMult becomes one graph launch. Every buffer the
+ * recorded calls touched (inputs, outputs, keys, workspaces, arena, context
+ * tables) must stay allocated at the same address while the plan is used;
+ * their contents may change between replays (new inputs in the same
+ * buffers give the new results). Host-side results of the recorded calls
+ * (output levels and scales) are those of the recording run. Launch shapes
+ * (ckks_ctx_set_tuning) are frozen at recording time.
+ * ckks_record_begin: EINVAL when already recording or misaligned; a call
+ * made while recording fails with ENOMEM if the arena runs out (recording
+ * continues; end it and start again with a larger arena).
+ * ckks_record_end: returns the plan (owned by the caller, released with
+ * ckks_plan_destroy) and the arena bytes used. Not thread safe against
+ * other calls on the same context. */
+typedef struct ckks_plan ckks_plan;
+int ckks_record_begin(ckks_ctx *ctx, void *arena, size_t arena_bytes);
+int ckks_record_end(ckks_ctx *ctx, ckks_plan **plan, size_t *arena_used);
+int ckks_plan_launch(const ckks_plan *plan, void *stream);
+uint32_t ckks_plan_launch_count(const ckks_plan *plan);
+void ckks_plan_destroy(ckks_plan *plan);
 
 /* ------------------------------------------------------------------ */
 /* tuning                                                               */

@@ -16,6 +16,11 @@ bit:
       acc = sum_i diag_i (x) rot(x, in_steps[i]) ; acc = rescale(acc) ;
       for r in post_steps: acc = acc + rot(acc, r) ; acc = acc + bias_pt
   square activation: rescale(relinearise(x (x) x))
+  polynomial activation p(x) = c0 + c1 x + ... + cd x^d (Horner's rule,
+  constants round(c * 2^40) for the product, round(c * scale) for sums):
+      h = rescale(x * c_d) ; for k = d-1 .. 1: h = h + c_k ;
+      h = rescale(relinearise(x' (x) h)) with x' = x switched down to h's
+      level ; h = h + c_0
 
 Rotations by a step that has its own Galois key use it directly;
 otherwise the step is composed from power-of-two keys in non-adjacent form,
@@ -101,6 +106,28 @@ def linear(orc, cts, scale, rows, w_scale, biases):
 
 def square(orc, keys, ct, scale):
     return orc.mul_relin_rescale(ct, ct, keys.rk), scale * scale / orc.q[ct.shape[1] - 1]
+
+
+def _round(v):
+    return int(np.sign(v) * np.floor(abs(v) + 0.5))
+
+
+def poly(orc, keys, ct, scale, coeffs, w_scale):
+    """Polynomial activation of degree d = len(coeffs) - 1 >= 1 (Section
+    4.4's approximations of ReLU and sigmoid). Returns (ct, scale); uses d
+    levels."""
+    d = len(coeffs) - 1
+    level = ct.shape[1] - 1
+    h = orc.rescale(orc.mul_const(ct, _round(coeffs[d] * w_scale)))
+    hs = scale * w_scale / orc.q[level]
+    for k in range(d - 1, 0, -1):
+        h = orc.add_const(h, _round(coeffs[k] * hs))
+        lv = h.shape[1] - 1
+        xs = orc.mod_switch(ct, lv)
+        h = orc.mul_relin_rescale(xs, h, keys.rk)
+        hs = scale * hs / orc.q[lv]
+    h = orc.add_const(h, _round(coeffs[0] * hs))
+    return h, hs
 
 
 def diag_dense(orc, keys, ct, scale, diag_pts, pt_scale, in_steps, post_steps, bias_pt=None):

@@ -212,3 +212,23 @@ def yield_packed(x, ws, bs, slots):
             y = z ** 2 if layer < 2 else z
         outs.append(y[:W])
     return np.concatenate(outs)[: x.shape[0]]
+
+
+# ---------------------------------------------------------------------------
+# polynomial activations (Section 4.4 and the appendix equations)
+# ---------------------------------------------------------------------------
+def relu_approx_coeffs(q):
+    """R_a(x) = 4/(3 pi q) x^2 + x/2 + q/(3 pi): coefficients c0, c1, c2 for
+    the approximation range q."""
+    return [q / (3.0 * np.pi), 0.5, 4.0 / (3.0 * np.pi * q)]
+
+
+def sigmoid_approx_coeffs():
+    """sigma_a(x) = 0.5 + 0.197 x - 0.004 x^3: coefficients c0..c3."""
+    return [0.5, 0.197, 0.0, -0.004]
+
+
+def poly_eval(coeffs, x):
+    """sum_k c_k x^k, term by term (no Horner), in FP64."""
+    x = np.asarray(x, dtype=np.float64)
+    return sum(c * x ** k for k, c in enumerate(coeffs))

@@ -19,6 +19,7 @@ ERROR_NAMES = {-1: "EINVAL", -2: "ELEVEL", -3: "ESCALE", -4: "EDEPTH", -5: "ENOK
 CKKS_KEY_SECRET, CKKS_KEY_PUBLIC, CKKS_KEY_SWITCH = 0, 1, 2
 (CKKS_OP_NTT, CKKS_OP_ELEMENTWISE, CKKS_OP_KEYSWITCH, CKKS_OP_RESCALE, CKKS_OP_HMULT, CKKS_OP_KEYGEN,
  CKKS_OP_ENCRYPT, CKKS_OP_LINEAR) = range(8)
+CKKS_OBJ_CT, CKKS_OBJ_PT, CKKS_OBJ_KEY = 0, 1, 2
 CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP, CKKS_TUNE_FUSE_TAIL = 0, 1, 2, 3
 
 
@@ -65,7 +66,12 @@ class ckks_diag_attrs(ctypes.Structure):
                 ("bias_coeffs", ctypes.POINTER(ctypes.c_int64))]
 
 
-CKKS_NODE_INPUT, CKKS_NODE_LINEAR, CKKS_NODE_DIAG_DENSE, CKKS_NODE_SQUARE, CKKS_NODE_OUTPUT = range(5)
+CKKS_NODE_INPUT, CKKS_NODE_LINEAR, CKKS_NODE_DIAG_DENSE, CKKS_NODE_SQUARE, CKKS_NODE_OUTPUT, CKKS_NODE_POLY = range(6)
+
+
+class ckks_poly_attrs(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_uint32), ("coeffs", ctypes.POINTER(ctypes.c_double)),
+                ("w_scale", ctypes.c_double)]
 
 _u32, _u64, _i32, _sz, _vp, _dbl = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_size_t,
                                     ctypes.c_void_p, ctypes.c_double)
@@ -124,6 +130,13 @@ _SIGS = {
     "ckks_graph_run": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _P(ckks_ct), _u32, _vp, _P(_u32), _P(_vp), _u32,
                                       _vp, _sz, _vp]),
     "ckks_graph_autohe": (ctypes.c_int, [_vp, _P(_u32), _P(_u32), _P(_u32), _u32]),
+    "ckks_serialize": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, _P(_sz), _vp]),
+    "ckks_deserialize": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _sz, _vp, ctypes.c_int, _vp]),
+    "ckks_record_begin": (ctypes.c_int, [_vp, _vp, _sz]),
+    "ckks_record_end": (ctypes.c_int, [_vp, _P(_vp), _P(_sz)]),
+    "ckks_plan_launch": (ctypes.c_int, [_vp, _vp]),
+    "ckks_plan_launch_count": (_u32, [_vp]),
+    "ckks_plan_destroy": (None, [_vp]),
     "ckks_ctx_set_tuning": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "ckks_ctx_get_tuning": (ctypes.c_int, [_vp, ctypes.c_int]),
     "ckks_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -346,6 +359,45 @@ def ckks_linear_csr(h, inp, n_out, row_ptr, col, w, w_scale, out, ws, ws_bytes, 
     """row_ptr/col: uint32 numpy arrays, w: int64 numpy array (host)"""
     _call("ckks_linear_csr", h, inp, len(inp), n_out, row_ptr.ctypes.data_as(_P(_u32)),
           col.ctypes.data_as(_P(_u32)), w.ctypes.data_as(_P(ctypes.c_int64)), w_scale, out, ws, ws_bytes, stream)
+
+
+def ckks_serialize(h, obj_kind, obj, key_kind=0, stream=None):
+    """bytes of a ciphertext / plaintext (ctypes struct, passed by reference)
+    or key (device pointer)"""
+    ref = ctypes.byref(obj) if obj_kind != CKKS_OBJ_KEY else obj
+    n = _sz()
+    _call("ckks_serialize", h, obj_kind, ref, key_kind, None, ctypes.byref(n), stream)
+    buf = ctypes.create_string_buffer(n.value)
+    _call("ckks_serialize", h, obj_kind, ref, key_kind, buf, ctypes.byref(n), stream)
+    return buf.raw[: n.value]
+
+
+def ckks_deserialize(h, obj_kind, data, obj, key_kind=0, stream=None):
+    ref = ctypes.byref(obj) if obj_kind != CKKS_OBJ_KEY else obj
+    _call("ckks_deserialize", h, obj_kind, data, len(data), ref, key_kind, stream)
+    return obj
+
+
+def ckks_record_begin(h, arena, arena_bytes):
+    _call("ckks_record_begin", h, arena, arena_bytes)
+
+
+def ckks_record_end(h):
+    plan, used = _vp(), _sz()
+    _call("ckks_record_end", h, ctypes.byref(plan), ctypes.byref(used))
+    return plan, used.value
+
+
+def ckks_plan_launch(plan, stream=None):
+    _call("ckks_plan_launch", plan, stream)
+
+
+def ckks_plan_launch_count(plan):
+    return lib().ckks_plan_launch_count(plan)
+
+
+def ckks_plan_destroy(plan):
+    lib().ckks_plan_destroy(plan)
 
 
 def ckks_ctx_set_tuning(h, knob, value):

@@ -80,6 +80,51 @@ class Ciphertext:
         return self.ctx.rescale(self.ctx.multiply_scalar(self, float(other)))
 
 
+class Plan:
+    """Recorded kernel launches of a sequence of calls on one context.
+
+    ``launch()`` re-issues them on the current stream (no copies, no
+    allocation), so it may run inside ``torch.cuda.graph`` capture. The
+    buffers the recorded calls used must stay alive: the plan keeps the
+    arena, and the caller keeps inputs, outputs and the context."""
+
+    def __init__(self, ctx, handle, arena, used):
+        self.ctx, self.h, self.arena, self.arena_used = ctx, handle, arena, used
+        self.workspace = ctx._ws  # the recorded launches address this buffer
+
+    @property
+    def n_launches(self):
+        return nat.ckks_plan_launch_count(self.h)
+
+    def launch(self):
+        nat.ckks_plan_launch(self.h, self.ctx.stream)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            nat.ckks_plan_destroy(h)
+            self.h = None
+
+
+class _Recording:
+    def __init__(self, ctx, arena_bytes):
+        self.ctx, self.arena_bytes, self.plan = ctx, arena_bytes, None
+
+    def __enter__(self):
+        self.arena = torch.empty(self.arena_bytes + 256, dtype=torch.uint8, device=self.ctx.device)
+        self.ctx._recording = True
+        nat.ckks_record_begin(self.ctx.h, _align(self.arena.data_ptr()), self.arena_bytes)
+        return self
+
+    def __exit__(self, *exc):
+        self.ctx._recording = False
+        h, used = nat.ckks_record_end(self.ctx.h)
+        self.plan = Plan(self.ctx, h, self.arena, used)
+        if exc[0] is not None:
+            self.plan = None
+        return False
+
+
 class Context:
     """Parameters, device tables, keys and a reusable workspace."""
 
@@ -94,6 +139,7 @@ class Context:
         self._tables = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         nat.ckks_ctx_upload(self.h, _align(self._tables.data_ptr()), self.stream)
         self._ws = None
+        self._recording = False
         self.sk = self.pk = self.rk = None
         self.gk = {}
 
@@ -135,9 +181,30 @@ class Context:
             nat.ckks_ctx_set_tuning(self.h, self.TUNING_KNOBS[k], int(v))
         return self
 
+    # --- serialisation (client <-> server transfer) ---------------------------
+    def serialize(self, ct):
+        return nat.ckks_serialize(self.h, nat.CKKS_OBJ_CT, ct.struct(), 0, self.stream)
+
+    def deserialize(self, data, level=None):
+        """a new ciphertext from bytes (room for ``level``, default the stored one)"""
+        import struct as _st
+        n_poly, lv = _st.unpack_from("<II", data, 28)
+        out = self.new_ct(n_poly, lv if level is None else level)
+        s = out.struct()
+        nat.ckks_deserialize(self.h, nat.CKKS_OBJ_CT, data, s, 0, self.stream)
+        return out.update(s)
+
+    def record(self, arena_bytes=64 << 20):
+        """``with ctx.record() as r: ...`` records the calls made in the
+        block; ``r.plan`` replays their launches. The workspace must not be
+        reallocated while recording (size it first with ``workspace``)."""
+        return _Recording(self, arena_bytes)
+
     def workspace(self, nbytes):
         nbytes = max(int(nbytes), 1 << 20)
         if self._ws is None or self._ws.numel() < nbytes + 256:
+            if self._recording and self._ws is not None:
+                raise RuntimeError("workspace would move while recording: size it with ctx.workspace() first")
             self._ws = None
             self._ws = torch.empty(int(nbytes * 1.25) + 256, dtype=torch.uint8, device=self.device)
         return ctypes.c_void_p(_align(self._ws.data_ptr())), self._ws.numel() - 256

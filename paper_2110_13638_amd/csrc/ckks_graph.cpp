@@ -24,6 +24,7 @@
 
 namespace ckks {
 int set_error(int code, const char *msg);
+int ctx_upload_bytes(const ckks_ctx *c, void *dst, const void *src, size_t bytes, void *stream, void **where);
 }
 
 namespace {
@@ -68,6 +69,8 @@ struct Node {
     double pt_scale = 1.0;
     std::vector<double> bias_slots;
     std::vector<i64> bias_coeffs;  // [N], at the output scale
+    // polynomial activation
+    std::vector<double> coeffs;  // c_0 .. c_d
     // wiring
     std::vector<u32> in_edges, out_edges;
     // plan
@@ -230,6 +233,64 @@ int fire_square(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
                                     scratch_avail(g), g->stream);
 }
 
+// p(x) by Horner's rule: h = rescale(x c_d); h = rescale(relin(x' (x) (h + c_k)))
+// for k = d-1..1 with x' switched down to h's level; h += c_0
+int fire_poly(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
+    GK(match_levels(in));
+    const u32 B = (u32)in.size(), l = in[0].level, d = (u32)n.coeffs.size() - 1;
+    if (l < d) return gfail(CKKS_EDEPTH, "graph: not enough levels for the polynomial activation");
+    const size_t cb = ct_bytes(g, l);
+    std::vector<ckks_ct> h = make_cts(g, n.out_off, B, l, l + 1, 1.0);
+    std::vector<ckks_ct> t = make_cts(g, n.out_off + al(B * cb), B, l, l + 1, 1.0);
+    const double s_x = in[0].scale;
+    n.out_count = B;
+    std::vector<u32> lv(B, l);
+    need(g, ckks_workspace_bytes(g->c, CKKS_OP_HMULT, B, lv.data()));
+    need(g, ckks_workspace_bytes(g->c, CKKS_OP_RESCALE, B, nullptr));
+    need(g, ckks_workspace_bytes(g->c, CKKS_OP_ELEMENTWISE, B, nullptr));
+    // h = rescale(x * c_d)
+    double hs = s_x * n.w_scale;
+    if (!g->dry) {
+        std::vector<i64> v(B, round_half_away(n.coeffs[d] * n.w_scale));
+        std::vector<double> vs(B, n.w_scale);
+        GK(ckks_multiply_scalar(g->c, in.data(), v.data(), vs.data(), h.data(), B, scratch(g), scratch_avail(g),
+                                g->stream));
+        GK(ckks_rescale(g->c, h.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
+    }
+    hs /= (double)ckks_ctx_prime(g->c, l);
+    u32 hl = l - 1;
+    auto set = [&](std::vector<ckks_ct> &v, u32 level, double scale) {
+        for (auto &x : v) x.level = level, x.scale = scale;
+    };
+    set(h, hl, hs);
+    for (u32 k = d - 1; k >= 1; k--) {
+        if (!g->dry) {
+            std::vector<i64> v(B, round_half_away(n.coeffs[k] * hs));
+            GK(ckks_add_scalar(g->c, h.data(), v.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
+        }
+        std::vector<ckks_ct> xs = in;
+        for (auto &x : xs) x.level = hl;  // switch down: a view
+        const double ps = s_x * hs;
+        if (!g->dry)
+            GK(ckks_hmult_relin_rescale(g->c, g->rk, xs.data(), h.data(), t.data(), B, scratch(g), scratch_avail(g),
+                                        g->stream));
+        hs = ps / (double)ckks_ctx_prime(g->c, hl);
+        hl -= 1;
+        std::swap(h, t);
+        set(h, hl, hs);
+        set(t, hl, hs);
+    }
+    if (!g->dry) {
+        std::vector<i64> v(B, round_half_away(n.coeffs[0] * hs));
+        GK(ckks_add_scalar(g->c, h.data(), v.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
+    }
+    n.out_level = hl;
+    n.out_scale = hs;
+    n.in_lvl_used = l;
+    n.out = h;
+    return CKKS_OK;
+}
+
 // acc = sum_i diag_i (x) rot(x, in_steps[i]); rescale; acc += rot(acc, r)
 // for r in post_steps; acc += bias
 int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
@@ -255,11 +316,9 @@ int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
     if (!g->dry) {
         // plaintexts: integer coefficients -> NTT form at level l (diagonals)
         for (u32 i = 0; i < nd; i++) {
-            u64 *coef = (u64 *)scratch(g);
+            void *coef = nullptr;
             u64 *pt = (u64 *)(g->ws + n.pt_off + (size_t)i * L * limb);
-            if (hipMemcpyAsync(coef, n.diag.data() + (size_t)i * g->N, limb, hipMemcpyHostToDevice,
-                               (hipStream_t)g->stream) != hipSuccess)
-                return gfail(CKKS_EDEVICE, "graph: plaintext upload failed");
+            GK(ckks::ctx_upload_bytes(g->c, scratch(g), n.diag.data() + (size_t)i * g->N, limb, g->stream, &coef));
             ckks_pt p{pt, l, 0, n.pt_scale};
             GK(ckks_pt_load(g->c, (const int64_t *)coef, &p, scratch(g) + al(limb), scratch_avail(g) - al(limb),
                             g->stream));
@@ -296,11 +355,9 @@ int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
         GK(ckks_encode(g->c, n.bias_slots.data(), nullptr, n.bias_slots.size(), n.out_scale, n.bias_coeffs.data()));
     }
     if (has_bias && !g->dry) {
-        u64 *coef = (u64 *)scratch(g);
+        void *coef = nullptr;
         u64 *pt = (u64 *)(g->ws + n.pt_off + (size_t)nd * L * limb);
-        if (hipMemcpyAsync(coef, n.bias_coeffs.data(), limb, hipMemcpyHostToDevice, (hipStream_t)g->stream) !=
-            hipSuccess)
-            return gfail(CKKS_EDEVICE, "graph: plaintext upload failed");
+        GK(ckks::ctx_upload_bytes(g->c, scratch(g), n.bias_coeffs.data(), limb, g->stream, &coef));
         ckks_pt p{pt, l - 1, 0, n.out_scale};
         GK(ckks_pt_load(g->c, (const int64_t *)coef, &p, scratch(g) + al(limb), scratch_avail(g) - al(limb),
                         g->stream));
@@ -315,6 +372,7 @@ size_t node_region(ckks_graph *g, const Node &n, u32 in_count, u32 in_level) {
     switch (n.kind) {
         case CKKS_NODE_LINEAR: return al((size_t)n.n_out * ct_bytes(g, in_level));
         case CKKS_NODE_SQUARE: return al((size_t)in_count * ct_bytes(g, in_level ? in_level - 1 : 0));
+        case CKKS_NODE_POLY: return 2 * al((size_t)in_count * ct_bytes(g, in_level));
         case CKKS_NODE_DIAG_DENSE:
             return 4 * al((size_t)in_count * ct_bytes(g, in_level)) +
                    al(((size_t)n.in_steps.size() + 1) * (in_level + 1) * g->N * 8);
@@ -360,6 +418,7 @@ int apply_signal(ckks_graph *g, u32 id, std::vector<ckks_ct> &s) {
         case CKKS_NODE_LINEAR: rc = fire_linear(g, n, s); break;
         case CKKS_NODE_SQUARE: rc = fire_square(g, n, s); break;
         case CKKS_NODE_DIAG_DENSE: rc = fire_diag(g, n, s); break;
+        case CKKS_NODE_POLY: rc = fire_poly(g, n, s); break;
         default: rc = gfail(CKKS_EINVAL, "graph: unknown node kind");
     }
     if (rc != CKKS_OK) return rc;
@@ -451,6 +510,13 @@ extern "C" int ckks_graph_add_node(ckks_graph *g, int kind, const void *attrs, u
             if (a->n_post) n.post_steps.assign(a->post_steps, a->post_steps + a->n_post);
             if (a->bias_coeffs) n.bias_coeffs.assign(a->bias_coeffs, a->bias_coeffs + g->N);
             else if (a->bias_slots) n.bias_slots.assign(a->bias_slots, a->bias_slots + a->n_bias_slots);
+            break;
+        }
+        case CKKS_NODE_POLY: {
+            const ckks_poly_attrs *a = (const ckks_poly_attrs *)attrs;
+            if (!a || a->degree < 1 || !a->coeffs || !(a->w_scale > 0)) return gfail(CKKS_EINVAL, "graph: poly attrs");
+            n.coeffs.assign(a->coeffs, a->coeffs + a->degree + 1);
+            n.w_scale = a->w_scale;
             break;
         }
         case CKKS_NODE_SQUARE:

@@ -16,6 +16,7 @@
 #include <complex>
 #include <type_traits>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/ckks.h"
@@ -187,8 +188,19 @@ using namespace ckks;
 // ---------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------
+// Launch recording (see ckks_record_begin): the arena receives every
+// host-to-device upload of launch data made while recording, and each
+// kernel launch is kept as a closure over its (device-resident) arguments.
+typedef std::function<hipError_t(hipStream_t)> LaunchFn;
+struct Recorder {
+    uint8_t *arena = nullptr;
+    size_t cap = 0, used = 0;
+    std::vector<LaunchFn> launches;
+};
+
 struct ckks_ctx {
     u32 log_n, N, n_q, n_p, n_prim, dnum, alpha, digits_top;
+    Recorder *rec = nullptr;  // non-null while recording
     std::vector<u64> primes;
     std::vector<u64> image;  // device table image (u64 words)
     size_t off_pc, off_tw, off_itw, off_modup, off_moddown, off_rescale;
@@ -672,6 +684,30 @@ struct Launch {
     int n;
     u64 seed;
 };
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Host-to-device copy of launch data (descriptors, pointer tables, weight
+// images). While recording, the bytes go to the recording arena, where they
+// stay for replays, and *where receives that address instead of dst.
+int upload(const ckks_ctx *c, uint8_t *dst, const void *src, size_t bytes, hipStream_t s, uint8_t **where) {
+    if (c->rec) {
+        Recorder &r = *c->rec;
+        const size_t off = al256(r.used);
+        if (off + bytes > r.cap) return fail(CKKS_ENOMEM, "record: arena of %zu bytes is too small", r.cap);
+        dst = r.arena + off;
+        r.used = off + bytes;
+    }
+    if (bytes) HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    *where = dst;
+    return CKKS_OK;
+}
+// Run a launch now and, while recording, keep it for replays.
+hipError_t issue(const ckks_ctx *c, hipStream_t s, LaunchFn f) {
+    const hipError_t e = f(s);
+    if (e == hipSuccess && c->rec) c->rec->launches.push_back(std::move(f));
+    return e;
+}
+
 struct Plan {
     const ckks_ctx *c;
     uint8_t *ws;          // device base (may be null when sizing)
@@ -701,9 +737,11 @@ struct Plan {
         if (!ws && total()) return fail(CKKS_EINVAL, "null workspace");
         if (((uintptr_t)ws) & 255) return fail(CKKS_EINVAL, "workspace not 256-byte aligned");
         const size_t doff = (scratch + 255) & ~(size_t)255;
-        if (!desc.empty()) HIP_TRY(hipMemcpyAsync(ws + doff, desc.data(), desc.size(), hipMemcpyHostToDevice, s));
+        uint8_t *dbase = ws + doff;
+        const int urc = upload(c, ws + doff, desc.data(), desc.size(), s, &dbase);
+        if (urc != CKKS_OK) return urc;
         for (const Launch &L : launches) {
-            const uint8_t *p = ws + doff + L.off;
+            const uint8_t *p = dbase + L.off;
             hipError_t e = hipSuccess;
             ProfRec rec;
             if (g_prof_on) {
@@ -713,12 +751,15 @@ struct Plan {
                 HIP_TRY(hipEventCreate(&rec.e1));
                 HIP_TRY(hipEventRecord(rec.e0, s));
             }
-            switch (L.kind) {
-                case 0: e = launch_fwd(c->tb, L.op, (const Item *)p, L.n, L.seed, s); break;
-                case 1: e = launch_inv(c->tb, L.op, (const Item *)p, L.n, s); break;
-                case 2: e = launch_ew(c->tb, (const EwItem *)p, L.n, L.seed, s); break;
-                case 3: e = launch_ip(c->tb, (const IpItem *)p, L.n, s); break;
-            }
+            e = issue(c, s, [tb = c->tb, L, p](hipStream_t st) {
+                switch (L.kind) {
+                    case 0: return launch_fwd(tb, L.op, (const Item *)p, L.n, L.seed, st);
+                    case 1: return launch_inv(tb, L.op, (const Item *)p, L.n, st);
+                    case 2: return launch_ew(tb, (const EwItem *)p, L.n, L.seed, st);
+                    case 3: return launch_ip(tb, (const IpItem *)p, L.n, st);
+                }
+                return hipErrorInvalidValue;
+            });
             if (e != hipSuccess) return fail(CKKS_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
             if (g_prof_on) {
                 HIP_TRY(hipEventRecord(rec.e1, s));
@@ -884,6 +925,213 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
     P.add(0, F_MODDOWN, mdown);
 }
 }  // namespace
+
+struct ckks_plan {
+    const ckks_ctx *c;
+    std::vector<LaunchFn> launches;
+};
+
+extern "C" int ckks_record_begin(ckks_ctx *c, void *arena, size_t arena_bytes) {
+    if (!c || (!arena && arena_bytes)) return fail(CKKS_EINVAL, "record_begin: null argument");
+    if (((uintptr_t)arena) & 255) return fail(CKKS_EINVAL, "record_begin: arena not 256-byte aligned");
+    if (c->rec) return fail(CKKS_EINVAL, "record_begin: already recording");
+    c->rec = new Recorder();
+    c->rec->arena = (uint8_t *)arena;
+    c->rec->cap = arena_bytes;
+    return CKKS_OK;
+}
+extern "C" int ckks_record_end(ckks_ctx *c, ckks_plan **plan, size_t *arena_used) {
+    if (!c || !plan) return fail(CKKS_EINVAL, "record_end: null argument");
+    if (!c->rec) return fail(CKKS_EINVAL, "record_end: not recording");
+    ckks_plan *p = new ckks_plan();
+    p->c = c;
+    p->launches = std::move(c->rec->launches);
+    if (arena_used) *arena_used = c->rec->used;
+    delete c->rec;
+    c->rec = nullptr;
+    *plan = p;
+    return CKKS_OK;
+}
+extern "C" int ckks_plan_launch(const ckks_plan *p, void *stream) {
+    if (!p) return fail(CKKS_EINVAL, "plan_launch: null plan");
+    for (const LaunchFn &f : p->launches) {
+        const hipError_t e = f((hipStream_t)stream);
+        if (e != hipSuccess) return fail(CKKS_EDEVICE, "plan_launch: %s", hipGetErrorString(e));
+    }
+    return CKKS_OK;
+}
+extern "C" uint32_t ckks_plan_launch_count(const ckks_plan *p) { return p ? (uint32_t)p->launches.size() : 0; }
+extern "C" void ckks_plan_destroy(ckks_plan *p) { delete p; }
+
+namespace ckks {
+// upload for the graph runtime (same recording rules as the entry points)
+int ctx_upload_bytes(const ckks_ctx *c, void *dst, const void *src, size_t bytes, void *stream, void **where) {
+    uint8_t *w = nullptr;
+    CK(upload(c, (uint8_t *)dst, src, bytes, (hipStream_t)stream, &w));
+    *where = w;
+    return CKKS_OK;
+}
+}  // namespace ckks
+
+// ---------------------------------------------------------------------
+// serialisation
+// ---------------------------------------------------------------------
+namespace {
+struct SerHeader {
+    uint32_t magic, version, kind, log_n, n_q, n_p, dnum, n_poly, level, key_kind;
+    double scale;
+    uint64_t chain, payload;
+};
+static_assert(sizeof(SerHeader) == 64, "serial header is 64 bytes");
+constexpr uint32_t kSerMagic = 0x534B4B43u;  // "CKKS"
+
+uint64_t chain_hash(const ckks_ctx *c) {
+    uint64_t h = 1469598103934665603ull;
+    for (u64 q : c->primes)
+        for (int b = 0; b < 8; b++) h = (h ^ ((q >> (8 * b)) & 0xFF)) * 1099511628211ull;
+    return h;
+}
+// shape of a serialisable object: base pointer, polys, limbs per poly, limb stride
+int ser_shape(const ckks_ctx *c, int obj_kind, const void *obj, int key_kind, SerHeader &h, u64 **base,
+              u32 *stride) {
+    memset(&h, 0, sizeof h);
+    h.magic = kSerMagic;
+    h.version = 1;
+    h.kind = (u32)obj_kind;
+    h.log_n = c->log_n;
+    h.n_q = c->n_q;
+    h.n_p = c->n_p;
+    h.dnum = c->dnum;
+    h.chain = chain_hash(c);
+    h.key_kind = (u32)key_kind;
+    if (!obj) return fail(CKKS_EINVAL, "serialize: null object");
+    switch (obj_kind) {
+        case CKKS_OBJ_CT: {
+            const ckks_ct *x = (const ckks_ct *)obj;
+            CK(check_ct(c, *x, "serialize"));
+            h.n_poly = x->n_poly;
+            h.level = x->level;
+            h.scale = x->scale;
+            *base = x->data;
+            *stride = x->limb_stride;
+            break;
+        }
+        case CKKS_OBJ_PT: {
+            const ckks_pt *x = (const ckks_pt *)obj;
+            if (!x->data || x->level >= c->n_q) return fail(CKKS_EINVAL, "serialize: bad plaintext");
+            h.n_poly = 1;
+            h.level = x->level;
+            h.scale = x->scale;
+            *base = x->data;
+            *stride = x->level + 1;
+            break;
+        }
+        case CKKS_OBJ_KEY: {
+            *base = (u64 *)obj;
+            switch (key_kind) {
+                case CKKS_KEY_SECRET: h.n_poly = 1, h.level = c->n_prim - 1; break;
+                case CKKS_KEY_PUBLIC: h.n_poly = 2, h.level = c->n_q - 1; break;
+                case CKKS_KEY_SWITCH: h.n_poly = 2 * c->digits_top, h.level = c->n_prim - 1; break;
+                default: return fail(CKKS_EINVAL, "serialize: unknown key kind %d", key_kind);
+            }
+            *stride = h.level + 1;
+            break;
+        }
+        default: return fail(CKKS_EINVAL, "serialize: unknown object kind %d", obj_kind);
+    }
+    h.payload = (u64)h.n_poly * (h.level + 1) * c->N * 8;
+    return CKKS_OK;
+}
+}  // namespace
+
+extern "C" int ckks_serialize(const ckks_ctx *c, int obj_kind, const void *obj, int key_kind, void *host_bytes,
+                              size_t *n, void *stream) {
+    if (!c || !n) return fail(CKKS_EINVAL, "serialize: null argument");
+    SerHeader h;
+    u64 *base = nullptr;
+    u32 stride = 0;
+    CK(ser_shape(c, obj_kind, obj, key_kind, h, &base, &stride));
+    const size_t need = sizeof h + h.payload;
+    if (!host_bytes) {
+        *n = need;
+        return CKKS_OK;
+    }
+    if (*n < need) {
+        *n = need;
+        return fail(CKKS_ENOMEM, "serialize: buffer of %zu bytes, need %zu", *n, need);
+    }
+    if (c->rec) return fail(CKKS_EINVAL, "serialize: not allowed while recording");
+    uint8_t *out = (uint8_t *)host_bytes;
+    memcpy(out, &h, sizeof h);
+    const size_t poly = (size_t)(h.level + 1) * c->N * 8;
+    hipStream_t s = (hipStream_t)stream;
+    for (u32 t = 0; t < h.n_poly; t++)
+        HIP_TRY(hipMemcpyAsync(out + sizeof h + t * poly, base + (size_t)t * stride * c->N, poly,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n = need;
+    return CKKS_OK;
+}
+
+extern "C" int ckks_deserialize(const ckks_ctx *c, int obj_kind, const void *host_bytes, size_t n, void *obj,
+                                int key_kind, void *stream) {
+    if (!c || !host_bytes || !obj) return fail(CKKS_EINVAL, "deserialize: null argument");
+    if (c->rec) return fail(CKKS_EINVAL, "deserialize: not allowed while recording");
+    if (n < sizeof(SerHeader)) return fail(CKKS_EINVAL, "deserialize: %zu bytes is shorter than the header", n);
+    SerHeader h;
+    memcpy(&h, host_bytes, sizeof h);
+    if (h.magic != kSerMagic || h.version != 1) return fail(CKKS_EINVAL, "deserialize: not a serialised object");
+    if (h.kind != (u32)obj_kind) return fail(CKKS_EINVAL, "deserialize: object kind %u, expected %d", h.kind, obj_kind);
+    if (h.log_n != c->log_n || h.n_q != c->n_q || h.n_p != c->n_p || h.dnum != c->dnum || h.chain != chain_hash(c))
+        return fail(CKKS_EPARAMS, "deserialize: parameters differ from the context");
+    if (h.level >= c->n_prim || h.n_poly == 0 || h.payload != (u64)h.n_poly * (h.level + 1) * c->N * 8 ||
+        n < sizeof h + h.payload)
+        return fail(CKKS_EINVAL, "deserialize: inconsistent header or truncated bytes");
+    u64 *base = nullptr;
+    u32 stride = h.level + 1;
+    switch (obj_kind) {
+        case CKKS_OBJ_CT: {
+            ckks_ct *x = (ckks_ct *)obj;
+            if (!x->data || h.level >= c->n_q || h.n_poly < 2 || h.n_poly > 3)
+                return fail(CKKS_EINVAL, "deserialize: bad ciphertext");
+            if (x->limb_stride < h.level + 1) return fail(CKKS_EINVAL, "deserialize: limb_stride too small");
+            base = x->data;
+            stride = x->limb_stride;
+            x->n_poly = h.n_poly;
+            x->level = h.level;
+            x->scale = h.scale;
+            break;
+        }
+        case CKKS_OBJ_PT: {
+            ckks_pt *x = (ckks_pt *)obj;
+            if (!x->data || h.level >= c->n_q || h.n_poly != 1) return fail(CKKS_EINVAL, "deserialize: bad plaintext");
+            base = x->data;
+            x->level = h.level;
+            x->scale = h.scale;
+            break;
+        }
+        case CKKS_OBJ_KEY: {
+            SerHeader want;
+            u64 *dummy = nullptr;
+            u32 st = 0;
+            CK(ser_shape(c, CKKS_OBJ_KEY, obj, key_kind, want, &dummy, &st));
+            if (h.key_kind != (u32)key_kind || h.n_poly != want.n_poly || h.level != want.level)
+                return fail(CKKS_EINVAL, "deserialize: key kind or shape differs");
+            base = (u64 *)obj;
+            break;
+        }
+        default: return fail(CKKS_EINVAL, "deserialize: unknown object kind %d", obj_kind);
+    }
+    const uint8_t *in = (const uint8_t *)host_bytes + sizeof h;
+    const size_t poly = (size_t)(h.level + 1) * c->N * 8;
+    hipStream_t s = (hipStream_t)stream;
+    for (u32 t = 0; t < h.n_poly; t++)
+        HIP_TRY(hipMemcpyAsync(base + (size_t)t * stride * c->N, in + t * poly, poly, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CKKS_OK;
+}
+
+
 
 // ---------------------------------------------------------------------
 // workspace sizing: run the planner on placeholder objects
@@ -1629,8 +1877,12 @@ extern "C" int ckks_linear(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, 
     for (u32 i = 0; i < n_in; i++) ptrs[i] = in[i].data;
     for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(w8 + ptr_off, ptrs.data(), ptrs.size() * 8, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_reduce_weights(c->tb, W, wt, n_out * n_in, L, s));
+    uint8_t *pt8 = nullptr;
+    CK(upload(c, w8 + ptr_off, ptrs.data(), ptrs.size() * 8, s, &pt8));
+    const u32 cnt = n_out * n_in;
+    HIP_TRY(issue(c, s, [tb = c->tb, W, wt, cnt, L](hipStream_t st) {
+        return launch_reduce_weights(tb, W, wt, cnt, L, st);
+    }));
     ProfRec rec;
     if (g_prof_on) {
         rec.name = launch_name(4, 0, c->log_n);
@@ -1639,8 +1891,10 @@ extern "C" int ckks_linear(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, 
         HIP_TRY(hipEventCreate(&rec.e1));
         HIP_TRY(hipEventRecord(rec.e0, s));
     }
-    HIP_TRY(launch_linear(c->tb, (const u64 *const *)(w8 + ptr_off), wt, (u64 *const *)(w8 + ptr_off + n_in * 8),
-                          n_in, n_out, L, stride, ostride, s));
+    HIP_TRY(issue(c, s, [tb = c->tb, pt8, wt, n_in, n_out, L, stride, ostride](hipStream_t st) {
+        return launch_linear(tb, (const u64 *const *)pt8, wt, (u64 *const *)(pt8 + (size_t)n_in * 8), n_in, n_out, L,
+                             stride, ostride, st);
+    }));
     if (g_prof_on) {
         HIP_TRY(hipEventRecord(rec.e1, s));
         g_prof.push_back(rec);
@@ -1657,7 +1911,6 @@ extern "C" int ckks_linear(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, 
 // ---------------------------------------------------------------------
 // encrypted linear layer, sparse rows (CSR)
 // ---------------------------------------------------------------------
-static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_in, uint32_t n_out, size_t nnz,
                                                   uint32_t level) {
@@ -1730,8 +1983,8 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
     for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
     memcpy(img.data() + o_ptr, ptrs.data(), ptrs.size() * 8);
     hipStream_t s = (hipStream_t)stream;
-    uint8_t *w8 = (uint8_t *)ws;
-    HIP_TRY(hipMemcpyAsync(w8, img.data(), need, hipMemcpyHostToDevice, s));
+    uint8_t *w8 = nullptr;
+    CK(upload(c, (uint8_t *)ws, img.data(), need, s, &w8));
     ProfRec rec;
     if (g_prof_on) {
         rec.name = launch_name(4, 0, c->log_n);
@@ -1740,10 +1993,13 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
         HIP_TRY(hipEventCreate(&rec.e1));
         HIP_TRY(hipEventRecord(rec.e0, s));
     }
-    HIP_TRY(launch_linear_grouped(c->tb, (const LinGroup *)(w8 + o_groups), (u32)groups.size(),
-                                  (const u32 *)(w8 + o_cols), (const u64 *)(w8 + o_wt), (u32)W,
-                                  (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L,
-                                  stride, ostride, s));
+    const u32 n_groups = (u32)groups.size();
+    HIP_TRY(issue(c, s, [tb = c->tb, w8, n_groups, o_groups, o_cols, o_wt, o_ptr, W, n_in, L, stride,
+                         ostride](hipStream_t st) {
+        return launch_linear_grouped(tb, (const LinGroup *)(w8 + o_groups), n_groups, (const u32 *)(w8 + o_cols),
+                                     (const u64 *)(w8 + o_wt), (u32)W, (const u64 *const *)(w8 + o_ptr),
+                                     (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L, stride, ostride, st);
+    }));
     if (g_prof_on) {
         HIP_TRY(hipEventRecord(rec.e1, s));
         g_prof.push_back(rec);

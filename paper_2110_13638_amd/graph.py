@@ -19,6 +19,7 @@ class Graph:
         self.g = nat.ckks_graph_create(ctx.h)
         self._ws = None
         self._ws_bytes = 0
+        self._keep = []
         self.n_out = 0
         self.n_inputs = 0
 
@@ -70,6 +71,14 @@ class Graph:
 
     def square(self):
         return nat.ckks_graph_add_node(self.g, nat.CKKS_NODE_SQUARE)
+
+    def poly(self, coeffs, w_scale=None):
+        """polynomial activation sum_k coeffs[k] x^k (degree >= 1)"""
+        c = np.ascontiguousarray(coeffs, dtype=np.float64)
+        self._keep.append(c)
+        a = nat.ckks_poly_attrs(len(c) - 1, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                w_scale or self.ctx.default_scale)
+        return nat.ckks_graph_add_node(self.g, nat.CKKS_NODE_POLY, a)
 
     def output(self):
         return nat.ckks_graph_add_node(self.g, nat.CKKS_NODE_OUTPUT)

@@ -14,6 +14,8 @@ container rescales after every product (Section 4.1). Three packings:
   * yield regressor: windows x 256 padded features per ciphertext,
     three hybrid-diagonal dense layers with power-of-two Galois keys.
 """
+import math
+
 import numpy as np
 
 from .graph import Graph
@@ -215,3 +217,17 @@ def build_yield(ctx, ws, bs, n_ct, in_level, scale, diag_coeffs=None, bias_coeff
     g.edge(prev, g.output())
     g.plan()
     return g
+
+
+# ---------------------------------------------------------------------------
+# polynomial activations (Section 4.4; coefficients from the appendix
+# equations), c_0 first
+# ---------------------------------------------------------------------------
+def relu_approx_coeffs(q):
+    """R_a(x) = 4/(3 pi q) x^2 + x/2 + q/(3 pi) for the approximation range q"""
+    return [q / (3.0 * math.pi), 0.5, 4.0 / (3.0 * math.pi * q)]
+
+
+def sigmoid_approx_coeffs():
+    """sigma_a(x) = 0.5 + 0.197 x - 0.004 x^3"""
+    return [0.5, 0.197, 0.0, -0.004]

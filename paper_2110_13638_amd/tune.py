@@ -18,7 +18,9 @@ DEFAULT_SPACE = {"ntt_wide": (0, 1), "ew_log": (1, 2, 3), "xcd_remap": (0, 1), "
 
 
 def _key(ctx, workload):
-    dev = torch.cuda.get_device_name(ctx.device)
+    props = torch.cuda.get_device_properties(ctx.device)
+    dev = getattr(props, "gcnArchName", "") or props.name or "device"
+    dev = dev.split(":")[0]
     return "%s|N=2^%d|q=%d|p=%d|dnum=%d|%s" % (dev, ctx.log_n, len(ctx.q), len(ctx.p), ctx.dnum, workload)
 
 

@@ -122,3 +122,90 @@ def test_tuning_knobs_host():
             nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_WIDE, 1)  # no wide variant at N = 2^10
     finally:
         nat.ckks_ctx_destroy(h)
+
+
+def test_record_api_host_errors():
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    primes = O.find_primes(12, [50, 50, 60])
+    h = nat.ckks_ctx_create(12, primes[:2], primes[2:], 2)
+    try:
+        with pytest.raises(nat.CkksError):
+            nat.ckks_record_end(h)  # not recording
+        with pytest.raises(nat.CkksError):
+            nat.ckks_record_begin(h, 0x1008, 4096)  # arena not 256-byte aligned
+        nat.ckks_record_begin(h, 0x1000, 4096)  # host-side bookkeeping only
+        with pytest.raises(nat.CkksError):
+            nat.ckks_record_begin(h, 0x1000, 4096)  # already recording
+        plan, used = nat.ckks_record_end(h)
+        assert used == 0 and nat.ckks_plan_launch_count(plan) == 0
+        nat.ckks_plan_destroy(plan)
+    finally:
+        nat.ckks_ctx_destroy(h)
+
+
+def test_poly_node_attrs_validated():
+    import ctypes
+    import numpy as np
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    primes = O.find_primes(12, [60, 40, 40, 60])
+    h = nat.ckks_ctx_create(12, primes[:3], primes[3:], 3)
+    g = nat.ckks_graph_create(h)
+    try:
+        c = np.array([0.5, 0.197, 0.0, -0.004])
+        ok = nat.ckks_poly_attrs(3, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2.0 ** 40)
+        nat.ckks_graph_add_node(g, nat.CKKS_NODE_POLY, ok)
+        for bad in (nat.ckks_poly_attrs(0, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2.0 ** 40),
+                    nat.ckks_poly_attrs(2, None, 2.0 ** 40),
+                    nat.ckks_poly_attrs(2, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.0)):
+            with pytest.raises(nat.CkksError):
+                nat.ckks_graph_add_node(g, nat.CKKS_NODE_POLY, bad)
+        # depth check at plan time: a degree-3 activation needs 3 levels
+        x = nat.ckks_graph_add_node(g, nat.CKKS_NODE_INPUT, nat.ckks_input_attrs(1, 2, 2.0 ** 40))
+        o = nat.ckks_graph_add_node(g, nat.CKKS_NODE_OUTPUT)
+        nat.ckks_graph_add_edge(g, x, 0)
+        nat.ckks_graph_add_edge(g, 0, o)
+        with pytest.raises(nat.CkksError) as e:
+            nat.ckks_graph_plan(g)
+        assert e.value.code == nat.CKKS_EDEPTH
+    finally:
+        nat.ckks_graph_destroy(g)
+        nat.ckks_ctx_destroy(h)
+
+
+def test_serialize_host_checks():
+    import struct
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    primes = O.find_primes(12, [50, 50, 60])
+    h = nat.ckks_ctx_create(12, primes[:2], primes[2:], 2)
+    other = nat.ckks_ctx_create(12, O.find_primes(12, [50, 40, 60])[:2], O.find_primes(12, [50, 40, 60])[2:], 2)
+    try:
+        ct = nat.ckks_ct(0x100000, 2, 1, 2, 0, 2.0 ** 40)
+        n = ctypes.c_size_t()
+        nat.lib().ckks_serialize(h, nat.CKKS_OBJ_CT, ctypes.byref(ct), 0, None, ctypes.byref(n), None)
+        assert n.value == 64 + 2 * 2 * 4096 * 8
+        nat.lib().ckks_serialize(h, nat.CKKS_OBJ_KEY, ctypes.c_void_p(0x100000), nat.CKKS_KEY_SWITCH, None,
+                                 ctypes.byref(n), None)
+        assert n.value == 64 + nat.ckks_key_bytes(h, nat.CKKS_KEY_SWITCH)
+
+        def header(log_n=12, n_q=2, n_p=1, dnum=2, magic=0x534B4B43, chain=None, payload=2 * 2 * 4096 * 8):
+            return struct.pack("<10IdQQ", magic, 1, 0, log_n, n_q, n_p, dnum, 2, 1, 0, 2.0 ** 40,
+                               chain or 0, payload)
+
+        dst = nat.ckks_ct(0x100000, 2, 1, 2, 0, 1.0)
+        body = bytes(2 * 2 * 4096 * 8)
+        for data, code in [(header(magic=0) + body, nat.CKKS_EINVAL),     # not a serialised object
+                           (header(log_n=13) + body, nat.CKKS_EPARAMS),   # other ring
+                           (header() + body, nat.CKKS_EPARAMS),           # chain hash differs
+                           (header()[:40], nat.CKKS_EINVAL)]:             # truncated
+            with pytest.raises(nat.CkksError) as e:
+                nat.ckks_deserialize(h, nat.CKKS_OBJ_CT, data, dst)
+            assert e.value.code == code
+        with pytest.raises(nat.CkksError) as e:
+            nat.ckks_deserialize(other, nat.CKKS_OBJ_CT, header() + body, dst)
+        assert e.value.code == nat.CKKS_EPARAMS
+    finally:
+        nat.ckks_ctx_destroy(h)
+        nat.ckks_ctx_destroy(other)

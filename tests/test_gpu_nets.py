@@ -162,3 +162,35 @@ def test_vision_small_ring(mods):
     err = _rel_err(got, want)
     print("vision: max relative error 2^%.1f" % np.log2(err))
     assert err <= TOL
+
+
+@pytest.mark.parametrize("which", ["relu", "sigmoid"])
+def test_poly_activation(mods, which):
+    # Section 4.4's activation approximations as a graph node, N = 2^12,
+    # [60, 40 x 4 | 60]: bit-exact vs the oracle's Horner lowering, decoded
+    # within tolerance of the FP64 polynomial
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 12, [60] + [40] * 4, [60], 5, 4)
+    keys = ON.Keys(orc, 4)
+    if which == "relu":
+        coeffs = nets.relu_approx_coeffs(4.0)
+        assert coeffs == PN.relu_approx_coeffs(4.0)
+        x = S.uniform_slots(5, ctx.N // 2) * 4.0
+    else:
+        coeffs = nets.sigmoid_approx_coeffs()
+        assert coeffs == PN.sigmoid_approx_coeffs()
+        x = S.uniform_slots(6, ctx.N // 2) * 5.0
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, x, 4, 13, i) for i in range(3)])
+    from paper_2110_13638_amd.graph import Graph
+    g = Graph(ctx)
+    g.chain(g.input(3, 4, SCALE), g.poly(coeffs, SCALE), g.output())
+    outs = g.run(list(cts))
+    for i in range(3):
+        y, s = ON.poly(orc, keys, ctos[i], SCALE, coeffs, SCALE)
+        assert outs[i].level == y.shape[1] - 1 and outs[i].scale == s
+        assert np.array_equal(outs[i].residues(), y), i
+    got = ctx.decrypt(outs[0], ctx.N // 2).real
+    want = PN.poly_eval(coeffs, x)
+    err = _rel_err(got, want)
+    print("%s approximation: max relative error 2^%.1f" % (which, np.log2(err)))
+    assert err <= TOL

@@ -76,3 +76,27 @@ def test_yield_network_small_ring():
     want = PN.yield_math(x, ws, bs)[:, 0]
     err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
     assert err <= TOL, err
+
+
+@pytest.mark.parametrize("which", ["relu", "sigmoid"])
+def test_polynomial_activation(which):
+    # Section 4.4's approximations by Horner's rule at N = 2^12, [60, 40 x 4 | 60]
+    logn = 12
+    primes = O.find_primes(logn, [60] + [40] * 4 + [60])
+    orc = O.Oracle(logn, primes[:5], primes[5:], 5)
+    keys = ON.Keys(orc, 4)
+    scale = 2.0 ** 40
+    if which == "relu":
+        rng_q = 4.0
+        coeffs = PN.relu_approx_coeffs(rng_q)
+        x = S.uniform_slots(5, orc.N // 2) * rng_q
+    else:
+        coeffs = PN.sigmoid_approx_coeffs()
+        x = S.uniform_slots(6, orc.N // 2) * 5.0
+    ct = _encrypt(orc, keys, x, 4, scale, 3, 0)
+    y, s = ON.poly(orc, keys, ct, scale, coeffs, scale)
+    assert y.shape[1] == 5 - (len(coeffs) - 1)
+    got = _decrypt(orc, keys, y, s, orc.N // 2)
+    want = PN.poly_eval(coeffs, x)
+    err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err

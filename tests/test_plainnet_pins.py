@@ -35,3 +35,39 @@ def test_yield_packed_equals_math():
     for slots in (4096, 8192):
         a, b = PN.yield_packed(x, ws, bs, slots), PN.yield_math(x, ws, bs)
         assert np.max(np.abs(a[:, None] - b)) < 1e-10 * max(1.0, np.max(np.abs(b)))
+
+
+def test_relu_approx_closed_forms():
+    # R_a(0) = q/(3 pi), R_a(+-q) = 5q/(3 pi) +- q/2; its largest distance
+    # to ReLU on [-q, q] is q/(3 pi), at 0
+    for q in (1.0, 4.0, 10.0):
+        c = PN.relu_approx_coeffs(q)
+        assert len(c) == 3
+        assert abs(PN.poly_eval(c, 0.0) - q / (3 * np.pi)) < 1e-12 * q
+        assert abs(PN.poly_eval(c, q) - (5 * q / (3 * np.pi) + q / 2)) < 1e-12 * q
+        assert abs(PN.poly_eval(c, -q) - (5 * q / (3 * np.pi) - q / 2)) < 1e-12 * q
+        xs = np.linspace(-q, q, 20001)
+        gap = np.abs(PN.poly_eval(c, xs) - np.maximum(xs, 0))
+        assert abs(gap.max() - q / (3 * np.pi)) < 1e-9 * q and abs(xs[gap.argmax()]) < 1e-9 * q
+        # the paper's derivative of the approximation: 8x/(3 pi q) + 1/2
+        h = 1e-6 * q
+        for x0 in (-0.7 * q, 0.0, 0.3 * q):
+            num = (PN.poly_eval(c, x0 + h) - PN.poly_eval(c, x0 - h)) / (2 * h)
+            assert abs(num - (8 * x0 / (3 * np.pi * q) + 0.5)) < 1e-6
+
+
+def test_sigmoid_approx_closed_forms():
+    c = PN.sigmoid_approx_coeffs()
+    assert PN.poly_eval(c, 0.0) == 0.5
+    assert abs(PN.poly_eval(c, 1.0) - 0.693) < 1e-15
+    # odd around 1/2: sigma_a(x) + sigma_a(-x) = 1
+    xs = np.linspace(-5, 5, 1001)
+    assert np.max(np.abs(PN.poly_eval(c, xs) + PN.poly_eval(c, -xs) - 1.0)) < 1e-15
+    # derivative 0.197 - 0.012 x^2 (the paper's approximate derivative)
+    h = 1e-6
+    for x0 in (-3.0, 0.5, 2.0):
+        num = (PN.poly_eval(c, x0 + h) - PN.poly_eval(c, x0 - h)) / (2 * h)
+        assert abs(num - (0.197 - 0.012 * x0 * x0)) < 1e-8
+    # it follows the sigmoid on the stated range [-5, 5] to within 0.06
+    # (largest gap 0.051 near |x| = 3.83)
+    assert np.max(np.abs(PN.poly_eval(c, xs) - 1 / (1 + np.exp(-xs)))) < 0.06

@@ -276,6 +276,66 @@ def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
     return ragged_rate, plain_rate, same, ntt
 
 
+def nets_leg(args, dev, log):
+    """Encrypted inference at full size: the vision network on 8192 images
+    (N = 2^14, [60, 40 x 7 | 60], one ciphertext per pixel, slot-batched) and
+    the yield regressor on 4096 windows (N = 2^14, [60, 40 x 5 | 60], 32
+    windows per ciphertext, rotation-based dense layers). One inference =
+    the whole batch through the graph runtime; inputs encrypted on the GPU
+    beforehand."""
+    import numpy as np
+    import torch
+    import synthetic as S
+    from paper_2110_13638_amd import _native as nat
+    from paper_2110_13638_amd import ckks, nets
+
+    out = {}
+    scale = 2.0 ** 40
+    # vision
+    pr = nat.ckks_find_primes(14, [60] + [40] * 7 + [60])
+    ctx = ckks.Context(14, pr[:8], pr[8:], 8, device=dev).keygen(21)
+    n_img = ctx.N // 2
+    x, P = S.vision_inputs(n_images=n_img)
+    pix = x.reshape(n_img, -1).T
+    cts = [ctx.encrypt(ctx.encode(pix[i], level=7), seed=22, obj=i) for i in range(pix.shape[0])]
+    g = nets.build_vision(ctx, P, 28, 7, scale)
+    g.run(cts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g.run(cts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.net_runs
+    out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
+                     "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt}
+    log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
+    del g, cts, ctx
+    torch.cuda.empty_cache()
+    # yield
+    pr = nat.ckks_find_primes(14, [60] + [40] * 5 + [60])
+    ctx = ckks.Context(14, pr[:6], pr[6:], 6, device=dev).keygen(31)
+    W = nets.yield_windows(ctx.N // 2)
+    xw, ws, bs = S.yield_inputs(n_windows=4096)
+    steps = nets.yield_steps(ws, W)
+    for ge in nets.galois_for_steps(ctx, steps):
+        ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
+    packed = nets.yield_pack(xw, ctx.N // 2)
+    cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
+    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale)
+    g.run(cts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g.run(cts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.net_runs
+    out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys"
+                              % (len(cts), len(ctx.gk)),
+                    "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
+    log("yield (4096 windows, N=2^14): %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
+    return out
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -294,6 +354,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
     ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-nets", action="store_true", help="skip the full-size network inferences")
+    ap.add_argument("--net-runs", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the batched HMult step (ragged, plain, NTT and serving legs skipped)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
@@ -428,6 +490,7 @@ def main():
         log("oracle: %.3f HMult/s on %d threads; GPU ciphertext == oracle: %s" %
             (cpu["value"], cores, cpu["gpu_matches_oracle"]))
 
+    networks = None if (args.no_nets or args.no_extra) else nets_leg(args, dev, log)
     serving = None if (args.no_serve or args.no_extra) else serve_leg(args, dev, log)
 
     line = {
@@ -444,7 +507,7 @@ def main():
                   "plain_one_op_per_launch_hmult_per_s": plain_rate and round(plain_rate, 2),
                   "batched_over_plain": plain_rate and round(value / plain_rate, 2),
                   "plain_equals_fused": same, "tuning": tuning,
-                  "ntt": ntt, "kernels": breakdown, "serving": serving},
+                  "ntt": ntt, "kernels": breakdown, "networks": networks, "serving": serving},
     }
     print(json.dumps(line))
 

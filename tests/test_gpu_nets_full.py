@@ -1,0 +1,125 @@
+"""The two benchmark networks at their full sizes (N = 2^14): the vision
+network on 8192 slot-batched images and the yield regressor on 4096
+windows. Sampled outputs are bit-exact against the oracle (the conv layer
+and its square for a few neurons; one yield ciphertext through all layers),
+and every decoded output is within 2^-18 * max(1, |y|) of the FP64 network."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+from oracle import encoding as E
+from oracle import nets as ON
+from oracle import plainnet as PN
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = 2.0 ** -18
+SCALE = 2.0 ** 40
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_13638_amd import ckks, nets
+    return ckks, nets
+
+
+def _rel_err(got, want):
+    return np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+
+
+def test_vision_full_size(mods):
+    ckks, nets = mods
+    logn = 14
+    primes = O.find_primes(logn, [60] + [40] * 7 + [60])
+    ctx = ckks.Context(logn, primes[:8], primes[8:], 8).keygen(21)
+    orc = O.Oracle(logn, primes[:8], primes[8:], 8)
+    keys = ON.Keys(orc, 21)
+    n_img = ctx.N // 2
+    x, P = S.vision_inputs(n_images=n_img)
+    pix = x.reshape(n_img, -1).T
+    ms = [E.encode(pix[i], SCALE, ctx.N) for i in range(pix.shape[0])]
+    cts = [ctx.encrypt(ctx.pt_from_coeffs(m, 7, SCALE), seed=22, obj=i) for i, m in enumerate(ms)]
+    print("vision full size: %d input ciphertexts encrypted" % len(cts), flush=True)
+    # sampled: three conv neurons and their squares through the oracle
+    rows, _ = PN.vision_conv_rows(P["conv_w"])
+    per = len(rows) // P["conv_w"].shape[0]
+    sample = [0, 400, len(rows) - 1]
+    need = sorted({i for j in sample for i, _ in rows[j]})
+    octs = {i: orc.encrypt(keys.pk, orc.reduce_int(ms[i], 7), 7, 22, i) for i in need}
+    for i in need:
+        assert np.array_equal(cts[i].residues(), octs[i]), i
+    from paper_2110_13638_amd.graph import Graph
+    for j in sample:
+        idx = [i for i, _ in rows[j]]
+        g1 = Graph(ctx)
+        inp = g1.input(len(idx), 7, SCALE)
+        lin = g1.linear([[(k, w) for k, (_, w) in enumerate(rows[j])]], SCALE, [P["conv_b"][j // per]])
+        g1.chain(inp, lin, g1.square(), g1.output())
+        got = g1.run([cts[i] for i in idx])[0]
+        h, s = ON.linear(orc, [octs[i] for i in idx], SCALE, [[(k, w) for k, (_, w) in enumerate(rows[j])]],
+                         SCALE, [P["conv_b"][j // per]])
+        y, s2 = ON.square(orc, keys, h[0], s)
+        assert got.scale == s2 and np.array_equal(got.residues(), y), j
+    # the whole network, decoded
+    g = nets.build_vision(ctx, P, 28, 7, SCALE)
+    outs = g.run(cts)
+    got = np.stack([ctx.decrypt(outs[j], n_img).real for j in range(10)], axis=1)
+    err = _rel_err(got, PN.vision_math(x, P))
+    print("vision full size: max relative error 2^%.1f over %d outputs" % (np.log2(err), got.size))
+    assert err <= TOL
+
+
+def test_yield_full_size(mods):
+    ckks, nets = mods
+    logn = 14
+    primes = O.find_primes(logn, [60] + [40] * 5 + [60])
+    ctx = ckks.Context(logn, primes[:6], primes[6:], 6).keygen(31)
+    orc = O.Oracle(logn, primes[:6], primes[6:], 6)
+    x, ws, bs = S.yield_inputs(n_windows=4096)
+    slots = ctx.N // 2
+    Wn = nets.yield_windows(slots)
+    steps = nets.yield_steps(ws, Wn)
+    elts = nets.galois_for_steps(ctx, steps)
+    assert elts == ON.naf_elements(orc, steps)
+    keys = ON.Keys(orc, 31, elts)
+    for ge in elts:
+        ctx.add_galois_key(ge, nets.galois_key_seed(31 + 3, ge))
+    packed = PN.yield_pack(x, slots)
+    n_ct = packed.shape[0]
+    assert n_ct == 128
+    ms = [E.encode(packed[c], SCALE, ctx.N) for c in range(n_ct)]
+    cts = [ctx.encrypt(ctx.pt_from_coeffs(m, 5, SCALE), seed=32, obj=c) for c, m in enumerate(ms)]
+    dcs, bcs = [], []
+    s, lvl = SCALE, 5
+    periods = [256, 64, 16]
+    for l in range(3):
+        d = PN.yield_diagonals(ws[l], periods[l], Wn)
+        dcs.append(np.stack([E.encode(di, SCALE, ctx.N) for di in d]))
+        out_scale = s * SCALE / orc.q[lvl]
+        bcs.append(E.encode(PN.yield_bias_vector(bs[l], Wn), out_scale, ctx.N))
+        s, lvl = out_scale, lvl - 1
+        if l < 2:
+            s, lvl = s * s / orc.q[lvl], lvl - 1
+    g = nets.build_yield(ctx, ws, bs, n_ct, 5, SCALE, diag_coeffs=dcs, bias_coeffs=bcs)
+    outs = g.run(cts)
+    print("yield full size: %d ciphertexts evaluated" % n_ct, flush=True)
+    # sampled: ciphertext 0 through the oracle's lowering
+    y = orc.encrypt(keys.pk, orc.reduce_int(ms[0], 5), 5, 32, 0)
+    assert np.array_equal(cts[0].residues(), y)
+    s = SCALE
+    for l in range(3):
+        in_steps, post = PN.yield_layer_plan(ws[l].shape[1], ws[l].shape[0], periods[l], Wn)
+        lv = y.shape[1] - 1
+        pts = [orc.reduce_int(c, lv) for c in dcs[l]]
+        y, s = ON.diag_dense(orc, keys, y, s, pts, SCALE, in_steps, post, orc.reduce_int(bcs[l], lv - 1))
+        if l < 2:
+            y, s = ON.square(orc, keys, y, s)
+    assert outs[0].scale == s and np.array_equal(outs[0].residues(), y)
+    want = PN.yield_math(x, ws, bs)[:, 0]
+    got = np.concatenate([ctx.decrypt(outs[c], Wn).real for c in range(n_ct)])
+    err = _rel_err(got[: len(want)], want)
+    print("yield full size: max relative error 2^%.1f over %d windows" % (np.log2(err), len(want)))
+    assert err <= TOL

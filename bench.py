@@ -119,16 +119,17 @@ def kernel_model(name, items, ctx, level):
 
 
 def serve_leg(args, dev, log):
-    """Serving mix: Poisson arrivals, half HMult pairs (rings 2^13..2^15,
-    4..16 limbs), half vision inferences (rings 2^13..2^14, starting level
-    5..7), keys resident, admission by HBM bytes; continuous batching vs the
-    plain one-op-per-launch path on the same requests."""
+    """Serving mix: half HMult pairs (rings 2^13..2^15, levels 3..15), half
+    vision inferences (rings 2^13..2^14, levels 5..7), keys resident,
+    admission by HBM bytes. (1) saturation: a burst of requests served by
+    continuous batching and by the plain one-op-per-launch path, same
+    requests, results compared; (2) load sweep: Poisson arrivals at several
+    rates, latency percentiles from arrival to result."""
     import numpy as np
     import synthetic as S
     from paper_2110_13638_amd import _native as nat
     from paper_2110_13638_amd import ckks, serve
 
-    rng = np.random.default_rng(2)
     ctxs, vision = {}, {}
     for log_n in (13, 14, 15):
         pr = nat.ckks_find_primes(log_n, Q_BITS + P_BITS)
@@ -140,12 +141,12 @@ def serve_leg(args, dev, log):
         ctxs[("vision", log_n)] = c
         vision[log_n] = serve.VisionModel(c, P)
 
-    def make(seed):
+    def make(seed, n, rate):
         reqs = []
         t = 0.0
         r2 = np.random.default_rng(seed)
-        for rid in range(args.serve_requests):
-            t += r2.exponential(1.0 / args.serve_rate)
+        for rid in range(n):
+            t += r2.exponential(1.0 / rate)
             if r2.random() < 0.5:
                 kind, log_n, level, n_ct = "hmult", int(r2.choice([13, 14, 15])), int(r2.integers(3, 16)), 2
             else:
@@ -157,34 +158,40 @@ def serve_leg(args, dev, log):
             reqs.append(serve.Request(rid, kind, log_n, t, cts))
         return reqs
 
-    # warm up every (kind, ring) once
-    serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30).run(
-        [r for r in make(99)[:6]])
+    def engine():
+        return serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30)
+
+    def summary(done):
+        span = max(r.finish for r in done) - min(r.arrival for r in done)
+        st = serve.latency_stats(done)
+        n_vis = sum(r.kind == "vision" for r in done)
+        return {"requests": len(done), "vision_requests": n_vis, "requests_per_s": len(done) / span,
+                "encrypted_infer_per_s": n_vis / span, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}
+
+    engine().run(make(99, 8, 1e4))  # warm-up of every kind and ring
     torch_sync()
-    reqs = make(3)
-    t0 = time.perf_counter()
-    done = serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30).run(reqs)
-    span = max(r.finish for r in done) - min(r.arrival for r in done)
-    st = serve.latency_stats(done)
-    n_vis = sum(r.kind == "vision" for r in done)
-    out = {"requests": len(done), "vision_requests": n_vis, "arrival_rate_per_s": args.serve_rate,
-           "requests_per_s": len(done) / span, "encrypted_infer_per_s": n_vis / span,
-           "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "hbm_cap_GiB": args.serve_cap}
-    log("serving: %d requests (%d vision) in %.2f s: %.1f req/s, p50 %.1f ms, p99 %.1f ms" %
-        (len(done), n_vis, span, out["requests_per_s"], st["p50_ms"], st["p99_ms"]))
-    # plain path on the same requests (same inputs), compared ciphertext by ciphertext
-    preqs = make(3)
-    plain = serve.run_plain(ctxs, vision, preqs)
-    pspan = max(r.finish for r in plain) - min(r.arrival for r in plain)
-    pst = serve.latency_stats(plain)
-    same = all(all(bool((a.buf[:, : a.level + 1] == b.buf[:, : b.level + 1]).all()) for a, b in
-                   zip(x.result, y.result)) for x, y in zip(sorted(done, key=lambda r: r.rid), plain))
-    out.update({"plain_requests_per_s": len(plain) / pspan, "plain_encrypted_infer_per_s": n_vis / pspan,
-                "plain_p50_ms": pst["p50_ms"], "plain_p99_ms": pst["p99_ms"],
-                "batched_over_plain": (len(done) / span) / (len(plain) / pspan), "results_equal_plain": same})
-    log("plain path: %.1f req/s, p50 %.1f ms, p99 %.1f ms; batched/plain %.1fx; identical results: %s" %
-        (out["plain_requests_per_s"], pst["p50_ms"], pst["p99_ms"], out["batched_over_plain"], same))
-    return out
+    # (1) saturation, batched vs plain on the same requests
+    n = args.serve_requests
+    done = engine().run(make(3, n, 1e4))
+    sat = {"batched": summary(done)}
+    plain = serve.run_plain(ctxs, vision, make(3, n, 1e4))
+    sat["plain"] = summary(plain)
+    sat["batched_over_plain"] = sat["batched"]["requests_per_s"] / sat["plain"]["requests_per_s"]
+    sat["results_equal_plain"] = all(
+        all(bool((a.buf[:, : a.level + 1] == b.buf[:, : b.level + 1]).all()) for a, b in zip(x.result, y.result))
+        for x, y in zip(sorted(done, key=lambda r: r.rid), sorted(plain, key=lambda r: r.rid)))
+    log("serving burst of %d: batched %.1f req/s (%.2f infer/s), plain %.1f req/s: %.1fx; identical results: %s" %
+        (n, sat["batched"]["requests_per_s"], sat["batched"]["encrypted_infer_per_s"],
+         sat["plain"]["requests_per_s"], sat["batched_over_plain"], sat["results_equal_plain"]))
+    # (2) load sweep, batched
+    load = []
+    for rate in args.serve_rates:
+        r = summary(engine().run(make(10 + int(rate), args.serve_sweep_requests, rate)))
+        r["arrival_rate_per_s"] = rate
+        load.append(r)
+        log("  Poisson %5.0f req/s: served %.1f req/s, p50 %.1f ms, p99 %.1f ms" %
+            (rate, r["requests_per_s"], r["p50_ms"], r["p99_ms"]))
+    return {"hbm_cap_GiB": args.serve_cap, "saturation": sat, "load": load}
 
 
 def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
@@ -329,10 +336,29 @@ def nets_leg(args, dev, log):
         g.run(cts)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.net_runs
-    out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys"
-                              % (len(cts), len(ctx.gk)),
+    out["yield_sequential"] = {
+        "config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d power-of-two Galois keys, "
+                  "rotations composed and key-switched one by one" % (len(cts), len(ctx.gk)),
+        "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
+    log("yield, sequential rotations (4096 windows, N=2^14): %.1f ms per inference, %.0f windows/s" %
+        (1e3 * dt, 4096 / dt))
+    del g
+    # hoisted: one decomposition and one ModDown per layer and ciphertext, a key per step
+    for ge in nets.galois_for_steps(ctx, steps, direct=True):
+        if ge not in ctx.gk:
+            ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
+    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
+    g.run(cts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g.run(cts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.net_runs
+    out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys, "
+                              "hoisted rotations" % (len(cts), len(ctx.gk)),
                     "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
-    log("yield (4096 windows, N=2^14): %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
+    log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
     return out
 
 
@@ -350,8 +376,10 @@ def main():
     ap.add_argument("--plain-pairs", type=int, default=32)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-rate", type=float, default=100.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests in the saturation burst")
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[25.0, 50.0, 100.0, 200.0],
+                    help="Poisson arrival rates (requests/s) of the load sweep")
+    ap.add_argument("--serve-sweep-requests", type=int, default=64)
     ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-nets", action="store_true", help="skip the full-size network inferences")

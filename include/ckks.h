@@ -325,6 +325,33 @@ int ckks_linear_csr(const ckks_ctx *ctx, const ckks_ct *in, uint32_t n_in, uint3
                     ckks_ct *out, void *ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* hoisted rotations with plaintext weights                             */
+/* ------------------------------------------------------------------ */
+/* The rotation-based matrix-vector product of a dense layer (Section 4.2.3
+ * on slot-packed inputs; the diagonal method) with all rotations of one
+ * ciphertext sharing a single decomposition. For each input x = (c0, c1)
+ * at level l, with D_j the ModUp of digit j of c1 to Q_l U P (NTT form;
+ * the digit's own limbs are c1's), sigma_g the NTT-domain automorphism
+ * X -> X^g and (b_{g,j}, a_{g,j}) the Galois key of g:
+ *   T0 = sum_i pt_i (x) ( sum_j sigma_gi(D_j) (x) b_{gi,j} + P sigma_gi(c0) )
+ *   T1 = sum_i pt_i (x) ( sum_j sigma_gi(D_j) (x) a_{gi,j} )
+ * over Q_l U P (P sigma(c0) is zero on the special primes; g_i = 1 is the
+ * identity and contributes (P c0, P c1)), and out = (ModDown(T0),
+ * ModDown(T1)) at level l with scale x.scale * pt_scale: one ModDown per
+ * ciphertext for the whole sum. Equals sum_i pt_i (x) rot_{g_i}(x) up to the
+ * rounding of ModDown.
+ * galois_elts [n_rot] (odd, < 2N; 1 = identity), galois_keys [n_rot]
+ * device key pointers (ignored for the identity; ENOKEY when missing),
+ * pt_coeffs: device int64 [n_rot][N] integer plaintext coefficients at
+ * pt_scale (reduced and transformed to every prime of Q_l U P inside the
+ * call). in[b] all at one level (ELEVEL), out[b] must not alias in[b].
+ * Workspace: ckks_hoisted_linear_workspace_bytes (ENOMEM when short). */
+size_t ckks_hoisted_linear_workspace_bytes(const ckks_ctx *ctx, uint32_t B, uint32_t level, uint32_t n_rot);
+int ckks_hoisted_linear(const ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, uint32_t B, uint32_t n_rot,
+                        const uint32_t *galois_elts, const uint64_t *const *galois_keys, const int64_t *pt_coeffs,
+                        double pt_scale, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* graph traversal (Algorithms 1-5, forward receptor only)              */
 /* ------------------------------------------------------------------ */
 /* A multi-directed graph of encrypted layers (Section 4): every edge
@@ -340,7 +367,8 @@ int ckks_linear_csr(const ckks_ctx *ctx, const ckks_ct *in, uint32_t n_in, uint3
  *               sum_i diag_i (x) rot(x, in_steps[i]), rescale, then
  *               x += rot(x, r) for every post step, + bias plaintext;
  *               steps without their own Galois key are composed from
- *               power-of-two keys in non-adjacent form (ckks_diag_attrs);
+ *               power-of-two keys in non-adjacent form; with `hoisted`
+ *               the sum is one ckks_hoisted_linear call (ckks_diag_attrs);
  *   SQUARE      x^2: ckks_hmult_relin_rescale(x, x) on each ciphertext;
  *   POLY        polynomial activation p(x) = sum_k c_k x^k of degree
  *               d >= 1 (Section 4.4: the ReLU approximation
@@ -381,6 +409,8 @@ typedef struct {
     const double *bias_slots;    /* [n_bias_slots] or NULL: encoded at plan */
     uint32_t n_bias_slots;
     const int64_t *bias_coeffs;  /* [N] integer plaintext at the output scale, or NULL */
+    uint32_t hoisted;            /* 1: all in_steps rotations hoisted (ckks_hoisted_linear);
+                                    every nonzero step needs its own Galois key */
 } ckks_diag_attrs;
 typedef struct {
     uint32_t degree;      /* d >= 1 */

@@ -78,6 +78,7 @@ def lib():
             "orc_apply_galois": (None, [vp, _U64P, u32, u64, _U64P, _U64P]),
             "orc_mul_relin_rescale": (None, [vp, _U64P, _U64P, u32, _U64P, _U64P]),
             "orc_lincomb": (None, [vp, ctypes.POINTER(_U64P), _I64P, u32, u32, u32, _U64P]),
+            "orc_hoisted_linear": (None, [vp, _U64P, u32, u32, _U64P, ctypes.POINTER(_U64P), _I64P, _U64P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -356,6 +357,19 @@ class Oracle:
         w = np.ascontiguousarray(weights, dtype=np.int64)
         out = np.zeros_like(cts[0])
         lib().orc_lincomb(self._h, arr, _pi64(w), len(cts), cts[0].shape[0], cts[0].shape[1] - 1, _p64(out))
+        return out
+
+    def hoisted_linear(self, ct, galois, gks, pt_coeffs):
+        """sum_i pt_i (x) rot_{g_i}(ct) with one shared decomposition and one
+        ModDown; g = 1 is the identity (its key entry is ignored)"""
+        ct = _u64(ct)
+        L = ct.shape[1]
+        g = np.ascontiguousarray(galois, dtype=np.uint64)
+        keys = [_u64(k) if k is not None else np.zeros(1, dtype=np.uint64) for k in gks]
+        arr = (_U64P * len(keys))(*[_p64(k) for k in keys])
+        pc = np.ascontiguousarray(pt_coeffs, dtype=np.int64)
+        out = np.zeros((2, L, self.N), dtype=np.uint64)
+        lib().orc_hoisted_linear(self._h, _p64(ct), L - 1, len(g), _p64(g), arr, _pi64(pc), _p64(out))
         return out
 
     def mul_relin_rescale(self, a, b, rk):

@@ -801,3 +801,82 @@ void orc_lincomb(const orc_ctx *c, const u64 *const *cts, const i64 *w, u32 n, u
             }
         }
 }
+
+/* ------------------------------------------------------------------ */
+/* Rotations of one ciphertext with plaintext weights, all rotations     */
+/* sharing one decomposition (hoisting) and one ModDown (the diagonal    */
+/* matrix-vector product of a dense layer, Section 4.2.3):               */
+/*   D_j  = ModUp of digit j of c1 to Q_l U P, NTT form (own limbs = c1) */
+/*   T0   = sum_i pt_i * ( sum_j sigma_gi(D_j) * b_{gi,j} + P sigma_gi(c0) ) */
+/*   T1   = sum_i pt_i * ( sum_j sigma_gi(D_j) * a_{gi,j} )              */
+/*   out  = (ModDown(T0), ModDown(T1)),  g = 1: the term pt_i * (P c0, P c1) */
+/* pt_i are integer polynomials reduced to every prime of Q_l U P.       */
+/* ------------------------------------------------------------------ */
+void orc_hoisted_linear(const orc_ctx *c, const u64 *ct, u32 level, u32 n_rot, const u64 *galois,
+                        const u64 *const *gks, const i64 *pt_coeffs, u64 *out)
+{
+    u32 n = nn(c), L = level + 1, k = c->n_p, E = L + k, tot = c->n_q + c->n_p;
+    u32 beta = orc_digits(c, level);
+    const u64 *c0 = ct, *c1 = ct + (size_t)L * n;
+    u64 *dc = (u64 *)malloc((size_t)L * n * sizeof(u64));
+    u64 *D = (u64 *)malloc((size_t)beta * E * n * sizeof(u64));
+    u64 *T = (u64 *)calloc((size_t)2 * E * n, sizeof(u64));
+    u64 *pt = (u64 *)malloc(n * sizeof(u64)), *sd = (u64 *)malloc(n * sizeof(u64));
+    u64 *b = (u64 *)malloc(n * sizeof(u64)), *a = (u64 *)malloc(n * sizeof(u64));
+    memcpy(dc, c1, (size_t)L * n * sizeof(u64));
+    for (u32 i = 0; i < L; i++) orc_intt(c, i, dc + (size_t)i * n);
+    for (u32 j = 0; j < beta; j++) {
+        u32 lo = j * c->alpha, hi = lo + c->alpha;
+        if (hi > L) hi = L;
+        for (u32 t = 0; t < E; t++) {
+            u64 *dst = D + ((size_t)j * E + t) * n;
+            if (t >= lo && t < hi) {
+                memcpy(dst, c1 + (size_t)t * n, n * sizeof(u64));
+            } else {
+                u32 p = ext_prime(c, level, t);
+                orc_modup_digit(c, dc + (size_t)lo * n, lo, hi, p, dst);
+                orc_ntt(c, p, dst);
+            }
+        }
+    }
+    for (u32 r = 0; r < n_rot; r++) {
+        u64 g = galois[r];
+        for (u32 t = 0; t < E; t++) {
+            u32 p = ext_prime(c, level, t);
+            u64 q = c->q[p];
+            u64 pmod = 1;
+            for (u32 m = 0; m < k; m++) pmod = mulmod(pmod, c->q[c->n_q + m] % q, q);
+            for (u32 x = 0; x < n; x++) pt[x] = reduce_signed(pt_coeffs[(size_t)r * n + x], q);
+            orc_ntt(c, p, pt);
+            if (g == 1) {
+                if (t >= L) continue; /* P c is zero on the special primes */
+                for (u32 x = 0; x < n; x++) {
+                    b[x] = mulmod(pmod, c0[(size_t)t * n + x], q);
+                    a[x] = mulmod(pmod, c1[(size_t)t * n + x], q);
+                }
+            } else {
+                for (u32 x = 0; x < n; x++) b[x] = a[x] = 0;
+                for (u32 j = 0; j < beta; j++) {
+                    orc_automorph_ntt(c, p, g, D + ((size_t)j * E + t) * n, sd);
+                    const u64 *k0 = gks[r] + (((size_t)j * 2 + 0) * tot + p) * n;
+                    const u64 *k1 = gks[r] + (((size_t)j * 2 + 1) * tot + p) * n;
+                    for (u32 x = 0; x < n; x++) {
+                        b[x] = addmod(b[x], mulmod(sd[x], k0[x], q), q);
+                        a[x] = addmod(a[x], mulmod(sd[x], k1[x], q), q);
+                    }
+                }
+                if (t < L) {
+                    orc_automorph_ntt(c, p, g, c0 + (size_t)t * n, sd);
+                    for (u32 x = 0; x < n; x++) b[x] = addmod(b[x], mulmod(pmod, sd[x], q), q);
+                }
+            }
+            for (u32 x = 0; x < n; x++) {
+                T[(size_t)t * n + x] = addmod(T[(size_t)t * n + x], mulmod(pt[x], b[x], q), q);
+                T[((size_t)E + t) * n + x] = addmod(T[((size_t)E + t) * n + x], mulmod(pt[x], a[x], q), q);
+            }
+        }
+    }
+    orc_moddown(c, T, level, out);
+    orc_moddown(c, T + (size_t)E * n, level, out + (size_t)L * n);
+    free(dc); free(D); free(T); free(pt); free(sd); free(b); free(a);
+}

@@ -130,6 +130,24 @@ def poly(orc, keys, ct, scale, coeffs, w_scale):
     return h, hs
 
 
+def diag_dense_hoisted(orc, keys, ct, scale, diag_coeffs, pt_scale, in_steps, post_steps, bias_pt=None):
+    """As diag_dense, with the in_steps rotations hoisted: one shared
+    decomposition of the input and one ModDown for the whole weighted sum
+    (orc.hoisted_linear); every nonzero step uses its own Galois key.
+    diag_coeffs: integer plaintext coefficients [n_diag][N] at pt_scale."""
+    elts = [1 if st % (orc.N // 2) == 0 else orc.galois_elt(st) for st in in_steps]
+    gks = [None if g == 1 else keys.gk[g] for g in elts]
+    acc = orc.hoisted_linear(ct, elts, gks, diag_coeffs)
+    level = ct.shape[1] - 1
+    acc = orc.rescale(acc)
+    out_scale = scale * pt_scale / orc.q[level]
+    for st in post_steps:
+        acc = orc.add(acc, rotate(orc, keys, acc, st))
+    if bias_pt is not None:
+        acc = orc.add_plain(acc, bias_pt)
+    return acc, out_scale
+
+
 def diag_dense(orc, keys, ct, scale, diag_pts, pt_scale, in_steps, post_steps, bias_pt=None):
     """diag_pts: NTT-form plaintexts at the ciphertext's level (integer
     encodings at pt_scale); bias_pt: NTT-form plaintext at the level and

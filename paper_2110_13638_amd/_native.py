@@ -63,7 +63,7 @@ class ckks_diag_attrs(ctypes.Structure):
                 ("diag_coeffs", ctypes.POINTER(ctypes.c_int64)), ("pt_scale", ctypes.c_double),
                 ("n_post", ctypes.c_uint32), ("post_steps", ctypes.POINTER(ctypes.c_int32)),
                 ("bias_slots", ctypes.POINTER(ctypes.c_double)), ("n_bias_slots", ctypes.c_uint32),
-                ("bias_coeffs", ctypes.POINTER(ctypes.c_int64))]
+                ("bias_coeffs", ctypes.POINTER(ctypes.c_int64)), ("hoisted", ctypes.c_uint32)]
 
 
 CKKS_NODE_INPUT, CKKS_NODE_LINEAR, CKKS_NODE_DIAG_DENSE, CKKS_NODE_SQUARE, CKKS_NODE_OUTPUT, CKKS_NODE_POLY = range(6)
@@ -120,6 +120,9 @@ _SIGS = {
                                                 _vp]),
     "ckks_linear": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _vp, _dbl, _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_linear_csr_workspace_bytes": (_sz, [_vp, _u32, _u32, _sz, _u32]),
+    "ckks_hoisted_linear_workspace_bytes": (_sz, [_vp, _u32, _u32, _u32]),
+    "ckks_hoisted_linear": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _u32, _u32, _P(_u32), _P(_vp), _vp, _dbl,
+                                          _vp, _sz, _vp]),
     "ckks_linear_csr": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _u32, _P(_u32), _P(_u32), _P(ctypes.c_int64), _dbl,
                                        _P(ckks_ct), _vp, _sz, _vp]),
     "ckks_graph_create": (ctypes.c_int, [_vp, _P(_vp)]),
@@ -353,6 +356,16 @@ def ckks_linear(h, inp, W_dev, w_scale, out, ws, ws_bytes, stream=None):
 
 def ckks_linear_csr_workspace_bytes(h, n_in, n_out, nnz, level):
     return int(lib().ckks_linear_csr_workspace_bytes(h, n_in, n_out, nnz, level))
+
+
+def ckks_hoisted_linear_workspace_bytes(h, B, level, n_rot):
+    return lib().ckks_hoisted_linear_workspace_bytes(h, B, level, n_rot)
+
+
+def ckks_hoisted_linear(h, inp, out, galois_elts, galois_keys, pt_coeffs_dev, pt_scale, ws, ws_bytes, stream=None):
+    n = len(galois_elts)
+    _call("ckks_hoisted_linear", h, inp, out, len(inp), n, _arr(_u32, galois_elts), _arr(_vp, galois_keys),
+          pt_coeffs_dev, pt_scale, ws, ws_bytes, stream)
 
 
 def ckks_linear_csr(h, inp, n_out, row_ptr, col, w, w_scale, out, ws, ws_bytes, stream=None):

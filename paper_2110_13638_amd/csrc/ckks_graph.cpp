@@ -69,6 +69,7 @@ struct Node {
     double pt_scale = 1.0;
     std::vector<double> bias_slots;
     std::vector<i64> bias_coeffs;  // [N], at the output scale
+    bool hoisted = false;
     // polynomial activation
     std::vector<double> coeffs;  // c_0 .. c_d
     // wiring
@@ -313,7 +314,30 @@ int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_ELEMENTWISE, B, nullptr));
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_RESCALE, B, nullptr));
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_NTT, L, nullptr) + al(limb));
-    if (!g->dry) {
+    if (n.hoisted) {
+        // one hoisted call: every diagonal's rotation shares the decomposition of x
+        need(g, al((size_t)nd * limb) + ckks_hoisted_linear_workspace_bytes(g->c, B, l, nd));
+        if (!g->dry) {
+            std::vector<u32> elts(nd);
+            std::vector<const u64 *> keys(nd, nullptr);
+            const i64 half = g->N / 2;
+            for (u32 i = 0; i < nd; i++) {
+                const i64 st = ((n.in_steps[i] % half) + half) % half;
+                elts[i] = st == 0 ? 1u : ckks_galois_elt(g->c, (int32_t)st);
+                if (st != 0) {
+                    auto it = g->gk.find(elts[i]);
+                    if (it == g->gk.end()) return gfail(CKKS_ENOKEY, "graph: hoisted rotation needs its own key");
+                    keys[i] = it->second;
+                }
+            }
+            void *coef = nullptr;
+            GK(ckks::ctx_upload_bytes(g->c, scratch(g), n.diag.data(), (size_t)nd * limb, g->stream, &coef));
+            GK(ckks_hoisted_linear(g->c, in.data(), acc.data(), B, nd, elts.data(), keys.data(),
+                                   (const int64_t *)coef, n.pt_scale, scratch(g) + al((size_t)nd * limb),
+                                   scratch_avail(g) - al((size_t)nd * limb), g->stream));
+            GK(ckks_rescale(g->c, acc.data(), acc.data(), B, scratch(g), scratch_avail(g), g->stream));
+        }
+    } else if (!g->dry) {
         // plaintexts: integer coefficients -> NTT form at level l (diagonals)
         for (u32 i = 0; i < nd; i++) {
             void *coef = nullptr;
@@ -324,7 +348,7 @@ int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
                             g->stream));
         }
     }
-    for (u32 i = 0; i < nd; i++) {
+    for (u32 i = 0; i < nd && !n.hoisted; i++) {
         const std::vector<ckks_ct> *src = &in;
         if (n.in_steps[i] != 0) {
             GK(rotate_all(g, in, rot, tmp, n.in_steps[i]));
@@ -340,7 +364,7 @@ int fire_diag(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
         if (i > 0)
             GK(ckks_add(g->c, acc.data(), prod.data(), acc.data(), B, scratch(g), scratch_avail(g), g->stream));
     }
-    if (!g->dry) GK(ckks_rescale(g->c, acc.data(), acc.data(), B, scratch(g), scratch_avail(g), g->stream));
+    if (!g->dry && !n.hoisted) GK(ckks_rescale(g->c, acc.data(), acc.data(), B, scratch(g), scratch_avail(g), g->stream));
     for (auto &x : acc) x.level = l - 1, x.scale = n.out_scale;
     for (auto &x : rot) x.level = l - 1, x.scale = n.out_scale;
     for (auto &x : tmp) x.level = l - 1, x.scale = n.out_scale;
@@ -508,6 +532,7 @@ extern "C" int ckks_graph_add_node(ckks_graph *g, int kind, const void *attrs, u
             n.diag.assign(a->diag_coeffs, a->diag_coeffs + (size_t)a->n_diag * g->N);
             n.pt_scale = a->pt_scale;
             if (a->n_post) n.post_steps.assign(a->post_steps, a->post_steps + a->n_post);
+            n.hoisted = a->hoisted != 0;
             if (a->bias_coeffs) n.bias_coeffs.assign(a->bias_coeffs, a->bias_coeffs + g->N);
             else if (a->bias_slots) n.bias_slots.assign(a->bias_slots, a->bias_slots + a->n_bias_slots);
             break;

@@ -27,6 +27,7 @@ hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
 hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s);
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s);
+hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s);
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,
                          u64 *const *out_ptrs, u32 n_in, u32 n_out, u32 limbs, u32 in_stride,
                          u32 out_stride, hipStream_t s);
@@ -640,6 +641,7 @@ std::string launch_name(int kind, int op, u32 log_n) {
         case 1: snprintf(b, sizeof b, "%s/N=2^%u", inv_names[op], log_n); break;
         case 2: snprintf(b, sizeof b, "%s/N=2^%u", op >= 0 && op < 15 ? ew_names[op] : "elementwise", log_n); break;
         case 3: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
+        case 5: snprintf(b, sizeof b, "hoisted_rotations/N=2^%u", log_n); break;
         default: snprintf(b, sizeof b, "linear/N=2^%u", log_n); break;
     }
     return b;
@@ -678,7 +680,7 @@ extern "C" int ckks_profile_collect(ckks_launch_record *out, uint32_t cap, uint3
 // ---------------------------------------------------------------------
 namespace {
 struct Launch {
-    int kind;  // 0 fwd, 1 inv, 2 ew, 3 ip
+    int kind;  // 0 fwd, 1 inv, 2 ew, 3 ip, 5 hoisted rotations
     int op;
     size_t off;
     int n;
@@ -757,6 +759,7 @@ struct Plan {
                     case 1: return launch_inv(tb, L.op, (const Item *)p, L.n, st);
                     case 2: return launch_ew(tb, (const EwItem *)p, L.n, L.seed, st);
                     case 3: return launch_ip(tb, (const IpItem *)p, L.n, st);
+                    case 5: return launch_hoist(tb, (const HoItem *)p, L.n, st);
                 }
                 return hipErrorInvalidValue;
             });
@@ -1843,6 +1846,161 @@ extern "C" int ckks_hmult_relin_rescale(const ckks_ctx *c, const uint64_t *rk, c
         out[x].n_poly = 2;
         out[x].level = a[x].level - 1;
         out[x].scale = a[x].scale * b[x].scale / (double)c->primes[a[x].level];
+    }
+    return CKKS_OK;
+}
+
+// ---------------------------------------------------------------------
+// hoisted rotations with plaintext weights
+// ---------------------------------------------------------------------
+extern "C" size_t ckks_hoisted_linear_workspace_bytes(const ckks_ctx *c, uint32_t B, uint32_t level,
+                                                      uint32_t n_rot) {
+    if (!c) return 0;
+    const size_t L = level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
+    const size_t limb = ((size_t)c->N * 8 + 255) & ~(size_t)255;
+    const size_t per_ct = (L + beta * E + 2 * E) * limb;
+    const size_t items = B * (L + beta * E + 2 * (c->n_p + L)) * sizeof(Item) +
+                         E * ((B + kHoCts - 1) / kHoCts) * sizeof(HoItem) + (size_t)n_rot * E * sizeof(Item);
+    return B * per_ct + ((size_t)n_rot * E + 1) * limb + items + 16 * 4096;
+}
+
+extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, uint32_t B, uint32_t n_rot,
+                                   const uint32_t *galois_elts, const uint64_t *const *galois_keys,
+                                   const int64_t *pt_coeffs, double pt_scale, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    CK(check_ctx(c));
+    if (!in || !out || !galois_elts || !pt_coeffs || !B || !n_rot) return fail(CKKS_EINVAL, "hoisted: bad argument");
+    const u32 l = in[0].level, L = l + 1, N = c->N, k = c->n_p, A = c->alpha, E = L + k, beta = (L + A - 1) / A;
+    for (u32 x = 0; x < B; x++) {
+        CK(check_ct(c, in[x], "hoisted"));
+        if (in[x].n_poly != 2) return fail(CKKS_EINVAL, "hoisted: inputs must have 2 polys");
+        if (in[x].level != l) return fail(CKKS_ELEVEL, "hoisted: input levels differ");
+        if (!out[x].data) return fail(CKKS_EINVAL, "hoisted: null output");
+        if (out[x].data == in[x].data) return fail(CKKS_EINVAL, "hoisted: out must not alias the input");
+        if (out[x].limb_stride < L) out[x].limb_stride = L;
+    }
+    for (u32 i = 0; i < n_rot; i++) {
+        const u32 g = galois_elts[i];
+        if (!(g & 1) || g >= 2 * N) return fail(CKKS_EINVAL, "hoisted: bad Galois element %u", g);
+        if (g != 1 && (!galois_keys || !galois_keys[i])) return fail(CKKS_ENOKEY, "hoisted: no key for element %u", g);
+    }
+    if ((size_t)n_rot * 12 > (size_t)N * 8) return fail(CKKS_EINVAL, "hoisted: too many rotations");
+    const size_t need = ckks_hoisted_linear_workspace_bytes(c, B, l, n_rot);
+    if (!ws || ws_bytes < need) return fail(CKKS_ENOMEM, "hoisted: workspace too small: need %zu", need);
+    hipStream_t s = (hipStream_t)stream;
+    Plan P(c, ws);
+    // rotation tables: key bases and Galois elements
+    uint8_t *tab_ws = (uint8_t *)P.limbs(1);
+    std::vector<uint8_t> tab((size_t)n_rot * 12, 0);
+    for (u32 i = 0; i < n_rot; i++) {
+        const u64 *kp = galois_elts[i] == 1 ? nullptr : galois_keys[i];
+        memcpy(tab.data() + (size_t)i * 8, &kp, 8);
+        memcpy(tab.data() + (size_t)n_rot * 8 + (size_t)i * 4, &galois_elts[i], 4);
+    }
+    uint8_t *tab_dev = nullptr;
+    CK(upload(c, tab_ws, tab.data(), tab.size(), s, &tab_dev));
+    // plaintexts over Q_l U P in NTT form
+    u64 *pts = P.limbs((size_t)n_rot * E);
+    std::vector<Item> ptl, isc, modup, scl, mdown;
+    for (u32 i = 0; i < n_rot; i++)
+        for (u32 t = 0; t < E; t++) {
+            Item it = item0();
+            it.in[0] = (const u64 *)(pt_coeffs + (size_t)i * N);
+            it.out = pts + ((size_t)i * E + t) * N;
+            it.prime = t < L ? t : c->n_q + (t - L);
+            ptl.push_back(it);
+        }
+    std::vector<HoItem> ho;
+    std::vector<u64 *> accs(B);
+    std::vector<u64 *> exts(B);
+    for (u32 x = 0; x < B; x++) {
+        u64 *dcoef = P.limbs(L);
+        u64 *ext = P.limbs((size_t)beta * E);
+        u64 *acc = P.limbs((size_t)2 * E);
+        accs[x] = acc;
+        exts[x] = ext;
+        for (u32 i = 0; i < L; i++) {
+            const u32 j = i / A, lo = j * A, sz = std::min(A, L - lo);
+            Item it = item0();
+            it.in[0] = limb(c, in[x], 1, i);
+            it.out = dcoef + (size_t)i * N;
+            it.prime = i;
+            it.b = 2;
+            it.c = j * A + sz - 1;
+            it.a = i - lo;
+            isc.push_back(it);
+        }
+        for (u32 j = 0; j < beta; j++) {
+            const u32 lo = j * A, sz = std::min(A, L - lo);
+            for (u32 t = 0; t < E; t++) {
+                if (t >= lo && t < lo + sz) continue;
+                Item it = item0();
+                it.in[0] = dcoef + (size_t)lo * N;
+                it.a = lo;
+                it.b = sz;
+                it.c = j;
+                it.v = 1;
+                it.prime = t < L ? t : c->n_q + (t - L);
+                it.out = ext + ((size_t)j * E + t) * N;
+                modup.push_back(it);
+            }
+        }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 m = 0; m < k; m++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L + m) * N;
+                it.out = (u64 *)it.in[0];
+                it.prime = c->n_q + m;
+                scl.push_back(it);
+            }
+        for (u32 cc = 0; cc < 2; cc++)
+            for (u32 i = 0; i < L; i++) {
+                Item it = item0();
+                it.in[0] = acc + ((size_t)cc * E + L) * N;
+                it.a = c->n_q;
+                it.b = k;
+                it.in[1] = acc + ((size_t)cc * E + i) * N;
+                it.prime = i;
+                it.out = limb(c, out[x], cc, i);
+                mdown.push_back(it);
+            }
+    }
+    for (u32 g0 = 0; g0 < B; g0 += kHoCts) {
+        const u32 n = std::min<u32>(kHoCts, B - g0);
+        for (u32 t = 0; t < E; t++) {
+            HoItem h;
+            memset(&h, 0, sizeof h);
+            h.n_ct = n;
+            h.prime = t < L ? t : c->n_q + (t - L);
+            h.pos = t;
+            h.E = E;
+            h.L = L;
+            h.beta = beta;
+            h.alpha = A;
+            h.n_rot = n_rot;
+            h.keys = (const u64 *const *)tab_dev;
+            h.galois = (const u32 *)(tab_dev + (size_t)n_rot * 8);
+            h.pts = pts;
+            for (u32 q = 0; q < n; q++) {
+                h.ext[q] = exts[g0 + q];
+                h.c0[q] = t < L ? limb(c, in[g0 + q], 0, t) : nullptr;
+                h.c1[q] = limb(c, in[g0 + q], 1, 0);
+                h.acc[q] = accs[g0 + q];
+            }
+            ho.push_back(h);
+        }
+    }
+    P.add(0, F_INT, ptl);
+    P.add(1, I_SCALE, isc);
+    P.add(0, F_MODUP, modup);
+    P.add(5, 0, ho);
+    P.add(1, I_COPY, scl);
+    P.add(0, F_MODDOWN, mdown);
+    CK(P.run(ws_bytes, s));
+    for (u32 x = 0; x < B; x++) {
+        out[x].n_poly = 2;
+        out[x].level = l;
+        out[x].scale = in[x].scale * pt_scale;
     }
     return CKKS_OK;
 }

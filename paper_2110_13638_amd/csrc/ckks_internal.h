@@ -104,4 +104,22 @@ struct IpItem {
     u32 n_ct, prime, beta, own_digit, E, pos;
 };
 
+// Hoisted rotations with plaintext weights (k_hoist): one item per target
+// limb `pos` of the extended basis and up to kHoCts ciphertexts of one
+// level. For every rotation i the ModUp'd digits of the ciphertext's second
+// polynomial are read through the NTT-domain automorphism g_i and
+// multiplied by that rotation's Galois key; P sigma(c0) joins the b-sum on
+// data limbs; the weighted sums over all rotations go to acc [2][E][N].
+constexpr int kHoCts = 4;
+struct HoItem {
+    const u64 *ext[kHoCts];  // ModUp'd digits of c1, [digit][E][N]
+    const u64 *c0[kHoCts];   // limb `pos` of c0 (data limbs only)
+    const u64 *c1[kHoCts];   // limb 0 of c1 (own-digit limbs)
+    u64 *acc[kHoCts];        // [2][E][N]
+    const u64 *const *keys;  // [n_rot] Galois key bases ([digits][2][n_prim][N])
+    const u32 *galois;       // [n_rot] Galois elements (1 = identity)
+    const u64 *pts;          // [n_rot][E][N] plaintexts over Q_l U P (NTT form)
+    u32 n_ct, prime, pos, E, L, beta, alpha, n_rot;
+};
+
 }  // namespace ckks

@@ -343,7 +343,8 @@ enum FwdOp : int {
 enum InvOp : int {
     I_COPY = 0,     // in[0] -> INTT -> out
     I_MUL = 1,      // in[0] * in[1] -> INTT -> out
-    I_SCALE = 2,    // in[0] -> INTT -> * (hat_m^-1 mod p_m, m = a | P^-1 mod q when b = 1) -> out
+    I_SCALE = 2,    // in[0] -> INTT -> * (hat_m^-1 mod p_m, m = a | P^-1 mod q when b = 1 |
+                    //   the ModUp source factor hat_i^-1 when b = 2) -> out
     I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out
 };
 
@@ -544,8 +545,11 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
             for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
         }
     } else if constexpr (OP == I_SCALE) {
-        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q
-        const u64 inv = it.b ? pc.pinv : tb.moddown[2 * it.a], inv_sh = it.b ? pc.pinv_sh : tb.moddown[2 * it.a + 1];
+        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q;
+        // b == 2: hat_i^-1 of ModUp digit block c, position a (a ModUp source)
+        const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
+        const u64 inv = it.b == 1 ? pc.pinv : it.b == 2 ? blk[2 * it.a] : tb.moddown[2 * it.a];
+        const u64 inv_sh = it.b == 1 ? pc.pinv_sh : it.b == 2 ? blk[2 * it.a + 1] : tb.moddown[2 * it.a + 1];
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
     }
@@ -712,6 +716,90 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
             }
             it.acc[c][(size_t)it.pos * N + x] = s0[c].reduce(pc);
             it.acc[c][((size_t)it.E + it.pos) * N + x] = s1[c].reduce(pc);
+        }
+    }
+}
+
+// source index of NTT slot j under X -> X^g (slot k holds a(psi^(2 brv(k) + 1)))
+__device__ __forceinline__ u32 automorph_src(u32 j, u32 g, u32 log_n) {
+    const u32 two_n_mask = (2u << log_n) - 1;
+    const u32 e = 2 * brev_n(j, log_n) + 1;
+    const u32 eg = (u32)(((u64)e * (u64)g) & two_n_mask);
+    return brev_n((eg - 1) >> 1, log_n);
+}
+
+// Hoisted rotations with plaintext weights; see HoItem. The 128-bit
+// weighted sums are reduced every kHoFold rotations (each term < q^2).
+constexpr int kHoFold = 8;
+template <int kEwPer>
+__global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const HoItem it = items[iid];
+    const PrimeConst pc = tb.pc[it.prime];
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+    const bool data = it.pos < it.L;
+    const u32 own = data ? it.pos / it.alpha : 0xFFFFFFFFu;
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (x >= N) break;
+        Acc128 tb_[kHoCts], ta_[kHoCts];
+        for (u32 i = 0; i < it.n_rot; i++) {
+            const u32 g = it.galois[i];
+            const u64 w = it.pts[((size_t)i * it.E + it.pos) * N + x];
+            if (g == 1) {
+                // identity: P (c0, c1) on data limbs, nothing on special limbs
+                if (data) {
+#pragma unroll
+                    for (int c = 0; c < kHoCts; c++) {
+                        if ((u32)c >= it.n_ct) break;
+                        const u64 p0 = shoup(it.c0[c][x], pc.pmod, pc.pmod_sh, pc.q);
+                        const u64 p1 = shoup(it.c1[c][(size_t)it.pos * N + x], pc.pmod, pc.pmod_sh, pc.q);
+                        tb_[c].mac(p0, w);
+                        ta_[c].mac(p1, w);
+                    }
+                }
+            } else {
+                const u32 src = automorph_src(x, g, tb.log_n);
+                const u64 *key = it.keys[i] + (size_t)it.prime * N + x;
+                Acc128 sb[kHoCts], sa[kHoCts];
+                for (u32 j = 0; j < it.beta; j++) {
+                    const u64 k0 = key[(size_t)(2 * j) * kstride], k1 = key[(size_t)(2 * j + 1) * kstride];
+#pragma unroll
+                    for (int c = 0; c < kHoCts; c++) {
+                        if ((u32)c >= it.n_ct) break;
+                        const u64 v = (j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                                 : it.ext[c][((size_t)j * it.E + it.pos) * N + src];
+                        sb[c].mac(v, k0);
+                        sa[c].mac(v, k1);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < kHoCts; c++) {
+                    if ((u32)c >= it.n_ct) break;
+                    u64 rb = sb[c].reduce(pc);
+                    if (data) rb = addm(rb, shoup(it.c0[c][src], pc.pmod, pc.pmod_sh, pc.q), pc.q);
+                    tb_[c].mac(rb, w);
+                    ta_[c].mac(sa[c].reduce(pc), w);
+                }
+            }
+            if ((i & (kHoFold - 1)) == kHoFold - 1) {
+#pragma unroll
+                for (int c = 0; c < kHoCts; c++) {
+                    tb_[c] = Acc128{tb_[c].reduce(pc), 0};
+                    ta_[c] = Acc128{ta_[c].reduce(pc), 0};
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kHoCts; c++) {
+            if ((u32)c >= it.n_ct) break;
+            it.acc[c][(size_t)it.pos * N + x] = tb_[c].reduce(pc);
+            it.acc[c][((size_t)it.E + it.pos) * N + x] = ta_[c].reduce(pc);
         }
     }
 }
@@ -908,6 +996,11 @@ hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, 
         case 3: hipLaunchKernelGGL(k_ew<8>, dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n, seed); break;
         default: hipLaunchKernelGGL(k_ew<4>, dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n, seed);
     }
+    return hipGetLastError();
+}
+hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hoist<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
     return hipGetLastError();
 }
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {

@@ -55,7 +55,8 @@ class Graph:
         W = np.asarray(W, dtype=np.float64)
         return self.linear([[(i, W[j, i]) for i in range(W.shape[1])] for j in range(W.shape[0])], w_scale, bias)
 
-    def diag_dense(self, diag_coeffs, in_steps, pt_scale, post_steps=(), bias_slots=None, bias_coeffs=None):
+    def diag_dense(self, diag_coeffs, in_steps, pt_scale, post_steps=(), bias_slots=None, bias_coeffs=None,
+                   hoisted=False):
         P = ctypes.POINTER
         d = np.ascontiguousarray(diag_coeffs, dtype=np.int64)
         st = np.ascontiguousarray(in_steps, dtype=np.int32)
@@ -66,7 +67,8 @@ class Graph:
                                 pt_scale, len(post_steps), ps.ctypes.data_as(P(ctypes.c_int32)) if ps is not None
                                 else None, bs.ctypes.data_as(P(ctypes.c_double)) if bs is not None else None,
                                 len(bs) if bs is not None else 0,
-                                bc.ctypes.data_as(P(ctypes.c_int64)) if bc is not None else None)
+                                bc.ctypes.data_as(P(ctypes.c_int64)) if bc is not None else None,
+                                1 if hoisted else 0)
         return nat.ckks_graph_add_node(self.g, nat.CKKS_NODE_DIAG_DENSE, a)
 
     def square(self):

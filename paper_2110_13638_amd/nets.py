@@ -194,9 +194,11 @@ def yield_steps(ws, W):
     return steps
 
 
-def build_yield(ctx, ws, bs, n_ct, in_level, scale, diag_coeffs=None, bias_coeffs=None):
+def build_yield(ctx, ws, bs, n_ct, in_level, scale, diag_coeffs=None, bias_coeffs=None, hoisted=False):
     """diag_coeffs / bias_coeffs: optional pre-encoded integer plaintexts
-    per layer (otherwise encoded here with the library's encoder)."""
+    per layer (otherwise encoded here with the library's encoder). hoisted:
+    each layer's rotations share one decomposition and one ModDown (every
+    step then needs its own Galois key: galois_for_steps(..., direct=True))."""
     W = yield_windows(ctx.N // 2)
     g = Graph(ctx)
     prev = g.input(n_ct, in_level, scale)
@@ -207,9 +209,9 @@ def build_yield(ctx, ws, bs, n_ct, in_level, scale, diag_coeffs=None, bias_coeff
         else:
             dc = diag_coeffs[l]
         if bias_coeffs is None:
-            node = g.diag_dense(dc, in_steps, scale, post, bias_slots=yield_bias(b, W))
+            node = g.diag_dense(dc, in_steps, scale, post, bias_slots=yield_bias(b, W), hoisted=hoisted)
         else:
-            node = g.diag_dense(dc, in_steps, scale, post, bias_coeffs=bias_coeffs[l])
+            node = g.diag_dense(dc, in_steps, scale, post, bias_coeffs=bias_coeffs[l], hoisted=hoisted)
         g.edge(prev, node)
         prev = node
         if l < len(ws) - 1:

@@ -123,3 +123,50 @@ def test_yield_full_size(mods):
     err = _rel_err(got[: len(want)], want)
     print("yield full size: max relative error 2^%.1f over %d windows" % (np.log2(err), len(want)))
     assert err <= TOL
+
+
+def test_yield_full_size_hoisted(mods):
+    ckks, nets = mods
+    logn = 14
+    primes = O.find_primes(logn, [60] + [40] * 5 + [60])
+    ctx = ckks.Context(logn, primes[:6], primes[6:], 6).keygen(31)
+    orc = O.Oracle(logn, primes[:6], primes[6:], 6)
+    x, ws, bs = S.yield_inputs(n_windows=4096)
+    slots = ctx.N // 2
+    Wn = nets.yield_windows(slots)
+    steps = nets.yield_steps(ws, Wn)
+    elts = nets.galois_for_steps(ctx, steps, direct=True)
+    keys = ON.Keys(orc, 31, elts)
+    for ge in elts:
+        ctx.add_galois_key(ge, nets.galois_key_seed(31 + 3, ge))
+    packed = PN.yield_pack(x, slots)
+    n_ct = packed.shape[0]
+    ms = [E.encode(packed[c], SCALE, ctx.N) for c in range(n_ct)]
+    cts = [ctx.encrypt(ctx.pt_from_coeffs(m, 5, SCALE), seed=32, obj=c) for c, m in enumerate(ms)]
+    dcs, bcs = [], []
+    s, lvl = SCALE, 5
+    periods = [256, 64, 16]
+    for l in range(3):
+        dcs.append(np.stack([E.encode(di, SCALE, ctx.N) for di in PN.yield_diagonals(ws[l], periods[l], Wn)]))
+        out_scale = s * SCALE / orc.q[lvl]
+        bcs.append(E.encode(PN.yield_bias_vector(bs[l], Wn), out_scale, ctx.N))
+        s, lvl = out_scale, lvl - 1
+        if l < 2:
+            s, lvl = s * s / orc.q[lvl], lvl - 1
+    g = nets.build_yield(ctx, ws, bs, n_ct, 5, SCALE, diag_coeffs=dcs, bias_coeffs=bcs, hoisted=True)
+    outs = g.run(cts)
+    print("yield full size, hoisted: %d ciphertexts evaluated, %d Galois keys" % (n_ct, len(elts)), flush=True)
+    y = orc.encrypt(keys.pk, orc.reduce_int(ms[0], 5), 5, 32, 0)
+    s = SCALE
+    for l in range(3):
+        in_steps, post = PN.yield_layer_plan(ws[l].shape[1], ws[l].shape[0], periods[l], Wn)
+        lv = y.shape[1] - 1
+        y, s = ON.diag_dense_hoisted(orc, keys, y, s, dcs[l], SCALE, in_steps, post, orc.reduce_int(bcs[l], lv - 1))
+        if l < 2:
+            y, s = ON.square(orc, keys, y, s)
+    assert outs[0].scale == s and np.array_equal(outs[0].residues(), y)
+    want = PN.yield_math(x, ws, bs)[:, 0]
+    got = np.concatenate([ctx.decrypt(outs[c], Wn).real for c in range(n_ct)])
+    err = _rel_err(got[: len(want)], want)
+    print("yield full size, hoisted: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL

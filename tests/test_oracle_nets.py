@@ -100,3 +100,71 @@ def test_polynomial_activation(which):
     want = PN.poly_eval(coeffs, x)
     err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
     assert err <= TOL, err
+
+
+def _hoist_setup(steps):
+    logn = 12
+    primes = O.find_primes(logn, [60, 40, 40, 60])
+    orc = O.Oracle(logn, primes[:3], primes[3:], 3)
+    keys = ON.Keys(orc, 5, sorted({orc.galois_elt(s) for s in steps if s}))
+    return orc, keys
+
+
+def test_hoisted_identity_is_plaintext_product():
+    # g = 1 only: ModDown(pt * P c) = pt * c exactly
+    orc, keys = _hoist_setup([0])
+    scale = 2.0 ** 40
+    z = S.uniform_slots(7, orc.N // 2)
+    ct = _encrypt(orc, keys, z, 2, scale, 3, 0)
+    d = S.uniform_slots(8, orc.N // 2)
+    m = E.encode(d, scale, orc.N)
+    got = orc.hoisted_linear(ct, [1], [None], m[None, :])
+    assert np.array_equal(got, orc.mul_plain(ct, orc.reduce_int(m, 2)))
+
+
+def test_hoisted_sum_decodes_to_weighted_rotations():
+    steps = [0, 1, 5, 100, 2047]
+    orc, keys = _hoist_setup(steps)
+    scale = 2.0 ** 40
+    z = S.uniform_slots(9, orc.N // 2)
+    ct = _encrypt(orc, keys, z, 2, scale, 3, 0)
+    ds = [S.uniform_slots(20 + i, orc.N // 2) for i in range(len(steps))]
+    coeffs = np.stack([E.encode(d, scale, orc.N) for d in ds])
+    y, s = ON.diag_dense_hoisted(orc, keys, ct, scale, coeffs, scale, steps, [])
+    got = _decrypt(orc, keys, y, s, orc.N // 2)
+    want = sum(d * np.roll(z, -st) for d, st in zip(ds, steps))
+    err = np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err
+    # a dropped or misplaced rotation term is caught
+    bad = sum(d * np.roll(z, -st) for d, st in zip(ds, [0, 1, 5, 101, 2047]))
+    assert np.max(np.abs(got - bad)) > 1e-3
+
+
+def test_yield_network_hoisted_small_ring():
+    logn = 12
+    primes = O.find_primes(logn, [60] + [40] * 5 + [60])
+    orc = O.Oracle(logn, primes[:6], primes[6:], 6)
+    x, ws, bs = S.yield_inputs(n_windows=8)
+    slots = orc.N // 2
+    Wn = PN.yield_layout(slots)
+    periods = [256, 64, 16]
+    plans = [PN.yield_layer_plan(ws[l].shape[1], ws[l].shape[0], periods[l], Wn) for l in range(3)]
+    steps = {st for a, b in plans for st in a + b if st}
+    keys = ON.Keys(orc, 2, sorted(orc.galois_elt(st) for st in steps))
+    scale = 2.0 ** 40
+    packed = PN.yield_pack(x, slots)
+    y = _encrypt(orc, keys, packed[0], 5, scale, 9, 0)
+    s = scale
+    for l in range(3):
+        in_steps, post = plans[l]
+        lv = y.shape[1] - 1
+        coeffs = np.stack([E.encode(di, scale, orc.N) for di in PN.yield_diagonals(ws[l], periods[l], Wn)])
+        out_scale = s * scale / orc.q[lv]
+        bias = orc.reduce_int(E.encode(PN.yield_bias_vector(bs[l], Wn), out_scale, orc.N), lv - 1)
+        y, s = ON.diag_dense_hoisted(orc, keys, y, s, coeffs, scale, in_steps, post, bias)
+        if l < 2:
+            y, s = ON.square(orc, keys, y, s)
+    got = _decrypt(orc, keys, y, s, Wn)
+    want = PN.yield_math(x, ws, bs)[:Wn, 0]
+    err = np.max(np.abs(got[: len(want)] - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err

@@ -483,8 +483,8 @@ void ckks_plan_destroy(ckks_plan *plan);
  * issued after the call (not thread safe against concurrent calls on the
  * same context).
  *   CKKS_TUNE_NTT_WIDE   0 (default): 16 residues per thread in the NTT
- *                        kernels for N < 2^15, 32 at 2^15; 1: twice that
- *                        (N >= 2^11 only).
+ *                        kernels for N < 2^15 (32 at 2^15); 1: 32 residues
+ *                        per thread (N in 2^11..2^14 only).
  *   CKKS_TUNE_EW_LOG     log2 of residues per thread in the streaming
  *                        (element-wise, key-switch inner product) kernels:
  *                        1, 2 (default) or 3.

@@ -38,7 +38,10 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
                                  u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
 
 // kernel op codes (mirrors of the enums in the kernel file)
-enum { F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_RELIN = 4, F_SAMPLE = 5, F_INT = 6, F_RELIN_RS = 7 };
+enum {
+    F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_RELIN = 4, F_SAMPLE = 5, F_INT = 6, F_RELIN_RS = 7,
+    F_MODUP_S1 = 8, F_RELIN_P1 = 12, F_RELIN_RS_P1 = 14
+};
 enum { I_COPY = 0, I_MUL = 1, I_SCALE = 2, I_DECRYPT = 3 };
 enum {
     EW_ADD = 0, EW_SUB = 1, EW_MUL = 2, EW_MUL_CONST = 3, EW_ADD_CONST = 4, EW_TENSOR = 5,
@@ -485,7 +488,7 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
     switch (knob) {
         case CKKS_TUNE_NTT_WIDE:
             if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: NTT_WIDE takes 0 or 1");
-            if (value && c->log_n < 11) return fail(CKKS_EINVAL, "set_tuning: NTT_WIDE needs N >= 2^11");
+            if (value && (c->log_n < 11 || c->log_n > 14)) return fail(CKKS_EINVAL, "set_tuning: NTT_WIDE needs N in 2^11..2^14");
             c->tb.ntt_wide = (u32)value;
             return CKKS_OK;
         case CKKS_TUNE_EW_LOG:
@@ -629,7 +632,9 @@ struct ProfRec {
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 const char *fwd_names[] = {"ntt_fwd", "ntt_fwd_modup", "ntt_fwd_rescale", "ntt_fwd_moddown",
-                           "ntt_fwd_moddown_z", "ntt_fwd_sample", "ntt_fwd_int", "ntt_fwd_relin_rescale"};
+                           "ntt_fwd_moddown_z", "ntt_fwd_sample", "ntt_fwd_int", "ntt_fwd_relin_rescale",
+                           "ntt_fwd_modup", "ntt_fwd_modup", "ntt_fwd_modup", "ntt_fwd_modup",
+                           "ntt_fwd_moddown_z", "ntt_fwd_moddown_z", "ntt_fwd_relin_rescale", "ntt_fwd_relin_rescale"};
 const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_scale", "ntt_inv_decrypt"};
 const char *ew_names[] = {"ew_add", "ew_sub", "ew_mul", "ew_mul_const", "ew_add_const", "ew_tensor", "ew_copy",
                           "ew_automorph", "ew_neg", "ew_keygen", "ew_encrypt", "ew_square_s", "ew_hmult_fin",
@@ -773,6 +778,21 @@ struct Plan {
     }
 };
 
+// ModUp items (sources pre-multiplied by hat_i^-1), one launch per digit
+// size: sizes 1..4 use the kernels with the size fixed at compile time
+void add_modup(Plan &P, const std::vector<Item> &v) {
+    std::vector<Item> by[5];
+    for (const Item &it : v) by[it.b <= 4 ? it.b : 0].push_back(it);
+    for (u32 sz = 1; sz <= 4; sz++) P.add(0, F_MODUP_S1 + (int)sz - 1, by[sz]);
+    P.add(0, F_MODUP, by[0]);
+}
+// ModDown + rescale kernel for the context's special-prime count
+int relin_op(const ckks_ctx *c, bool rescale) {
+    const int base = rescale ? F_RELIN_RS_P1 : F_RELIN_P1;
+    if (c->n_p <= 2) return base + (int)c->n_p - 1;
+    return rescale ? F_RELIN_RS : F_RELIN;
+}
+
 // one ciphertext's share of the key-switch inner product
 struct IpCt {
     u32 level;
@@ -871,10 +891,14 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
         u64 *ext = P.limbs((size_t)beta * E);
         u64 *acc = P.limbs((size_t)2 * E);
         for (u32 i = 0; i < L; i++) {
+            const u32 j = i / A, lo = j * A, sz = std::min(A, L - lo);
             Item it = item0();
             it.in[0] = J.dl[i];
             it.out = dcoef + (size_t)i * N;
             it.prime = i;
+            it.b = 2;  // times hat_i^-1 of its digit: the ModUp source
+            it.c = j * A + sz - 1;
+            it.a = i - lo;
             icopy.push_back(it);
         }
         for (u32 j = 0; j < beta; j++) {
@@ -921,8 +945,8 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
             }
     }
     add_ip_items(c, ip, ipc, key);
-    P.add(1, I_COPY, icopy);
-    P.add(0, F_MODUP, modup);
+    P.add(1, I_SCALE, icopy);
+    add_modup(P, modup);
     P.add(3, 0, ip);
     P.add(1, I_COPY, ipP);
     P.add(0, F_MODDOWN, mdown);
@@ -1815,11 +1839,11 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
     }
     add_ip_items(c, ip, ipc, rk);
     P.add(1, I_MUL, mul);
-    P.add(0, F_MODUP, modup);
+    add_modup(P, modup);
     P.add(3, 0, ip);
     P.add(1, I_SCALE, scale);
     P.add(2, 0, tt);
-    P.add(0, fuse ? F_RELIN_RS : F_RELIN, fin);
+    P.add(0, relin_op(c, fuse), fin);
     if (!fuse) P.add(2, 0, tail);
     return CKKS_OK;
 }
@@ -1992,7 +2016,7 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
     }
     P.add(0, F_INT, ptl);
     P.add(1, I_SCALE, isc);
-    P.add(0, F_MODUP, modup);
+    add_modup(P, modup);
     P.add(5, 0, ho);
     P.add(1, I_COPY, scl);
     P.add(0, F_MODDOWN, mdown);

@@ -1,562 +1,10 @@
-// gfx950 kernels for RNS-CKKS ciphertext arithmetic.
-//
-// Every kernel works on u64 residues in [0, q) (limb-major: one limb = N
-// contiguous residues modulo one prime). Modular arithmetic runs on the
-// VALU (no MFMA: the work is modular integer arithmetic, not a float
-// contraction):
-//   - fixed operands (twiddles, conversion constants) use Shoup's
-//     multiplication with a precomputed companion floor(w 2^64 / q), lazy
-//     in [0, 2q);
-//   - variable x variable products use a 128-bit product and an exact
-//     128-bit Barrett reduction with floor(2^128 / q);
-//   - NTT butterflies keep Harvey's lazy ranges ([0, 4q) forward, [0, 2q)
-//     inverse), so primes must stay below 2^61.
-//
-// NTT-shaped kernels: one workgroup per limb. N = 2^LOGN residues live in
-// registers, E = 2^LOGE per thread (T = N / E threads). The log N butterfly
-// stages are grouped in phases of LOGE stages; inside a phase every thread
-// owns the whole butterfly closure of its E residues, so a phase runs with
-// no communication. Between phases the residues are re-distributed through
-// LDS (two 32-bit half-word rounds, one pad word per 32 to spread banks).
-// Loads and stores use the coalesced layout "residue c of thread t is
-// index c*T + t"; an element-wise prologue (what to load) and epilogue
-// (what to store) fuse basis conversions, rescale and key-switch steps
-// into the transform so intermediate limbs do not round-trip through HBM.
-#include <type_traits>
-
-#include "ckks_internal.h"
+// gfx950 kernels for RNS-CKKS ciphertext arithmetic: element-wise ops,
+// the key-switch inner product, hoisted rotations, linear layers, and the
+// launch dispatch to the per-ring NTT translation units (ckks_ntt_*.hip).
+// Modular arithmetic and the NTT engine are in ckks_device.h.
+#include "ckks_device.h"
 
 namespace ckks {
-
-// ---------------------------------------------------------------------
-// modular arithmetic
-// ---------------------------------------------------------------------
-__device__ __forceinline__ u64 shoup_lazy(u64 y, u64 w, u64 wsh, u64 q) {
-    u64 qt = __umul64hi(y, wsh);
-    return y * w - qt * q;  // in [0, 2q) for any y < 2^64 when w < q
-}
-__device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
-__device__ __forceinline__ u64 shoup(u64 y, u64 w, u64 wsh, u64 q) {
-    return csub(shoup_lazy(y, w, wsh, q), q);
-}
-__device__ __forceinline__ u64 addm(u64 a, u64 b, u64 q) { return csub(a + b, q); }
-__device__ __forceinline__ u64 subm(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
-
-// Exact floor((hi:lo) * floor(2^128/q) / 2^128) is either floor(z/q) or one
-// less, so one conditional subtraction completes the reduction.
-__device__ __forceinline__ u64 barrett128(u64 lo, u64 hi, const PrimeConst &pc) {
-    u64 c1 = __umul64hi(lo, pc.br_lo);
-    u64 t_lo = lo * pc.br_hi, t_hi = __umul64hi(lo, pc.br_hi);
-    u64 s = t_lo + c1;
-    u64 k1 = s < c1;
-    u64 u_lo = hi * pc.br_lo, u_hi = __umul64hi(hi, pc.br_lo);
-    u64 s2 = s + u_lo;
-    u64 k2 = s2 < u_lo;
-    u64 quot = hi * pc.br_hi + t_hi + u_hi + k1 + k2;
-    u64 r = lo - quot * pc.q;
-    return csub(r, pc.q);
-}
-__device__ __forceinline__ u64 mulm(u64 a, u64 b, const PrimeConst &pc) {
-    return barrett128(a * b, __umul64hi(a, b), pc);
-}
-struct Acc128 {
-    u64 lo = 0, hi = 0;
-    __device__ __forceinline__ void mac(u64 a, u64 b) {
-        u64 l = a * b, h = __umul64hi(a, b);
-        lo += l;
-        hi += h + (lo < l);
-    }
-    __device__ __forceinline__ void add(u64 a) {
-        lo += a;
-        hi += (lo < a);
-    }
-    __device__ __forceinline__ u64 reduce(const PrimeConst &pc) const { return barrett128(lo, hi, pc); }
-};
-// x < 2^64 reduced mod q with floor(2^64/q): quotient estimate off by at most one
-__device__ __forceinline__ u64 reduce64(u64 x, const PrimeConst &pc) {
-    u64 qt = __umul64hi(x, pc.mu);
-    return csub(x - qt * pc.q, pc.q);
-}
-__device__ __forceinline__ u64 reduce_signed(i64 v, const PrimeConst &pc) {
-    if (v >= 0) return reduce64((u64)v, pc);
-    u64 m = reduce64((u64)(-(v + 1)) + 1, pc);
-    return m == 0 ? 0 : pc.q - m;
-}
-
-// (r - h) mod q for r, h in [0, q_l): branch-free (one 64-bit reduction)
-__device__ __forceinline__ u64 centered_mod(u64 r, u64 h, const PrimeConst &pc) {
-    const bool ge = r >= h;
-    const u64 m = reduce64(ge ? r - h : h - r, pc);
-    return ge ? m : (m ? pc.q - m : 0);
-}
-
-// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
-// ---------------------------------------------------------------------
-// Buffer-resource access to limbs: one VGPR offset (the thread's residue)
-// plus a scalar byte offset per residue slot, so the 32 loads of a
-// workgroup-per-limb kernel share one address register. Out-of-range
-// offsets read zero / drop the write instead of faulting.
-// ---------------------------------------------------------------------
-typedef __attribute__((ext_vector_type(2))) unsigned u32x2;
-struct Buf {
-    __amdgpu_buffer_rsrc_t r;
-    __device__ __forceinline__ explicit Buf(const u64 *p)
-        : r(__builtin_amdgcn_make_buffer_rsrc((void *)p, 0, 0x7fffffff, 0x00020000)) {}
-    __device__ __forceinline__ u64 ld(u32 voff, u32 soff) const {
-        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
-        return ((u64)v.y << 32) | v.x;
-    }
-    __device__ __forceinline__ void st(u32 voff, u32 soff, u64 x) const {
-        u32x2 v;
-        v.x = (u32)x;
-        v.y = (u32)(x >> 32);
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, 0);
-    }
-};
-
-// ---------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11) and the samplers
-// ---------------------------------------------------------------------
-__device__ __forceinline__ uint4 philox(u32 c0, u32 c1, u32 c2, u32 c3, u64 seed) {
-    u32 k0 = (u32)seed, k1 = (u32)(seed >> 32);
-#pragma unroll
-    for (int r = 0; r < 10; r++) {
-        u32 hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-        u32 hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
-        u32 n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-constexpr u32 kNoLimb = 0xFFFFFFFFu;
-enum SampleKind : u32 { kTernary = 0, kCbd = 1 };
-__device__ __forceinline__ i64 sample_small(u32 kind, u32 j, u32 obj, u32 tag, u64 seed) {
-    uint4 w = philox(j, kNoLimb, obj, tag, seed);
-    if (kind == kTernary) return (i64)(((u64)w.x * 3u) >> 32) - 1;
-    return (i64)__popc(w.x & 0x1FFFFFu) - (i64)__popc(w.y & 0x1FFFFFu);
-}
-__device__ __forceinline__ u64 sample_uniform(u32 j, u32 limb, u32 obj, u32 tag, u64 seed,
-                                              const PrimeConst &pc) {
-    uint4 w = philox(j, limb, obj, tag, seed);
-    u64 lo = ((u64)w.y << 32) | w.x, hi = ((u64)w.w << 32) | w.z;
-    return barrett128(lo, hi, pc);
-}
-
-// ---------------------------------------------------------------------
-// NTT engine
-// ---------------------------------------------------------------------
-// butterflies issued between scheduling barriers: bounds how many twiddle
-// pairs the scheduler keeps in flight (register pressure at 32 residues per
-// thread)
-constexpr int kTwiddleChunk = 8;
-// residues converted per pass over the source limbs of a basis conversion
-constexpr int kConvChunk = 8;
-// residues whose epilogue inputs are loaded together before any is stored
-constexpr int kEpiChunk = 8;
-
-template <int LOGN, int LOGE>
-struct Ntt {
-    static constexpr int N = 1 << LOGN;
-    static constexpr int E = 1 << LOGE;
-    static constexpr int T = N >> LOGE;
-    static constexpr int NPH = (LOGN + LOGE - 1) / LOGE;
-    static constexpr int LDS_WORDS = N + (N >> 5);
-
-    static __host__ __device__ __forceinline__ constexpr int width(int p) {
-        return (LOGN - p * LOGE) < LOGE ? (LOGN - p * LOGE) : LOGE;
-    }
-    // Residue index held in register `reg` by thread `tid` during phase p:
-    // index = base(p, tid) | off(p, reg), the two parts having disjoint
-    // bits (thread bits vs. register bits), so index = base + off and the
-    // LDS pad below also splits: pad(base | off) = pad(base) + pad(off).
-    static __device__ __forceinline__ u32 base(int p, u32 tid) {
-        const int s0 = p * LOGE, w = width(p), lo_bits = LOGN - s0 - w;
-        const u32 gamma = (w == LOGE) ? tid : (tid << (LOGE - w));
-        const u32 lo = gamma & ((1u << lo_bits) - 1);
-        const u32 hi = gamma >> lo_bits;
-        return (hi << (LOGN - s0)) | lo;
-    }
-    static __device__ __forceinline__ constexpr u32 off(int p, int reg) {
-        const int s0 = p * LOGE, w = width(p), lo_bits = LOGN - s0 - w;
-        const u32 g = (u32)(reg >> w), c = (u32)(reg & ((1 << w) - 1));
-        // g only exists in the (last, partial) phase where lo_bits == 0
-        return (g << (LOGN - s0)) | (c << lo_bits);
-    }
-    static __device__ __forceinline__ u32 index(int p, u32 tid, int reg) { return base(p, tid) | off(p, reg); }
-    // the "hi" coordinate (butterfly group base) of group g in phase p
-    static __device__ __forceinline__ u32 group_hi(int p, u32 tid, int g) {
-        const int s0 = p * LOGE, w = width(p), lo_bits = LOGN - s0 - w;
-        if (p == 0) return 0;
-        const u32 gamma = (w == LOGE) ? tid : ((tid << (LOGE - w)) + (u32)g);
-        return gamma >> lo_bits;
-    }
-    static __device__ __forceinline__ constexpr u32 pad(u32 j) { return j + (j >> 5); }
-
-    // move residues from phase layout PF to phase layout PT through LDS
-    template <int PF, int PT>
-    static __device__ __forceinline__ void exchange(u64 (&r)[E], u32 *lds, u32 tid) {
-        u32 tmp[E];
-        u32 *wb = lds + pad(base(PF, tid));
-        const u32 *rb = lds + pad(base(PT, tid));
-#pragma unroll
-        for (int k = 0; k < E; k++) wb[pad(off(PF, k))] = (u32)r[k];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; k++) tmp[k] = rb[pad(off(PT, k))];
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; k++) wb[pad(off(PF, k))] = (u32)(r[k] >> 32);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; k++) r[k] = ((u64)rb[pad(off(PT, k))] << 32) | tmp[k];
-        __syncthreads();
-    }
-
-    // Forward stage s = P * LOGE + D of phase P: Cooley-Tukey butterflies
-    // (X, Y) -> (X + W Y, X - W Y), W = tw[2^s + group], Harvey lazy ranges.
-    template <int P, int D>
-    static __device__ __forceinline__ void fwd_stage(u64 (&r)[E], u32 tid, const ulonglong2 *__restrict__ tw,
-                                                     u64 q) {
-        constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
-        const u64 two_q = q << 1;
-#pragma unroll
-        for (int b = 0; b < E / 2; b++) {
-            const int g = b >> (w - 1);
-            const int bl = b & ((1 << (w - 1)) - 1);
-            const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
-            const u32 hi = group_hi(P, tid, g);
-            const int x = g * (1 << w) + c, y = x + half;
-            const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
-            const ulonglong2 W = tw[ti];
-            u64 X = r[x];
-            X = X >= two_q ? X - two_q : X;
-            const u64 Tm = shoup_lazy(r[y], W.x, W.y, q);
-            r[x] = X + Tm;
-            r[y] = X - Tm + two_q;
-            if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (D + 1 < w) fwd_stage<P, D + 1>(r, tid, tw, q);
-    }
-    template <int P>
-    static __device__ __forceinline__ void fwd_phase(u64 (&r)[E], u32 *lds, u32 tid,
-                                                     const ulonglong2 *__restrict__ tw, u64 q) {
-        if constexpr (P > 0) exchange<P - 1, P>(r, lds, tid);
-        fwd_stage<P, 0>(r, tid, tw, q);
-        if constexpr (P + 1 < NPH) fwd_phase<P + 1>(r, lds, tid, tw, q);
-    }
-
-    // forward: natural order in, "slot k = a(psi^(2brv(k)+1))" out, stage s
-    // (2^s groups, half-size N >> (s+1)) multiplies by tw[2^s + group].
-    // Inputs in [0, q) in the coalesced layout; outputs fully reduced.
-    static __device__ __forceinline__ void forward(u64 (&r)[E], u32 *lds, u32 tid, const ulonglong2 *__restrict__ tw,
-                                                   u64 q) {
-        fwd_phase<0>(r, lds, tid, tw, q);
-        exchange<NPH - 1, 0>(r, lds, tid);
-        const u64 two_q = q << 1;
-#pragma unroll
-        for (int k = 0; k < E; k++) {
-            u64 v = r[k];
-            v = v >= two_q ? v - two_q : v;
-            r[k] = v >= q ? v - q : v;
-        }
-    }
-
-    // Inverse stage s = P * LOGE + D: Gentleman-Sande (X, Y) -> (X + Y,
-    // (X - Y) W^-1) with the inverse twiddles; stage 0 folds in N^-1.
-    template <int P, int D>
-    static __device__ __forceinline__ void inv_stage(u64 (&r)[E], u32 tid, const ulonglong2 *__restrict__ itw,
-                                                     const PrimeConst &pc) {
-        constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
-        constexpr bool last = (s0 + D) == 0;
-        const u64 q = pc.q, two_q = q << 1;
-#pragma unroll
-        for (int b = 0; b < E / 2; b++) {
-            const int g = b >> (w - 1);
-            const int bl = b & ((1 << (w - 1)) - 1);
-            const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
-            const u32 hi = group_hi(P, tid, g);
-            const int x = g * (1 << w) + c, y = x + half;
-            const u64 X = r[x], Y = r[y];
-            if constexpr (last) {
-                r[x] = shoup_lazy(X + Y, pc.ninv, pc.ninv_sh, q);
-                r[y] = shoup_lazy(X - Y + two_q, pc.last_w, pc.last_w_sh, q);
-            } else {
-                const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
-                const ulonglong2 W = itw[ti];
-                const u64 U = X + Y;
-                r[x] = U >= two_q ? U - two_q : U;
-                r[y] = shoup_lazy(X - Y + two_q, W.x, W.y, q);
-            }
-            if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
-        }
-        if constexpr (D > 0) inv_stage<P, D - 1>(r, tid, itw, pc);
-    }
-    template <int P>
-    static __device__ __forceinline__ void inv_phase(u64 (&r)[E], u32 *lds, u32 tid,
-                                                     const ulonglong2 *__restrict__ itw, const PrimeConst &pc) {
-        if constexpr (P < NPH - 1) exchange<P + 1, P>(r, lds, tid);
-        inv_stage<P, width(P) - 1>(r, tid, itw, pc);
-        if constexpr (P > 0) inv_phase<P - 1>(r, lds, tid, itw, pc);
-    }
-
-    // inverse: exactly the forward stages undone in reverse order. Inputs
-    // in [0, q) in the coalesced layout; outputs fully reduced, coalesced.
-    static __device__ __forceinline__ void inverse(u64 (&r)[E], u32 *lds, u32 tid, const ulonglong2 *__restrict__ itw,
-                                                   const PrimeConst &pc) {
-        exchange<0, NPH - 1>(r, lds, tid);
-        inv_phase<NPH - 1>(r, lds, tid, itw, pc);
-#pragma unroll
-        for (int k = 0; k < E; k++) r[k] = csub(r[k], pc.q);
-    }
-};
-
-// ---------------------------------------------------------------------
-// fused prologues / epilogues
-// ---------------------------------------------------------------------
-enum FwdOp : int {
-    F_COPY = 0,     // in[0] -> NTT -> out
-    F_MODUP = 1,    // ModUp digit conversion -> NTT -> out
-    F_RESCALE = 2,  // rescale correction -> NTT -> (in[1] - .) q_l^-1 -> out
-    F_MODDOWN = 3,  // ModDown conversion -> NTT -> (in[1] - .) P^-1 (+ in[2]) -> out
-    // ModDown + rescale of one limb i < l of an HMult accumulator:
-    // z = conv_i(y) P^-1 + [t]_centred -> NTT, with y (in[0], n_p limbs) =
-    // INTT(acc_P) hat_m^-1 and t (in[1]) the relinearised top limb in the
-    // coefficient domain; l = a; out = z
-    F_RELIN = 4,
-    F_SAMPLE = 5,   // sampled small polynomial -> NTT -> out
-    F_INT = 6,      // signed int64 coefficients -> NTT -> out
-    F_RELIN_RS = 7, // F_RELIN, then out = (acc' P^-1 - z) q_l^-1, acc' (in[2]) the accumulator limb
-};
-enum InvOp : int {
-    I_COPY = 0,     // in[0] -> INTT -> out
-    I_MUL = 1,      // in[0] * in[1] -> INTT -> out
-    I_SCALE = 2,    // in[0] -> INTT -> * (hat_m^-1 mod p_m, m = a | P^-1 mod q when b = 1 |
-                    //   the ModUp source factor hat_i^-1 when b = 2) -> out
-    I_DECRYPT = 3,  // c0 + c1 s (+ c2 s^2) -> INTT -> out
-};
-
-// XCD-aware item order: the chip dispatches workgroup b to XCD (b mod 8).
-// Consecutive items (which often read the same source limbs) are mapped
-// to one XCD so those limbs are reused from that XCD's L2.
-__device__ __forceinline__ int xcd_item(int nitems, u32 remap) {
-    const int b = blockIdx.x, nb = gridDim.x;
-    if (!remap) return b < nitems ? b : -1;
-    const int per = nb >> 3;  // grid is padded to a multiple of 8
-    const int it = (b & 7) * per + (b >> 3);
-    return it < nitems ? it : -1;
-}
-__host__ __device__ inline int xcd_grid(int nitems) { return (nitems + 7) & ~7; }
-
-template <int LOGN, int LOGE, int OP>
-__global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
-    using NT = Ntt<LOGN, LOGE>;
-    constexpr int N = NT::N, E = NT::E, T = NT::T;
-    __shared__ u32 lds[NT::LDS_WORDS];
-    const int iid = xcd_item(nitems, tb.xcd_remap);
-    if (iid < 0) return;
-    const Item it = items[iid];
-    const u32 tid = threadIdx.x, vo = tid * 8;
-    const PrimeConst pc = tb.pc[it.prime];
-    const u64 q = pc.q;
-    u64 r[E];
-
-    // ---- prologue: residues of the polynomial to transform (coefficients)
-    if constexpr (OP == F_COPY) {
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
-    } else if constexpr (OP == F_MODUP || OP == F_MODDOWN) {
-        // sum_i [x_i * hat_i^-1]_{q_i} * (hat_i mod t), one Barrett at the end
-        const u32 lo = it.a, s = it.b;  // first source prime index, count
-        const u64 *blk;
-        const u64 *hat;
-        u32 hat_stride;
-        if constexpr (OP == F_MODUP) {
-            blk = tb.modup + (size_t)(it.c * tb.alpha + s - 1) * modup_block_words(tb.alpha, tb.n_prim);
-            hat = blk + 2 * tb.alpha + it.prime;  // hat[i * n_prim + t]
-            hat_stride = tb.n_prim;
-        } else {
-            blk = tb.moddown;
-            hat = blk + 2 * tb.n_p + it.prime;  // hat[m * n_q + t]
-            hat_stride = tb.n_q;
-        }
-        const Buf src(it.in[0]);
-        constexpr int kCC = E >= 32 ? 4 : kConvChunk;
-        static_for<0, E / kCC>([&](auto C0) {
-            constexpr int c0 = decltype(C0)::value * kCC;
-            Acc128 acc[kCC];
-            for (u32 i = 0; i < s; i++) {
-                const u64 inv = blk[2 * i], inv_sh = blk[2 * i + 1], qi = tb.pc[lo + i].q, h = hat[i * hat_stride];
-#pragma unroll
-                for (int c = 0; c < kCC; c++) {
-                    const u64 x = src.ld(vo, (i * N + (c0 + c) * T) * 8);
-                    // ModUp sources arrive pre-multiplied by hat_i^-1 (it.v == 1)
-                    const u64 y = (OP == F_MODUP && it.v == 1) ? x : shoup(x, inv, inv_sh, qi);
-                    acc[c].mac(y, h);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kCC; c++) r[c0 + c] = acc[c].reduce(pc);
-        });
-    } else if constexpr (OP == F_RELIN || OP == F_RELIN_RS) {
-        const PrimeConst pl = tb.pc[it.a];  // q_l
-        const u64 hl = pl.q >> 1;
-        const u64 *hat = tb.moddown + 2 * tb.n_p + it.prime;  // hat[m * n_q]: P/p_m mod q_i
-        const Buf ys(it.in[0]), ts(it.in[1]);
-        constexpr int kCC = E >= 32 ? 4 : kConvChunk;
-        static_for<0, E / kCC>([&](auto C0) {
-            constexpr int c0 = decltype(C0)::value * kCC;
-            Acc128 acc[kCC];
-            for (u32 m = 0; m < tb.n_p; m++) {
-                const u64 h = hat[(size_t)m * tb.n_q];
-#pragma unroll
-                for (int c = 0; c < kCC; c++) acc[c].mac(ys.ld(vo, (m * N + (c0 + c) * T) * 8), h);
-            }
-#pragma unroll
-            for (int c = 0; c < kCC; c++) {
-                const u64 tc = centered_mod(addm(ts.ld(vo, (c0 + c) * T * 8), hl, pl.q), hl, pc);
-                r[c0 + c] = addm(shoup(acc[c].reduce(pc), pc.pinv, pc.pinv_sh, q), tc, q);
-            }
-        });
-    } else if constexpr (OP == F_RESCALE) {
-        const PrimeConst pl = tb.pc[it.a];  // q_l
-        const u64 hl = pl.q >> 1;
-#pragma unroll
-        for (int c = 0; c < E; c++) {
-            r[c] = centered_mod(addm(Buf(it.in[0]).ld(vo, c * T * 8), hl, pl.q), hl, pc);
-        }
-    } else if constexpr (OP == F_SAMPLE) {
-        // it.a = kind, it.b = object id, it.c = domain tag
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = reduce_signed(sample_small(it.a, c * T + tid, it.b, it.c, seed), pc);
-    } else if constexpr (OP == F_INT) {
-        const i64 *src = reinterpret_cast<const i64 *>(it.in[0]);
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = reduce_signed((i64)Buf((const u64 *)src).ld(vo, c * T * 8), pc);
-    }
-
-    NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
-
-    // ---- epilogue
-    if constexpr (OP == F_COPY || OP == F_MODUP || OP == F_SAMPLE || OP == F_INT || OP == F_RELIN) {
-#pragma unroll
-        for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
-    } else if constexpr (OP == F_RESCALE) {
-        const ulonglong2 qi = tb.rescale[(size_t)it.a * tb.n_q + it.prime];
-        const Buf in1(it.in[1]), dst(it.out);
-#pragma unroll
-        for (int c0 = 0; c0 < E; c0 += kEpiChunk) {
-            u64 x[kEpiChunk];
-#pragma unroll
-            for (int c = 0; c < kEpiChunk; c++) x[c] = in1.ld(vo, (c0 + c) * T * 8);
-#pragma unroll
-            for (int c = 0; c < kEpiChunk; c++)
-                dst.st(vo, (c0 + c) * T * 8, shoup(subm(x[c], r[c0 + c], q), qi.x, qi.y, q));
-        }
-    } else if constexpr (OP == F_RELIN_RS) {
-        // y = (acc' P^-1 - z) q_l^-1 with acc' (in[2]) the accumulator limb
-        const ulonglong2 qi = tb.rescale[(size_t)it.a * tb.n_q + it.prime];
-        const Buf accb(it.in[2]), dst(it.out);
-        constexpr int kRC = 4;
-#pragma unroll
-        for (int c0 = 0; c0 < E; c0 += kRC) {
-            u64 x[kRC];
-#pragma unroll
-            for (int c = 0; c < kRC; c++) x[c] = accb.ld(vo, (c0 + c) * T * 8);
-#pragma unroll
-            for (int c = 0; c < kRC; c++) {
-                const u64 u = shoup(x[c], pc.pinv, pc.pinv_sh, q);
-                dst.st(vo, (c0 + c) * T * 8, shoup(subm(u, r[c0 + c], q), qi.x, qi.y, q));
-            }
-        }
-    } else if constexpr (OP == F_MODDOWN) {
-        const Buf in1(it.in[1]), in2(it.in[2] ? it.in[2] : it.in[1]), dst(it.out);
-        const bool add = it.in[2] != nullptr;
-#pragma unroll
-        for (int c0 = 0; c0 < E; c0 += kEpiChunk) {
-            u64 x[kEpiChunk], a[kEpiChunk];
-#pragma unroll
-            for (int c = 0; c < kEpiChunk; c++) {
-                x[c] = in1.ld(vo, (c0 + c) * T * 8);
-                a[c] = add ? in2.ld(vo, (c0 + c) * T * 8) : 0;
-            }
-#pragma unroll
-            for (int c = 0; c < kEpiChunk; c++) {
-                u64 y = shoup(subm(x[c], r[c0 + c], q), pc.pinv, pc.pinv_sh, q);
-                dst.st(vo, (c0 + c) * T * 8, add ? addm(y, a[c], q) : y);
-            }
-        }
-    }
-}
-
-template <int LOGN, int LOGE, int OP>
-__global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
-    using NT = Ntt<LOGN, LOGE>;
-    constexpr int N = NT::N, E = NT::E, T = NT::T;
-    __shared__ u32 lds[NT::LDS_WORDS];
-    const int iid = xcd_item(nitems, tb.xcd_remap);
-    if (iid < 0) return;
-    const Item it = items[iid];
-    const u32 tid = threadIdx.x, vo = tid * 8;
-    const PrimeConst pc = tb.pc[it.prime];
-    const u64 q = pc.q;
-    u64 r[E];
-
-    if constexpr (OP == I_COPY || OP == I_SCALE) {
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
-    } else if constexpr (OP == I_MUL) {
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = mulm(Buf(it.in[0]).ld(vo, c * T * 8), Buf(it.in[1]).ld(vo, c * T * 8), pc);
-    } else if constexpr (OP == I_DECRYPT) {
-        const u64 *s = it.in[3];
-#pragma unroll
-        for (int c = 0; c < E; c++) {
-            const u32 so = c * T * 8;
-            const u64 sj = Buf(s).ld(vo, so);
-            u64 m = addm(Buf(it.in[0]).ld(vo, so), mulm(Buf(it.in[1]).ld(vo, so), sj, pc), q);
-            if (it.a == 3) m = addm(m, mulm(Buf(it.in[2]).ld(vo, so), mulm(sj, sj, pc), pc), q);
-            r[c] = m;
-        }
-    }
-
-    NT::inverse(r, lds, tid, tb.itw + (size_t)it.prime * N, pc);
-
-    if constexpr (OP == I_MUL) {
-        // it.v == 1: store [x * hat_i^-1]_{q_i}, the ModUp input (digit block it.c, position it.a)
-        if (it.v == 1) {
-            const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
-            const u64 inv = blk[2 * it.a], inv_sh = blk[2 * it.a + 1];
-#pragma unroll
-            for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
-        }
-    } else if constexpr (OP == I_SCALE) {
-        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q;
-        // b == 2: hat_i^-1 of ModUp digit block c, position a (a ModUp source)
-        const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
-        const u64 inv = it.b == 1 ? pc.pinv : it.b == 2 ? blk[2 * it.a] : tb.moddown[2 * it.a];
-        const u64 inv_sh = it.b == 1 ? pc.pinv_sh : it.b == 2 ? blk[2 * it.a + 1] : tb.moddown[2 * it.a + 1];
-#pragma unroll
-        for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
-    }
-#pragma unroll
-    for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
-}
-
 // ---------------------------------------------------------------------
 // elementwise kernels (grid-stride over items x N/2 pairs of residues)
 // ---------------------------------------------------------------------
@@ -892,89 +340,30 @@ __global__ void k_reduce_weights(DevTables tb, const i64 *__restrict__ W, u64 *_
     }
 }
 
-// ---------------------------------------------------------------------
-// host-side launchers
-// ---------------------------------------------------------------------
-template <int LOGN, int LOGE, int OP>
-static hipError_t launch_fwd_t(const DevTables &tb, const Item *items, int n, u64 seed, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd<LOGN, LOGE, OP>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
-                       items, n, seed);
-    return hipGetLastError();
-}
-template <int LOGN, int LOGE, int OP>
-static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv<LOGN, LOGE, OP>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
-                       items, n);
-    return hipGetLastError();
-}
-
-// residues per thread: 32 for the large rings (one 1024-thread workgroup
-// per 2^15 limb), 16 below.
-#define CKKS_FWD_CASE(LN, LE)                                                        \
-    case LN:                                                                         \
-        switch (op) {                                                                \
-            case F_COPY: return launch_fwd_t<LN, LE, F_COPY>(tb, items, n, seed, s);       \
-            case F_MODUP: return launch_fwd_t<LN, LE, F_MODUP>(tb, items, n, seed, s);     \
-            case F_RESCALE: return launch_fwd_t<LN, LE, F_RESCALE>(tb, items, n, seed, s); \
-            case F_MODDOWN: return launch_fwd_t<LN, LE, F_MODDOWN>(tb, items, n, seed, s); \
-            case F_RELIN: return launch_fwd_t<LN, LE, F_RELIN>(tb, items, n, seed, s);     \
-            case F_RELIN_RS: return launch_fwd_t<LN, LE, F_RELIN_RS>(tb, items, n, seed, s); \
-            case F_SAMPLE: return launch_fwd_t<LN, LE, F_SAMPLE>(tb, items, n, seed, s);   \
-            case F_INT: return launch_fwd_t<LN, LE, F_INT>(tb, items, n, seed, s);         \
-        }                                                                            \
-        break;
-#define CKKS_INV_CASE(LN, LE)                                                        \
-    case LN:                                                                         \
-        switch (op) {                                                                \
-            case I_COPY: return launch_inv_t<LN, LE, I_COPY>(tb, items, n, s);             \
-            case I_MUL: return launch_inv_t<LN, LE, I_MUL>(tb, items, n, s);               \
-            case I_SCALE: return launch_inv_t<LN, LE, I_SCALE>(tb, items, n, s);           \
-            case I_DECRYPT: return launch_inv_t<LN, LE, I_DECRYPT>(tb, items, n, s);       \
-        }                                                                            \
-        break;
-
 // Residues per thread: 16 below N = 2^15 and 32 at 2^15 by default; the
 // wide variant doubles that (32 for 2^11..2^14, 64 at 2^15) and is a
-// tuning choice.
+// tuning choice. Each ring's kernels live in their own translation unit.
 hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (tb.ntt_wide) {
-        switch (tb.log_n) {
-            CKKS_FWD_CASE(11, 5)
-            CKKS_FWD_CASE(12, 5)
-            CKKS_FWD_CASE(13, 5)
-            CKKS_FWD_CASE(14, 5)
-            CKKS_FWD_CASE(15, 6)
-        }
-    }
     switch (tb.log_n) {
-        CKKS_FWD_CASE(10, 4)
-        CKKS_FWD_CASE(11, 4)
-        CKKS_FWD_CASE(12, 4)
-        CKKS_FWD_CASE(13, 4)
-        CKKS_FWD_CASE(14, 4)
-        CKKS_FWD_CASE(15, 5)
+        case 15: return launch_fwd_15(tb, op, items, n, seed, s);
+        case 14: return launch_fwd_14(tb, op, items, n, seed, s);
+        case 13: return launch_fwd_13(tb, op, items, n, seed, s);
+        case 10:
+        case 11:
+        case 12: return launch_fwd_small(tb, op, items, n, seed, s);
     }
     return hipErrorInvalidValue;
 }
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (tb.ntt_wide) {
-        switch (tb.log_n) {
-            CKKS_INV_CASE(11, 5)
-            CKKS_INV_CASE(12, 5)
-            CKKS_INV_CASE(13, 5)
-            CKKS_INV_CASE(14, 5)
-            CKKS_INV_CASE(15, 6)
-        }
-    }
     switch (tb.log_n) {
-        CKKS_INV_CASE(10, 4)
-        CKKS_INV_CASE(11, 4)
-        CKKS_INV_CASE(12, 4)
-        CKKS_INV_CASE(13, 4)
-        CKKS_INV_CASE(14, 4)
-        CKKS_INV_CASE(15, 5)
+        case 15: return launch_inv_15(tb, op, items, n, s);
+        case 14: return launch_inv_14(tb, op, items, n, s);
+        case 13: return launch_inv_13(tb, op, items, n, s);
+        case 10:
+        case 11:
+        case 12: return launch_inv_small(tb, op, items, n, s);
     }
     return hipErrorInvalidValue;
 }

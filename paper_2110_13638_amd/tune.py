@@ -26,7 +26,7 @@ def _key(ctx, workload):
 
 def candidates(ctx, space=None):
     space = dict(space or DEFAULT_SPACE)
-    if ctx.log_n < 11:
+    if ctx.log_n < 11 or ctx.log_n > 14:
         space["ntt_wide"] = (0,)
     names = sorted(space)
     for vals in itertools.product(*(space[n] for n in names)):

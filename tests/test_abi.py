@@ -122,6 +122,13 @@ def test_tuning_knobs_host():
             nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_WIDE, 1)  # no wide variant at N = 2^10
     finally:
         nat.ckks_ctx_destroy(h)
+    big = O.find_primes(15, [50, 60])
+    h = nat.ckks_ctx_create(15, big[:1], big[1:], 1)
+    try:
+        with pytest.raises(nat.CkksError):
+            nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_WIDE, 1)  # nor at N = 2^15
+    finally:
+        nat.ckks_ctx_destroy(h)
 
 
 def test_record_api_host_errors():

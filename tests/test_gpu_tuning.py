@@ -39,7 +39,7 @@ def test_ntt_variants_bit_exact(ck, log_n):
     ctx = ck.Context(log_n, primes[:3], primes[3:], 1)
     x = S.residues(9 + log_n, primes, 1 << log_n)[0]
     want = [orc.ntt(x[i], i) for i in range(len(primes))]
-    for wide, remap in itertools.product((0, 1), (0, 1)):
+    for wide, remap in itertools.product((0, 1) if log_n <= 14 else (0,), (0, 1)):
         print("ntt variant log_n=%d wide=%d remap=%d" % (log_n, wide, remap), flush=True)
         ctx.set_tuning(ntt_wide=wide, xcd_remap=remap)
         dev = torch.from_numpy(x.view(np.int64)).cuda()

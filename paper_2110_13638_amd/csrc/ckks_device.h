@@ -166,6 +166,8 @@ __device__ __forceinline__ u64 sample_uniform(u32 j, u32 limb, u32 obj, u32 tag,
 // pairs the scheduler keeps in flight (register pressure at 32 residues per
 // thread)
 constexpr int kTwiddleChunk = 8;
+// the inverse stages keep more constants live: fewer barriers spill less
+constexpr int kTwiddleChunkInv = 16;
 // residues converted per pass over the source limbs of a basis conversion
 constexpr int kConvChunk = 8;
 // residues whose epilogue inputs are loaded together before any is stored
@@ -304,7 +306,7 @@ struct Ntt {
                 r[x] = U >= two_q ? U - two_q : U;
                 r[y] = shoup_lazy(X - Y + two_q, W.x, W.y, q);
             }
-            if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
+            if ((b & (kTwiddleChunkInv - 1)) == kTwiddleChunkInv - 1) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (D > 0) inv_stage<P, D - 1>(r, tid, itw, pc);
     }

@@ -273,6 +273,7 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     c->tb.ew_log = 2;
     c->tb.xcd_remap = 1;
     c->tb.fuse_tail = 0;
+    c->tb.ip_cts = kIpCts;
     c->log_n = p->log_n;
     c->N = 1u << p->log_n;
     c->n_q = p->n_q;
@@ -503,6 +504,10 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
             if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: FUSE_TAIL takes 0 or 1");
             c->tb.fuse_tail = (u32)value;
             return CKKS_OK;
+        case CKKS_TUNE_IP_CTS:
+            if (value != 2 && value != kIpCts) return fail(CKKS_EINVAL, "set_tuning: IP_CTS takes 2 or %d", kIpCts);
+            c->tb.ip_cts = (u32)value;
+            return CKKS_OK;
     }
     return fail(CKKS_EINVAL, "set_tuning: unknown knob");
 }
@@ -513,6 +518,7 @@ extern "C" int ckks_ctx_get_tuning(const ckks_ctx *c, int knob) {
         case CKKS_TUNE_EW_LOG: return (int)c->tb.ew_log;
         case CKKS_TUNE_XCD_REMAP: return (int)c->tb.xcd_remap;
         case CKKS_TUNE_FUSE_TAIL: return (int)c->tb.fuse_tail;
+        case CKKS_TUNE_IP_CTS: return (int)c->tb.ip_cts;
     }
     return -1;
 }
@@ -809,7 +815,8 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
     for (size_t g = 0; g < order.size();) {
         size_t h = g;
-        while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < (size_t)kIpCts) h++;
+        const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;
+        while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < group) h++;
         const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
         for (u32 t = 0; t < E; t++) {
             IpItem it;

@@ -43,6 +43,7 @@ struct DevTables {
     u32 ew_log;     // log2 of residues per thread in streaming kernels (1..3)
     u32 xcd_remap;  // 1: consecutive work items on one XCD
     u32 fuse_tail;  // 1: HMult's rescale epilogue inside the last NTT
+    u32 ip_cts;     // ciphertexts sharing each key load in the inner product (2 or 4)
 };
 
 // ModUp constants for digit j truncated to s primes (1 <= s <= alpha):

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restri
 // multiplied by the key limbs (b_j, a_j) of that prime; sums are 128-bit and
 // reduced once. Each key residue is loaded once for all the item's
 // ciphertexts. acc + pos N receives the b-sum, acc + (E + pos) N the a-sum.
-template <int kEwPer>
+template <int kEwPer, int NCT>
 __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restrict__ items, int nitems) {
     const u32 N = 1u << tb.log_n;
     const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
@@ -134,12 +134,12 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
     for (int e = 0; e < kEwPer; e++) {
         const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
         if (x >= N) break;
-        Acc128 s0[kIpCts], s1[kIpCts];
+        Acc128 s0[NCT], s1[NCT];
         for (u32 j = 0; j < it.beta; j++) {
             const u64 *kb = it.key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
             const u64 k0 = kb[x], k1 = kb[kstride + x];
 #pragma unroll
-            for (int c = 0; c < kIpCts; c++) {
+            for (int c = 0; c < NCT; c++) {
                 if ((u32)c >= it.n_ct) break;
                 u64 v;
                 if (j == it.own_digit) {
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
             }
         }
 #pragma unroll
-        for (int c = 0; c < kIpCts; c++) {
+        for (int c = 0; c < NCT; c++) {
             if ((u32)c >= it.n_ct) break;
             if (it.own2[c]) {
                 const u64 a0 = it.own2[c][x], b0 = it.own3[c][x], a1 = it.own0[c][x], b1 = it.own1[c][x];
@@ -392,13 +392,20 @@ hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStre
     hipLaunchKernelGGL(k_hoist<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
     return hipGetLastError();
 }
+template <int NCT>
+static void launch_ip_t(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {
+    switch (tb.ew_log) {
+        case 1: hipLaunchKernelGGL((k_ip<2, NCT>), dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
+        case 3: hipLaunchKernelGGL((k_ip<8, NCT>), dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
+        default: hipLaunchKernelGGL((k_ip<4, NCT>), dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
+    }
+}
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    switch (tb.ew_log) {
-        case 1: hipLaunchKernelGGL(k_ip<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
-        case 3: hipLaunchKernelGGL(k_ip<8>, dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
-        default: hipLaunchKernelGGL(k_ip<4>, dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
-    }
+    if (tb.ip_cts == 2)
+        launch_ip_t<2>(tb, items, n, s);
+    else
+        launch_ip_t<kIpCts>(tb, items, n, s);
     return hipGetLastError();
 }
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,

@@ -105,6 +105,11 @@ def test_tuning_knobs_host():
         assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_FUSE_TAIL) == 0
         nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_FUSE_TAIL, 1)
         assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_FUSE_TAIL) == 1
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_IP_CTS) == 4
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 2)
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_IP_CTS) == 2
+        with pytest.raises(nat.CkksError):
+            nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 3)
         for knob, bad in [(nat.CKKS_TUNE_EW_LOG, 0), (nat.CKKS_TUNE_EW_LOG, 4), (nat.CKKS_TUNE_NTT_WIDE, 2),
                           (nat.CKKS_TUNE_XCD_REMAP, -1), (7, 0)]:
             with pytest.raises(nat.CkksError) as e:

@@ -27,8 +27,8 @@ def _u(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f)
-            for w, e, x, f in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1))]
+SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f, ip_cts=i)
+            for w, e, x, f, i in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4))]
 
 
 @pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15])
@@ -71,7 +71,8 @@ def hm(ck):
     return ctx, ins, want
 
 
-@pytest.mark.parametrize("st", SETTINGS, ids=lambda d: "w%d_e%d_x%d_f%d" % (d["ntt_wide"], d["ew_log"], d["xcd_remap"], d["fuse_tail"]))
+@pytest.mark.parametrize("st", SETTINGS, ids=lambda d: "w%d_e%d_x%d_f%d_i%d" % (d["ntt_wide"], d["ew_log"], d["xcd_remap"], d["fuse_tail"],
+                                                     d["ip_cts"]))
 def test_hmult_variants_bit_exact(hm, st):
     ctx, ins, want = hm
     print("hmult variant", st, flush=True)
@@ -79,7 +80,7 @@ def test_hmult_variants_bit_exact(hm, st):
     outs = ctx.hmult_relin_rescale([a for a, _ in ins], [b for _, b in ins])
     for o, w in zip(outs, want):
         assert np.array_equal(o.residues(), w)
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)
 
 
 def test_autotune_pick_and_cache(hm, tmp_path):
@@ -88,15 +89,16 @@ def test_autotune_pick_and_cache(hm, tmp_path):
     A, B = [a for a, _ in ins], [b for _, b in ins]
     cache = str(tmp_path / "tune.json")
     best, times = tune.autotune(ctx, lambda: ctx.hmult_relin_rescale(A, B), "hmult-ragged", cache=cache,
-                                space={"ntt_wide": (0, 1), "ew_log": (2, 3), "xcd_remap": (1,), "fuse_tail": (0,)}, reps=2)
+                                space={"ntt_wide": (0, 1), "ew_log": (2, 3), "xcd_remap": (1,), "fuse_tail": (0,), "ip_cts": (4,)},
+                                reps=2)
     assert len(times) == 4 and all(t > 0 for t in times.values())
     assert ctx.tuning() == best
     # the cached pick is applied without timing again
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)
     again, times2 = tune.autotune(ctx, None, "hmult-ragged", cache=cache)
     assert again == best and times2 == {} and ctx.tuning() == best
     assert json.load(open(cache))
     outs = ctx.hmult_relin_rescale(A, B)
     for o, w in zip(outs, want):
         assert np.array_equal(o.residues(), w)
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)

@@ -165,7 +165,7 @@ __device__ __forceinline__ u64 sample_uniform(u32 j, u32 limb, u32 obj, u32 tag,
 // butterflies issued between scheduling barriers: bounds how many twiddle
 // pairs the scheduler keeps in flight (register pressure at 32 residues per
 // thread)
-constexpr int kTwiddleChunk = 8;
+constexpr int kTwiddleChunk = 16;
 // the inverse stages keep more constants live: fewer barriers spill less
 constexpr int kTwiddleChunkInv = 16;
 // residues converted per pass over the source limbs of a basis conversion

@@ -58,8 +58,11 @@ def measured_traffic(kernel):
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    src = b"".join(open(os.path.join(ROOT, "paper_2110_13638_amd", "csrc", f), "rb").read()
-                   for f in ("ckks_kernels.hip", "ckks_internal.h"))
+    import glob
+    csrc = os.path.join(ROOT, "paper_2110_13638_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hip"))) + [os.path.join(csrc, f) for f in
+                                                               ("ckks_device.h", "ckks_internal.h")]
+    src = b"".join(open(f, "rb").read() for f in files)
     text = open(TRAFFIC_FILE).read()
     if hashlib.sha256(src).hexdigest() not in text:
         return None

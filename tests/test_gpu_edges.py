@@ -1,0 +1,90 @@
+"""Edge cases of the device entry points: empty batches, the bench's exact
+launch configuration (256 pairs at N = 2^15, autotuned launch shapes) with
+sampled outputs against the oracle, and the error paths (no level left,
+mismatched levels and scales, aliasing)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synthetic as S
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ck():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_13638_amd import ckks
+    return ckks
+
+
+@pytest.fixture(scope="module")
+def small(ck):
+    primes = O.find_primes(12, [60, 40, 40, 60])
+    ctx = ck.Context(12, primes[:3], primes[3:], 3).keygen(3)
+    return ctx, O.Oracle(12, primes[:3], primes[3:], 3)
+
+
+def test_empty_batches_are_no_ops(small):
+    ctx, _ = small
+    from paper_2110_13638_amd import _native as nat
+    ws, wb = ctx.workspace(1 << 20)
+    empty = (nat.ckks_ct * 0)()
+    nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr(), empty, empty, empty, ws, wb, ctx.stream)
+    nat.ckks_add(ctx.h, empty, empty, empty, ws, wb, ctx.stream)
+    nat.ckks_ntt(ctx.h, [], [], ws, wb, ctx.stream)
+    torch.cuda.synchronize()
+
+
+def test_error_paths(small):
+    ctx, _ = small
+    from paper_2110_13638_amd import _native as nat
+    a = ctx.ct_from_residues(S.residues(1, ctx.q, ctx.N, 2), 2.0 ** 40)
+    b = ctx.ct_from_residues(S.residues(2, ctx.q[:2], ctx.N, 2), 2.0 ** 40)
+    with pytest.raises(nat.CkksError) as e:
+        ctx.hmult_relin_rescale([a], [b])  # levels differ
+    assert e.value.code == nat.CKKS_ELEVEL
+    z = ctx.ct_from_residues(S.residues(3, ctx.q[:1], ctx.N, 2), 2.0 ** 40)
+    with pytest.raises(nat.CkksError) as e:
+        ctx.hmult_relin_rescale([z], [z])  # no prime left to rescale
+    assert e.value.code == nat.CKKS_EDEPTH
+    c = ctx.ct_from_residues(S.residues(4, ctx.q, ctx.N, 2), 2.0 ** 30)
+    with pytest.raises(nat.CkksError) as e:
+        ctx.add(a, c)  # scales differ
+    assert e.value.code == nat.CKKS_ESCALE
+    with pytest.raises(nat.CkksError) as e:
+        ctx.hmult_relin_rescale([a], [a], outs=[a])  # output aliases an input
+    assert e.value.code == nat.CKKS_EINVAL
+    ws, wb = ctx.workspace(1 << 20)
+    with pytest.raises(nat.CkksError) as e:  # workspace too small for the batch
+        nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr(), ctx._structs([a] * 64), ctx._structs([a] * 64),
+                                     ctx._structs([ctx.new_ct(2, 1) for _ in range(64)]), ws, 4096, ctx.stream)
+    assert e.value.code == nat.CKKS_ENOMEM
+
+
+def test_bench_configuration_sampled(ck):
+    # the timed workload: 256 pairs at 16 limbs, N = 2^15, dnum 4, with the
+    # launch shapes the autotuner picks; three outputs checked against the oracle
+    from paper_2110_13638_amd import _native as nat, tune
+    primes = O.find_primes(15, [50] * 16 + [60, 60])
+    q, p = primes[:16], primes[16:]
+    ctx = ck.Context(15, q, p, 4).keygen(1)
+    orc = O.Oracle(15, q, p, 4)
+    _, sn = orc.keygen_secret(1)
+    rk = orc.keygen_relin(sn, 3)
+    B, top = 256, 15
+    res = S.residues_device(0, q, ctx.N, 4 * B, ctx.device).view(B, 2, 2, 16, ctx.N)
+    A = [ck.Ciphertext(ctx, res[i, 0], 2, top, 1.0) for i in range(B)]
+    Bc = [ck.Ciphertext(ctx, res[i, 1], 2, top, 1.0) for i in range(B)]
+    outs = [ctx.new_ct(2, top - 1, 1.0) for _ in range(B)]
+    best, _ = tune.autotune(ctx, lambda: ctx.hmult_relin_rescale(A, Bc, outs=outs), "edge-test", reps=1,
+                            space={"ew_log": (1, 2), "fuse_tail": (0, 1), "ip_cts": (2, 4)})
+    print("bench configuration, launch shapes", best, flush=True)
+    ctx.hmult_relin_rescale(A, Bc, outs=outs)
+    torch.cuda.synchronize()
+    for i in (0, 97, 255):
+        a, b = A[i].residues(), Bc[i].residues()
+        want = orc.mul_relin_rescale(a, b, rk)
+        assert np.array_equal(outs[i].residues(), want), i

@@ -494,8 +494,11 @@ void ckks_plan_destroy(ckks_plan *plan);
  *                        ckks_hmult_relin_rescale runs as its own
  *                        element-wise pass; 1: inside the last NTT.
  *   CKKS_TUNE_IP_CTS     ciphertexts of one level that share each key load
- *                        in the key-switch inner product: 4 (default) or 2
- *                        (fewer registers, more key traffic).
+ *                        in the key-switch inner product: 4 (default), 2
+ *                        (fewer registers, more key traffic) or 16 (key
+ *                        residues of every digit held in registers and the
+ *                        ciphertexts processed one after another; levels
+ *                        with more than 8 digits fall back to 4).
  * Returns CKKS_EINVAL for an unknown knob or a value out of range. */
 enum { CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2, CKKS_TUNE_FUSE_TAIL = 3, CKKS_TUNE_IP_CTS = 4 };
 int ckks_ctx_set_tuning(ckks_ctx *ctx, int knob, int value);

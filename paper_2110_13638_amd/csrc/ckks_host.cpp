@@ -28,6 +28,7 @@ hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hip
 hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s);
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s);
 hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s);
+hipError_t launch_ip_seq(const DevTables &tb, const IpSeqItem *items, int n, hipStream_t s);
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,
                          u64 *const *out_ptrs, u32 n_in, u32 n_out, u32 limbs, u32 in_stride,
                          u32 out_stride, hipStream_t s);
@@ -505,7 +506,8 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
             c->tb.fuse_tail = (u32)value;
             return CKKS_OK;
         case CKKS_TUNE_IP_CTS:
-            if (value != 2 && value != kIpCts) return fail(CKKS_EINVAL, "set_tuning: IP_CTS takes 2 or %d", kIpCts);
+            if (value != 2 && value != kIpCts && value != kIpSeqCts)
+                return fail(CKKS_EINVAL, "set_tuning: IP_CTS takes 2, %d or %d", kIpCts, kIpSeqCts);
             c->tb.ip_cts = (u32)value;
             return CKKS_OK;
     }
@@ -651,7 +653,8 @@ std::string launch_name(int kind, int op, u32 log_n) {
         case 0: snprintf(b, sizeof b, "%s/N=2^%u", fwd_names[op], log_n); break;
         case 1: snprintf(b, sizeof b, "%s/N=2^%u", inv_names[op], log_n); break;
         case 2: snprintf(b, sizeof b, "%s/N=2^%u", op >= 0 && op < 15 ? ew_names[op] : "elementwise", log_n); break;
-        case 3: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
+        case 3:
+        case 6: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
         case 5: snprintf(b, sizeof b, "hoisted_rotations/N=2^%u", log_n); break;
         default: snprintf(b, sizeof b, "linear/N=2^%u", log_n); break;
     }
@@ -691,7 +694,7 @@ extern "C" int ckks_profile_collect(ckks_launch_record *out, uint32_t cap, uint3
 // ---------------------------------------------------------------------
 namespace {
 struct Launch {
-    int kind;  // 0 fwd, 1 inv, 2 ew, 3 ip, 5 hoisted rotations
+    int kind;  // 0 fwd, 1 inv, 2 ew, 3 ip, 5 hoisted rotations, 6 ip (sequential ciphertexts)
     int op;
     size_t off;
     int n;
@@ -771,6 +774,7 @@ struct Plan {
                     case 2: return launch_ew(tb, (const EwItem *)p, L.n, L.seed, st);
                     case 3: return launch_ip(tb, (const IpItem *)p, L.n, st);
                     case 5: return launch_hoist(tb, (const HoItem *)p, L.n, st);
+                    case 6: return launch_ip_seq(tb, (const IpSeqItem *)p, L.n, st);
                 }
                 return hipErrorInvalidValue;
             });
@@ -815,7 +819,7 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
     for (size_t g = 0; g < order.size();) {
         size_t h = g;
-        const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;
+        const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;  // 16 -> 4 for the deep-digit rest
         while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < group) h++;
         const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
         for (u32 t = 0; t < E; t++) {
@@ -841,6 +845,58 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
         }
         g = h;
     }
+}
+
+// the inner product of a batch: with IP_CTS = 16 and at most kIpSeqBeta
+// digits, ciphertexts of one level go 16 at a time through k_ip_seq;
+// otherwise groups of 2 or 4 through k_ip
+void add_ip(Plan &P, const std::vector<IpCt> &cts, const u64 *key) {
+    const ckks_ctx *c = P.c;
+    std::vector<IpItem> ip;
+    std::vector<IpSeqItem> seq;
+    if (c->tb.ip_cts == (u32)kIpSeqCts) {
+        std::vector<IpCt> rest;
+        std::vector<size_t> order(cts.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
+        for (size_t g = 0; g < order.size();) {
+            size_t h = g;
+            while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < (size_t)kIpSeqCts) h++;
+            const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
+            if (beta > (u32)kIpSeqBeta) {
+                for (size_t k = g; k < h; k++) rest.push_back(cts[order[k]]);
+                g = h;
+                continue;
+            }
+            for (u32 t = 0; t < E; t++) {
+                IpSeqItem it;
+                memset(&it, 0, sizeof it);
+                it.n_ct = (u32)(h - g);
+                it.prime = t < L ? t : c->n_q + (t - L);
+                it.beta = beta;
+                it.own_digit = t < L ? t / c->alpha : 0xFFFFFFFFu;
+                it.E = E;
+                it.pos = t;
+                it.key = key;
+                for (size_t k = g; k < h; k++) {
+                    const IpCt &x = cts[order[k]];
+                    it.ext[k - g] = x.ext;
+                    it.acc[k - g] = x.acc;
+                    it.own0[k - g] = t < L ? x.own0[t] : nullptr;
+                    it.own1[k - g] = (t < L && !x.own1.empty()) ? x.own1[t] : nullptr;
+                    it.own2[k - g] = (t < L && !x.own2.empty()) ? x.own2[t] : nullptr;
+                    it.own3[k - g] = (t < L && !x.own3.empty()) ? x.own3[t] : nullptr;
+                }
+                seq.push_back(it);
+            }
+            g = h;
+        }
+        add_ip_items(c, ip, rest, key);
+    } else {
+        add_ip_items(c, ip, cts, key);
+    }
+    P.add(6, 0, seq);
+    P.add(3, 0, ip);
 }
 
 inline u64 *limb(const ckks_ctx *c, const ckks_ct &ct, u32 poly, u32 i) {
@@ -891,7 +947,6 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
     const u32 N = c->N, k = c->n_p, A = c->alpha;
     std::vector<Item> icopy, modup, ipP, mdown;
     std::vector<IpCt> ipc;
-    std::vector<IpItem> ip;
     for (const KsJob &J : jobs) {
         const u32 L = J.level + 1, E = L + k, beta = (L + A - 1) / A;
         u64 *dcoef = P.limbs(L);
@@ -951,10 +1006,9 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
                 mdown.push_back(it);
             }
     }
-    add_ip_items(c, ip, ipc, key);
     P.add(1, I_SCALE, icopy);
     add_modup(P, modup);
-    P.add(3, 0, ip);
+    add_ip(P, ipc, key);
     P.add(1, I_COPY, ipP);
     P.add(0, F_MODDOWN, mdown);
 }
@@ -1741,7 +1795,6 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
     std::vector<Item> mul, modup, scale, fin;
     std::vector<EwItem> tt, tail;
     std::vector<IpCt> ipc;
-    std::vector<IpItem> ip;
     for (u32 x = 0; x < B; x++) {
         const u32 l = a[x].level, L = l + 1, E = L + k, beta = (L + A - 1) / A;
         u64 *dcoef = P.limbs(L);
@@ -1844,10 +1897,9 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
                 tail.push_back(w);
             }
     }
-    add_ip_items(c, ip, ipc, rk);
     P.add(1, I_MUL, mul);
     add_modup(P, modup);
-    P.add(3, 0, ip);
+    add_ip(P, ipc, rk);
     P.add(1, I_SCALE, scale);
     P.add(2, 0, tt);
     P.add(0, relin_op(c, fuse), fin);

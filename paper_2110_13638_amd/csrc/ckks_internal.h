@@ -105,6 +105,23 @@ struct IpItem {
     u32 n_ct, prime, beta, own_digit, E, pos;
 };
 
+// The same inner product with the key residues of every digit held in
+// registers and up to kIpSeqCts ciphertexts processed one after another
+// (k_ip_seq; beta <= kIpSeqBeta): each key residue is loaded once for all of
+// them while only one ciphertext's sums are live.
+constexpr int kIpSeqCts = 16;
+constexpr int kIpSeqBeta = 8;
+struct IpSeqItem {
+    const u64 *ext[kIpSeqCts];
+    u64 *acc[kIpSeqCts];
+    const u64 *own0[kIpSeqCts];
+    const u64 *own1[kIpSeqCts];
+    const u64 *own2[kIpSeqCts];
+    const u64 *own3[kIpSeqCts];
+    const u64 *key;
+    u32 n_ct, prime, beta, own_digit, E, pos;
+};
+
 // Hoisted rotations with plaintext weights (k_hoist): one item per target
 // limb `pos` of the extended basis and up to kHoCts ciphertexts of one
 // level. For every rotation i the ModUp'd digits of the ciphertext's second

@@ -168,6 +168,57 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
     }
 }
 
+template <int kEwPer>
+__global__ void __launch_bounds__(256) k_ip_seq(DevTables tb, const IpSeqItem *__restrict__ items, int nitems) {
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const IpSeqItem &it = items[iid];
+    const u32 n_ct = it.n_ct, beta = it.beta, own = it.own_digit, E = it.E, pos = it.pos;
+    const PrimeConst pc = tb.pc[it.prime];
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+    const u64 *kb = it.key + (size_t)it.prime * N;
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (x >= N) break;
+        u64 k0[kIpSeqBeta], k1[kIpSeqBeta];
+#pragma unroll
+        for (int j = 0; j < kIpSeqBeta; j++) {
+            if ((u32)j >= beta) break;
+            k0[j] = kb[(size_t)(2 * j) * kstride + x];
+            k1[j] = kb[(size_t)(2 * j + 1) * kstride + x];
+        }
+        for (u32 c = 0; c < n_ct; c++) {
+            Acc128 s0, s1;
+#pragma unroll
+            for (int j = 0; j < kIpSeqBeta; j++) {
+                if ((u32)j >= beta) break;
+                u64 v;
+                if ((u32)j == own) {
+                    v = it.own1[c] ? mulm(it.own0[c][x], it.own1[c][x], pc) : it.own0[c][x];
+                } else {
+                    v = it.ext[c][((size_t)j * E + pos) * N + x];
+                }
+                s0.mac(v, k0[j]);
+                s1.mac(v, k1[j]);
+            }
+            if (it.own2[c]) {
+                const u64 a0 = it.own2[c][x], b0 = it.own3[c][x], a1 = it.own0[c][x], b1 = it.own1[c][x];
+                Acc128 t;
+                t.mac(a0, b1);
+                t.mac(a1, b0);
+                s0.add(shoup(mulm(a0, b0, pc), pc.pmod, pc.pmod_sh, pc.q));
+                s1.add(shoup(t.reduce(pc), pc.pmod, pc.pmod_sh, pc.q));
+            }
+            it.acc[c][(size_t)pos * N + x] = s0.reduce(pc);
+            it.acc[c][((size_t)E + pos) * N + x] = s1.reduce(pc);
+        }
+    }
+}
+
 // source index of NTT slot j under X -> X^g (slot k holds a(psi^(2 brv(k) + 1)))
 __device__ __forceinline__ u32 automorph_src(u32 j, u32 g, u32 log_n) {
     const u32 two_n_mask = (2u << log_n) - 1;
@@ -399,6 +450,15 @@ static void launch_ip_t(const DevTables &tb, const IpItem *items, int n, hipStre
         case 3: hipLaunchKernelGGL((k_ip<8, NCT>), dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
         default: hipLaunchKernelGGL((k_ip<4, NCT>), dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
     }
+}
+hipError_t launch_ip_seq(const DevTables &tb, const IpSeqItem *items, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (tb.ew_log) {
+        case 1: hipLaunchKernelGGL(k_ip_seq<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
+        case 3: hipLaunchKernelGGL(k_ip_seq<8>, dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
+        default: hipLaunchKernelGGL(k_ip_seq<4>, dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
+    }
+    return hipGetLastError();
 }
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;

@@ -108,6 +108,7 @@ def test_tuning_knobs_host():
         assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_IP_CTS) == 4
         nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 2)
         assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_IP_CTS) == 2
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 16)
         with pytest.raises(nat.CkksError):
             nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 3)
         for knob, bad in [(nat.CKKS_TUNE_EW_LOG, 0), (nat.CKKS_TUNE_EW_LOG, 4), (nat.CKKS_TUNE_NTT_WIDE, 2),

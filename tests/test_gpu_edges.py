@@ -80,7 +80,7 @@ def test_bench_configuration_sampled(ck):
     Bc = [ck.Ciphertext(ctx, res[i, 1], 2, top, 1.0) for i in range(B)]
     outs = [ctx.new_ct(2, top - 1, 1.0) for _ in range(B)]
     best, _ = tune.autotune(ctx, lambda: ctx.hmult_relin_rescale(A, Bc, outs=outs), "edge-test", reps=1,
-                            space={"ew_log": (1, 2), "fuse_tail": (0, 1), "ip_cts": (2, 4)})
+                            space={"ew_log": (1, 2), "fuse_tail": (0, 1), "ip_cts": (2, 4, 16)})
     print("bench configuration, launch shapes", best, flush=True)
     ctx.hmult_relin_rescale(A, Bc, outs=outs)
     torch.cuda.synchronize()

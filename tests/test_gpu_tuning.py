@@ -28,7 +28,7 @@ def _u(t):
 
 
 SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f, ip_cts=i)
-            for w, e, x, f, i in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4))]
+            for w, e, x, f, i in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4, 16))]
 
 
 @pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15])

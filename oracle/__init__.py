@@ -110,7 +110,7 @@ def is_prime(n: int) -> bool:
 
 
 def find_primes(logn: int, bits):
-    """Reading C1: per requested bit size, in order, the largest unused
+    """Prime choice: per requested bit size, in order, the largest unused
     prime below 2^bits that is 1 mod 2N."""
     b = (ctypes.c_uint32 * len(bits))(*bits)
     out = np.zeros(len(bits), dtype=np.uint64)
@@ -158,7 +158,7 @@ class Oracle:
 
     ``q``: data primes q_0..q_L (q_0 the base prime that holds the final
     result); ``p``: key-switching special primes; ``dnum``: digits at the
-    top level, alpha = ceil((L+1)/dnum) primes per digit (reading C8).
+    top level, alpha = ceil((L+1)/dnum) primes per digit (hybrid key switching).
     All arrays are numpy uint64 in [0, q), polys in NTT form unless a
     method says otherwise, layout [poly][limb][N].
     """
@@ -333,7 +333,7 @@ class Oracle:
         return out
 
     def galois_elt(self, step):
-        """Reading C4: left rotation by r uses g = 5^(r mod N/2) mod 2N."""
+        """Left rotation by r uses g = 5^(r mod N/2) mod 2N (slot j <-> zeta^(5^j))."""
         two_n = 2 * self.N
         return pow(5, step % (self.N // 2), two_n)
 

@@ -17,7 +17,7 @@
  * after a ciphertext product and rescales / matches levels before binary
  * operations).
  * The paper defers every integer-level detail to its CKKS backend, so the
- * conventions below are this project's readings (listed in the design doc):
+ * conventions below are this project's readings of the paper:
  *   - NTT slot k holds a(psi^(2*brv(k)+1)), psi = smallest primitive
  *     2N-th root of unity mod q;
  *   - hybrid key switching with digits of alpha consecutive primes,
@@ -72,7 +72,7 @@ u64 orc_mulmod(u64 a, u64 b, u64 q) { return mulmod(a, b, q); }
 u64 orc_powmod(u64 a, u64 e, u64 q) { return powmod(a, e, q); }
 
 /* ------------------------------------------------------------------ */
-/* primes and roots (reading C1 / C3)                                   */
+/* primes and roots (prime choice rule, smallest primitive root)       */
 /* ------------------------------------------------------------------ */
 /* Deterministic Miller-Rabin for 64-bit n (first 12 prime bases). */
 int orc_is_prime(u64 n)
@@ -207,7 +207,7 @@ orc_ctx *orc_ctx_create(u32 logn, const u64 *primes, u32 n_q, u32 n_p, u32 dnum)
 u64 orc_ctx_psi(const orc_ctx *c, u32 i) { return c->psi[i]; }
 
 /* ------------------------------------------------------------------ */
-/* negacyclic NTT (reading C3)                                          */
+/* negacyclic NTT (slot k holds a(psi^(2 brv(k) + 1)))                */
 /* a_hat[k] = sum_j a[j] psi^((2 brv(k) + 1) j)  (mod q)               */
 /* Computed as: twist b[j] = a[j] psi^j, cyclic length-N DFT with       */
 /* omega = psi^2 (B[m] = sum_j b[j] omega^(m j)), then a_hat[k] =       */
@@ -259,7 +259,7 @@ void orc_intt(const orc_ctx *c, u32 pi, u64 *a)
 }
 
 /* ------------------------------------------------------------------ */
-/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and samplers (C12) */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and samplers      */
 /* ------------------------------------------------------------------ */
 void orc_philox4x32_10(const u32 ctr_in[4], const u32 key_in[2], u32 out[4])
 {
@@ -463,7 +463,7 @@ void orc_keygen_relin(const orc_ctx *c, const u64 *sk_ntt, u64 seed, u64 *rk)
 }
 
 /* ------------------------------------------------------------------ */
-/* encryption / decryption (readings C10, C12)                          */
+/* encryption / decryption (public key, at the plaintext's level)     */
 /* ------------------------------------------------------------------ */
 /* pt: NTT form at level l, [l+1][N]. ct out: [2][l+1][N].
  * v ternary (tag ENC_V), e0, e1 CBD (tags ENC_E0, ENC_E1), object obj. */
@@ -562,7 +562,7 @@ void orc_mul_plain(const orc_ctx *c, const u64 *a, const u64 *pt, u32 n_poly, u3
 }
 
 /* multiply by the constant polynomial v (signed integer), i.e. every
- * residue of limb i times v mod q_i (reading C6) */
+ * residue of limb i times v mod q_i (a constant is a constant polynomial) */
 void orc_mul_const(const orc_ctx *c, const u64 *a, i64 v, u32 n_poly, u32 level, u64 *out)
 {
     u32 n = nn(c), L = level + 1;
@@ -605,7 +605,7 @@ void orc_tensor(const orc_ctx *c, const u64 *a, const u64 *b, u32 level, u64 *ou
 }
 
 /* ------------------------------------------------------------------ */
-/* rescale (reading C7)                                                 */
+/* rescale (rounding division by the top prime)                        */
 /* c' = floor((c + h) / q_l), h = floor(q_l / 2), per coefficient of the */
 /* CRT value; RNS form: r = [c_l + h]_{q_l}, c'_i = (c_i - (r - h)) q_l^-1 */
 /* ------------------------------------------------------------------ */
@@ -644,7 +644,7 @@ void orc_mod_switch(const orc_ctx *c, const u64 *in, u32 n_poly, u32 level, u32 
 }
 
 /* ------------------------------------------------------------------ */
-/* hybrid key switching (reading C8, C9)                                */
+/* hybrid key switching (approximate ModUp, floor ModDown)            */
 /* ------------------------------------------------------------------ */
 /* prime index of target t in the extended basis Q_l U P: t <= l -> data
  * prime t, t > l -> special prime t - (l+1). */

@@ -6,9 +6,9 @@ Definitions (paper Section 2.1: a sequence of values is encoded into one
 polynomial and only the whole can be operated on; CKKS slots = N/2):
   zeta = exp(i pi / N), a primitive 2N-th root of unity;
   slot j (0 <= j < N/2) is the evaluation point zeta^(5^j mod 2N)
-  (reading C4), its conjugate point zeta^(-5^j) carries conj(z_j);
+  (slot order by powers of 5), its conjugate point zeta^(-5^j) carries conj(z_j);
   encode(z, Delta) = round_half_away(Delta * sigma^-1(z)) where
-  sigma^-1(z)_i = (1/N) sum_{k odd} v(zeta^k) zeta^(-i k) (reading C5);
+  sigma^-1(z)_i = (1/N) sum_{k odd} v(zeta^k) zeta^(-i k) (the inverse canonical embedding);
   decode(m, Delta) = m(zeta^(5^j)) / Delta.
 Both directions use numpy's length-2N FFT as the transform primitive: the
 value vector V (V[k] = value at zeta^k, zero at even k) gives
@@ -35,7 +35,7 @@ def round_half_away(x):
 
 def encode(z, scale, N):
     """z: up to N/2 real or complex values (zero-padded). Returns int64
-    coefficients, or raises when a coefficient reaches 2^62 (reading C5)."""
+    coefficients, or raises when a coefficient reaches 2^62 (round half away from zero)."""
     z = np.asarray(z, dtype=np.complex128)
     if z.size > N // 2:
         raise ValueError("too many slots")

@@ -53,7 +53,7 @@ def test_samplers_distribution():
 
 
 # ---------------------------------------------------------------------------
-# primes and roots (reading C1 / C3), pinned with sympy's primality test
+# primes and roots (prime choice rule, smallest root), pinned with sympy's primality test
 # ---------------------------------------------------------------------------
 def _primes_by_rule_sympy(logn, bits):
     two_n = 2 << logn

@@ -319,7 +319,46 @@ def nets_leg(args, dev, log):
     out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
                      "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt}
     log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
-    del g, cts, ctx
+    # conv + bias + x^2 in the two layouts: slot-batched (one ciphertext per
+    # pixel) and the paper's image-in-slots masked kernels (8 images per
+    # ciphertext, taps summed by hoisted rotations)
+    from paper_2110_13638_amd.graph import Graph
+    rows, _ = nets.conv_rows(P["conv_w"], 28)
+    per = len(rows) // P["conv_w"].shape[0]
+    g1 = Graph(ctx)
+    g1.chain(g1.input(784, 7, scale), g1.linear(rows, scale, [P["conv_b"][j // per] for j in range(len(rows))]),
+             g1.square(), g1.output())
+    g1.plan()
+    g1.run(cts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g1.run(cts)
+    torch.cuda.synchronize()
+    dt_sb = (time.perf_counter() - t0) / args.net_runs
+    del g1
+    steps = nets.conv_slots_steps()
+    for ge in nets.galois_for_steps(ctx, steps, direct=True):
+        ctx.add_galois_key(ge, nets.galois_key_seed(24, ge))
+    n_slot_img = 1024
+    packed = nets.conv_slots_pack(x[:n_slot_img], ctx.N // 2)
+    scts = [ctx.encrypt(ctx.encode(packed[c], level=7), seed=23, obj=c) for c in range(packed.shape[0])]
+    g2 = nets.build_conv_slots(ctx, P, len(scts), 7, scale)
+    g2.run(scts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g2.run(scts)
+    torch.cuda.synchronize()
+    dt_is = (time.perf_counter() - t0) / args.net_runs
+    out["conv_layouts"] = {
+        "workload": "conv 5x5x5 stride 2 + bias + x^2, N=2^14, level 7",
+        "slot_batched": {"images": n_img, "ms": 1e3 * dt_sb, "images_per_s": n_img / dt_sb},
+        "image_in_slots": {"images": n_slot_img, "ciphertexts": len(scts), "ms": 1e3 * dt_is,
+                           "images_per_s": n_slot_img / dt_is, "rotations_per_ciphertext": 5 * (len(steps) - 1)}}
+    log("conv+square: slot-batched %.0f images/s, image-in-slots (hoisted taps) %.0f images/s" %
+        (n_img / dt_sb, n_slot_img / dt_is))
+    del g, g2, cts, scts, ctx
     torch.cuda.empty_cache()
     # yield
     pr = nat.ckks_find_primes(14, [60] + [40] * 5 + [60])

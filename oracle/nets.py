@@ -164,3 +164,17 @@ def diag_dense(orc, keys, ct, scale, diag_pts, pt_scale, in_steps, post_steps, b
     if bias_pt is not None:
         acc = orc.add_plain(acc, bias_pt)
     return acc, out_scale
+
+
+def conv_slots(orc, keys, ct, scale, mask_coeffs, steps, bias_pts, pt_scale):
+    """The paper's conv layout on one image-in-slots ciphertext: per filter f
+    the masked-kernel taps summed with hoisted rotations, rescale, + bias at
+    the anchors, then x^2. mask_coeffs[f]: [k*k][N] integer plaintexts at
+    pt_scale; bias_pts[f]: NTT-form plaintext at the level and scale after
+    the rescale. Returns ([F] ciphertexts, scale)."""
+    outs, s_out = [], None
+    for f in range(len(mask_coeffs)):
+        y, s = diag_dense_hoisted(orc, keys, ct, scale, mask_coeffs[f], pt_scale, steps, [], bias_pts[f])
+        y, s_out = square(orc, keys, y, s)
+        outs.append(y)
+    return outs, s_out

@@ -232,3 +232,84 @@ def poly_eval(coeffs, x):
     """sum_k c_k x^k, term by term (no Horner), in FP64."""
     x = np.asarray(x, dtype=np.float64)
     return sum(c * x ** k for k, c in enumerate(coeffs))
+
+
+# ---------------------------------------------------------------------------
+# the paper's conv layout (Section 4.2.2, kernel masquerading): the image in
+# the slots of one ciphertext (image b in the slot block [b*block, (b+1)*block),
+# pixel p = 28 r + c), each filter a sparse masked kernel per tap
+# ---------------------------------------------------------------------------
+def conv_slots_layout(conv_w, conv_b, slots, side=28, block=1024, stride=2):
+    """Rotation steps of the k*k taps, per filter and tap the mask (the tap
+    weight at every output anchor whose tap pixel lies inside the image),
+    and per filter the bias at the anchors; anchors are p = (2y) 28 + 2x.
+    Returns (steps [k*k], masks [F][k*k][slots], bias [F][slots])."""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    n_blk = slots // block
+    steps = [dy * side + dx for dy in range(k) for dx in range(k)]
+    masks = np.zeros((F, k * k, slots))
+    bias = np.zeros((F, slots))
+    for y in range(out_side):
+        for xx in range(out_side):
+            p = stride * y * side + stride * xx
+            for b in range(n_blk):
+                bias[:, b * block + p] = conv_b
+            for t, (dy, dx) in enumerate((dy, dx) for dy in range(k) for dx in range(k)):
+                if stride * y + dy < side and stride * xx + dx < side:
+                    for b in range(n_blk):
+                        masks[:, t, b * block + p] = conv_w[:, dy, dx]
+    return steps, masks, bias
+
+
+def conv_slots_pack(x, slots, block=1024):
+    """images [n][side][side] -> slot vectors [n_ct][slots]"""
+    n = x.shape[0]
+    per = slots // block
+    n_ct = -(-n // per)
+    v = np.zeros((n_ct, slots))
+    flat = x.reshape(n, -1)
+    for i in range(n):
+        v[i // per, (i % per) * block:(i % per) * block + flat.shape[1]] = flat[i]
+    return v
+
+
+def conv_slots_packed(x, P, slots, block=1024):
+    """conv + bias + x^2 in the image-in-slots layout with np.roll for the
+    rotations: [n_ct][F][slots] (values at the anchors, zero elsewhere)"""
+    steps, masks, bias = conv_slots_layout(P["conv_w"], P["conv_b"], slots, block=block)
+    v = conv_slots_pack(x, slots, block)
+    out = np.zeros((v.shape[0], masks.shape[0], slots))
+    for c in range(v.shape[0]):
+        for f in range(masks.shape[0]):
+            acc = sum(masks[f, t] * np.roll(v[c], -s) for t, s in enumerate(steps))
+            out[c, f] = (acc + bias[f]) ** 2
+    return out
+
+
+def conv_slots_anchor_values(out, n, side=28, block=1024, out_side=13):
+    """[n_ct][F][slots] -> [n][F][out_side][out_side] read at the anchors"""
+    F, slots = out.shape[1], out.shape[2]
+    per = slots // block
+    res = np.zeros((n, F, out_side, out_side))
+    for i in range(n):
+        for y in range(out_side):
+            for xx in range(out_side):
+                res[i, :, y, xx] = out[i // per, :, (i % per) * block + 2 * y * side + 2 * xx]
+    return res
+
+
+def vision_conv_square_math(x, P):
+    """the first two layers of vision_math: (conv + bias)^2 [n][F][13][13]"""
+    n, side, _ = x.shape
+    F, k, _ = P["conv_w"].shape
+    pad = np.zeros((n, side + 1, side + 1))
+    pad[:, :side, :side] = x
+    out_side = (side + 1 - k) // 2 + 1
+    conv = np.zeros((n, F, out_side, out_side))
+    for o in range(F):
+        for y in range(out_side):
+            for xx in range(out_side):
+                patch = pad[:, 2 * y:2 * y + k, 2 * xx:2 * xx + k]
+                conv[:, o, y, xx] = np.tensordot(patch, P["conv_w"][o], axes=([1, 2], [0, 1])) + P["conv_b"][o]
+    return conv ** 2

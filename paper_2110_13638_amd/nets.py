@@ -233,3 +233,68 @@ def relu_approx_coeffs(q):
 def sigmoid_approx_coeffs():
     """sigma_a(x) = 0.5 + 0.197 x - 0.004 x^3"""
     return [0.5, 0.197, 0.0, -0.004]
+
+
+# ---------------------------------------------------------------------------
+# the paper's conv layout (Section 4.2.2, kernel masquerading): each image in
+# a block of `block` slots of one ciphertext (pixel p = 28 r + c), each
+# filter a masked kernel per tap; the k*k taps are summed with hoisted
+# rotations in one DIAG_DENSE node per filter
+# ---------------------------------------------------------------------------
+def conv_slots_layout(conv_w, conv_b, slots, side=28, block=1024, stride=2):
+    """(steps [k*k], masks [F][k*k][slots], bias [F][slots]): tap t = (dy, dx)
+    rotates by 28 dy + dx; its mask holds w_f[dy, dx] at every output anchor
+    p = 2y * 28 + 2x whose tap pixel lies inside the image; the bias sits at
+    the anchors."""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    n_blk = slots // block
+    taps = [(dy, dx) for dy in range(k) for dx in range(k)]
+    steps = [dy * side + dx for dy, dx in taps]
+    masks = np.zeros((F, len(taps), slots))
+    bias = np.zeros((F, slots))
+    anchors = [(y, xx, stride * y * side + stride * xx) for y in range(out_side) for xx in range(out_side)]
+    for b in range(n_blk):
+        base = b * block
+        for y, xx, p in anchors:
+            bias[:, base + p] = conv_b
+            for t, (dy, dx) in enumerate(taps):
+                if stride * y + dy < side and stride * xx + dx < side:
+                    masks[:, t, base + p] = conv_w[:, dy, dx]
+    return steps, masks, bias
+
+
+def conv_slots_pack(x, slots, block=1024):
+    """images [n][side][side] -> [n_ct][slots], image i in block i mod (slots / block)"""
+    n = x.shape[0]
+    per = slots // block
+    flat = x.reshape(n, -1)
+    v = np.zeros((-(-n // per), slots))
+    for i in range(n):
+        v[i // per, (i % per) * block:(i % per) * block + flat.shape[1]] = flat[i]
+    return v
+
+
+def build_conv_slots(ctx, P, n_ct, in_level, scale, mask_coeffs=None, bias_coeffs=None, block=1024):
+    """input (image-in-slots ciphertexts) -> per filter: masked taps summed by
+    hoisted rotations, rescale, + bias, x^2 -> one output node per filter
+    (outputs filter-major). Every tap step needs its own Galois key."""
+    slots = ctx.N // 2
+    steps, masks, bias = conv_slots_layout(P["conv_w"], P["conv_b"], slots, block=block)
+    g = Graph(ctx)
+    x = g.input(n_ct, in_level, scale)
+    for f in range(masks.shape[0]):
+        dc = mask_coeffs[f] if mask_coeffs is not None else np.stack(
+            [ctx.encode_coeffs(masks[f, t], scale) for t in range(len(steps))])
+        if bias_coeffs is None:
+            node = g.diag_dense(dc, steps, scale, (), bias_slots=bias[f], hoisted=True)
+        else:
+            node = g.diag_dense(dc, steps, scale, (), bias_coeffs=bias_coeffs[f], hoisted=True)
+        g.edge(x, node)
+        g.chain(node, g.square(), g.output())
+    g.plan()
+    return g
+
+
+def conv_slots_steps(side=28, k=5):
+    return [dy * side + dx for dy in range(k) for dx in range(k)]

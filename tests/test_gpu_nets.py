@@ -194,3 +194,41 @@ def test_poly_activation(mods, which):
     err = _rel_err(got, want)
     print("%s approximation: max relative error 2^%.1f" % (which, np.log2(err)))
     assert err <= TOL
+
+
+def test_conv_slots_layer(mods):
+    # the paper's image-in-slots conv layout at N = 2^12 (two images per
+    # ciphertext): bit-exact vs the oracle's lowering, decoded conv^2 at the
+    # anchors within tolerance of the FP64 layers
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 12, [60] + [40] * 3, [60], 4, 7)
+    slots = ctx.N // 2
+    x, P = S.vision_inputs(n_images=4)
+    steps, masks, bias = PN.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    s2, m2, b2 = nets.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    assert s2 == steps and np.array_equal(m2, masks) and np.array_equal(b2, bias)
+    elts = nets.galois_for_steps(ctx, steps, direct=True)
+    keys = ON.Keys(orc, 7, elts)
+    for g in elts:
+        ctx.add_galois_key(g, nets.galois_key_seed(7 + 3, g))
+    v = PN.conv_slots_pack(x, slots)
+    assert np.array_equal(nets.conv_slots_pack(x, slots), v)
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, v[c], 3, 5, c) for c in range(v.shape[0])])
+    mcs = [np.stack([E.encode(masks[f, t], SCALE, ctx.N) for t in range(len(steps))]) for f in range(5)]
+    out_scale = SCALE * SCALE / orc.q[3]
+    bcs = [E.encode(bias[f], out_scale, ctx.N) for f in range(5)]
+    g = nets.build_conv_slots(ctx, P, len(cts), 3, SCALE, mask_coeffs=mcs, bias_coeffs=bcs)
+    outs = g.run(list(cts))  # filter-major: outs[f * n_ct + c]
+    n_ct = len(cts)
+    got = np.zeros((n_ct, 5, slots))
+    for c in range(n_ct):
+        ys, s = ON.conv_slots(orc, keys, ctos[c], SCALE, mcs, steps,
+                              [orc.reduce_int(b, 2) for b in bcs], SCALE)
+        for f in range(5):
+            o = outs[f * n_ct + c]
+            assert o.scale == s and np.array_equal(o.residues(), ys[f]), (c, f)
+            got[c, f] = ctx.decrypt(o, slots).real
+    vals = PN.conv_slots_anchor_values(got, 4)
+    err = _rel_err(vals, PN.vision_conv_square_math(x, P))
+    print("conv in slots: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL

@@ -168,3 +168,27 @@ def test_yield_network_hoisted_small_ring():
     want = PN.yield_math(x, ws, bs)[:Wn, 0]
     err = np.max(np.abs(got[: len(want)] - want) / np.maximum(1.0, np.abs(want)))
     assert err <= TOL, err
+
+
+def test_conv_slots_layer_small_ring():
+    # the paper's image-in-slots conv (kernel masquerading, taps summed by
+    # hoisted rotations) + x^2 at N = 2^12: two images per ciphertext
+    logn = 12
+    primes = O.find_primes(logn, [60] + [40] * 3 + [60])
+    orc = O.Oracle(logn, primes[:4], primes[4:], 4)
+    scale = 2.0 ** 40
+    x, P = S.vision_inputs(n_images=2)
+    slots = orc.N // 2
+    steps, masks, bias = PN.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    keys = ON.Keys(orc, 7, sorted(orc.galois_elt(s) for s in steps if s))
+    v = PN.conv_slots_pack(x, slots)
+    ct = _encrypt(orc, keys, v[0], 3, scale, 5, 0)
+    mcs = [np.stack([E.encode(masks[f, t], scale, orc.N) for t in range(len(steps))]) for f in range(masks.shape[0])]
+    out_scale = scale * scale / orc.q[3]
+    bps = [orc.reduce_int(E.encode(bias[f], out_scale, orc.N), 2) for f in range(masks.shape[0])]
+    outs, s = ON.conv_slots(orc, keys, ct, scale, mcs, steps, bps, scale)
+    got = np.stack([_decrypt(orc, keys, y, s, slots) for y in outs])[None]
+    vals = PN.conv_slots_anchor_values(got, 2)
+    want = PN.vision_conv_square_math(x, P)
+    err = np.max(np.abs(vals - want) / np.maximum(1.0, np.abs(want)))
+    assert err <= TOL, err

@@ -71,3 +71,21 @@ def test_sigmoid_approx_closed_forms():
     # it follows the sigmoid on the stated range [-5, 5] to within 0.06
     # (largest gap 0.051 near |x| = 3.83)
     assert np.max(np.abs(PN.poly_eval(c, xs) - 1 / (1 + np.exp(-xs)))) < 0.06
+
+
+def test_conv_slots_packed_equals_math():
+    # the image-in-slots layout (masked kernels, rotations) reproduces the
+    # strided cross-correlation + bias + square at every anchor
+    x, P = S.vision_inputs(n_images=5)
+    slots = 2048  # two images per ciphertext
+    out = PN.conv_slots_packed(x, P, slots)
+    got = PN.conv_slots_anchor_values(out, 5)
+    assert np.max(np.abs(got - PN.vision_conv_square_math(x, P))) < 1e-12
+    # the first two layers of the full network agree with it
+    steps, masks, bias = PN.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    assert steps == [dy * 28 + dx for dy in range(5) for dx in range(5)]
+    # no weighted tap reads outside its image (rotations never mix images)
+    for t, st in enumerate(steps):
+        for b in range(2):
+            for p in np.nonzero(masks[0, t, b * 1024:(b + 1) * 1024])[0]:
+                assert p + st < 784

@@ -303,6 +303,11 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
     }
 }
 
+// The 128-bit sums of the linear layers are reduced every kLinFold terms:
+// each product is below q^2 < 2^122, so 32 terms plus a reduced carry stay
+// below 2^128 for any layer width.
+constexpr u32 kLinFold = 32;
+
 // Encrypted linear layer: out[j][p][t][k] = sum_i Wt[j][i] * in[i][p][t][k]
 // with Wt the weights reduced mod q_t (done by k_reduce_weights). One
 // thread owns one residue position for JT outputs; inputs are read once
@@ -334,6 +339,10 @@ k_linear(DevTables tb, const u64 *const *__restrict__ in_ptrs, const u64 *__rest
 #pragma unroll
             for (int jj = 0; jj < JT; jj++)
                 if (j0 + jj < n_out) acc[jj].mac(x, wrow[(size_t)jj * n_in + i]);
+            if ((i & (kLinFold - 1)) == kLinFold - 1) {
+#pragma unroll
+                for (int jj = 0; jj < JT; jj++) acc[jj] = Acc128{acc[jj].reduce(pc), 0};
+            }
         }
         const size_t out_off = ((size_t)p * out_stride + t) * N + k;
 #pragma unroll
@@ -372,6 +381,10 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 #pragma unroll
             for (int r = 0; r < kLinRows; r++)
                 if ((u32)r < G.nrows) acc[r].mac(x, w[(size_t)r * G.ncols + c]);
+            if ((c & (kLinFold - 1)) == kLinFold - 1) {
+#pragma unroll
+                for (int r = 0; r < kLinRows; r++) acc[r] = Acc128{acc[r].reduce(pc), 0};
+            }
         }
         const size_t out_off = ((size_t)p * out_stride + t) * N + k;
 #pragma unroll

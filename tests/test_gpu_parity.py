@@ -231,3 +231,30 @@ def test_full_size_hmult_sampled(ck):
     want = orc.mul_relin_rescale(res[:2], res[2:], rk)
     assert np.array_equal(out[0].residues(), want)
     assert np.array_equal(out[1].residues(), want)
+
+
+def test_wide_linear_no_accumulator_overflow(ck):
+    # 2000 inputs with every residue q - 1 and weights -1 (= q - 1 mod q):
+    # the exact sum of products exceeds 2^128 on the 60-bit prime, so the
+    # kernel's running sums must be reduced along the way
+    primes = O.find_primes(10, [60, 40, 60])
+    q = primes[:2]
+    ctx = ck.Context(10, q, primes[2:], 2)
+    orc = O.Oracle(10, q, primes[2:], 2)
+    n_in = 2000
+    full = np.stack([np.full((1, ctx.N), qi - 1, dtype=np.uint64) for qi in q], axis=1)  # [1][2][N]
+    one = np.concatenate([full, full])  # [2][2][N]
+    cts = [ctx.ct_from_residues(one, 2.0 ** 40) for _ in range(n_in)]
+    rows = np.zeros((2, n_in))
+    rows[0, :] = -1.0 / 2 ** 40
+    rows[1, ::2] = 3.0 / 2 ** 40
+    for sparse in (False, True):
+        if sparse:
+            outs = ctx.linear_csr(cts, np.array([0, n_in, n_in + n_in // 2]),
+                                  np.concatenate([np.arange(n_in), np.arange(0, n_in, 2)]),
+                                  np.concatenate([np.full(n_in, -1), np.full(n_in // 2, 3)]).astype(np.int64), 2.0 ** 40)
+        else:
+            outs = ctx.linear(cts, rows, w_scale=2.0 ** 40)
+        for j, w in enumerate(([-1] * n_in, [3 if i % 2 == 0 else 0 for i in range(n_in)])):
+            want = orc.lincomb([one] * n_in, w)
+            assert np.array_equal(outs[j].residues(), want), (sparse, j)

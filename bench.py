@@ -146,7 +146,7 @@ def serve_leg(args, dev, log, tuning=None):
         ctxs[("vision", log_n)] = c
         vision[log_n] = serve.VisionModel(c, P)
 
-    def make(seed, n, rate):
+    def make(seed, n, rate, lazy=False):
         reqs = []
         t = 0.0
         r2 = np.random.default_rng(seed)
@@ -157,10 +157,15 @@ def serve_leg(args, dev, log, tuning=None):
             else:
                 kind, log_n, level, n_ct = "vision", int(r2.choice([13, 14])), int(r2.integers(5, 8)), 784
             ctx = ctxs[(kind, log_n)]
-            res = S.residues_device(1000 + rid, ctx.q[: level + 1], ctx.N, 2 * n_ct, dev).view(n_ct, 2, level + 1,
-                                                                                            ctx.N)
-            cts = [ckks.Ciphertext(ctx, res[i], 2, level, ctx.default_scale) for i in range(n_ct)]
-            reqs.append(serve.Request(rid, kind, log_n, t, cts))
+
+            def inputs(ctx=ctx, rid=rid, level=level, n_ct=n_ct):
+                res = S.residues_device(1000 + rid, ctx.q[: level + 1], ctx.N, 2 * n_ct, dev).view(
+                    n_ct, 2, level + 1, ctx.N)
+                return [ckks.Ciphertext(ctx, res[i], 2, level, ctx.default_scale) for i in range(n_ct)]
+
+            # long runs create each request's input at admission (HBM holds
+            # only what is in flight)
+            reqs.append(serve.Request(rid, kind, log_n, t, inputs if lazy else inputs(), level=level))
         return reqs
 
     def engine():
@@ -191,7 +196,7 @@ def serve_leg(args, dev, log, tuning=None):
     # (2) load sweep, batched
     load = []
     for rate in args.serve_rates:
-        r = summary(engine().run(make(10 + int(rate), args.serve_sweep_requests, rate)))
+        r = summary(engine().run(make(10 + int(rate), args.serve_sweep_requests, rate, lazy=True)))
         r["arrival_rate_per_s"] = rate
         load.append(r)
         log("  Poisson %5.0f req/s: served %.1f req/s, p50 %.1f ms, p99 %.1f ms" %

@@ -38,7 +38,9 @@ class Request:
     kind: str            # "hmult" | "vision"
     log_n: int
     arrival: float       # seconds from the start of the run
-    inputs: list         # device Ciphertexts (owned by the request)
+    inputs: object       # device Ciphertexts (owned by the request), or a callable
+                         # that creates them when the request is admitted
+    level: int = -1      # input level (needed before a lazy request is admitted)
     stage: int = 0
     state: list = field(default_factory=list)
     footprint: int = 0
@@ -107,7 +109,7 @@ class Engine:
     # --- memory accounting ---------------------------------------------------
     def footprint(self, req):
         ctx = self.ctx[(req.kind, req.log_n)]
-        lvl = req.inputs[0].level
+        lvl = req.level if callable(req.inputs) else req.inputs[0].level
         if req.kind == "hmult":
             levels = [lvl]
             return 2 * nat.ckks_ct_bytes(ctx.h, 2, lvl) + nat.ckks_workspace_bytes(ctx.h, nat.CKKS_OP_HMULT, 1, levels)
@@ -115,7 +117,8 @@ class Engine:
         n1 = m.layers[0]["n_out"]
         # inputs, conv outputs, square outputs, fused-HMult scratch per ciphertext
         per = nat.ckks_ct_bytes(ctx.h, 2, lvl)
-        return (len(req.inputs) + 2 * n1) * per + n1 * nat.ckks_workspace_bytes(ctx.h, nat.CKKS_OP_HMULT, 1, [lvl])
+        n_in = m.n_pix if callable(req.inputs) else len(req.inputs)
+        return (n_in + 2 * n1) * per + n1 * nat.ckks_workspace_bytes(ctx.h, nat.CKKS_OP_HMULT, 1, [lvl])
 
     # --- lifecycle -------------------------------------------------------------
     def submit(self, req):
@@ -130,6 +133,8 @@ class Engine:
             if r.arrival <= now and self.used + r.footprint <= self.cap:
                 self.used += r.footprint
                 r.admitted = now
+                if callable(r.inputs):
+                    r.inputs = r.inputs()
                 r.state = list(r.inputs)
                 self.active.append(r)
             else:
@@ -142,6 +147,7 @@ class Engine:
             if r.done_event is not None and r.done_event.query():
                 r.finish = now
                 self.used -= r.footprint
+                r.inputs = r.state = None  # the result stays; inputs and intermediates are released
                 self.done.append(r)
             else:
                 keep.append(r)
@@ -235,6 +241,8 @@ def run_plain(contexts, vision, requests, clock=time.perf_counter):
     for req in sorted(requests, key=lambda r: r.arrival):
         while clock() - t0 < req.arrival:
             time.sleep(0.0005)
+        if callable(req.inputs):
+            req.inputs = req.inputs()
         ctx = contexts[(req.kind, req.log_n)]
         if req.kind == "hmult":
             a, b = req.inputs

@@ -499,8 +499,16 @@ void ckks_plan_destroy(ckks_plan *plan);
  *                        residues of every digit held in registers and the
  *                        ciphertexts processed one after another; levels
  *                        with more than 8 digits fall back to 4).
+ *   CKKS_TUNE_LIN_MFMA   1 (default): ckks_linear_csr layers whose rows
+ *                        share one column list (dense layers), with
+ *                        |weight| <= 2^40 and at most 40000 inputs, run on
+ *                        the matrix cores (exact int8 digit products);
+ *                        0: always the vector-ALU kernel.
  * Returns CKKS_EINVAL for an unknown knob or a value out of range. */
-enum { CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2, CKKS_TUNE_FUSE_TAIL = 3, CKKS_TUNE_IP_CTS = 4 };
+enum {
+    CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2, CKKS_TUNE_FUSE_TAIL = 3, CKKS_TUNE_IP_CTS = 4,
+    CKKS_TUNE_LIN_MFMA = 5
+};
 int ckks_ctx_set_tuning(ckks_ctx *ctx, int knob, int value);
 /* Current value of a knob, or -1 for a null context / unknown knob. */
 int ckks_ctx_get_tuning(const ckks_ctx *ctx, int knob);

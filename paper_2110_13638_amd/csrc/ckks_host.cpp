@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <complex>
+#include <deque>
 #include <type_traits>
 #include <string>
 #include <functional>
@@ -34,6 +35,11 @@ hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u
                          u32 out_stride, hipStream_t s);
 hipError_t launch_reduce_weights(const DevTables &tb, const i64 *W, u64 *wt, u32 count, u32 limbs,
                                  hipStream_t s);
+hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pad, u32 k_pad, const u32 *cols,
+                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 limbs,
+                              u32 in_stride, u32 out_stride, hipStream_t s);
+hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,
+                                hipStream_t s);
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
                                  const u64 *wt, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
                                  u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
@@ -203,9 +209,33 @@ struct Recorder {
     std::vector<LaunchFn> launches;
 };
 
+// Pinned host ring for launch-data uploads: a copy from pinned memory is
+// asynchronous, so the host keeps planning the next call while the device
+// works. Each region stays reserved until the event recorded after its copy
+// has completed.
+struct Staging {
+    uint8_t *buf = nullptr;
+    size_t cap = 0, head = 0;
+    struct Region {
+        size_t lo, hi;
+        hipEvent_t done;
+    };
+    std::deque<Region> inflight;
+    ~Staging() {
+        for (auto &r : inflight) {
+            hipEventSynchronize(r.done);
+            hipEventDestroy(r.done);
+        }
+        if (buf) hipHostFree(buf);
+    }
+};
+constexpr size_t kStagingBytes = (size_t)64 << 20;
+
 struct ckks_ctx {
     u32 log_n, N, n_q, n_p, n_prim, dnum, alpha, digits_top;
     Recorder *rec = nullptr;  // non-null while recording
+    Staging *stage = nullptr;  // created on the first upload
+    ~ckks_ctx() { delete stage; }
     std::vector<u64> primes;
     std::vector<u64> image;  // device table image (u64 words)
     size_t off_pc, off_tw, off_itw, off_modup, off_moddown, off_rescale;
@@ -275,6 +305,7 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     c->tb.xcd_remap = 1;
     c->tb.fuse_tail = 0;
     c->tb.ip_cts = kIpCts;
+    c->tb.lin_mfma = 1;
     c->log_n = p->log_n;
     c->N = 1u << p->log_n;
     c->n_q = p->n_q;
@@ -505,6 +536,10 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
             if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: FUSE_TAIL takes 0 or 1");
             c->tb.fuse_tail = (u32)value;
             return CKKS_OK;
+        case CKKS_TUNE_LIN_MFMA:
+            if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: LIN_MFMA takes 0 or 1");
+            c->tb.lin_mfma = (u32)value;
+            return CKKS_OK;
         case CKKS_TUNE_IP_CTS:
             if (value != 2 && value != kIpCts && value != kIpSeqCts)
                 return fail(CKKS_EINVAL, "set_tuning: IP_CTS takes 2, %d or %d", kIpCts, kIpSeqCts);
@@ -521,6 +556,7 @@ extern "C" int ckks_ctx_get_tuning(const ckks_ctx *c, int knob) {
         case CKKS_TUNE_XCD_REMAP: return (int)c->tb.xcd_remap;
         case CKKS_TUNE_FUSE_TAIL: return (int)c->tb.fuse_tail;
         case CKKS_TUNE_IP_CTS: return (int)c->tb.ip_cts;
+        case CKKS_TUNE_LIN_MFMA: return (int)c->tb.lin_mfma;
     }
     return -1;
 }
@@ -713,8 +749,48 @@ int upload(const ckks_ctx *c, uint8_t *dst, const void *src, size_t bytes, hipSt
         dst = r.arena + off;
         r.used = off + bytes;
     }
-    if (bytes) HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
     *where = dst;
+    if (!bytes) return CKKS_OK;
+    ckks_ctx *cm = const_cast<ckks_ctx *>(c);
+    if (!cm->stage) {
+        Staging *st = new Staging();
+        if (hipHostMalloc((void **)&st->buf, kStagingBytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            st->buf = nullptr;
+        } else {
+            st->cap = kStagingBytes;
+        }
+        cm->stage = st;
+    }
+    Staging &st = *cm->stage;
+    if (!st.buf || bytes > st.cap / 2) {
+        // pageable copy (synchronous with respect to the host)
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        return CKKS_OK;
+    }
+    size_t lo = al256(st.head);
+    if (lo + bytes > st.cap) lo = 0;
+    const size_t hi = lo + bytes;
+    // wait for the in-flight regions this one overlaps (oldest first)
+    while (!st.inflight.empty()) {
+        const Staging::Region &r = st.inflight.front();
+        const bool overlap = r.lo < hi && lo < r.hi;
+        if (!overlap && hipEventQuery(r.done) != hipSuccess) break;
+        HIP_TRY(hipEventSynchronize(r.done));
+        HIP_TRY(hipEventDestroy(r.done));
+        st.inflight.pop_front();
+    }
+    for (const Staging::Region &r : st.inflight)
+        if (r.lo < hi && lo < r.hi) {  // an older region further back still overlaps
+            HIP_TRY(hipEventSynchronize(r.done));
+        }
+    memcpy(st.buf + lo, src, bytes);
+    HIP_TRY(hipMemcpyAsync(dst, st.buf + lo, bytes, hipMemcpyHostToDevice, s));
+    hipEvent_t ev;
+    HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ev, s));
+    st.inflight.push_back({lo, hi, ev});
+    st.head = hi;
     return CKKS_OK;
 }
 // Run a launch now and, while recording, keep it for replays.
@@ -2157,9 +2233,47 @@ extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_
                                                   uint32_t level) {
     if (!c) return 0;
     const size_t L = level + 1;
-    return al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8) + al256((size_t)(n_in + n_out) * 8) +
-           1024;
+    const size_t grouped = al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8);
+    // matrix-core path: weights as int64 and their digit planes
+    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)n_in + 31) / 32 * 32;
+    const size_t mfma = al256((size_t)n_in * 4) + al256(nnz * 8) + al256((size_t)kWDig * rows_pad * k_pad);
+    return std::max(grouped, mfma) + al256((size_t)(n_in + n_out) * 8) + 1024;
 }
+
+namespace {
+// the matrix-core path for a layer whose rows all use one column list
+int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const u32 *cols, u32 ncols,
+                const int64_t *w, u32 L, u32 stride, u32 ostride, ckks_ct *out, void *ws, size_t ws_bytes,
+                hipStream_t s) {
+    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)ncols + 31) / 32 * 32;
+    const size_t o_cols = 0, o_w = al256((size_t)ncols * 4), o_ptr = o_w + al256((size_t)n_out * ncols * 8),
+                 o_wd = o_ptr + al256((size_t)(n_in + n_out) * 8),
+                 need = o_wd + al256((size_t)kWDig * rows_pad * k_pad);
+    if (need > ws_bytes) return fail(CKKS_ENOMEM, "linear_csr: workspace too small: need %zu", need);
+    std::vector<uint8_t> img(o_wd, 0);
+    memcpy(img.data() + o_cols, cols, (size_t)ncols * 4);
+    memcpy(img.data() + o_w, w, (size_t)n_out * ncols * 8);
+    std::vector<const u64 *> ptrs(n_in + n_out);
+    for (u32 i = 0; i < n_in; i++) ptrs[i] = in[i].data;
+    for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
+    memcpy(img.data() + o_ptr, ptrs.data(), ptrs.size() * 8);
+    uint8_t *w8 = nullptr;
+    CK(upload(c, (uint8_t *)ws, img.data(), img.size(), s, &w8));
+    // the digit planes live in the workspace (or right after the recorded image)
+    int8_t *wd = (int8_t *)((uint8_t *)ws + o_wd);
+    const u32 rp = (u32)rows_pad, kp = (u32)k_pad;
+    HIP_TRY(issue(c, s, [w8, o_w, n_out, ncols, rp, kp, wd](hipStream_t st) {
+        return launch_weight_digits((const i64 *)(w8 + o_w), n_out, ncols, rp, kp, wd, st);
+    }));
+    HIP_TRY(issue(c, s, [tb = c->tb, wd, rp, kp, w8, o_cols, o_ptr, ncols, n_in, n_out, L, stride,
+                         ostride](hipStream_t st) {
+        return launch_linear_mfma(tb, wd, rp, kp, (const u32 *)(w8 + o_cols), ncols, n_out,
+                                  (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L,
+                                  stride, ostride, st);
+    }));
+    return CKKS_OK;
+}
+}  // namespace
 
 extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_in, uint32_t n_out,
                                const uint32_t *row_ptr, const uint32_t *col, const int64_t *w, double w_scale,
@@ -2183,6 +2297,24 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
         if (row_ptr[j + 1] < row_ptr[j]) return fail(CKKS_EINVAL, "linear_csr: row_ptr not monotone");
     for (size_t e = 0; e < nnz; e++)
         if (col[e] >= n_in) return fail(CKKS_EINVAL, "linear_csr: column %u out of range", col[e]);
+    if (c->tb.lin_mfma) {
+        // one column list for every row and small weights: the matrix cores
+        const u32 nc = row_ptr[1] - row_ptr[0];
+        bool same = nc > 0 && nc <= kMfmaMaxIn && (size_t)nc * n_out == nnz;
+        for (u32 j = 1; same && j < n_out; j++) same = memcmp(col, col + (size_t)j * nc, (size_t)nc * 4) == 0;
+        for (size_t e = 0; same && e < nnz; e++) same = w[e] <= kWMax && w[e] >= -kWMax;
+        if (same) {
+            CK(linear_mfma(c, in, n_in, n_out, col, nc, w, L, stride, ostride, out, ws, ws_bytes,
+                           (hipStream_t)stream));
+            for (u32 j = 0; j < n_out; j++) {
+                out[j].n_poly = 2;
+                out[j].level = l;
+                out[j].limb_stride = ostride;
+                out[j].scale = in[0].scale * w_scale;
+            }
+            return CKKS_OK;
+        }
+    }
     // groups of consecutive rows with identical column lists
     std::vector<LinGroup> groups;
     std::vector<u32> cols;

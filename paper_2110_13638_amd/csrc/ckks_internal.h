@@ -44,6 +44,7 @@ struct DevTables {
     u32 xcd_remap;  // 1: consecutive work items on one XCD
     u32 fuse_tail;  // 1: HMult's rescale epilogue inside the last NTT
     u32 ip_cts;     // ciphertexts sharing each key load in the inner product (2 or 4)
+    u32 lin_mfma;   // 1: dense linear layers on the matrix cores
 };
 
 // ModUp constants for digit j truncated to s primes (1 <= s <= alpha):
@@ -87,6 +88,15 @@ struct LinGroup {
     u32 w_off, pad;
 };
 constexpr int kLinRows = 8;  // rows per group (accumulators per thread)
+
+// Dense modular linear layer on the matrix cores (k_linear_mfma): every
+// weight is split into kWDig signed base-128 digits and every residue into
+// kXDig unsigned base-128 digits; int8 MFMA products of digit planes are
+// summed exactly in int32 per digit weight 128^s and recombined before one
+// reduction mod q. Valid for |w| <= kWMax and at most kMfmaMaxIn inputs.
+constexpr int kWDig = 6, kXDig = 9;
+constexpr int64_t kWMax = (int64_t)1 << 40;
+constexpr uint32_t kMfmaMaxIn = 40000;
 
 // Key-switch inner product over up to kIpCts ciphertexts of one level that
 // share the key: target limb `pos` of the extended basis (prime `prime`).

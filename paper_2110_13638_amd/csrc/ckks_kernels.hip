@@ -393,6 +393,98 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
     }
 }
 
+// Dense linear layer on the matrix cores. One workgroup = 4 waves on one
+// tile of 16 consecutive residues (poly p, limb t, slots k0..k0+15); wave w
+// owns output rows 32 (4 blockIdx.y + w) .. +31 (two 16-row MFMA tiles).
+// Per chunk of 32 inputs a lane loads its 8 residues (one column, inputs
+// 8 (lane / 16) .. +7), splits them into kXDig 7-bit digits packed as int8
+// B fragments, and multiplies them with the weight-digit A fragments
+// (Wd [kWDig][rows_pad][k_pad], row-major, 8 bytes per lane) by
+// v_mfma_i32_16x16x32_i8, accumulating digit products of weight
+// 128^(a + b) together. Lane layout of that instruction (checked on the
+// device): A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16],
+// D[4 (l / 16) + r][l % 16].
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kMfmaS = kWDig + kXDig - 1;  // digit weights 128^0 .. 128^(s-1)
+__global__ void __launch_bounds__(256)
+k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
+              u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
+              u32 limbs, u32 in_stride, u32 out_stride) {
+    const u32 N = 1u << tb.log_n;
+    const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32 tile = blockIdx.x;  // 16 residues of one (p, t)
+    const u32 pt = (tile * 16) >> tb.log_n, k0 = (tile * 16) & (N - 1);
+    const u32 p = pt / limbs, t = pt - p * limbs;
+    const u32 row0 = (blockIdx.y * 4 + wave) * 32;
+    if (row0 >= rows_pad) return;
+    const u32 col = lane & 15, grp = lane >> 4;
+    const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + col;
+    v4i acc[2][kMfmaS];
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int s = 0; s < kMfmaS; s++) acc[h][s] = v4i{0, 0, 0, 0};
+    const size_t plane = (size_t)rows_pad * k_pad;
+    for (u32 kc = 0; kc < k_pad; kc += 32) {
+        // B fragments: this lane's column, inputs kc + 8 grp + e
+        long bd[kXDig];
+#pragma unroll
+        for (int b = 0; b < kXDig; b++) bd[b] = 0;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const u32 i = kc + 8 * grp + e;
+            const u64 x = i < n_in ? in_ptrs[cols[i]][in_off] : 0;
+#pragma unroll
+            for (int b = 0; b < kXDig; b++) bd[b] |= (long)((x >> (7 * b)) & 127) << (8 * e);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 8 * grp;
+#pragma unroll
+            for (int a = 0; a < kWDig; a++) {
+                const long ad = *reinterpret_cast<const long *>(wd + a * plane + aoff);
+#pragma unroll
+                for (int b = 0; b < kXDig; b++)
+                    acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
+            }
+        }
+    }
+    const PrimeConst pc = tb.pc[t];
+    const size_t out_off = ((size_t)p * out_stride + t) * N + k0 + col;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const u32 j = row0 + 16 * h + 4 * grp + r;
+            // v = sum_s acc_s 2^(7 s), signed, |v| < 2^120
+            __int128 v = 0;
+#pragma unroll
+            for (int s = kMfmaS - 1; s >= 0; s--) v = v * 128 + (__int128)acc[h][s][r];
+            const bool neg = v < 0;
+            const unsigned __int128 m = neg ? (unsigned __int128)(-v) : (unsigned __int128)v;
+            const u64 red = barrett128((u64)m, (u64)(m >> 64), pc);
+            if (j < n_out) out_ptrs[j][out_off] = neg && red ? pc.q - red : red;
+        }
+}
+
+// balanced base-128 digits of the weights: W[j][i] = sum_a d_a 128^a with
+// d_a in [-64, 63]; wd [kWDig][rows_pad][k_pad] int8, zero padded
+__global__ void k_weight_digits(const i64 *__restrict__ W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad,
+                                int8_t *__restrict__ wd) {
+    const size_t total = (size_t)rows_pad * k_pad;
+    for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+         g += (size_t)gridDim.x * blockDim.x) {
+        const u32 j = (u32)(g / k_pad), i = (u32)(g - (size_t)j * k_pad);
+        i64 w = (j < n_out && i < n_in) ? W[(size_t)j * n_in + i] : 0;
+#pragma unroll
+        for (int a = 0; a < kWDig; a++) {
+            const i64 d = ((w + 64) & 127) - 64;
+            wd[(size_t)a * total + g] = (int8_t)d;
+            w = (w - d) >> 7;  // exact: w - d is a multiple of 128
+        }
+    }
+}
+
 // Wt[t][j][i] = W[j][i] mod q_t
 __global__ void k_reduce_weights(DevTables tb, const i64 *__restrict__ W, u64 *__restrict__ wt, u32 count,
                                  u32 limbs) {
@@ -496,6 +588,22 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
     const size_t work = ((size_t)2 * limbs << tb.log_n) * n_groups;
     hipLaunchKernelGGL(k_linear_grouped, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt,
                        wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
+    return hipGetLastError();
+}
+hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pad, u32 k_pad, const u32 *cols,
+                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 limbs,
+                              u32 in_stride, u32 out_stride, hipStream_t s) {
+    const u32 N = 1u << tb.log_n;
+    const u32 tiles = (u32)(((size_t)2 * limbs * N) / 16);
+    const u32 row_blocks = (rows_pad + 127) / 128;
+    hipLaunchKernelGGL(k_linear_mfma, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad, cols, n_in,
+                       n_out, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
+    return hipGetLastError();
+}
+hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,
+                                hipStream_t s) {
+    const size_t work = (size_t)rows_pad * k_pad;
+    hipLaunchKernelGGL(k_weight_digits, dim3(ew_grid(work)), dim3(256), 0, s, W, n_out, n_in, rows_pad, k_pad, wd);
     return hipGetLastError();
 }
 hipError_t launch_reduce_weights(const DevTables &tb, const i64 *W, u64 *wt, u32 count, u32 limbs,

@@ -258,3 +258,29 @@ def test_wide_linear_no_accumulator_overflow(ck):
         for j, w in enumerate(([-1] * n_in, [3 if i % 2 == 0 else 0 for i in range(n_in)])):
             want = orc.lincomb([one] * n_in, w)
             assert np.array_equal(outs[j].residues(), want), (sparse, j)
+
+
+@pytest.mark.parametrize("shape", [(845, 100), (37, 5), (64, 33)])
+def test_dense_linear_matrix_cores_bit_exact(ck, shape):
+    # dense rows (one shared column list) go to the int8-digit MFMA kernel:
+    # bit-exact against the oracle's integer linear combination and against
+    # the vector-ALU kernel, for odd sizes and negative weights
+    n_in, n_out = shape
+    primes = O.find_primes(12, [60, 40, 40, 60])
+    ctx = ck.Context(12, primes[:3], primes[3:], 3)
+    orc = O.Oracle(12, primes[:3], primes[3:], 3)
+    ins = [S.residues(500 + i, ctx.q, ctx.N, 2) for i in range(n_in)]
+    cts = [ctx.ct_from_residues(r, 2.0 ** 40) for r in ins]
+    W = np.round(S.gaussian(7, (n_out, n_in), 0.1) * 2.0 ** 40).astype(np.int64)
+    W[0, :] = -(2 ** 40)  # the largest weight magnitude the kernel takes
+    row_ptr = np.arange(n_out + 1) * n_in
+    col = np.tile(np.arange(n_in), n_out)
+    outs = {}
+    for mfma in (1, 0):
+        ctx.set_tuning(lin_mfma=mfma)
+        outs[mfma] = [o.residues().copy() for o in ctx.linear_csr(cts, row_ptr, col, W.reshape(-1), 2.0 ** 40)]
+    ctx.set_tuning(lin_mfma=1)
+    for j in range(n_out):
+        want = orc.lincomb(ins, list(W[j]))
+        assert np.array_equal(outs[1][j], want), j
+        assert np.array_equal(outs[0][j], want), j

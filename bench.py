@@ -45,7 +45,12 @@ def limb_bytes(n):
 #   MAC  64x64 -> 128-bit product accumulated into a 128-bit sum
 #   RED  Barrett reduction of a 128-bit sum to [0, q)
 #   MULM Shoup multiplication by a precomputed constant
-OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23}
+#   BF_FP butterfly of the FP64 engine (primes below 2^50): product with
+#         FMA low part and rounded quotient (6 FP64 operations, one slot
+#         each at gfx950's full FP64 FMA rate), sum and difference (2), and
+#         the re-centring of X on every third stage (3 / 3)
+OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23, "BF_FP": 9}
+FP_PRIME_BOUND = 1 << 50
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hmult_b256_n32768_hbm_traffic.md")
@@ -73,17 +78,26 @@ def measured_traffic(kernel):
 
 
 def kernel_model(name, items, ctx, level):
-    """Algorithmic work of one launch of a kernel family in the fused HMult
-    pipeline, every item of the launch at ``level``: (HBM bytes, 32-bit
-    VALU slots). Bytes count each operand that must cross HBM once per
-    launch (a key limb shared by all ciphertexts of the batch once)."""
+    """Algorithmic work of one step's launches of a kernel family in the
+    fused HMult pipeline, every item at ``level``: (HBM bytes, 32-bit VALU
+    slots). Bytes count each operand that must cross HBM once per step (a
+    key limb shared by all ciphertexts of the batch once). A transform
+    costs N/2 log N butterflies of the engine its prime takes."""
     N, logN, k, A = ctx.N, ctx.log_n, len(ctx.p), -(-len(ctx.q) // ctx.dnum)
     L = level + 1
     E = L + k
     beta = -(-L // A)
     digit = [min(A, L - j * A) for j in range(beta)]
     lb = limb_bytes(N)
-    ntt = (N // 2) * logN * OPS["BF"]
+    fp_on = ctx.tuning().get("ntt_fp", 0) == 1
+    primes = list(ctx.q[:L]) + list(ctx.p)  # extended basis Q_l u P
+
+    def ntt_of(prime):
+        bf = OPS["BF_FP"] if fp_on and prime < FP_PRIME_BOUND else OPS["BF"]
+        return (N // 2) * logN * bf
+
+    ntt_data = sum(ntt_of(q) for q in ctx.q[:L]) / L  # mean over the data limbs
+    ntt = ntt_data
     fam = name.split("/")[0]
     if fam == "ntt_fwd_modup":
         # per ciphertext: each digit's coefficient limbs read once, every
@@ -91,8 +105,11 @@ def kernel_model(name, items, ctx, level):
         # per coefficient), transformed and written once
         per_ct_items = sum(E - s for s in digit)
         cts = items / per_ct_items
-        ops = cts * sum((E - s) * (N * (s * OPS["MAC"] + OPS["RED"]) + ntt) for s in digit)
-        return cts * (L + per_ct_items) * lb, ops
+        ops = 0
+        for j, s in enumerate(digit):
+            own = set(range(j * A, j * A + s))
+            ops += sum(N * (s * OPS["MAC"] + OPS["RED"]) + ntt_of(t) for i, t in enumerate(primes) if i not in own)
+        return cts * (L + per_ct_items) * lb, cts * ops
     if fam == "keyswitch_inner_product":
         cts = items / E
         # extended limbs (own-digit limbs come from the input limbs a1, b1),
@@ -278,8 +295,9 @@ def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
     torch.cuda.synchronize()
     nat.ckks_profile_enable(False)
     nrec = nat.ckks_profile_collect()
-    fwd_ms = np.mean([r[2] for r in nrec if r[0].startswith("ntt_fwd/")])
-    inv_ms = np.mean([r[2] for r in nrec if r[0].startswith("ntt_inv/")])
+    # per call (a call's limbs may be split into one launch per engine)
+    fwd_ms = sum(r[2] for r in nrec if r[0].startswith("ntt_fwd/")) / 3
+    inv_ms = sum(r[2] for r in nrec if r[0].startswith("ntt_inv/")) / 3
     ntt_bytes = len(limbs) * 2 * limb_bytes(N)
     ntt = {"limbs": len(limbs), "fwd_ms": fwd_ms, "inv_ms": inv_ms,
            "fwd_limb_ntt_per_s": len(limbs) / (fwd_ms * 1e-3),
@@ -520,18 +538,23 @@ def main():
     value = B * args.steps / elapsed
     log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
 
-    # per-kernel breakdown
+    # per-kernel-family breakdown. A family's NTT work items are split by
+    # prime class into one launch per arithmetic engine (FP64 for primes
+    # below 2^50, 64-bit integer above), so a family is timed per step: the
+    # sum of its launches' event durations and items over a step.
     fam = {}
     for name, items, ms in recs:
         f = fam.setdefault(name, [0, 0.0, 0])
         f[0] += 1
         f[1] += ms
-        f[2] = items
-    breakdown = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "items": v[2]} for k, v in fam.items()}
+        f[2] += items
+    st = args.steps
+    breakdown = {k: {"launches_per_step": v[0] / st, "ms_per_step": v[1] / st, "items_per_step": v[2] / st}
+                 for k, v in fam.items()}
     dom = max(fam, key=lambda k: fam[k][1])
     d = breakdown[dom]
-    alg_bytes, alg_ops = kernel_model(dom, d["items"], ctx, top)
-    sec = d["avg_ms"] * 1e-3
+    alg_bytes, alg_ops = kernel_model(dom, d["items_per_step"], ctx, top)
+    sec = d["ms_per_step"] * 1e-3
     hbm = {"achieved": round(alg_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     hbm["frac"] = round(hbm["achieved"] / HBM_PEAK_GBS, 4)
     alu = {"achieved": round(alg_ops / sec / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s"}
@@ -541,10 +564,10 @@ def main():
     roofline = {"kernel": dom, "bound": bound, "achieved": prim["achieved"], "peak": prim["peak"],
                 "unit": prim["unit"], "frac": prim["frac"], "traffic": traffic,
                 "other": dict(other, bound="hbm" if bound == "alu" else "alu"),
-                "alg_bytes_per_launch": alg_bytes, "alg_ops_per_launch": alg_ops, "avg_launch_ms": d["avg_ms"],
-                "launches": d["launches"]}
-    log("dominant kernel %s: %.3f ms/launch, %s %.1f %s (%.1f%% of peak); %s %.1f%%" %
-        (dom, d["avg_ms"], bound, prim["achieved"], prim["unit"], 100 * prim["frac"],
+                "alg_bytes_per_step": alg_bytes, "alg_ops_per_step": alg_ops, "ms_per_step": d["ms_per_step"],
+                "launches_per_step": d["launches_per_step"]}
+    log("dominant kernel family %s: %.3f ms/step in %g launches, %s %.1f %s (%.1f%% of peak); %s %.1f%%" %
+        (dom, d["ms_per_step"], d["launches_per_step"], bound, prim["achieved"], prim["unit"], 100 * prim["frac"],
          other["unit"], 100 * other["frac"]))
 
     ragged_rate = plain_rate = same = ntt = None

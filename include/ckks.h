@@ -504,10 +504,14 @@ void ckks_plan_destroy(ckks_plan *plan);
  *                        |weight| <= 2^40 and at most 40000 inputs, run on
  *                        the matrix cores (exact int8 digit products);
  *                        0: always the vector-ALU kernel.
+ *   CKKS_TUNE_NTT_FP     1 (default): transforms of limbs whose prime is
+ *                        below 2^50 use FP64 modular arithmetic (exact
+ *                        FMA products, quotients from w/q); 0: 64-bit
+ *                        integer arithmetic for every prime.
  * Returns CKKS_EINVAL for an unknown knob or a value out of range. */
 enum {
     CKKS_TUNE_NTT_WIDE = 0, CKKS_TUNE_EW_LOG = 1, CKKS_TUNE_XCD_REMAP = 2, CKKS_TUNE_FUSE_TAIL = 3, CKKS_TUNE_IP_CTS = 4,
-    CKKS_TUNE_LIN_MFMA = 5
+    CKKS_TUNE_LIN_MFMA = 5, CKKS_TUNE_NTT_FP = 6
 };
 int ckks_ctx_set_tuning(ckks_ctx *ctx, int knob, int value);
 /* Current value of a knob, or -1 for a null context / unknown knob. */

@@ -22,6 +22,7 @@ CKKS_KEY_SECRET, CKKS_KEY_PUBLIC, CKKS_KEY_SWITCH = 0, 1, 2
 CKKS_OBJ_CT, CKKS_OBJ_PT, CKKS_OBJ_KEY = 0, 1, 2
 CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP, CKKS_TUNE_FUSE_TAIL, CKKS_TUNE_IP_CTS = 0, 1, 2, 3, 4
 CKKS_TUNE_LIN_MFMA = 5
+CKKS_TUNE_NTT_FP = 6
 
 
 class CkksError(RuntimeError):

@@ -172,7 +172,8 @@ class Context:
 
     TUNING_KNOBS = {"ntt_wide": nat.CKKS_TUNE_NTT_WIDE, "ew_log": nat.CKKS_TUNE_EW_LOG,
                     "xcd_remap": nat.CKKS_TUNE_XCD_REMAP, "fuse_tail": nat.CKKS_TUNE_FUSE_TAIL,
-                    "ip_cts": nat.CKKS_TUNE_IP_CTS, "lin_mfma": nat.CKKS_TUNE_LIN_MFMA}
+                    "ip_cts": nat.CKKS_TUNE_IP_CTS, "lin_mfma": nat.CKKS_TUNE_LIN_MFMA,
+                    "ntt_fp": nat.CKKS_TUNE_NTT_FP}
 
     def tuning(self):
         return {k: nat.ckks_ctx_get_tuning(self.h, v) for k, v in self.TUNING_KNOBS.items()}

@@ -94,6 +94,48 @@ __device__ __forceinline__ u64 centered_mod(u64 r, u64 h, const PrimeConst &pc) 
     return ge ? m : (m ? pc.q - m : 0);
 }
 
+// ---------------------------------------------------------------------
+// FP64 modular arithmetic for primes below 2^50 (the double-precision
+// scheme of van der Hoeven, Lecerf and Quintin, "Modular SIMD arithmetic in
+// Mathemagix", ACM TOMS 43(1), 2016): a residue is an integer-valued double,
+// an FMA returns the exact low part of a product and a rounded
+// multiplication by w/q (or 1/q) the quotient. gfx950 issues one FP64 FMA
+// per lane per cycle, the rate of a single 32-bit integer operation, while
+// an exact 64-bit Shoup product takes about twenty of those.
+//   fp_mulmod(y, w, w/q): exact y w - k q with k the integer nearest to
+//   y (w/q); |result| <= q (0.5 + |y| 2^-53) < q for |y| <= 2^52, and every
+//   intermediate is an integer below 2^53 in magnitude, so no step rounds.
+// The arithmetic is written out operation by operation: no contraction
+// into FMAs beyond the explicit ones.
+// ---------------------------------------------------------------------
+constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52: (x + kRound) - kRound rounds |x| < 2^51
+constexpr double kTwo52 = 4503599627370496.0;
+constexpr u64 kMant52 = (1ull << 52) - 1;
+__device__ __forceinline__ double fp_mulmod(double y, double w, double wq, double q) {
+#pragma clang fp contract(off)
+    const double h = y * w;
+    const double l = __builtin_fma(y, w, -h);
+    const double k = __builtin_fma(y, wq, kRound) - kRound;
+    return __builtin_fma(-k, q, h) + l;
+}
+// x - q round(x / q): |result| <= q / 2 + 1 for |x| <= 2^52
+__device__ __forceinline__ double fp_center(double x, double q, double qinv) {
+#pragma clang fp contract(off)
+    const double k = __builtin_fma(x, qinv, kRound) - kRound;
+    return __builtin_fma(-k, q, x);
+}
+// x < 2^52 as a double (exact): the integer placed in the mantissa of 2^52
+__device__ __forceinline__ double fp_from_u64(u64 x) {
+#pragma clang fp contract(off)
+    return __builtin_bit_cast(double, x | 0x4330000000000000ull) - kTwo52;
+}
+// integer-valued v with |v| < q to its residue in [0, q); qm = 2^52 + q
+__device__ __forceinline__ u64 fp_to_residue(double v, double qm, u64 q) {
+#pragma clang fp contract(off)
+    const u64 u = __builtin_bit_cast(u64, v + qm) & kMant52;  // v + q, in (0, 2q)
+    return csub(u, q);
+}
+
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -327,7 +369,121 @@ struct Ntt {
 #pragma unroll
         for (int k = 0; k < E; k++) r[k] = csub(r[k], pc.q);
     }
+
+    // ---- the same transforms in FP64 arithmetic (q < 2^50), same stage
+    // order, twiddle indices and data movement; residues are signed
+    // integer-valued doubles between the stages.
+    template <int PF, int PT>
+    static __device__ __forceinline__ void exchange_f(double (&d)[E], u32 *lds, u32 tid) {
+        u64 t[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) t[k] = __builtin_bit_cast(u64, d[k]);
+        exchange<PF, PT>(t, lds, tid);
+#pragma unroll
+        for (int k = 0; k < E; k++) d[k] = __builtin_bit_cast(double, t[k]);
+    }
+
+    // Forward stage s: (X, Y) -> (X + W Y, X - W Y). With |W Y mod q| < q the
+    // magnitude bound grows by q per stage; X is re-centred (|X| <= q/2 + 1)
+    // on stages s = 2 mod 3, so with inputs below 2q every value stays below
+    // 4q <= 2^52 (the multiplier's input range) and every sum is exact.
+    template <int P, int D>
+    static __device__ __forceinline__ void fwd_stage_f(double (&r)[E], u32 tid, const double2 *__restrict__ tw,
+                                                       double q, double qinv) {
+#pragma clang fp contract(off)
+        constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
+        constexpr bool recentre = ((s0 + D) % 3) == 2;
+#pragma unroll
+        for (int b = 0; b < E / 2; b++) {
+            const int g = b >> (w - 1);
+            const int bl = b & ((1 << (w - 1)) - 1);
+            const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
+            const u32 hi = group_hi(P, tid, g);
+            const int x = g * (1 << w) + c, y = x + half;
+            const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
+            const double2 W = tw[ti];
+            double X = r[x];
+            if constexpr (recentre) X = fp_center(X, q, qinv);
+            const double Tm = fp_mulmod(r[y], W.x, W.y, q);
+            r[x] = X + Tm;
+            r[y] = X - Tm;
+            if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (D + 1 < w) fwd_stage_f<P, D + 1>(r, tid, tw, q, qinv);
+    }
+    template <int P>
+    static __device__ __forceinline__ void fwd_phase_f(double (&r)[E], u32 *lds, u32 tid,
+                                                       const double2 *__restrict__ tw, double q, double qinv) {
+        if constexpr (P > 0) exchange_f<P - 1, P>(r, lds, tid);
+        fwd_stage_f<P, 0>(r, tid, tw, q, qinv);
+        if constexpr (P + 1 < NPH) fwd_phase_f<P + 1>(r, lds, tid, tw, q, qinv);
+    }
+    // forward() for q < 2^50: inputs in [0, q), outputs fully reduced
+    static __device__ __forceinline__ void forward_fp(u64 (&r)[E], u32 *lds, u32 tid,
+                                                      const double2 *__restrict__ tw, const PrimeConst &pc) {
+        double d[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) d[k] = fp_from_u64(r[k]);
+        fwd_phase_f<0>(d, lds, tid, tw, pc.qf, pc.qinvf);
+        exchange_f<NPH - 1, 0>(d, lds, tid);
+#pragma unroll
+        for (int k = 0; k < E; k++) r[k] = fp_to_residue(fp_center(d[k], pc.qf, pc.qinvf), pc.qmf, pc.q);
+    }
+
+    // Inverse stage s: (X, Y) -> (X + Y, (X - Y) W^-1); the sum is re-centred
+    // on every second stage executed, so inputs stay below 2q and
+    // differences below 4q. The last stage multiplies both outputs
+    // (by N^-1 and by W^-1 N^-1), leaving |.| < q.
+    template <int P, int D>
+    static __device__ __forceinline__ void inv_stage_f(double (&r)[E], u32 tid, const double2 *__restrict__ itw,
+                                                       const PrimeConst &pc) {
+#pragma clang fp contract(off)
+        constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
+        constexpr bool last = (s0 + D) == 0;
+        constexpr bool recentre = ((LOGN - 1 - (s0 + D)) & 1) == 1;
+        const double q = pc.qf;
+#pragma unroll
+        for (int b = 0; b < E / 2; b++) {
+            const int g = b >> (w - 1);
+            const int bl = b & ((1 << (w - 1)) - 1);
+            const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
+            const u32 hi = group_hi(P, tid, g);
+            const int x = g * (1 << w) + c, y = x + half;
+            const double X = r[x], Y = r[y];
+            if constexpr (last) {
+                r[x] = fp_mulmod(X + Y, pc.ninvf, pc.ninvqf, q);
+                r[y] = fp_mulmod(X - Y, pc.last_wf, pc.last_wqf, q);
+            } else {
+                const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
+                const double2 W = itw[ti];
+                const double U = X + Y;
+                r[x] = recentre ? fp_center(U, q, pc.qinvf) : U;
+                r[y] = fp_mulmod(X - Y, W.x, W.y, q);
+            }
+            if ((b & (kTwiddleChunkInv - 1)) == kTwiddleChunkInv - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (D > 0) inv_stage_f<P, D - 1>(r, tid, itw, pc);
+    }
+    template <int P>
+    static __device__ __forceinline__ void inv_phase_f(double (&r)[E], u32 *lds, u32 tid,
+                                                       const double2 *__restrict__ itw, const PrimeConst &pc) {
+        if constexpr (P < NPH - 1) exchange_f<P + 1, P>(r, lds, tid);
+        inv_stage_f<P, width(P) - 1>(r, tid, itw, pc);
+        if constexpr (P > 0) inv_phase_f<P - 1>(r, lds, tid, itw, pc);
+    }
+    // inverse() for q < 2^50: inputs in [0, q), outputs fully reduced
+    static __device__ __forceinline__ void inverse_fp(u64 (&r)[E], u32 *lds, u32 tid,
+                                                      const double2 *__restrict__ itw, const PrimeConst &pc) {
+        double d[E];
+#pragma unroll
+        for (int k = 0; k < E; k++) d[k] = fp_from_u64(r[k]);
+        exchange_f<0, NPH - 1>(d, lds, tid);
+        inv_phase_f<NPH - 1>(d, lds, tid, itw, pc);
+#pragma unroll
+        for (int k = 0; k < E; k++) r[k] = fp_to_residue(d[k], pc.qmf, pc.q);
+    }
 };
+
 
 // ---------------------------------------------------------------------
 // fused prologues / epilogues
@@ -378,15 +534,13 @@ __device__ __forceinline__ int xcd_item(int nitems, u32 remap) {
 }
 __host__ __device__ inline int xcd_grid(int nitems) { return (nitems + 7) & ~7; }
 
-template <int LOGN, int LOGE, int OP>
-__global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
+// One work item of k_fwd; FP selects the transform's arithmetic. The whole
+// item (prologue, transform, epilogue) is instantiated per engine so no
+// register assignment has to be shared across the two.
+template <int LOGN, int LOGE, int OP, bool FP>
+__device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u32 *lds, u64 seed) {
     using NT = Ntt<LOGN, LOGE>;
     constexpr int N = NT::N, E = NT::E, T = NT::T;
-    __shared__ u32 lds[NT::LDS_WORDS];
-    const int iid = xcd_item(nitems, tb.xcd_remap);
-    if (iid < 0) return;
-    const Item it = items[iid];
     const u32 tid = threadIdx.x, vo = tid * 8;
     const PrimeConst pc = tb.pc[it.prime];
     const u64 q = pc.q;
@@ -483,7 +637,10 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
         for (int c = 0; c < E; c++) r[c] = reduce_signed((i64)Buf((const u64 *)src).ld(vo, c * T * 8), pc);
     }
 
-    NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
+    if constexpr (FP)
+        NT::forward_fp(r, lds, tid, tb.twf + (size_t)it.prime * N, pc);
+    else
+        NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
 
     // ---- epilogue
     if constexpr (OP == F_COPY || is_modup(OP) || OP == F_SAMPLE || OP == F_INT || (is_relin(OP) && !is_relin_rs(OP))) {
@@ -537,15 +694,23 @@ k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
     }
 }
 
-template <int LOGN, int LOGE, int OP>
+// FP: every item's prime is below 2^50 and the transforms run in FP64
+// arithmetic (the host splits a launch by prime class); else 64-bit integer
+template <int LOGN, int LOGE, int OP, bool FP>
 __global__ void __launch_bounds__(1 << (LOGN - LOGE))
-k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
-    using NT = Ntt<LOGN, LOGE>;
-    constexpr int N = NT::N, E = NT::E, T = NT::T;
-    __shared__ u32 lds[NT::LDS_WORDS];
+k_fwd(DevTables tb, const Item *__restrict__ items, int nitems, u64 seed) {
+    __shared__ u32 lds[Ntt<LOGN, LOGE>::LDS_WORDS];
     const int iid = xcd_item(nitems, tb.xcd_remap);
     if (iid < 0) return;
     const Item it = items[iid];
+    fwd_item<LOGN, LOGE, OP, FP>(tb, it, lds, seed);
+}
+
+// One work item of k_inv (see fwd_item).
+template <int LOGN, int LOGE, int OP, bool FP>
+__device__ __forceinline__ void inv_item(const DevTables &tb, const Item &it, u32 *lds) {
+    using NT = Ntt<LOGN, LOGE>;
+    constexpr int N = NT::N, E = NT::E, T = NT::T;
     const u32 tid = threadIdx.x, vo = tid * 8;
     const PrimeConst pc = tb.pc[it.prime];
     const u64 q = pc.q;
@@ -569,7 +734,10 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
         }
     }
 
-    NT::inverse(r, lds, tid, tb.itw + (size_t)it.prime * N, pc);
+    if constexpr (FP)
+        NT::inverse_fp(r, lds, tid, tb.itwf + (size_t)it.prime * N, pc);
+    else
+        NT::inverse(r, lds, tid, tb.itw + (size_t)it.prime * N, pc);
 
     if constexpr (OP == I_MUL) {
         // it.v == 1: store [x * hat_i^-1]_{q_i}, the ModUp input (digit block it.c, position it.a)
@@ -591,20 +759,38 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
 #pragma unroll
     for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
 }
+template <int LOGN, int LOGE, int OP, bool FP>
+__global__ void __launch_bounds__(1 << (LOGN - LOGE))
+k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
+    __shared__ u32 lds[Ntt<LOGN, LOGE>::LDS_WORDS];
+    const int iid = xcd_item(nitems, tb.xcd_remap);
+    if (iid < 0) return;
+    const Item it = items[iid];
+    inv_item<LOGN, LOGE, OP, FP>(tb, it, lds);
+}
 
 // ---------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------
+// tb.ntt_fp set: the launch's items all have primes below 2^50 (FP64 engine)
 template <int LOGN, int LOGE, int OP>
 static hipError_t launch_fwd_t(const DevTables &tb, const Item *items, int n, u64 seed, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd<LOGN, LOGE, OP>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
-                       items, n, seed);
+    if (tb.ntt_fp)
+        hipLaunchKernelGGL((k_fwd<LOGN, LOGE, OP, true>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
+                           items, n, seed);
+    else
+        hipLaunchKernelGGL((k_fwd<LOGN, LOGE, OP, false>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
+                           items, n, seed);
     return hipGetLastError();
 }
 template <int LOGN, int LOGE, int OP>
 static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hipStream_t s) {
-    hipLaunchKernelGGL((k_inv<LOGN, LOGE, OP>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
-                       items, n);
+    if (tb.ntt_fp)
+        hipLaunchKernelGGL((k_inv<LOGN, LOGE, OP, true>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
+                           items, n);
+    else
+        hipLaunchKernelGGL((k_inv<LOGN, LOGE, OP, false>), dim3(xcd_grid(n)), dim3(Ntt<LOGN, LOGE>::T), 0, s, tb,
+                           items, n);
     return hipGetLastError();
 }
 

@@ -238,7 +238,7 @@ struct ckks_ctx {
     ~ckks_ctx() { delete stage; }
     std::vector<u64> primes;
     std::vector<u64> image;  // device table image (u64 words)
-    size_t off_pc, off_tw, off_itw, off_modup, off_moddown, off_rescale;
+    size_t off_pc, off_tw, off_itw, off_twf, off_itwf, off_modup, off_moddown, off_rescale;
     DevTables tb{};
     bool uploaded = false;
     // encoder
@@ -306,6 +306,7 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     c->tb.fuse_tail = 0;
     c->tb.ip_cts = kIpCts;
     c->tb.lin_mfma = 1;
+    c->tb.ntt_fp = 1;
     c->log_n = p->log_n;
     c->N = 1u << p->log_n;
     c->n_q = p->n_q;
@@ -338,6 +339,10 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
     c->off_tw = w;
     w = align_words(w + (size_t)np * N * 2);
     c->off_itw = w;
+    w = align_words(w + (size_t)np * N * 2);
+    c->off_twf = w;
+    w = align_words(w + (size_t)np * N * 2);
+    c->off_itwf = w;
     w = align_words(w + (size_t)np * N * 2);
     c->off_modup = w;
     const u32 blockw = modup_block_words(A, np);
@@ -382,6 +387,23 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
         pc.ninv_sh = shoup_companion(pc.ninv, q);
         pc.last_w = mulmod(itw[1].x, pc.ninv, q);
         pc.last_w_sh = shoup_companion(pc.last_w, q);
+        // FP64 copies (exact for q < 2^50; w / q and 1 / q correctly rounded)
+        const double qd = (double)q;
+        double *twf = reinterpret_cast<double *>(img + c->off_twf) + (size_t)i * N * 2;
+        double *itwf = reinterpret_cast<double *>(img + c->off_itwf) + (size_t)i * N * 2;
+        for (u32 k = 0; k < N; k++) {
+            twf[2 * k] = (double)tw[k].x;
+            twf[2 * k + 1] = (double)tw[k].x / qd;
+            itwf[2 * k] = (double)itw[k].x;
+            itwf[2 * k + 1] = (double)itw[k].x / qd;
+        }
+        pc.qf = qd;
+        pc.qinvf = 1.0 / qd;
+        pc.qmf = 4503599627370496.0 + qd;
+        pc.ninvf = (double)pc.ninv;
+        pc.ninvqf = (double)pc.ninv / qd;
+        pc.last_wf = (double)pc.last_w;
+        pc.last_wqf = (double)pc.last_w / qd;
         u64 P = 1;
         for (u32 m = 0; m < npp; m++) P = mulmod(P, c->primes[nq + m] % q, q);
         Pmod[i] = P;
@@ -503,6 +525,8 @@ extern "C" int ckks_ctx_upload(ckks_ctx *c, void *dev, void *stream) {
     t.pc = reinterpret_cast<const PrimeConst *>(base + c->off_pc);
     t.tw = reinterpret_cast<const ulonglong2 *>(base + c->off_tw);
     t.itw = reinterpret_cast<const ulonglong2 *>(base + c->off_itw);
+    t.twf = reinterpret_cast<const double2 *>(base + c->off_twf);
+    t.itwf = reinterpret_cast<const double2 *>(base + c->off_itwf);
     t.modup = base + c->off_modup;
     t.moddown = base + c->off_moddown;
     t.rescale = reinterpret_cast<const ulonglong2 *>(base + c->off_rescale);
@@ -540,6 +564,10 @@ extern "C" int ckks_ctx_set_tuning(ckks_ctx *c, int knob, int value) {
             if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: LIN_MFMA takes 0 or 1");
             c->tb.lin_mfma = (u32)value;
             return CKKS_OK;
+        case CKKS_TUNE_NTT_FP:
+            if (value != 0 && value != 1) return fail(CKKS_EINVAL, "set_tuning: NTT_FP takes 0 or 1");
+            c->tb.ntt_fp = (u32)value;
+            return CKKS_OK;
         case CKKS_TUNE_IP_CTS:
             if (value != 2 && value != kIpCts && value != kIpSeqCts)
                 return fail(CKKS_EINVAL, "set_tuning: IP_CTS takes 2, %d or %d", kIpCts, kIpSeqCts);
@@ -557,6 +585,7 @@ extern "C" int ckks_ctx_get_tuning(const ckks_ctx *c, int knob) {
         case CKKS_TUNE_FUSE_TAIL: return (int)c->tb.fuse_tail;
         case CKKS_TUNE_IP_CTS: return (int)c->tb.ip_cts;
         case CKKS_TUNE_LIN_MFMA: return (int)c->tb.lin_mfma;
+        case CKKS_TUNE_NTT_FP: return (int)c->tb.ntt_fp;
     }
     return -1;
 }
@@ -735,6 +764,7 @@ struct Launch {
     size_t off;
     int n;
     u64 seed;
+    int fp = 0;  // NTT launches: every item's prime is below 2^50 and takes the FP64 engine
 };
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -816,11 +846,28 @@ struct Plan {
     template <class T>
     void add(int kind, int op, const std::vector<T> &v, u64 seed = 0) {
         if (v.empty()) return;
+        if constexpr (std::is_same<T, Item>::value) {
+            // NTT launches: with the FP64 engine enabled, items whose prime
+            // is below 2^50 go to one launch and the rest to another (each
+            // kernel carries one engine); relative order is kept
+            if ((kind == 0 || kind == 1) && c->tb.ntt_fp) {
+                std::vector<Item> fp, in;
+                for (const Item &it : v) (c->primes[it.prime] < kFpPrimeBound ? fp : in).push_back(it);
+                put(kind, op, fp, seed, 1);
+                put(kind, op, in, seed, 0);
+                return;
+            }
+        }
         if constexpr (std::is_same<T, EwItem>::value) op = (int)v[0].op;  // for the launch name
+        put(kind, op, v, seed, 0);
+    }
+    template <class T>
+    void put(int kind, int op, const std::vector<T> &v, u64 seed, int fp) {
+        if (v.empty()) return;
         size_t off = (desc.size() + 255) & ~(size_t)255;
         desc.resize(off + v.size() * sizeof(T));
         memcpy(desc.data() + off, v.data(), v.size() * sizeof(T));
-        launches.push_back({kind, op, off, (int)v.size(), seed});
+        launches.push_back({kind, op, off, (int)v.size(), seed, fp});
     }
     size_t total() const { return ((scratch + 255) & ~(size_t)255) + desc.size(); }
     int run(size_t ws_bytes, hipStream_t s) {
@@ -843,7 +890,9 @@ struct Plan {
                 HIP_TRY(hipEventCreate(&rec.e1));
                 HIP_TRY(hipEventRecord(rec.e0, s));
             }
-            e = issue(c, s, [tb = c->tb, L, p](hipStream_t st) {
+            DevTables tl = c->tb;
+            tl.ntt_fp = (u32)L.fp;
+            e = issue(c, s, [tb = tl, L, p](hipStream_t st) {
                 switch (L.kind) {
                     case 0: return launch_fwd(tb, L.op, (const Item *)p, L.n, L.seed, st);
                     case 1: return launch_inv(tb, L.op, (const Item *)p, L.n, st);

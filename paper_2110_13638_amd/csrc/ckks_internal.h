@@ -26,7 +26,13 @@ struct PrimeConst {
     u64 last_w, last_w_sh; // (psi^-1 table entry 1) * N^-1: merged last inverse stage
     u64 pinv, pinv_sh;     // P^-1 mod q (data primes; P = product of special primes)
     u64 pmod, pmod_sh;     // P mod q
+    // FP64 transform constants (used only when q < 2^50): q, 1/q, 2^52 + q,
+    // and the merged last inverse stage's N^-1 and last_w with their ratios to q
+    double qf, qinvf, qmf;
+    double ninvf, ninvqf, last_wf, last_wqf;
 };
+// primes below this bound may use the FP64 transforms
+constexpr u64 kFpPrimeBound = 1ull << 50;
 
 // Device view of the uploaded context tables. Built by the host from the
 // device base address; passed by value to every kernel.
@@ -34,6 +40,8 @@ struct DevTables {
     const PrimeConst *pc;        // [n_prim]
     const ulonglong2 *tw;        // [n_prim][N] (w, w') forward psi^brv(k)
     const ulonglong2 *itw;       // [n_prim][N] (w, w') inverse: (psi^brv(k))^-1
+    const double2 *twf;          // [n_prim][N] (w, w / q) in FP64, forward
+    const double2 *itwf;         // [n_prim][N] (w, w / q) in FP64, inverse
     const u64 *modup;            // ModUp blocks, see modup_block()
     const u64 *moddown;          // ModDown block
     const ulonglong2 *rescale;   // [n_q][n_q] (q_l^-1 mod q_i, Shoup)
@@ -45,6 +53,8 @@ struct DevTables {
     u32 fuse_tail;  // 1: HMult's rescale epilogue inside the last NTT
     u32 ip_cts;     // ciphertexts sharing each key load in the inner product (2 or 4)
     u32 lin_mfma;   // 1: dense linear layers on the matrix cores
+    u32 ntt_fp;     // context: 1 = transforms of primes below 2^50 in FP64 arithmetic;
+                    // per NTT launch: 1 = every item's prime is below 2^50 and takes that engine
 };
 
 // ModUp constants for digit j truncated to s primes (1 <= s <= alpha):

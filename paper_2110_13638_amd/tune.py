@@ -14,7 +14,8 @@ import os
 
 import torch
 
-DEFAULT_SPACE = {"ntt_wide": (0, 1), "ew_log": (1, 2, 3), "xcd_remap": (0, 1), "fuse_tail": (0, 1), "ip_cts": (2, 4, 16)}
+DEFAULT_SPACE = {"ntt_wide": (0, 1), "ew_log": (1, 2, 3), "xcd_remap": (0, 1), "fuse_tail": (0, 1), "ip_cts": (2, 4, 16),
+                 "ntt_fp": (0, 1)}
 
 
 def _key(ctx, workload):

@@ -111,8 +111,11 @@ def test_tuning_knobs_host():
         nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 16)
         with pytest.raises(nat.CkksError):
             nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_IP_CTS, 3)
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_NTT_FP) == 1
+        nat.ckks_ctx_set_tuning(h, nat.CKKS_TUNE_NTT_FP, 0)
+        assert nat.ckks_ctx_get_tuning(h, nat.CKKS_TUNE_NTT_FP) == 0
         for knob, bad in [(nat.CKKS_TUNE_EW_LOG, 0), (nat.CKKS_TUNE_EW_LOG, 4), (nat.CKKS_TUNE_NTT_WIDE, 2),
-                          (nat.CKKS_TUNE_XCD_REMAP, -1), (7, 0)]:
+                          (nat.CKKS_TUNE_XCD_REMAP, -1), (nat.CKKS_TUNE_NTT_FP, 2), (7, 0)]:
             with pytest.raises(nat.CkksError) as e:
                 nat.ckks_ctx_set_tuning(h, knob, bad)
             assert e.value.code == nat.CKKS_EINVAL

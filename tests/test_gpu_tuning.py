@@ -27,8 +27,8 @@ def _u(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f, ip_cts=i)
-            for w, e, x, f, i in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4, 16))]
+SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f, ip_cts=i, ntt_fp=p)
+            for w, e, x, f, i, p in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4, 16), (0, 1))]
 
 
 @pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15])
@@ -39,9 +39,10 @@ def test_ntt_variants_bit_exact(ck, log_n):
     ctx = ck.Context(log_n, primes[:3], primes[3:], 1)
     x = S.residues(9 + log_n, primes, 1 << log_n)[0]
     want = [orc.ntt(x[i], i) for i in range(len(primes))]
-    for wide, remap in itertools.product((0, 1) if log_n <= 14 else (0,), (0, 1)):
-        print("ntt variant log_n=%d wide=%d remap=%d" % (log_n, wide, remap), flush=True)
-        ctx.set_tuning(ntt_wide=wide, xcd_remap=remap)
+    # the 60-bit prime takes the integer engine, the others the FP64 one when enabled
+    for wide, remap, fp in itertools.product((0, 1) if log_n <= 14 else (0,), (0, 1), (0, 1)):
+        print("ntt variant log_n=%d wide=%d remap=%d fp=%d" % (log_n, wide, remap, fp), flush=True)
+        ctx.set_tuning(ntt_wide=wide, xcd_remap=remap, ntt_fp=fp)
         dev = torch.from_numpy(x.view(np.int64)).cuda()
         ptrs = [dev[i].data_ptr() for i in range(len(primes))]
         ws, wb = ctx.ws_for(nat.CKKS_OP_NTT, len(primes))
@@ -71,8 +72,8 @@ def hm(ck):
     return ctx, ins, want
 
 
-@pytest.mark.parametrize("st", SETTINGS, ids=lambda d: "w%d_e%d_x%d_f%d_i%d" % (d["ntt_wide"], d["ew_log"], d["xcd_remap"], d["fuse_tail"],
-                                                     d["ip_cts"]))
+@pytest.mark.parametrize("st", SETTINGS, ids=lambda d: "w%d_e%d_x%d_f%d_i%d_p%d" % (d["ntt_wide"], d["ew_log"], d["xcd_remap"],
+                                                                              d["fuse_tail"], d["ip_cts"], d["ntt_fp"]))
 def test_hmult_variants_bit_exact(hm, st):
     ctx, ins, want = hm
     print("hmult variant", st, flush=True)
@@ -80,7 +81,7 @@ def test_hmult_variants_bit_exact(hm, st):
     outs = ctx.hmult_relin_rescale([a for a, _ in ins], [b for _, b in ins])
     for o, w in zip(outs, want):
         assert np.array_equal(o.residues(), w)
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4, ntt_fp=1)
 
 
 def test_autotune_pick_and_cache(hm, tmp_path):
@@ -99,11 +100,11 @@ def test_autotune_pick_and_cache(hm, tmp_path):
 
     assert applied() == best
     # the cached pick is applied without timing again
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4, ntt_fp=1)
     again, times2 = tune.autotune(ctx, None, "hmult-ragged", cache=cache)
     assert again == best and times2 == {} and applied() == best
     assert json.load(open(cache))
     outs = ctx.hmult_relin_rescale(A, B)
     for o, w in zip(outs, want):
         assert np.array_equal(o.residues(), w)
-    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4)
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4, ntt_fp=1)

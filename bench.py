@@ -49,7 +49,11 @@ def limb_bytes(n):
 #         FMA low part and rounded quotient (6 FP64 operations, one slot
 #         each at gfx950's full FP64 FMA rate), sum and difference (2), and
 #         the re-centring of X on every third stage (3 / 3)
-OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23, "BF_FP": 9}
+#   MAC_FP one term of an FP64 basis conversion: source residue to double
+#         (2), modular product (6), accumulate (1)
+#   RED_FP re-centring of an FP64 sum (3)
+#   MULV_FP FP64 product of two residues (2 + 2 conversions, 6)
+OPS = {"BF": 34, "MAC": 11, "RED": 24, "MULM": 23, "BF_FP": 9, "MAC_FP": 9, "RED_FP": 3, "MULV_FP": 10}
 FP_PRIME_BOUND = 1 << 50
 
 
@@ -92,9 +96,11 @@ def kernel_model(name, items, ctx, level):
     fp_on = ctx.tuning().get("ntt_fp", 0) == 1
     primes = list(ctx.q[:L]) + list(ctx.p)  # extended basis Q_l u P
 
+    def is_fp(prime):
+        return fp_on and prime < FP_PRIME_BOUND
+
     def ntt_of(prime):
-        bf = OPS["BF_FP"] if fp_on and prime < FP_PRIME_BOUND else OPS["BF"]
-        return (N // 2) * logN * bf
+        return (N // 2) * logN * (OPS["BF_FP"] if is_fp(prime) else OPS["BF"])
 
     ntt_data = sum(ntt_of(q) for q in ctx.q[:L]) / L  # mean over the data limbs
     ntt = ntt_data
@@ -108,7 +114,13 @@ def kernel_model(name, items, ctx, level):
         ops = 0
         for j, s in enumerate(digit):
             own = set(range(j * A, j * A + s))
-            ops += sum(N * (s * OPS["MAC"] + OPS["RED"]) + ntt_of(t) for i, t in enumerate(primes) if i not in own)
+            for i, t in enumerate(primes):
+                if i in own:
+                    continue
+                # the FP64 engine converts too when the target and the digit's primes are below 2^50
+                fp_conv = is_fp(t) and all(is_fp(ctx.q[m]) for m in own)
+                conv = s * OPS["MAC_FP"] + OPS["RED_FP"] if fp_conv else s * OPS["MAC"] + OPS["RED"]
+                ops += N * conv + ntt_of(t)
         return cts * (L + per_ct_items) * lb, cts * ops
     if fam == "keyswitch_inner_product":
         cts = items / E
@@ -122,7 +134,9 @@ def kernel_model(name, items, ctx, level):
         return (cts * per_ct + 2 * beta * E) * lb, ops
     if fam == "ntt_inv_mul":
         # product of two limbs, inverse transform, scaling by the CRT constant
-        return items * 3 * lb, items * (N * (OPS["MAC"] + OPS["RED"] + OPS["MULM"]) + ntt)
+        per = sum(N * ((OPS["MULV_FP"] if is_fp(q) else OPS["MAC"] + OPS["RED"]) + OPS["MULM"]) + ntt_of(q)
+                  for q in ctx.q[:L]) / L
+        return items * 3 * lb, items * per
     if fam in ("ntt_fwd_moddown_z", "ntt_fwd_relin_rescale"):
         # per ciphertext (2 l items): both polys' n_p converted limbs and top
         # limb read once, one limb out per item; the fused variant also reads
@@ -353,6 +367,29 @@ def nets_leg(args, dev, log, tuning=None):
                      "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
                      "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])}}
     log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
+    # the same inference recorded once and replayed as a HIP graph: new
+    # images are written into the recorded input ciphertexts, no host work
+    # per inference; the replayed outputs are checked against an eager run
+    with ctx.record(1 << 30) as rec:
+        routs = g.run(cts)
+    cap = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(cap):
+        rec.plan.launch()
+    cap.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        cap.replay()
+    torch.cuda.synchronize()
+    dt_g = (time.perf_counter() - t0) / args.net_runs
+    eager = g.run(cts)
+    same = all(np.array_equal(a.residues(), b.residues()) for a, b in zip(routs, eager))
+    out["vision"].update({"graph_replay": {"ms_per_inference": 1e3 * dt_g, "encrypted_infer_per_s": 1.0 / dt_g,
+                                           "images_per_s": n_img / dt_g, "launches": rec.plan.n_launches,
+                                           "same_as_eager": bool(same)}})
+    log("vision, recorded graph replay: %.1f ms per inference, %.0f images/s (%d launches), same as eager: %s" %
+        (1e3 * dt_g, n_img / dt_g, rec.plan.n_launches, same))
+    del cap, rec, routs, eager
     # conv + bias + x^2 in the two layouts: slot-batched (one ciphertext per
     # pixel) and the paper's image-in-slots masked kernels (8 images per
     # ciphertext, taps summed by hoisted rotations)

@@ -424,6 +424,11 @@ struct Ntt {
         double d[E];
 #pragma unroll
         for (int k = 0; k < E; k++) d[k] = fp_from_u64(r[k]);
+        forward_fpd(d, r, lds, tid, tw, pc);
+    }
+    // the same from integer-valued doubles with |d| < 2q; residues to r
+    static __device__ __forceinline__ void forward_fpd(double (&d)[E], u64 (&r)[E], u32 *lds, u32 tid,
+                                                       const double2 *__restrict__ tw, const PrimeConst &pc) {
         fwd_phase_f<0>(d, lds, tid, tw, pc.qf, pc.qinvf);
         exchange_f<NPH - 1, 0>(d, lds, tid);
 #pragma unroll
@@ -477,6 +482,11 @@ struct Ntt {
         double d[E];
 #pragma unroll
         for (int k = 0; k < E; k++) d[k] = fp_from_u64(r[k]);
+        inverse_fpd(d, r, lds, tid, itw, pc);
+    }
+    // the same from integer-valued doubles with |d| <= q; residues to r
+    static __device__ __forceinline__ void inverse_fpd(double (&d)[E], u64 (&r)[E], u32 *lds, u32 tid,
+                                                       const double2 *__restrict__ itw, const PrimeConst &pc) {
         exchange_f<0, NPH - 1>(d, lds, tid);
         inv_phase_f<NPH - 1>(d, lds, tid, itw, pc);
 #pragma unroll
@@ -547,9 +557,50 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
     u64 r[E];
 
     // ---- prologue: residues of the polynomial to transform (coefficients)
+    // FP64 ModUp: the conversion sum stays in doubles and feeds the transform
+    constexpr bool kFpModup = FP && is_modup(OP);
+    double d[kFpModup ? E : 1];
     if constexpr (OP == F_COPY) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
+    } else if constexpr (kFpModup) {
+        // sum_i src_i (hat_i mod t) with the target t and every source prime
+        // below 2^50: each term is an FP64 modular product of magnitude
+        // <= 0.75 t (its quotient from hat_i * (1/t), relative error
+        // <= 2^-52); partial sums are re-centred every four terms and at the
+        // end, so the transform starts from |d| <= t/2 + 1
+#pragma clang fp contract(off)
+        constexpr int S = modup_s(OP);
+        const u32 s = S ? (u32)S : it.b;
+        const u64 *blk = tb.modup + (size_t)(it.c * tb.alpha + s - 1) * modup_block_words(tb.alpha, tb.n_prim);
+        const u64 *hat = blk + 2 * tb.alpha + it.prime;
+        const Buf src(it.in[0]);
+        const double t = pc.qf, tinv = pc.qinvf;
+#pragma unroll
+        for (int c = 0; c < E; c++) d[c] = 0.0;
+        auto term = [&](u32 i) {
+            const double h = fp_from_u64(hat[i * tb.n_prim]);
+            const double hq = h * tinv;
+#pragma unroll
+            for (int c0 = 0; c0 < E; c0 += kConvChunk) {
+                double x[kConvChunk];
+#pragma unroll
+                for (int c = 0; c < kConvChunk; c++) x[c] = fp_from_u64(src.ld(vo, (i * N + (c0 + c) * T) * 8));
+#pragma unroll
+                for (int c = 0; c < kConvChunk; c++) {
+                    d[c0 + c] = d[c0 + c] + fp_mulmod(x[c], h, hq, t);
+                    if ((i & 3) == 3) d[c0 + c] = fp_center(d[c0 + c], t, tinv);
+                }
+            }
+        };
+        if constexpr (S > 0) {
+#pragma unroll
+            for (int i = 0; i < S; i++) term((u32)i);
+        } else {
+            for (u32 i = 0; i < s; i++) term(i);
+        }
+#pragma unroll
+        for (int c = 0; c < E; c++) d[c] = fp_center(d[c], t, tinv);
     } else if constexpr (is_modup(OP)) {
         // sources arrive as [x_i hat_i^-1]_{q_i}: sum_i src_i (hat_i mod t), one Barrett at the end
         constexpr int S = modup_s(OP);  // 0: digit size from the item
@@ -637,7 +688,9 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
         for (int c = 0; c < E; c++) r[c] = reduce_signed((i64)Buf((const u64 *)src).ld(vo, c * T * 8), pc);
     }
 
-    if constexpr (FP)
+    if constexpr (kFpModup)
+        NT::forward_fpd(d, r, lds, tid, tb.twf + (size_t)it.prime * N, pc);
+    else if constexpr (FP)
         NT::forward_fp(r, lds, tid, tb.twf + (size_t)it.prime * N, pc);
     else
         NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, q);
@@ -716,9 +769,25 @@ __device__ __forceinline__ void inv_item(const DevTables &tb, const Item &it, u3
     const u64 q = pc.q;
     u64 r[E];
 
+    // FP64 product: x y - k q with k the integer nearest to fl(x y) (1/q),
+    // |k - x y / q| <= 0.75 for x, y < q < 2^50, so |d| <= 0.75 q, exactly
+    constexpr bool kFpMul = FP && OP == I_MUL;
+    double d[kFpMul ? E : 1];
     if constexpr (OP == I_COPY || OP == I_SCALE) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
+    } else if constexpr (kFpMul) {
+#pragma clang fp contract(off)
+        const double qf = pc.qf, qinv = pc.qinvf;
+#pragma unroll
+        for (int c = 0; c < E; c++) {
+            const double x = fp_from_u64(Buf(it.in[0]).ld(vo, c * T * 8));
+            const double y = fp_from_u64(Buf(it.in[1]).ld(vo, c * T * 8));
+            const double h = x * y;
+            const double l = __builtin_fma(x, y, -h);
+            const double k = __builtin_fma(h, qinv, kRound) - kRound;
+            d[c] = __builtin_fma(-k, qf, h) + l;
+        }
     } else if constexpr (OP == I_MUL) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = mulm(Buf(it.in[0]).ld(vo, c * T * 8), Buf(it.in[1]).ld(vo, c * T * 8), pc);
@@ -734,7 +803,9 @@ __device__ __forceinline__ void inv_item(const DevTables &tb, const Item &it, u3
         }
     }
 
-    if constexpr (FP)
+    if constexpr (kFpMul)
+        NT::inverse_fpd(d, r, lds, tid, tb.itwf + (size_t)it.prime * N, pc);
+    else if constexpr (FP)
         NT::inverse_fp(r, lds, tid, tb.itwf + (size_t)it.prime * N, pc);
     else
         NT::inverse(r, lds, tid, tb.itw + (size_t)it.prime * N, pc);

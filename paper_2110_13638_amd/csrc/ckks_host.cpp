@@ -851,23 +851,40 @@ struct Plan {
             // is below 2^50 go to one launch and the rest to another (each
             // kernel carries one engine); relative order is kept
             if ((kind == 0 || kind == 1) && c->tb.ntt_fp) {
-                std::vector<Item> fp, in;
-                for (const Item &it : v) (c->primes[it.prime] < kFpPrimeBound ? fp : in).push_back(it);
-                put(kind, op, fp, seed, 1);
-                put(kind, op, in, seed, 0);
+                // a ModUp item converts in FP64 too: its digit's primes must also be below 2^50
+                const bool modup = kind == 0 && (op == F_MODUP || (op >= F_MODUP_S1 && op < F_MODUP_S1 + 4));
+                auto fp_ok = [&](const Item &it) {
+                    if (c->primes[it.prime] >= kFpPrimeBound) return false;
+                    if (modup) {
+                        const u32 sz = op == F_MODUP ? it.b : (u32)(op - F_MODUP_S1 + 1);
+                        for (u32 i = 0; i < sz; i++)
+                            if (c->primes[it.c * c->alpha + i] >= kFpPrimeBound) return false;
+                    }
+                    return true;
+                };
+                // written straight into the descriptor buffer: FP64 items, then the rest
+                std::vector<uint8_t> cls(v.size());
+                size_t n_fp = 0;
+                for (size_t i = 0; i < v.size(); i++) n_fp += (cls[i] = fp_ok(v[i]) ? 1 : 0);
+                for (int want = 1; want >= 0; want--) {
+                    const size_t n = want ? n_fp : v.size() - n_fp;
+                    if (!n) continue;
+                    Item *dst = (Item *)reserve(n * sizeof(Item), kind, op, (int)n, seed, want);
+                    for (size_t i = 0; i < v.size(); i++)
+                        if (cls[i] == want) *dst++ = v[i];
+                }
                 return;
             }
         }
         if constexpr (std::is_same<T, EwItem>::value) op = (int)v[0].op;  // for the launch name
-        put(kind, op, v, seed, 0);
+        memcpy(reserve(v.size() * sizeof(T), kind, op, (int)v.size(), seed, 0), v.data(), v.size() * sizeof(T));
     }
-    template <class T>
-    void put(int kind, int op, const std::vector<T> &v, u64 seed, int fp) {
-        if (v.empty()) return;
-        size_t off = (desc.size() + 255) & ~(size_t)255;
-        desc.resize(off + v.size() * sizeof(T));
-        memcpy(desc.data() + off, v.data(), v.size() * sizeof(T));
-        launches.push_back({kind, op, off, (int)v.size(), seed, fp});
+    // space for one launch's descriptors (256-byte aligned) and its record
+    void *reserve(size_t bytes, int kind, int op, int n, u64 seed, int fp) {
+        const size_t off = (desc.size() + 255) & ~(size_t)255;
+        desc.resize(off + bytes);
+        launches.push_back({kind, op, off, n, seed, fp});
+        return desc.data() + off;
     }
     size_t total() const { return ((scratch + 255) & ~(size_t)255) + desc.size(); }
     int run(size_t ws_bytes, hipStream_t s) {

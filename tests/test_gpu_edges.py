@@ -88,3 +88,49 @@ def test_bench_configuration_sampled(ck):
         a, b = A[i].residues(), Bc[i].residues()
         want = orc.mul_relin_rescale(a, b, rk)
         assert np.array_equal(outs[i].residues(), want), i
+
+
+@pytest.mark.parametrize("log_n", [13, 15])
+def test_fp64_engine_prime_boundary(ck, log_n):
+    """Primes on both sides of the FP64 engine's 2^50 bound in one chain: the
+    largest primes below 2^50 (the engine's tightest magnitude bounds), 51-
+    and 60-bit primes (integer engine), digits that mix both classes (ModUp
+    converts with the integer engine) and a special prime below 2^50.
+    Transforms and the fused HMult are bit-exact against the oracle with the
+    FP64 engine on and off."""
+    from paper_2110_13638_amd import _native as nat
+    bits_q = [51, 50, 50, 49, 50, 51, 50, 50]
+    bits_p = [50, 60]
+    primes = O.find_primes(log_n, bits_q + bits_p)
+    assert any(p < (1 << 50) for p in primes) and any(p > (1 << 50) for p in primes)
+    nq = len(bits_q)
+    ctx = ck.Context(log_n, primes[:nq], primes[nq:], 4).keygen(5)
+    orc = O.Oracle(log_n, primes[:nq], primes[nq:], 4)
+    _, sn = orc.keygen_secret(5)
+    rk = orc.keygen_relin(sn, 5 + 2)
+    x = S.residues(70 + log_n, primes, 1 << log_n)[0]
+    want = [orc.ntt(x[i], i) for i in range(len(primes))]
+    levels = [nq - 1, 5, 3, 1]
+    ins, outs_want = [], []
+    for i, lv in enumerate(levels):
+        res = S.residues(80 + i, ctx.q[: lv + 1], ctx.N, 4)
+        ins.append((ctx.ct_from_residues(res[:2]), ctx.ct_from_residues(res[2:])))
+        outs_want.append(orc.mul_relin_rescale(res[:2], res[2:], rk))
+    for fp in (1, 0):
+        print("engine boundary log_n=%d fp=%d" % (log_n, fp), flush=True)
+        ctx.set_tuning(ntt_fp=fp)
+        dev = torch.from_numpy(x.view(np.int64)).cuda()
+        ptrs = [dev[i].data_ptr() for i in range(len(primes))]
+        ws, wb = ctx.ws_for(nat.CKKS_OP_NTT, len(primes))
+        nat.ckks_ntt(ctx.h, ptrs, list(range(len(primes))), ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy().view(np.uint64)
+        for i in range(len(primes)):
+            assert np.array_equal(got[i], want[i]), (fp, i, primes[i])
+        nat.ckks_intt(ctx.h, ptrs, list(range(len(primes))), ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy().view(np.uint64), x)
+        outs = ctx.hmult_relin_rescale([a for a, _ in ins], [b for _, b in ins])
+        for o, w in zip(outs, outs_want):
+            assert np.array_equal(o.residues(), w), fp
+    ctx.set_tuning(ntt_fp=1)

@@ -557,9 +557,11 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
     u64 r[E];
 
     // ---- prologue: residues of the polynomial to transform (coefficients)
-    // FP64 ModUp: the conversion sum stays in doubles and feeds the transform
+    // FP64 ModUp / ModDown + rescale: the conversion sum stays in doubles
+    // and feeds the transform
     constexpr bool kFpModup = FP && is_modup(OP);
-    double d[kFpModup ? E : 1];
+    constexpr bool kFpRelin = FP && is_relin(OP);
+    double d[kFpModup || kFpRelin ? E : 1];
     if constexpr (OP == F_COPY) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
@@ -644,6 +646,52 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
             for (int c = 0; c < kCC; c++) r[c0 + c] = acc[c].reduce(pc);
         });
+    } else if constexpr (kFpRelin) {
+        // z = conv_i(y) P^-1 + [t]_centred with q_i and q_l below 2^50. A
+        // special-prime residue y_m (up to 61 bits) enters as
+        // hi 2^26 + lo: hi (2^26 hat_m mod q_i) + lo hat_m, two FP64 modular
+        // products of magnitude <= q_i (0.5 + 2^-16); the sum is re-centred
+        // every two special primes and before the P^-1 product
+#pragma clang fp contract(off)
+        const PrimeConst pl = tb.pc[it.a];  // q_l
+        const u64 hl = pl.q >> 1;
+        const double hlf = fp_from_u64(hl);
+        const u64 *hat = tb.moddown + 2 * tb.n_p + it.prime;  // hat[m * n_q]: P/p_m mod q_i
+        const Buf ys(it.in[0]), ts(it.in[1]);
+        constexpr int NP = relin_np(OP);
+        const double qf = pc.qf, qinv = pc.qinvf;
+        const double pv = fp_from_u64(pc.pinv), pvq = pv * qinv;
+#pragma unroll
+        for (int c = 0; c < E; c++) d[c] = 0.0;
+        auto term = [&](u32 m) {
+            const u64 h = hat[(size_t)m * tb.n_q];
+            const double hd = fp_from_u64(h), hq = hd * qinv;
+            const double hd26 = fp_from_u64(mulm(h, 1ull << 26, pc)), hq26 = hd26 * qinv;
+#pragma unroll
+            for (int c0 = 0; c0 < E; c0 += kConvChunk) {
+                u64 y[kConvChunk];
+#pragma unroll
+                for (int c = 0; c < kConvChunk; c++) y[c] = ys.ld(vo, (m * N + (c0 + c) * T) * 8);
+#pragma unroll
+                for (int c = 0; c < kConvChunk; c++) {
+                    const double hi = fp_from_u64(y[c] >> 26), lo = fp_from_u64(y[c] & ((1ull << 26) - 1));
+                    d[c0 + c] = d[c0 + c] + (fp_mulmod(hi, hd26, hq26, qf) + fp_mulmod(lo, hd, hq, qf));
+                    if (m & 1) d[c0 + c] = fp_center(d[c0 + c], qf, qinv);
+                }
+            }
+        };
+        if constexpr (NP > 0) {
+#pragma unroll
+            for (int m = 0; m < NP; m++) term((u32)m);
+        } else {
+            for (u32 m = 0; m < tb.n_p; m++) term(m);
+        }
+#pragma unroll
+        for (int c = 0; c < E; c++) {
+            const double z = fp_mulmod(fp_center(d[c], qf, qinv), pv, pvq, qf);  // |z| < q_i
+            const double tc = fp_from_u64(addm(ts.ld(vo, c * T * 8), hl, pl.q)) - hlf;  // |tc| <= q_l / 2
+            d[c] = fp_center(z + tc, qf, qinv);
+        }
     } else if constexpr (is_relin(OP)) {
         const PrimeConst pl = tb.pc[it.a];  // q_l
         const u64 hl = pl.q >> 1;
@@ -688,7 +736,7 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
         for (int c = 0; c < E; c++) r[c] = reduce_signed((i64)Buf((const u64 *)src).ld(vo, c * T * 8), pc);
     }
 
-    if constexpr (kFpModup)
+    if constexpr (kFpModup || kFpRelin)
         NT::forward_fpd(d, r, lds, tid, tb.twf + (size_t)it.prime * N, pc);
     else if constexpr (FP)
         NT::forward_fp(r, lds, tid, tb.twf + (size_t)it.prime * N, pc);
@@ -710,6 +758,28 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
             for (int c = 0; c < kEpiChunk; c++)
                 dst.st(vo, (c0 + c) * T * 8, shoup(subm(x[c], r[c0 + c], q), qi.x, qi.y, q));
+        }
+    } else if constexpr (is_relin_rs(OP) && FP) {
+        // y = (acc' P^-1 - z) q_l^-1 in FP64: |acc' P^-1| < q, |. - z| < 2q,
+        // |(.) q_l^-1| < q (multipliers' ratios to q from 1/q, error <= 2^-52)
+#pragma clang fp contract(off)
+        const ulonglong2 qi = tb.rescale[(size_t)it.a * tb.n_q + it.prime];
+        const double qf = pc.qf, qinv = pc.qinvf;
+        const double pv = fp_from_u64(pc.pinv), pvq = pv * qinv;
+        const double lv = fp_from_u64(qi.x), lvq = lv * qinv;
+        const Buf accb(it.in[2]), dst(it.out);
+        constexpr int kRC = 4;
+#pragma unroll
+        for (int c0 = 0; c0 < E; c0 += kRC) {
+            u64 x[kRC];
+#pragma unroll
+            for (int c = 0; c < kRC; c++) x[c] = accb.ld(vo, (c0 + c) * T * 8);
+#pragma unroll
+            for (int c = 0; c < kRC; c++) {
+                const double u = fp_mulmod(fp_from_u64(x[c]), pv, pvq, qf);
+                const double w = fp_mulmod(u - fp_from_u64(r[c0 + c]), lv, lvq, qf);
+                dst.st(vo, (c0 + c) * T * 8, fp_to_residue(w, pc.qmf, q));
+            }
         }
     } else if constexpr (is_relin_rs(OP)) {
         // y = (acc' P^-1 - z) q_l^-1 with acc' (in[2]) the accumulator limb

@@ -851,10 +851,13 @@ struct Plan {
             // is below 2^50 go to one launch and the rest to another (each
             // kernel carries one engine); relative order is kept
             if ((kind == 0 || kind == 1) && c->tb.ntt_fp) {
-                // a ModUp item converts in FP64 too: its digit's primes must also be below 2^50
+                // a ModUp item converts in FP64 too: its digit's primes must also be below 2^50;
+                // a ModDown + rescale item needs the dropped prime q_l below 2^50
                 const bool modup = kind == 0 && (op == F_MODUP || (op >= F_MODUP_S1 && op < F_MODUP_S1 + 4));
+                const bool relin = kind == 0 && (op == F_RELIN || op == F_RELIN_RS || (op >= F_RELIN_P1 && op <= F_RELIN_RS_P1 + 1));
                 auto fp_ok = [&](const Item &it) {
                     if (c->primes[it.prime] >= kFpPrimeBound) return false;
+                    if (relin && c->primes[it.a] >= kFpPrimeBound) return false;
                     if (modup) {
                         const u32 sz = op == F_MODUP ? it.b : (u32)(op - F_MODUP_S1 + 1);
                         for (u32 i = 0; i < sz; i++)

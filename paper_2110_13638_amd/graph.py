@@ -96,11 +96,14 @@ class Graph:
 
     # --- planning / execution ----------------------------------------------------------
     def plan(self):
+        # workspace sizes depend on the context's launch shapes (e.g. the
+        # fused HMult tail needs fewer scratch limbs): remember them
+        self._planned_tuning = self.ctx.tuning()
         self._ws_bytes, self.n_out = nat.ckks_graph_plan(self.g)
         return self._ws_bytes, self.n_out
 
     def run(self, inputs, galois=None):
-        if not self._ws_bytes:
+        if not self._ws_bytes or getattr(self, "_planned_tuning", None) != self.ctx.tuning():
             self.plan()
         ctx = self.ctx
         if self._ws is None or self._ws.numel() < self._ws_bytes + 256:

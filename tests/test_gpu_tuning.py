@@ -108,3 +108,26 @@ def test_autotune_pick_and_cache(hm, tmp_path):
     for o, w in zip(outs, want):
         assert np.array_equal(o.residues(), w)
     ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4, ntt_fp=1)
+
+
+def test_graph_replans_when_launch_shapes_change(ck):
+    """A graph planned under one setting (fused HMult tail: fewer scratch
+    limbs) runs under another (separate tail pass: more) without a workspace
+    error, with identical results."""
+    from paper_2110_13638_amd import graph as G
+    primes = O.find_primes(11, [60, 40, 40, 40, 60])
+    ctx = ck.Context(11, primes[:4], primes[4:], 4).keygen(8)
+    ctx.set_tuning(fuse_tail=1)
+    g = G.Graph(ctx)
+    g.chain(g.input(6, 3, ctx.default_scale), g.square(), g.square(), g.output())
+    g.plan()
+    res = S.residues(90, ctx.q, ctx.N, 12)
+    cts = [ctx.ct_from_residues(res[2 * i: 2 * i + 2], ctx.default_scale) for i in range(6)]
+    want = [o.residues().copy() for o in g.run(cts)]
+    for st in (dict(fuse_tail=0), dict(fuse_tail=0, ip_cts=2), dict(fuse_tail=1, ip_cts=16), dict(ntt_fp=0)):
+        print("graph under", st, flush=True)
+        ctx.set_tuning(**st)
+        got = [o.residues() for o in g.run(cts)]
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b), st
+    ctx.set_tuning(ntt_wide=0, ew_log=2, xcd_remap=1, fuse_tail=0, ip_cts=4, ntt_fp=1)

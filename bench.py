@@ -61,7 +61,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hmult_b256_n32768_hbm_traffic.md"
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    """HBM bytes per step of kernel family ``kernel`` from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
     the kernel sources changed since the counters were taken."""
     import hashlib
@@ -76,7 +76,7 @@ def measured_traffic(kernel):
     if hashlib.sha256(src).hexdigest() not in text:
         return None
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch %s:" % kernel):
+        if line.startswith("traffic_bytes_per_step %s:" % kernel):
             return int(line.split(":")[1])
     return None
 

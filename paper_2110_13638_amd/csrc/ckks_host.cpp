@@ -957,38 +957,52 @@ struct IpCt {
     std::vector<const u64 *> own2, own3;  // a0, b0 of a product (P d folded into the sums)
 };
 // items of the inner product: ciphertexts of one level are grouped by
-// kIpCts so that each key residue is loaded once per group
+// kIpCts so that each key residue is loaded once per group. Items are
+// emitted prime by prime (every group's item for prime 0, then prime 1, ...)
+// so that the blocks in flight at any time share one prime's key limbs
+// (2 beta limbs), which then stay in L2 instead of every group re-reading
+// all primes' keys.
 void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<IpCt> &cts, const u64 *key) {
     std::vector<size_t> order(cts.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
+    struct Grp {
+        size_t g, h;
+        u32 L, E, beta;
+    };
+    std::vector<Grp> groups;
+    const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;  // 16 -> 4 for the deep-digit rest
     for (size_t g = 0; g < order.size();) {
         size_t h = g;
-        const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;  // 16 -> 4 for the deep-digit rest
         while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < group) h++;
-        const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
-        for (u32 t = 0; t < E; t++) {
+        const u32 L = cts[order[g]].level + 1;
+        groups.push_back({g, h, L, L + c->n_p, (L + c->alpha - 1) / c->alpha});
+        g = h;
+    }
+    for (u32 p = 0; p < c->n_prim; p++) {
+        for (const Grp &G : groups) {
+            if (p < c->n_q && p >= G.L) continue;  // data prime above this group's level
+            const u32 t = p < c->n_q ? p : G.L + (p - c->n_q);
             IpItem it;
             memset(&it, 0, sizeof it);
-            it.n_ct = (u32)(h - g);
-            it.prime = t < L ? t : c->n_q + (t - L);
-            it.beta = beta;
-            it.own_digit = t < L ? t / c->alpha : 0xFFFFFFFFu;
-            it.E = E;
+            it.n_ct = (u32)(G.h - G.g);
+            it.prime = p;
+            it.beta = G.beta;
+            it.own_digit = t < G.L ? t / c->alpha : 0xFFFFFFFFu;
+            it.E = G.E;
             it.pos = t;
             it.key = key;
-            for (size_t k = g; k < h; k++) {
+            for (size_t k = G.g; k < G.h; k++) {
                 const IpCt &x = cts[order[k]];
-                it.ext[k - g] = x.ext;
-                it.acc[k - g] = x.acc;
-                it.own0[k - g] = t < L ? x.own0[t] : nullptr;
-                it.own1[k - g] = (t < L && !x.own1.empty()) ? x.own1[t] : nullptr;
-                it.own2[k - g] = (t < L && !x.own2.empty()) ? x.own2[t] : nullptr;
-                it.own3[k - g] = (t < L && !x.own3.empty()) ? x.own3[t] : nullptr;
+                it.ext[k - G.g] = x.ext;
+                it.acc[k - G.g] = x.acc;
+                it.own0[k - G.g] = t < G.L ? x.own0[t] : nullptr;
+                it.own1[k - G.g] = (t < G.L && !x.own1.empty()) ? x.own1[t] : nullptr;
+                it.own2[k - G.g] = (t < G.L && !x.own2.empty()) ? x.own2[t] : nullptr;
+                it.own3[k - G.g] = (t < G.L && !x.own3.empty()) ? x.own3[t] : nullptr;
             }
             v.push_back(it);
         }
-        g = h;
     }
 }
 

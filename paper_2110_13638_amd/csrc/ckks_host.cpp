@@ -879,6 +879,22 @@ struct Plan {
                 return;
             }
         }
+        if constexpr (std::is_same<T, IpItem>::value) {
+            // key-switch inner product: items of primes below 2^50 take the FP64 kernel
+            if (kind == 3 && c->tb.ntt_fp) {
+                std::vector<uint8_t> cls(v.size());
+                size_t n_fp = 0;
+                for (size_t i = 0; i < v.size(); i++) n_fp += (cls[i] = c->primes[v[i].prime] < kFpPrimeBound ? 1 : 0);
+                for (int want = 1; want >= 0; want--) {
+                    const size_t n = want ? n_fp : v.size() - n_fp;
+                    if (!n) continue;
+                    IpItem *dst = (IpItem *)reserve(n * sizeof(IpItem), kind, op, (int)n, seed, want);
+                    for (size_t i = 0; i < v.size(); i++)
+                        if (cls[i] == want) *dst++ = v[i];
+                }
+                return;
+            }
+        }
         if constexpr (std::is_same<T, EwItem>::value) op = (int)v[0].op;  // for the launch name
         memcpy(reserve(v.size() * sizeof(T), kind, op, (int)v.size(), seed, 0), v.data(), v.size() * sizeof(T));
     }

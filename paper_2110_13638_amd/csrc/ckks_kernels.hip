@@ -120,6 +120,79 @@ __global__ void __launch_bounds__(256) k_ew(DevTables tb, const EwItem *__restri
 // multiplied by the key limbs (b_j, a_j) of that prime; sums are 128-bit and
 // reduced once. Each key residue is loaded once for all the item's
 // ciphertexts. acc + pos N receives the b-sum, acc + (E + pos) N the a-sum.
+// FP64 product of two residues below t < 2^50: x y - k t with k the integer
+// nearest to fl(x y) (1/t), so |result| <= 0.75 t, exactly
+__device__ __forceinline__ double fp_mulv(double x, double y, double t, double tinv) {
+#pragma clang fp contract(off)
+    const double h = x * y;
+    const double l = __builtin_fma(x, y, -h);
+    const double k = __builtin_fma(h, tinv, kRound) - kRound;
+    return __builtin_fma(-k, t, h) + l;
+}
+
+// The inner product in FP64 for an item whose prime t is below 2^50: each
+// digit term is an FP64 product (<= 0.75 t), sums are re-centred every four
+// digits, the P d fold multiplies by P mod t (ratio P/t from 1/t, error
+// <= 2^-52), and the final re-centred sum (|.| <= t/2 + 1) becomes a residue.
+template <int kEwPer, int NCT>
+__global__ void __launch_bounds__(256) k_ip_fp(DevTables tb, const IpItem *__restrict__ items, int nitems) {
+#pragma clang fp contract(off)
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const IpItem it = items[iid];
+    const PrimeConst pc = tb.pc[it.prime];
+    const double t = pc.qf, tinv = pc.qinvf;
+    const double pm = fp_from_u64(pc.pmod), pmq = pm * tinv;
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (x >= N) break;
+        double s0[NCT], s1[NCT];
+#pragma unroll
+        for (int c = 0; c < NCT; c++) s0[c] = s1[c] = 0.0;
+        for (u32 j = 0; j < it.beta; j++) {
+            const u64 *kb = it.key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
+            const double k0 = fp_from_u64(kb[x]), k1 = fp_from_u64(kb[kstride + x]);
+#pragma unroll
+            for (int c = 0; c < NCT; c++) {
+                if ((u32)c >= it.n_ct) break;
+                double v;
+                if (j == it.own_digit) {
+                    const double o = fp_from_u64(it.own0[c][x]);
+                    v = it.own1[c] ? fp_mulv(o, fp_from_u64(it.own1[c][x]), t, tinv) : o;
+                } else {
+                    v = fp_from_u64(it.ext[c][((size_t)j * it.E + it.pos) * N + x]);
+                }
+                s0[c] = s0[c] + fp_mulv(v, k0, t, tinv);
+                s1[c] = s1[c] + fp_mulv(v, k1, t, tinv);
+                if ((j & 3) == 3) {
+                    s0[c] = fp_center(s0[c], t, tinv);
+                    s1[c] = fp_center(s1[c], t, tinv);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; c++) {
+            if ((u32)c >= it.n_ct) break;
+            double r0 = fp_center(s0[c], t, tinv), r1 = fp_center(s1[c], t, tinv);
+            if (it.own2[c]) {
+                const double a0 = fp_from_u64(it.own2[c][x]), b0 = fp_from_u64(it.own3[c][x]);
+                const double a1 = fp_from_u64(it.own0[c][x]), b1 = fp_from_u64(it.own1[c][x]);
+                const double d0 = fp_mulv(a0, b0, t, tinv);
+                const double d1 = fp_mulv(a0, b1, t, tinv) + fp_mulv(a1, b0, t, tinv);
+                r0 = fp_center(r0 + fp_mulmod(d0, pm, pmq, t), t, tinv);
+                r1 = fp_center(r1 + fp_mulmod(d1, pm, pmq, t), t, tinv);
+            }
+            it.acc[c][(size_t)it.pos * N + x] = fp_to_residue(r0, pc.qmf, pc.q);
+            it.acc[c][((size_t)it.E + it.pos) * N + x] = fp_to_residue(r1, pc.qmf, pc.q);
+        }
+    }
+}
+
 template <int kEwPer, int NCT>
 __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restrict__ items, int nitems) {
     const u32 N = 1u << tb.log_n;
@@ -550,6 +623,14 @@ hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStre
 }
 template <int NCT>
 static void launch_ip_t(const DevTables &tb, const IpItem *items, int n, hipStream_t s) {
+    if (tb.ntt_fp) {  // every item's prime is below 2^50
+        switch (tb.ew_log) {
+            case 1: hipLaunchKernelGGL((k_ip_fp<2, NCT>), dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
+            case 3: hipLaunchKernelGGL((k_ip_fp<8, NCT>), dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;
+            default: hipLaunchKernelGGL((k_ip_fp<4, NCT>), dim3(ew_blocks(tb, n, 4)), dim3(256), 0, s, tb, items, n);
+        }
+        return;
+    }
     switch (tb.ew_log) {
         case 1: hipLaunchKernelGGL((k_ip<2, NCT>), dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n); break;
         case 3: hipLaunchKernelGGL((k_ip<8, NCT>), dim3(ew_blocks(tb, n, 8)), dim3(256), 0, s, tb, items, n); break;

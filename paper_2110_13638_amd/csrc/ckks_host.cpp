@@ -830,13 +830,28 @@ hipError_t issue(const ckks_ctx *c, hipStream_t s, LaunchFn f) {
     return e;
 }
 
+// Descriptor buffers are recycled per host thread: a large batch's tables
+// (megabytes) are then written into memory that is already mapped instead
+// of freshly faulted-in pages on every call.
+static std::vector<uint8_t> &desc_pool() {
+    thread_local std::vector<uint8_t> pool;
+    return pool;
+}
 struct Plan {
     const ckks_ctx *c;
     uint8_t *ws;          // device base (may be null when sizing)
     size_t scratch = 0;   // bytes of scratch carved so far
     std::vector<uint8_t> desc;
     std::vector<Launch> launches;
-    explicit Plan(const ckks_ctx *cc, void *w) : c(cc), ws((uint8_t *)w) {}
+    explicit Plan(const ckks_ctx *cc, void *w) : c(cc), ws((uint8_t *)w) {
+        desc.swap(desc_pool());
+        desc.clear();
+    }
+    ~Plan() {
+        if (desc.capacity() > desc_pool().capacity()) desc_pool().swap(desc);
+    }
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
     u64 *limbs(size_t count) {
         const size_t bytes = count * c->N * 8;
         u64 *p = ws ? (u64 *)(ws + scratch) : (u64 *)(uintptr_t)(0x1000 + scratch);
@@ -953,6 +968,9 @@ struct Plan {
 // size: sizes 1..4 use the kernels with the size fixed at compile time
 void add_modup(Plan &P, const std::vector<Item> &v) {
     std::vector<Item> by[5];
+    size_t cnt[5] = {0, 0, 0, 0, 0};
+    for (const Item &it : v) cnt[it.b <= 4 ? it.b : 0]++;
+    for (int i = 0; i < 5; i++) by[i].reserve(cnt[i]);
     for (const Item &it : v) by[it.b <= 4 ? it.b : 0].push_back(it);
     for (u32 sz = 1; sz <= 4; sz++) P.add(0, F_MODUP_S1 + (int)sz - 1, by[sz]);
     P.add(0, F_MODUP, by[0]);
@@ -1970,6 +1988,22 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
     std::vector<Item> mul, modup, scale, fin;
     std::vector<EwItem> tt, tail;
     std::vector<IpCt> ipc;
+    {
+        size_t n_mul = 0, n_modup = 0, n_fin = 0;
+        for (u32 x = 0; x < B; x++) {
+            const u32 L = a[x].level + 1, E = L + k, beta = (L + A - 1) / A;
+            n_mul += L;
+            n_modup += (size_t)beta * E - L;
+            n_fin += 2 * (size_t)(L - 1);
+        }
+        mul.reserve(n_mul);
+        modup.reserve(n_modup);
+        fin.reserve(n_fin);
+        scale.reserve((size_t)B * 2 * (k + 1));
+        tt.reserve((size_t)B * 2);
+        ipc.reserve(B);
+        if (!fuse) tail.reserve(n_fin / 2);
+    }
     for (u32 x = 0; x < B; x++) {
         const u32 l = a[x].level, L = l + 1, E = L + k, beta = (L + A - 1) / A;
         u64 *dcoef = P.limbs(L);

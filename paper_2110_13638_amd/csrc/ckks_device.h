@@ -566,8 +566,9 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
     } else if constexpr (kFpModup) {
-        // sum_i src_i (hat_i mod t) with the target t and every source prime
-        // below 2^50: each term is an FP64 modular product of magnitude
+        // sum_i src_i (hat_i mod t) with the target t below 2^50 (and, for
+        // the fixed-size kernels, every source prime): each term is an FP64
+        // modular product of magnitude
         // <= 0.75 t (its quotient from hat_i * (1/t), relative error
         // <= 2^-52); partial sums are re-centred every four terms and at the
         // end, so the transform starts from |d| <= t/2 + 1
@@ -581,8 +582,31 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
         for (int c = 0; c < E; c++) d[c] = 0.0;
         auto term = [&](u32 i) {
-            const double h = fp_from_u64(hat[i * tb.n_prim]);
+            const u64 hh = hat[i * tb.n_prim];
+            const double h = fp_from_u64(hh);
             const double hq = h * tinv;
+            // generic kernel below 2^15: a source prime of 2^50 or more (a
+            // 60-bit base prime) enters as hi 2^26 + lo, two products
+            // (<= 0.5 t each)
+            if constexpr (S == 0 && LOGN <= 14) {
+                if (tb.pc[it.c * tb.alpha + i].q >= kFpPrimeBound) {
+                    constexpr int kSC = kConvChunk / 2;
+                    const double h26 = fp_from_u64(mulm(hh, 1ull << 26, pc)), h26q = h26 * tinv;
+#pragma unroll
+                    for (int c0 = 0; c0 < E; c0 += kSC) {
+                        u64 y[kSC];
+#pragma unroll
+                        for (int c = 0; c < kSC; c++) y[c] = src.ld(vo, (i * N + (c0 + c) * T) * 8);
+#pragma unroll
+                        for (int c = 0; c < kSC; c++) {
+                            const double hi = fp_from_u64(y[c] >> 26), lo = fp_from_u64(y[c] & ((1ull << 26) - 1));
+                            d[c0 + c] = d[c0 + c] + (fp_mulmod(hi, h26, h26q, t) + fp_mulmod(lo, h, hq, t));
+                            if ((i & 3) == 3) d[c0 + c] = fp_center(d[c0 + c], t, tinv);
+                        }
+                    }
+                    return;
+                }
+            }
 #pragma unroll
             for (int c0 = 0; c0 < E; c0 += kConvChunk) {
                 double x[kConvChunk];

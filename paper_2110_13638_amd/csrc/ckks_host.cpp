@@ -873,7 +873,9 @@ struct Plan {
                 auto fp_ok = [&](const Item &it) {
                     if (c->primes[it.prime] >= kFpPrimeBound) return false;
                     if (relin && c->primes[it.a] >= kFpPrimeBound) return false;
-                    if (modup) {
+                    // below 2^15 (the generic ModUp kernel) sources of 2^50 or more
+                    // are converted too; at 2^15 every source must be below 2^50
+                    if (modup && c->log_n >= 15) {
                         const u32 sz = op == F_MODUP ? it.b : (u32)(op - F_MODUP_S1 + 1);
                         for (u32 i = 0; i < sz; i++)
                             if (c->primes[it.c * c->alpha + i] >= kFpPrimeBound) return false;
@@ -894,16 +896,17 @@ struct Plan {
                 return;
             }
         }
-        if constexpr (std::is_same<T, IpItem>::value) {
-            // key-switch inner product: items of primes below 2^50 take the FP64 kernel
-            if (kind == 3 && c->tb.ntt_fp) {
+        if constexpr (std::is_same<T, IpItem>::value || std::is_same<T, HoItem>::value) {
+            // key-switch inner product and hoisted rotations: items of primes
+            // below 2^50 take the FP64 kernel
+            if ((kind == 3 || kind == 5) && c->tb.ntt_fp) {
                 std::vector<uint8_t> cls(v.size());
                 size_t n_fp = 0;
                 for (size_t i = 0; i < v.size(); i++) n_fp += (cls[i] = c->primes[v[i].prime] < kFpPrimeBound ? 1 : 0);
                 for (int want = 1; want >= 0; want--) {
                     const size_t n = want ? n_fp : v.size() - n_fp;
                     if (!n) continue;
-                    IpItem *dst = (IpItem *)reserve(n * sizeof(IpItem), kind, op, (int)n, seed, want);
+                    T *dst = (T *)reserve(n * sizeof(T), kind, op, (int)n, seed, want);
                     for (size_t i = 0; i < v.size(); i++)
                         if (cls[i] == want) *dst++ = v[i];
                 }

@@ -376,6 +376,95 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
     }
 }
 
+// Hoisted rotations in FP64 for an item whose prime t is below 2^50: every
+// product is an FP64 product of two residues (<= 0.75 t), the digit sums
+// and the per-rotation sums are re-centred every four terms, P (c0, c1)
+// uses an FP64 product by P mod t (ratio from 1/t, error <= 2^-52).
+template <int kEwPer>
+__global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+#pragma clang fp contract(off)
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const HoItem it = items[iid];
+    const PrimeConst pc = tb.pc[it.prime];
+    const double t = pc.qf, tinv = pc.qinvf;
+    const double pm = fp_from_u64(pc.pmod), pmq = pm * tinv;
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+    const bool data = it.pos < it.L;
+    const u32 own = data ? it.pos / it.alpha : 0xFFFFFFFFu;
+#pragma unroll
+    for (int e = 0; e < kEwPer; e++) {
+        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
+        if (x >= N) break;
+        double tb_[kHoCts], ta_[kHoCts];
+#pragma unroll
+        for (int c = 0; c < kHoCts; c++) tb_[c] = ta_[c] = 0.0;
+        for (u32 i = 0; i < it.n_rot; i++) {
+            const u32 g = it.galois[i];
+            const double w = fp_from_u64(it.pts[((size_t)i * it.E + it.pos) * N + x]);
+            if (g == 1) {
+                // identity: P (c0, c1) on data limbs, nothing on special limbs
+                if (data) {
+#pragma unroll
+                    for (int c = 0; c < kHoCts; c++) {
+                        if ((u32)c >= it.n_ct) break;
+                        const double p0 = fp_mulmod(fp_from_u64(it.c0[c][x]), pm, pmq, t);
+                        const double p1 = fp_mulmod(fp_from_u64(it.c1[c][(size_t)it.pos * N + x]), pm, pmq, t);
+                        tb_[c] = tb_[c] + fp_mulv(p0, w, t, tinv);
+                        ta_[c] = ta_[c] + fp_mulv(p1, w, t, tinv);
+                    }
+                }
+            } else {
+                const u32 src = automorph_src(x, g, tb.log_n);
+                const u64 *key = it.keys[i] + (size_t)it.prime * N + x;
+                double sb[kHoCts], sa[kHoCts];
+#pragma unroll
+                for (int c = 0; c < kHoCts; c++) sb[c] = sa[c] = 0.0;
+                for (u32 j = 0; j < it.beta; j++) {
+                    const double k0 = fp_from_u64(key[(size_t)(2 * j) * kstride]);
+                    const double k1 = fp_from_u64(key[(size_t)(2 * j + 1) * kstride]);
+#pragma unroll
+                    for (int c = 0; c < kHoCts; c++) {
+                        if ((u32)c >= it.n_ct) break;
+                        const double v = fp_from_u64((j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                                                : it.ext[c][((size_t)j * it.E + it.pos) * N + src]);
+                        sb[c] = sb[c] + fp_mulv(v, k0, t, tinv);
+                        sa[c] = sa[c] + fp_mulv(v, k1, t, tinv);
+                        if ((j & 3) == 3) {
+                            sb[c] = fp_center(sb[c], t, tinv);
+                            sa[c] = fp_center(sa[c], t, tinv);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < kHoCts; c++) {
+                    if ((u32)c >= it.n_ct) break;
+                    double rb = fp_center(sb[c], t, tinv);
+                    if (data) rb = fp_center(rb + fp_mulmod(fp_from_u64(it.c0[c][src]), pm, pmq, t), t, tinv);
+                    tb_[c] = tb_[c] + fp_mulv(rb, w, t, tinv);
+                    ta_[c] = ta_[c] + fp_mulv(fp_center(sa[c], t, tinv), w, t, tinv);
+                }
+            }
+            if ((i & 3) == 3) {
+#pragma unroll
+                for (int c = 0; c < kHoCts; c++) {
+                    tb_[c] = fp_center(tb_[c], t, tinv);
+                    ta_[c] = fp_center(ta_[c], t, tinv);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kHoCts; c++) {
+            if ((u32)c >= it.n_ct) break;
+            it.acc[c][(size_t)it.pos * N + x] = fp_to_residue(fp_center(tb_[c], t, tinv), pc.qmf, pc.q);
+            it.acc[c][((size_t)it.E + it.pos) * N + x] = fp_to_residue(fp_center(ta_[c], t, tinv), pc.qmf, pc.q);
+        }
+    }
+}
+
 // The 128-bit sums of the linear layers are reduced every kLinFold terms:
 // each product is below q^2 < 2^122, so 32 terms plus a reduced carry stay
 // below 2^128 for any layer width.
@@ -618,7 +707,10 @@ hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, 
 }
 hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hoist<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
+    if (tb.ntt_fp)  // every item's prime is below 2^50
+        hipLaunchKernelGGL(k_hoist_fp<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
+    else
+        hipLaunchKernelGGL(k_hoist<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
     return hipGetLastError();
 }
 template <int NCT>

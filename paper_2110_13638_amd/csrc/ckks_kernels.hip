@@ -558,13 +558,15 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 // Dense linear layer on the matrix cores. One workgroup = 4 waves on one
 // tile of 16 consecutive residues (poly p, limb t, slots k0..k0+15); wave w
 // owns output rows 32 (4 blockIdx.y + w) .. +31 (two 16-row MFMA tiles).
-// Per chunk of 32 inputs a lane loads its 8 residues (one column, inputs
-// 8 (lane / 16) .. +7), splits them into kXDig 7-bit digits packed as int8
-// B fragments, and multiplies them with the weight-digit A fragments
-// (Wd [kWDig][rows_pad][k_pad], row-major, 8 bytes per lane) by
-// v_mfma_i32_16x16x32_i8, accumulating digit products of weight
-// 128^(a + b) together. Lane layout of that instruction (checked on the
-// device): A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16],
+// The four waves share the tile's inputs: per chunk of 32 inputs each
+// thread loads two residues (input 16 v + tid / 16, slot tid % 16), splits
+// them into kXDig 7-bit digits and stores them as int8 B fragments in LDS
+// (double-buffered: the next chunk's residues are loaded while the matrix
+// cores work on the current one). Each wave multiplies the B fragments with
+// its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad], row-major, 8
+// bytes per lane) by v_mfma_i32_16x16x32_i8, accumulating digit products of
+// weight 128^(a + b) together. Lane layout of that instruction (checked on
+// the device): A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16],
 // D[4 (l / 16) + r][l % 16].
 typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kMfmaS = kWDig + kXDig - 1;  // digit weights 128^0 .. 128^(s-1)
@@ -572,45 +574,72 @@ __global__ void __launch_bounds__(256)
 k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
               u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
               u32 limbs, u32 in_stride, u32 out_stride) {
+    // B fragments of two chunks: [buffer][digit][slot][input group of 8], 8 int8 each
+    __shared__ long bfrag[2][kXDig][16][4];
     const u32 N = 1u << tb.log_n;
-    const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32 tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const u32 tile = blockIdx.x;  // 16 residues of one (p, t)
     const u32 pt = (tile * 16) >> tb.log_n, k0 = (tile * 16) & (N - 1);
     const u32 p = pt / limbs, t = pt - p * limbs;
     const u32 row0 = (blockIdx.y * 4 + wave) * 32;
-    if (row0 >= rows_pad) return;
+    const bool rows = row0 < rows_pad;  // every wave still stages inputs and meets the barriers
     const u32 col = lane & 15, grp = lane >> 4;
-    const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + col;
+    const u32 scol = tid & 15, srow = tid >> 4;  // staging: slot, input within a half chunk
+    const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + scol;
+    auto load = [&](u32 kc, u64 (&x)[2]) {
+#pragma unroll
+        for (int v = 0; v < 2; v++) {
+            const u32 i = kc + 16 * v + srow;
+            x[v] = i < n_in ? in_ptrs[cols[i]][in_off] : 0;
+        }
+    };
+    auto stage = [&](int buf, const u64 (&x)[2]) {
+        int8_t *b8 = reinterpret_cast<int8_t *>(&bfrag[buf][0][0][0]);
+#pragma unroll
+        for (int v = 0; v < 2; v++) {
+            const u32 ip = 16 * v + srow;  // position in the chunk: group ip / 8, byte ip % 8
+#pragma unroll
+            for (int b = 0; b < kXDig; b++)
+                b8[((b * 16 + scol) * 4 + (ip >> 3)) * 8 + (ip & 7)] = (int8_t)((x[v] >> (7 * b)) & 127);
+        }
+    };
     v4i acc[2][kMfmaS];
 #pragma unroll
     for (int h = 0; h < 2; h++)
 #pragma unroll
         for (int s = 0; s < kMfmaS; s++) acc[h][s] = v4i{0, 0, 0, 0};
     const size_t plane = (size_t)rows_pad * k_pad;
-    for (u32 kc = 0; kc < k_pad; kc += 32) {
-        // B fragments: this lane's column, inputs kc + 8 grp + e
-        long bd[kXDig];
+    {
+        u64 x[2];
+        load(0, x);
+        stage(0, x);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (u32 kc = 0; kc < k_pad; kc += 32, buf ^= 1) {
+        const bool more = kc + 32 < k_pad;
+        u64 xn[2] = {0, 0};
+        if (more) load(kc + 32, xn);
+        if (rows) {
+            long bd[kXDig];
 #pragma unroll
-        for (int b = 0; b < kXDig; b++) bd[b] = 0;
+            for (int b = 0; b < kXDig; b++) bd[b] = bfrag[buf][b][col][grp];
 #pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const u32 i = kc + 8 * grp + e;
-            const u64 x = i < n_in ? in_ptrs[cols[i]][in_off] : 0;
+            for (int h = 0; h < 2; h++) {
+                const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 8 * grp;
 #pragma unroll
-            for (int b = 0; b < kXDig; b++) bd[b] |= (long)((x >> (7 * b)) & 127) << (8 * e);
-        }
+                for (int a = 0; a < kWDig; a++) {
+                    const long ad = *reinterpret_cast<const long *>(wd + a * plane + aoff);
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 8 * grp;
-#pragma unroll
-            for (int a = 0; a < kWDig; a++) {
-                const long ad = *reinterpret_cast<const long *>(wd + a * plane + aoff);
-#pragma unroll
-                for (int b = 0; b < kXDig; b++)
-                    acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
+                    for (int b = 0; b < kXDig; b++)
+                        acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
+                }
             }
         }
+        if (more) stage(buf ^ 1, xn);
+        __syncthreads();
     }
+    if (!rows) return;
     const PrimeConst pc = tb.pc[t];
     const size_t out_off = ((size_t)p * out_stride + t) * N + k0 + col;
 #pragma unroll

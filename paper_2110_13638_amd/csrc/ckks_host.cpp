@@ -41,7 +41,7 @@ hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pa
 hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,
                                 hipStream_t s);
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
-                                 const u64 *wt, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
+                                 const u64 *wt, const double2 *wf, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
                                  u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
 
 // kernel op codes (mirrors of the enums in the kernel file)
@@ -2369,7 +2369,7 @@ extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_
                                                   uint32_t level) {
     if (!c) return 0;
     const size_t L = level + 1;
-    const size_t grouped = al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8);
+    const size_t grouped = al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8) + al256(L * nnz * 16);
     // matrix-core path: weights as int64 and their digit planes
     const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)n_in + 31) / 32 * 32;
     const size_t mfma = al256((size_t)n_in * 4) + al256(nnz * 8) + al256((size_t)kWDig * rows_pad * k_pad);
@@ -2398,6 +2398,14 @@ int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const
     // the digit planes live in the workspace (or right after the recorded image)
     int8_t *wd = (int8_t *)((uint8_t *)ws + o_wd);
     const u32 rp = (u32)rows_pad, kp = (u32)k_pad;
+    ProfRec rec;
+    if (g_prof_on) {
+        rec.name = launch_name(4, 0, c->log_n);
+        rec.items = n_out;
+        HIP_TRY(hipEventCreate(&rec.e0));
+        HIP_TRY(hipEventCreate(&rec.e1));
+        HIP_TRY(hipEventRecord(rec.e0, s));
+    }
     HIP_TRY(issue(c, s, [w8, o_w, n_out, ncols, rp, kp, wd](hipStream_t st) {
         return launch_weight_digits((const i64 *)(w8 + o_w), n_out, ncols, rp, kp, wd, st);
     }));
@@ -2407,6 +2415,10 @@ int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const
                                   (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L,
                                   stride, ostride, st);
     }));
+    if (g_prof_on) {
+        HIP_TRY(hipEventRecord(rec.e1, s));
+        g_prof.push_back(rec);
+    }
     return CKKS_OK;
 }
 }  // namespace
@@ -2479,14 +2491,27 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
             wt[(size_t)t * W + e] = m;
         }
     }
+    // FP64 copies (w, w / q) for the limbs whose prime is below 2^50
+    std::vector<double> wf((size_t)L * W * 2, 0.0);
+    for (u32 t = 0; t < L; t++) {
+        const u64 q = c->primes[t];
+        if (q >= kFpPrimeBound) continue;
+        for (size_t e = 0; e < W; e++) {
+            const double v = (double)wt[(size_t)t * W + e];
+            wf[2 * ((size_t)t * W + e)] = v;
+            wf[2 * ((size_t)t * W + e) + 1] = v / (double)q;
+        }
+    }
     const size_t o_groups = 0, o_cols = al256(groups.size() * sizeof(LinGroup)), o_wt = o_cols + al256(cols.size() * 4),
-                 o_ptr = o_wt + al256(wt.size() * 8), need = o_ptr + al256((size_t)(n_in + n_out) * 8);
+                 o_wf = o_wt + al256(wt.size() * 8), o_ptr = o_wf + al256(wf.size() * 8),
+                 need = o_ptr + al256((size_t)(n_in + n_out) * 8);
     if (need > ws_bytes) return fail(CKKS_ENOMEM, "linear_csr: workspace too small: need %zu", need);
     if (!ws || (((uintptr_t)ws) & 255)) return fail(CKKS_EINVAL, "linear_csr: null or unaligned workspace");
     std::vector<uint8_t> img(need, 0);
     memcpy(img.data() + o_groups, groups.data(), groups.size() * sizeof(LinGroup));
     memcpy(img.data() + o_cols, cols.data(), cols.size() * 4);
     memcpy(img.data() + o_wt, wt.data(), wt.size() * 8);
+    memcpy(img.data() + o_wf, wf.data(), wf.size() * 8);
     std::vector<const u64 *> ptrs(n_in + n_out);
     for (u32 i = 0; i < n_in; i++) ptrs[i] = in[i].data;
     for (u32 j = 0; j < n_out; j++) ptrs[n_in + j] = out[j].data;
@@ -2503,10 +2528,11 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
         HIP_TRY(hipEventRecord(rec.e0, s));
     }
     const u32 n_groups = (u32)groups.size();
-    HIP_TRY(issue(c, s, [tb = c->tb, w8, n_groups, o_groups, o_cols, o_wt, o_ptr, W, n_in, L, stride,
+    HIP_TRY(issue(c, s, [tb = c->tb, w8, n_groups, o_groups, o_cols, o_wt, o_wf, o_ptr, W, n_in, L, stride,
                          ostride](hipStream_t st) {
         return launch_linear_grouped(tb, (const LinGroup *)(w8 + o_groups), n_groups, (const u32 *)(w8 + o_cols),
-                                     (const u64 *)(w8 + o_wt), (u32)W, (const u64 *const *)(w8 + o_ptr),
+                                     (const u64 *)(w8 + o_wt), (const double2 *)(w8 + o_wf), (u32)W,
+                                     (const u64 *const *)(w8 + o_ptr),
                                      (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L, stride, ostride, st);
     }));
     if (g_prof_on) {

@@ -520,8 +520,9 @@ k_linear(DevTables tb, const u64 *const *__restrict__ in_ptrs, const u64 *__rest
 // descriptor are wave-uniform and read through the scalar cache.
 __global__ void __launch_bounds__(256)
 k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups, const u32 *__restrict__ cols,
-                 const u64 *__restrict__ wt, u32 wt_stride, const u64 *const *__restrict__ in_ptrs,
-                 u64 *const *__restrict__ out_ptrs, u32 limbs, u32 in_stride, u32 out_stride) {
+                 const u64 *__restrict__ wt, const double2 *__restrict__ wf, u32 wt_stride,
+                 const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs, u32 limbs, u32 in_stride,
+                 u32 out_stride) {
     const u32 N = 1u << tb.log_n;
     const size_t per_group = (size_t)2 * limbs * N;
     const size_t total = per_group * n_groups;
@@ -535,8 +536,36 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
         const u32 p = pt / limbs, t = pt - p * limbs;
         const LinGroup G = groups[gi];
         const PrimeConst pc = tb.pc[t];
-        const u64 *w = wt + (size_t)t * wt_stride + G.w_off;
         const size_t in_off = ((size_t)p * in_stride + t) * N + k;
+        const size_t out_off = ((size_t)p * out_stride + t) * N + k;
+        if (tb.ntt_fp && pc.q < kFpPrimeBound) {
+            // FP64: products by (w, w/q) from the table, |term| < q, sums
+            // re-centred every four columns (wave-uniform branch on the limb)
+#pragma clang fp contract(off)
+            const double2 *wv = wf + (size_t)t * wt_stride + G.w_off;
+            const double q = pc.qf, qinv = pc.qinvf;
+            double acc[kLinRows];
+#pragma unroll
+            for (int r = 0; r < kLinRows; r++) acc[r] = 0.0;
+            for (u32 c = 0; c < G.ncols; c++) {
+                const double x = fp_from_u64(in_ptrs[cols[G.col_off + c]][in_off]);
+#pragma unroll
+                for (int r = 0; r < kLinRows; r++)
+                    if ((u32)r < G.nrows) {
+                        const double2 w2 = wv[(size_t)r * G.ncols + c];
+                        acc[r] = acc[r] + fp_mulmod(x, w2.x, w2.y, q);
+                    }
+                if ((c & 3) == 3) {
+#pragma unroll
+                    for (int r = 0; r < kLinRows; r++) acc[r] = fp_center(acc[r], q, qinv);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kLinRows; r++)
+                if ((u32)r < G.nrows) out_ptrs[G.row0 + r][out_off] = fp_to_residue(fp_center(acc[r], q, qinv), pc.qmf, pc.q);
+            continue;
+        }
+        const u64 *w = wt + (size_t)t * wt_stride + G.w_off;
         Acc128 acc[kLinRows];
         for (u32 c = 0; c < G.ncols; c++) {
             const u64 x = in_ptrs[cols[G.col_off + c]][in_off];
@@ -548,7 +577,6 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
                 for (int r = 0; r < kLinRows; r++) acc[r] = Acc128{acc[r].reduce(pc), 0};
             }
         }
-        const size_t out_off = ((size_t)p * out_stride + t) * N + k;
 #pragma unroll
         for (int r = 0; r < kLinRows; r++)
             if ((u32)r < G.nrows) out_ptrs[G.row0 + r][out_off] = acc[r].reduce(pc);
@@ -785,10 +813,10 @@ hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u
     return hipGetLastError();
 }
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
-                                 const u64 *wt, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
-                                 u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s) {
+                                 const u64 *wt, const double2 *wf, u32 wt_stride, const u64 *const *in_ptrs,
+                                 u64 *const *out_ptrs, u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s) {
     const size_t work = ((size_t)2 * limbs << tb.log_n) * n_groups;
-    hipLaunchKernelGGL(k_linear_grouped, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt,
+    hipLaunchKernelGGL(k_linear_grouped, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt, wf,
                        wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
     return hipGetLastError();
 }

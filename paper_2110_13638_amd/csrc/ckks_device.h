@@ -4,16 +4,18 @@
 // ckks_ntt_*.hip translation units, which compile in parallel).
 //
 // Every kernel works on u64 residues in [0, q) (limb-major: one limb = N
-// contiguous residues modulo one prime). Modular arithmetic runs on the
-// VALU (no MFMA: the work is modular integer arithmetic, not a float
-// contraction):
-//   - fixed operands (twiddles, conversion constants) use Shoup's
-//     multiplication with a precomputed companion floor(w 2^64 / q), lazy
-//     in [0, 2q);
-//   - variable x variable products use a 128-bit product and an exact
-//     128-bit Barrett reduction with floor(2^128 / q);
-//   - NTT butterflies keep Harvey's lazy ranges ([0, 4q) forward, [0, 2q)
-//     inverse), so primes must stay below 2^61.
+// contiguous residues modulo one prime) at its boundaries. Modular
+// arithmetic runs on the VALU in one of two engines, chosen per launch by
+// the primes of its items (the host splits launches by prime class):
+//   - FP64 (primes below 2^50): residues are integer-valued doubles inside
+//     the kernel; products are split exactly by an FMA and reduced with a
+//     rounded quotient (fp_mulmod below), at the full FP64 FMA rate;
+//   - 64-bit integer (every prime): fixed operands (twiddles, conversion
+//     constants) use Shoup's multiplication with a precomputed companion
+//     floor(w 2^64 / q), lazy in [0, 2q); variable x variable products use
+//     a 128-bit product and an exact 128-bit Barrett reduction with
+//     floor(2^128 / q); NTT butterflies keep Harvey's lazy ranges ([0, 4q)
+//     forward, [0, 2q) inverse), so primes must stay below 2^61.
 //
 // NTT-shaped kernels: one workgroup per limb. N = 2^LOGN residues live in
 // registers, E = 2^LOGE per thread (T = N / E threads). The log N butterfly

@@ -2371,7 +2371,7 @@ extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_
     const size_t L = level + 1;
     const size_t grouped = al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8) + al256(L * nnz * 16);
     // matrix-core path: weights as int64 and their digit planes
-    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)n_in + 31) / 32 * 32;
+    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)n_in + 63) / 64 * 64;
     const size_t mfma = al256((size_t)n_in * 4) + al256(nnz * 8) + al256((size_t)kWDig * rows_pad * k_pad);
     return std::max(grouped, mfma) + al256((size_t)(n_in + n_out) * 8) + 1024;
 }
@@ -2381,7 +2381,7 @@ namespace {
 int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const u32 *cols, u32 ncols,
                 const int64_t *w, u32 L, u32 stride, u32 ostride, ckks_ct *out, void *ws, size_t ws_bytes,
                 hipStream_t s) {
-    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)ncols + 31) / 32 * 32;
+    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)ncols + 63) / 64 * 64;
     const size_t o_cols = 0, o_w = al256((size_t)ncols * 4), o_ptr = o_w + al256((size_t)n_out * ncols * 8),
                  o_wd = o_ptr + al256((size_t)(n_in + n_out) * 8),
                  need = o_wd + al256((size_t)kWDig * rows_pad * k_pad);

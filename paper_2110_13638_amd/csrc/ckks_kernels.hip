@@ -586,24 +586,24 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 // Dense linear layer on the matrix cores. One workgroup = 4 waves on one
 // tile of 16 consecutive residues (poly p, limb t, slots k0..k0+15); wave w
 // owns output rows 32 (4 blockIdx.y + w) .. +31 (two 16-row MFMA tiles).
-// The four waves share the tile's inputs: per chunk of 32 inputs each
-// thread loads two residues (input 16 v + tid / 16, slot tid % 16), splits
+// The four waves share the tile's inputs: per chunk of 64 inputs each
+// thread loads four residues (input 16 v + tid / 16, slot tid % 16), splits
 // them into kXDig 7-bit digits and stores them as int8 B fragments in LDS
 // (double-buffered: the next chunk's residues are loaded while the matrix
 // cores work on the current one). Each wave multiplies the B fragments with
-// its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad], row-major, 8
-// bytes per lane) by v_mfma_i32_16x16x32_i8, accumulating digit products of
+// its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad], row-major, 16
+// bytes per lane) by v_mfma_i32_16x16x64_i8, accumulating digit products of
 // weight 128^(a + b) together. Lane layout of that instruction (checked on
-// the device): A[l % 16][8 (l / 16) + e], B[8 (l / 16) + e][l % 16],
+// the device): A[l % 16][16 (l / 16) + e], B[16 (l / 16) + e][l % 16]
 // D[4 (l / 16) + r][l % 16].
 typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int kMfmaS = kWDig + kXDig - 1;  // digit weights 128^0 .. 128^(s-1)
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
               u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
               u32 limbs, u32 in_stride, u32 out_stride) {
-    // B fragments of two chunks: [buffer][digit][slot][input group of 8], 8 int8 each
-    __shared__ long bfrag[2][kXDig][16][4];
+    // B fragments of two chunks: [buffer][digit][slot][lane group], 16 int8 each
+    __shared__ v4i bfrag[2][kXDig][16][4];
     const u32 N = 1u << tb.log_n;
     const u32 tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const u32 tile = blockIdx.x;  // 16 residues of one (p, t)
@@ -612,23 +612,24 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     const u32 row0 = (blockIdx.y * 4 + wave) * 32;
     const bool rows = row0 < rows_pad;  // every wave still stages inputs and meets the barriers
     const u32 col = lane & 15, grp = lane >> 4;
-    const u32 scol = tid & 15, srow = tid >> 4;  // staging: slot, input within a half chunk
+    const u32 scol = tid & 15, srow = tid >> 4;  // staging: slot, input within a quarter chunk
     const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + scol;
-    auto load = [&](u32 kc, u64 (&x)[2]) {
+    auto load = [&](u32 kc, u64 (&x)[4]) {
 #pragma unroll
-        for (int v = 0; v < 2; v++) {
+        for (int v = 0; v < 4; v++) {
             const u32 i = kc + 16 * v + srow;
             x[v] = i < n_in ? in_ptrs[cols[i]][in_off] : 0;
         }
     };
-    auto stage = [&](int buf, const u64 (&x)[2]) {
+    auto stage = [&](int buf, const u64 (&x)[4]) {
         int8_t *b8 = reinterpret_cast<int8_t *>(&bfrag[buf][0][0][0]);
 #pragma unroll
-        for (int v = 0; v < 2; v++) {
-            const u32 ip = 16 * v + srow;  // position in the chunk: group ip / 8, byte ip % 8
+        for (int v = 0; v < 4; v++) {
+            const u32 ip = 16 * v + srow;  // position in the chunk
+            const u32 g = ip >> 4, e = ip & 15;
 #pragma unroll
             for (int b = 0; b < kXDig; b++)
-                b8[((b * 16 + scol) * 4 + (ip >> 3)) * 8 + (ip & 7)] = (int8_t)((x[v] >> (7 * b)) & 127);
+                b8[((b * 16 + scol) * 4 + g) * 16 + e] = (int8_t)((x[v] >> (7 * b)) & 127);
         }
     };
     v4i acc[2][kMfmaS];
@@ -638,29 +639,29 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
         for (int s = 0; s < kMfmaS; s++) acc[h][s] = v4i{0, 0, 0, 0};
     const size_t plane = (size_t)rows_pad * k_pad;
     {
-        u64 x[2];
+        u64 x[4];
         load(0, x);
         stage(0, x);
     }
     __syncthreads();
     int buf = 0;
-    for (u32 kc = 0; kc < k_pad; kc += 32, buf ^= 1) {
-        const bool more = kc + 32 < k_pad;
-        u64 xn[2] = {0, 0};
-        if (more) load(kc + 32, xn);
+    for (u32 kc = 0; kc < k_pad; kc += 64, buf ^= 1) {
+        const bool more = kc + 64 < k_pad;
+        u64 xn[4] = {0, 0, 0, 0};
+        if (more) load(kc + 64, xn);
         if (rows) {
-            long bd[kXDig];
+            v4i bd[kXDig];
 #pragma unroll
             for (int b = 0; b < kXDig; b++) bd[b] = bfrag[buf][b][col][grp];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 8 * grp;
+                const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 16 * grp;
 #pragma unroll
                 for (int a = 0; a < kWDig; a++) {
-                    const long ad = *reinterpret_cast<const long *>(wd + a * plane + aoff);
+                    const v4i ad = *reinterpret_cast<const v4i *>(wd + a * plane + aoff);
 #pragma unroll
                     for (int b = 0; b < kXDig; b++)
-                        acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x32_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
+                        acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
                 }
             }
         }

@@ -95,11 +95,11 @@ def linear(orc, cts, scale, rows, w_scale, biases):
     outs = []
     for j, row in enumerate(rows):
         idx = [i for i, _ in row]
-        w = [int(np.sign(x * w_scale) * np.floor(abs(x * w_scale) + 0.5)) for _, x in row]
+        w = [round_half_away(x * w_scale) for _, x in row]
         acc = orc.lincomb([cts[i] for i in idx], w)
         acc = orc.rescale(acc)
         if biases is not None and biases[j] is not None:
-            acc = orc.add_const(acc, int(np.sign(biases[j] * out_scale) * np.floor(abs(biases[j] * out_scale) + 0.5)))
+            acc = orc.add_const(acc, round_half_away(biases[j] * out_scale))
         outs.append(acc)
     return outs, out_scale
 
@@ -108,7 +108,8 @@ def square(orc, keys, ct, scale):
     return orc.mul_relin_rescale(ct, ct, keys.rk), scale * scale / orc.q[ct.shape[1] - 1]
 
 
-def _round(v):
+def round_half_away(v):
+    """integer nearest to v, halves away from zero (the encoding rounding)"""
     return int(np.sign(v) * np.floor(abs(v) + 0.5))
 
 
@@ -118,15 +119,15 @@ def poly(orc, keys, ct, scale, coeffs, w_scale):
     levels."""
     d = len(coeffs) - 1
     level = ct.shape[1] - 1
-    h = orc.rescale(orc.mul_const(ct, _round(coeffs[d] * w_scale)))
+    h = orc.rescale(orc.mul_const(ct, round_half_away(coeffs[d] * w_scale)))
     hs = scale * w_scale / orc.q[level]
     for k in range(d - 1, 0, -1):
-        h = orc.add_const(h, _round(coeffs[k] * hs))
+        h = orc.add_const(h, round_half_away(coeffs[k] * hs))
         lv = h.shape[1] - 1
         xs = orc.mod_switch(ct, lv)
         h = orc.mul_relin_rescale(xs, h, keys.rk)
         hs = scale * hs / orc.q[lv]
-    h = orc.add_const(h, _round(coeffs[0] * hs))
+    h = orc.add_const(h, round_half_away(coeffs[0] * hs))
     return h, hs
 
 

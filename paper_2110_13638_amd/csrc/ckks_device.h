@@ -104,13 +104,20 @@ __device__ __forceinline__ u64 centered_mod(u64 r, u64 h, const PrimeConst &pc) 
 // multiplication by w/q (or 1/q) the quotient. gfx950 issues one FP64 FMA
 // per lane per cycle, the rate of a single 32-bit integer operation, while
 // an exact 64-bit Shoup product takes about twenty of those.
-//   fp_mulmod(y, w, w/q): exact y w - k q with k the integer nearest to
-//   y (w/q); |result| <= q (0.5 + |y| 2^-53) < q for |y| <= 2^52, and every
-//   intermediate is an integer below 2^53 in magnitude, so no step rounds.
+//   fp_mulmod(y, w, w/q): y w - k q with k = fl(y (w/q) + 1.5 2^52) -
+//   1.5 2^52. For integer-valued y, w with |y w| < 2^104 the result is
+//   exactly y w - k q (h - k q and h + l are integers below 2^53), so the
+//   residue is always right; its size depends on k. While |y (w/q)| < 2^51
+//   the sum lands in [2^52, 2^53), where doubles are the integers, and k is
+//   the integer nearest to y (w/q): |result| <= q (1/2 + |y| |w/q| 2^-53).
+//   Beyond 2^51 the spacing is 2 and k can be off by one more. The
+//   transform multipliers are therefore stored centred (|w/q| <= 1/2), so
+//   every |y| < 2^52 takes the nearest quotient (a committed CPU emulation
+//   of both transform schedules checks the bounds below exactly).
 // The arithmetic is written out operation by operation: no contraction
 // into FMAs beyond the explicit ones.
 // ---------------------------------------------------------------------
-constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52: (x + kRound) - kRound rounds |x| < 2^51
+constexpr double kRound = 6755399441055744.0;  // 1.5 * 2^52: (x + kRound) - kRound rounds |x| < 2^51 to nearest
 constexpr double kTwo52 = 4503599627370496.0;
 constexpr u64 kMant52 = (1ull << 52) - 1;
 __device__ __forceinline__ double fp_mulmod(double y, double w, double wq, double q) {
@@ -385,10 +392,11 @@ struct Ntt {
         for (int k = 0; k < E; k++) d[k] = __builtin_bit_cast(double, t[k]);
     }
 
-    // Forward stage s: (X, Y) -> (X + W Y, X - W Y). With |W Y mod q| < q the
-    // magnitude bound grows by q per stage; X is re-centred (|X| <= q/2 + 1)
-    // on stages s = 2 mod 3, so with inputs below 2q every value stays below
-    // 4q <= 2^52 (the multiplier's input range) and every sum is exact.
+    // Forward stage s: (X, Y) -> (X + W Y, X - W Y). With centred twiddles
+    // |W Y mod q| <= q (1/2 + |Y| 2^-54), so the magnitude bound grows by at
+    // most 0.63 q per stage; X is re-centred (|X| <= q/2 + 1) on stages
+    // s = 2 mod 3, so with inputs below q every value stays below 2.4 q
+    // < 2^52 (the multiplier's input range) and every sum is exact.
     template <int P, int D>
     static __device__ __forceinline__ void fwd_stage_f(double (&r)[E], u32 tid, const double2 *__restrict__ tw,
                                                        double q, double qinv) {
@@ -440,7 +448,7 @@ struct Ntt {
     // Inverse stage s: (X, Y) -> (X + Y, (X - Y) W^-1); the sum is re-centred
     // on every second stage executed, so inputs stay below 2q and
     // differences below 4q. The last stage multiplies both outputs
-    // (by N^-1 and by W^-1 N^-1), leaving |.| < q.
+    // (by centred N^-1 and W^-1 N^-1), leaving |.| <= q (1/2 + 4q 2^-54) < q.
     template <int P, int D>
     static __device__ __forceinline__ void inv_stage_f(double (&r)[E], u32 tid, const double2 *__restrict__ itw,
                                                        const PrimeConst &pc) {

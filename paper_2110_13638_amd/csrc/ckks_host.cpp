@@ -387,23 +387,28 @@ extern "C" int ckks_ctx_create(const ckks_params *p, ckks_ctx **out) {
         pc.ninv_sh = shoup_companion(pc.ninv, q);
         pc.last_w = mulmod(itw[1].x, pc.ninv, q);
         pc.last_w_sh = shoup_companion(pc.last_w, q);
-        // FP64 copies (exact for q < 2^50; w / q and 1 / q correctly rounded)
+        // FP64 copies (exact for q < 2^50; w / q and 1 / q correctly rounded).
+        // Transform multipliers are stored centred, |w| <= (q - 1) / 2, so
+        // that |w / q| <= 1/2: a product with any |y| < 2^52 then has
+        // |y w / q| < 2^51, where the rounding constant of fp_mulmod gives
+        // the nearest integer quotient
         const double qd = (double)q;
+        auto centred = [q, qd](u64 v) { return v > q / 2 ? (double)v - qd : (double)v; };
         double *twf = reinterpret_cast<double *>(img + c->off_twf) + (size_t)i * N * 2;
         double *itwf = reinterpret_cast<double *>(img + c->off_itwf) + (size_t)i * N * 2;
         for (u32 k = 0; k < N; k++) {
-            twf[2 * k] = (double)tw[k].x;
-            twf[2 * k + 1] = (double)tw[k].x / qd;
-            itwf[2 * k] = (double)itw[k].x;
-            itwf[2 * k + 1] = (double)itw[k].x / qd;
+            twf[2 * k] = centred(tw[k].x);
+            twf[2 * k + 1] = twf[2 * k] / qd;
+            itwf[2 * k] = centred(itw[k].x);
+            itwf[2 * k + 1] = itwf[2 * k] / qd;
         }
         pc.qf = qd;
         pc.qinvf = 1.0 / qd;
         pc.qmf = 4503599627370496.0 + qd;
-        pc.ninvf = (double)pc.ninv;
-        pc.ninvqf = (double)pc.ninv / qd;
-        pc.last_wf = (double)pc.last_w;
-        pc.last_wqf = (double)pc.last_w / qd;
+        pc.ninvf = centred(pc.ninv);
+        pc.ninvqf = pc.ninvf / qd;
+        pc.last_wf = centred(pc.last_w);
+        pc.last_wqf = pc.last_wf / qd;
         u64 P = 1;
         for (u32 m = 0; m < npp; m++) P = mulmod(P, c->primes[nq + m] % q, q);
         Pmod[i] = P;

@@ -7,6 +7,7 @@ import pytest
 import oracle as O
 import synthetic as S
 from oracle import encoding as OE
+from oracle import nets as ON
 
 pytestmark = pytest.mark.gpu
 
@@ -139,9 +140,10 @@ def test_elementwise_bit_exact(request, which):
     pto = orc.reduce_int(w, level)
     assert np.array_equal(ctx.multiply_plain(a, pt).residues(), orc.mul_plain(ao, pto))
     assert np.array_equal(ctx.add_plain(a, pt).residues(), orc.add_plain(ao, pto))
-    v = ctx.const_int(-0.3, ctx.default_scale)
+    # expected constants from the oracle's own rounding (half away from zero)
+    v = ON.round_half_away(-0.3 * ctx.default_scale)
     assert np.array_equal(ctx.multiply_scalar(a, -0.3).residues(), orc.mul_const(ao, v))
-    v2 = ctx.const_int(0.7, a.scale)
+    v2 = ON.round_half_away(0.7 * a.scale)
     assert np.array_equal(ctx.add_scalar(a, 0.7).residues(), orc.add_const(ao, v2))
 
 
@@ -214,7 +216,7 @@ def test_linear_bit_exact(small):
     for j in range(3):
         want = None
         for i in range(5):
-            term = orc.mul_const(cos[i], ctx.const_int(W[j, i], ctx.default_scale))
+            term = orc.mul_const(cos[i], ON.round_half_away(W[j, i] * ctx.default_scale))
             want = term if want is None else orc.add(want, term)
         assert np.array_equal(outs[j].residues(), want)
 
@@ -284,3 +286,49 @@ def test_dense_linear_matrix_cores_bit_exact(ck, shape):
         want = orc.lincomb(ins, list(W[j]))
         assert np.array_equal(outs[1][j], want), j
         assert np.array_equal(outs[0][j], want), j
+
+
+@pytest.mark.parametrize("ntt_fp", [1, 0])
+def test_full_size_ragged_hmult(ck, ntt_fp):
+    # N = 2^15, 16 x 50-bit + 2 x 60-bit primes, dnum 4 (four primes per
+    # digit): a ragged batch of 13 pairs at 4..16 limbs, so the top digit
+    # holds 1, 2, 3 or 4 primes and every fixed-size ModUp kernel runs;
+    # both arithmetic engines, element-wise against the oracle
+    ctx, orc = _pair(ck, 15, [50] * 16, [60, 60], 4, seed=5)
+    _, _, _, rk = _keys_oracle(orc, 5)
+    ctx.set_tuning(ntt_fp=ntt_fp)
+    try:
+        levels = [l - 1 for l in S.ragged_limbs(13)]
+        A, Bs, AO, BO = [], [], [], []
+        for i, lv in enumerate(levels):
+            res = S.residues(300 + i, ctx.q[: lv + 1], ctx.N, 4)
+            AO.append(res[:2])
+            BO.append(res[2:])
+            A.append(ctx.ct_from_residues(res[:2]))
+            Bs.append(ctx.ct_from_residues(res[2:]))
+        print("full-size ragged hmult ntt_fp=%d levels=%s" % (ntt_fp, levels), flush=True)
+        outs = ctx.hmult_relin_rescale(A, Bs)
+        for i, lv in enumerate(levels):
+            assert np.array_equal(outs[i].residues(), orc.mul_relin_rescale(AO[i], BO[i], rk)), (i, lv)
+    finally:
+        ctx.set_tuning(ntt_fp=1)
+
+
+@pytest.mark.parametrize("which", ["small", "wide"])
+def test_conjugation_bit_exact(request, which):
+    # Galois element 2N - 1 (complex conjugation of the slots)
+    ctx, orc = request.getfixturevalue(which)
+    level = ctx.max_level
+    z = S.uniform_slots(13, ctx.N // 2) + 1j * S.uniform_slots(14, ctx.N // 2)
+    m = ctx.encode_coeffs(z, ctx.default_scale)
+    s, sn, pk, rk = _keys_oracle(orc, 3)
+    ct = ctx.encrypt(ctx.pt_from_coeffs(m, level, ctx.default_scale), seed=99, obj=6)
+    ct_o = orc.encrypt(pk, orc.reduce_int(m, level), level, 99, 6)
+    g = 2 * ctx.N - 1
+    ctx.add_galois_key(g, 77)
+    got = ctx.rotate(ct, g=g)
+    want = orc.apply_galois(ct_o, g, orc.keygen_galois(s, sn, g, 77))
+    assert np.array_equal(got.residues(), want)
+    if which == "small":
+        dec = ctx.decode(ctx.decrypt_residues(got), level, got.scale)
+        assert np.max(np.abs(dec - np.conj(z))) < 2 ** -18

@@ -243,6 +243,19 @@ int ckks_encode(const ckks_ctx *ctx, const double *re, const double *im, size_t 
  * slots = m(zeta^(5^j)) / scale for j < n. im may be NULL. */
 int ckks_decode(const ckks_ctx *ctx, const uint64_t *residues, uint32_t level, double scale,
                 double *re, double *im, size_t n);
+/* Constants (Section 4.2: weights and biases enter conv and dense nodes as
+ * plaintext constants). A constant c at scale s is the constant polynomial
+ * round_half_away(c * s) (only coefficient 0 nonzero), so its NTT form
+ * holds the same residue in every slot of a limb.
+ * ckks_encode_scalars: the integers round_half_away(c[k] * scale) for n
+ * host values into out[n] (host), the form ckks_multiply_scalar,
+ * ckks_add_scalar and the linear layers take. CKKS_EINVAL when a product is
+ * not finite or reaches 2^62 in magnitude (nothing after it is written).
+ * ckks_encode_scalar: the same constant as its residues per limb,
+ * per_limb[i] = round_half_away(c * scale) mod q_i for i <= level (host,
+ * level + 1 entries); CKKS_ELEVEL for a level beyond the chain. */
+int ckks_encode_scalars(const ckks_ctx *ctx, const double *c, size_t n, double scale, int64_t *out);
+int ckks_encode_scalar(const ckks_ctx *ctx, double c, double scale, uint32_t level, uint64_t *per_limb);
 /* Integer polynomial (device int64[N]) -> device plaintext in NTT form
  * at out->level; out->scale is left as set by the caller. */
 int ckks_pt_load(const ckks_ctx *ctx, const int64_t *coeffs, ckks_pt *out, void *ws,
@@ -285,8 +298,12 @@ int ckks_multiply(const ckks_ctx *ctx, const ckks_ct *a, const ckks_ct *b, ckks_
 /* hybrid key switch of c2 with the relinearisation key:
  * out = (c0 + ks0, c1 + ks1). ModUp is the approximate basis conversion
  * of each digit; ModDown subtracts the conversion of the special-prime
- * part and multiplies by P^-1. out must not alias in3. */
-int ckks_relinearize(const ckks_ctx *ctx, const uint64_t *rk, const ckks_ct *in3, ckks_ct *out,
+ * part and multiplies by P^-1. out must not alias in3.
+ * rk[b]: device pointer to the relinearisation key of item b. Each client
+ * holds its own keys (the threat model of Section 2.3), so items of
+ * different clients carry different keys and still share one launch;
+ * items with the same key share its loads. CKKS_ENOKEY for a null key. */
+int ckks_relinearize(const ckks_ctx *ctx, const uint64_t *const *rk, const ckks_ct *in3, ckks_ct *out,
                      uint32_t B, void *ws, size_t ws_bytes, void *stream);
 /* rescale by the top prime q_l: c' = floor((c + floor(q_l/2)) / q_l)
  * coefficient-wise, scale / q_l, level - 1. out may alias in. */
@@ -295,14 +312,18 @@ int ckks_rescale(const ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, uint32_t 
 /* modulus-chain level match: a view change (no device work) */
 int ckks_mod_switch_to(const ckks_ctx *ctx, ckks_ct *inout, uint32_t level);
 /* slot rotation: X -> X^g on both polys, then key switch of the second
- * with the Galois key for g: out = (sigma(c0) + ks0, ks1). All B use
- * the same key. out must not alias in. */
-int ckks_rotate(const ckks_ctx *ctx, const uint64_t *gk, uint32_t galois_elt, const ckks_ct *in,
+ * with the Galois key for g: out = (sigma(c0) + ks0, ks1). Item b uses the
+ * Galois element galois_elts[b] (odd, < 2N; see ckks_galois_elt) and the
+ * device key gk[b] made for that element (per item, so one launch can
+ * rotate ciphertexts of several clients by different steps). EINVAL for a
+ * bad element, ENOKEY for a null key. out must not alias in. */
+int ckks_rotate(const ckks_ctx *ctx, const uint64_t *const *gk, const uint32_t *galois_elts, const ckks_ct *in,
                 ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream);
 /* Fused, batched HMult + relinearise + rescale (the ciphertext product as
  * the container performs it): out[b] = rescale(relin(a[b] x b[b])),
- * ragged levels allowed. Bit-identical to the three calls in sequence. */
-int ckks_hmult_relin_rescale(const ckks_ctx *ctx, const uint64_t *rk, const ckks_ct *a,
+ * ragged levels allowed. Bit-identical to the three calls in sequence.
+ * rk[b]: the relinearisation key of item b (as in ckks_relinearize). */
+int ckks_hmult_relin_rescale(const ckks_ctx *ctx, const uint64_t *const *rk, const ckks_ct *a,
                              const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws,
                              size_t ws_bytes, void *stream);
 /* Encrypted linear layer with integer weights (conv and dense of the

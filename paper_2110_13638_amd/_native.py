@@ -7,6 +7,8 @@ library has not been built: there is no fallback path.
 import ctypes
 import os
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libckks_hip.so")
 
@@ -114,12 +116,14 @@ _SIGS = {
                                             _vp, _sz, _vp]),
     "ckks_add_scalar": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ctypes.c_int64), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_multiply": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
-    "ckks_relinearize": (ctypes.c_int, [_vp, _vp, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_relinearize": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_rescale": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_mod_switch_to": (ctypes.c_int, [_vp, _P(ckks_ct), _u32]),
-    "ckks_rotate": (ctypes.c_int, [_vp, _vp, _u32, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
-    "ckks_hmult_relin_rescale": (ctypes.c_int, [_vp, _vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz,
-                                                _vp]),
+    "ckks_rotate": (ctypes.c_int, [_vp, _P(_vp), _P(_u32), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_hmult_relin_rescale": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp,
+                                                _sz, _vp]),
+    "ckks_encode_scalars": (ctypes.c_int, [_vp, _P(_dbl), _sz, _dbl, _P(ctypes.c_int64)]),
+    "ckks_encode_scalar": (ctypes.c_int, [_vp, _dbl, _dbl, _u32, _P(_u64)]),
     "ckks_linear": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _vp, _dbl, _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_linear_csr_workspace_bytes": (_sz, [_vp, _u32, _u32, _sz, _u32]),
     "ckks_hoisted_linear_workspace_bytes": (_sz, [_vp, _u32, _u32, _u32]),
@@ -332,8 +336,18 @@ def ckks_multiply(h, a, b, out3, ws, ws_bytes, stream=None):
     _call("ckks_multiply", h, a, b, out3, len(out3), ws, ws_bytes, stream)
 
 
+def _per_item(x, n):
+    """one value for every item, or a sequence of n"""
+    if isinstance(x, (list, tuple, np.ndarray)):
+        if len(x) != n:
+            raise ValueError("expected %d per-item values, got %d" % (n, len(x)))
+        return [int(v) for v in x]
+    return [int(x)] * n
+
+
 def ckks_relinearize(h, rk, in3, out, ws, ws_bytes, stream=None):
-    _call("ckks_relinearize", h, rk, in3, out, len(out), ws, ws_bytes, stream)
+    """rk: one key pointer for every item, or one per item"""
+    _call("ckks_relinearize", h, _arr(_vp, _per_item(rk, len(out))), in3, out, len(out), ws, ws_bytes, stream)
 
 
 def ckks_rescale(h, a, out, ws, ws_bytes, stream=None):
@@ -345,11 +359,32 @@ def ckks_mod_switch_to(h, ct, level):
 
 
 def ckks_rotate(h, gk, galois_elt, a, out, ws, ws_bytes, stream=None):
-    _call("ckks_rotate", h, gk, galois_elt, a, out, len(out), ws, ws_bytes, stream)
+    """gk, galois_elt: one key pointer / element for every item, or one per item"""
+    n = len(out)
+    _call("ckks_rotate", h, _arr(_vp, _per_item(gk, n)), _arr(_u32, _per_item(galois_elt, n)), a, out, n, ws,
+          ws_bytes, stream)
 
 
 def ckks_hmult_relin_rescale(h, rk, a, b, out, ws, ws_bytes, stream=None):
-    _call("ckks_hmult_relin_rescale", h, rk, a, b, out, len(out), ws, ws_bytes, stream)
+    """rk: one relinearisation key pointer for every item, or one per item"""
+    _call("ckks_hmult_relin_rescale", h, _arr(_vp, _per_item(rk, len(out))), a, b, out, len(out), ws, ws_bytes,
+          stream)
+
+
+def ckks_encode_scalars(h, values, scale):
+    """round_half_away(values[k] * scale) as an int64 array (computed in C)"""
+    v = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+    out = np.zeros(v.size, dtype=np.int64)
+    _call("ckks_encode_scalars", h, v.ctypes.data_as(_P(_dbl)), v.size, float(scale),
+          out.ctypes.data_as(_P(ctypes.c_int64)))
+    return out
+
+
+def ckks_encode_scalar(h, value, scale, level):
+    """per-limb residues of the constant polynomial round_half_away(value * scale)"""
+    out = np.zeros(level + 1, dtype=np.uint64)
+    _call("ckks_encode_scalar", h, float(value), float(scale), level, out.ctypes.data_as(_P(_u64)))
+    return out
 
 
 def ckks_linear(h, inp, W_dev, w_scale, out, ws, ws_bytes, stream=None):

@@ -125,6 +125,15 @@ class _Recording:
         return False
 
 
+class KeySet:
+    """One client's keys on a ring: secret (client side only), public,
+    relinearisation and Galois keys by element (server resident)."""
+
+    def __init__(self):
+        self.sk = self.pk = self.rk = None
+        self.gk = {}
+
+
 class Context:
     """Parameters, device tables, keys and a reusable workspace."""
 
@@ -228,16 +237,37 @@ class Context:
 
     # --- keys -----------------------------------------------------------------
     def keygen(self, seed=1, galois_steps=()):
-        self.sk = torch.empty(len(self.primes), self.N, dtype=torch.int64, device=self.device)
-        ws, wb = self.ws_for(nat.CKKS_OP_KEYGEN, 1)
-        nat.ckks_keygen_secret(self.h, seed, self.sk.data_ptr(), ws, wb, self.stream)
-        self.pk = torch.empty(2, len(self.q), self.N, dtype=torch.int64, device=self.device)
-        nat.ckks_keygen_public(self.h, self.sk.data_ptr(), seed + 1, self.pk.data_ptr(), ws, wb, self.stream)
-        self.rk = self.new_switch_key()
-        nat.ckks_keygen_relin(self.h, self.sk.data_ptr(), seed + 2, self.rk.data_ptr(), ws, wb, self.stream)
+        """this context's default key set (secret seed, public seed + 1,
+        relinearisation seed + 2, Galois seed + 3)"""
+        k = self.client_keys(seed)
+        self.sk, self.pk, self.rk = k.sk, k.pk, k.rk
         for s in galois_steps:
             self.add_galois_key(self.galois_elt(s), seed + 3)
         return self
+
+    def client_keys(self, seed, galois_steps=()):
+        """Another client's key set on the same ring (same seeds rule as
+        keygen). Its rk / gk pointers go into the per-item key arrays of the
+        batched key-switching calls, so requests of several clients share
+        launches."""
+        k = KeySet()
+        k.sk = torch.empty(len(self.primes), self.N, dtype=torch.int64, device=self.device)
+        ws, wb = self.ws_for(nat.CKKS_OP_KEYGEN, 1)
+        nat.ckks_keygen_secret(self.h, seed, k.sk.data_ptr(), ws, wb, self.stream)
+        k.pk = torch.empty(2, len(self.q), self.N, dtype=torch.int64, device=self.device)
+        nat.ckks_keygen_public(self.h, k.sk.data_ptr(), seed + 1, k.pk.data_ptr(), ws, wb, self.stream)
+        k.rk = self.new_switch_key()
+        nat.ckks_keygen_relin(self.h, k.sk.data_ptr(), seed + 2, k.rk.data_ptr(), ws, wb, self.stream)
+        for st in galois_steps:
+            g = self.galois_elt(st)
+            gk = self.new_switch_key()
+            nat.ckks_keygen_galois(self.h, k.sk.data_ptr(), g, seed + 3, gk.data_ptr(), ws, wb, self.stream)
+            k.gk[g] = gk
+        return k
+
+    def key_bytes(self):
+        """device bytes of one switching key (relinearisation or Galois)"""
+        return nat.ckks_key_bytes(self.h, nat.CKKS_KEY_SWITCH)
 
     def new_switch_key(self):
         return torch.empty(self.digits(self.max_level), 2, len(self.primes), self.N, dtype=torch.int64,
@@ -290,21 +320,23 @@ class Context:
         return re + 1j * im
 
     # --- encryption ---------------------------------------------------------------
-    def encrypt(self, pt, seed=7, obj=0):
+    def encrypt(self, pt, seed=7, obj=0, keys=None):
         ct = self.new_ct(2, pt.level, pt.scale)
         s = ct.struct()
         ws, wb = self.ws_for(nat.CKKS_OP_ENCRYPT, 1, [pt.level])
-        nat.ckks_encrypt(self.h, self.pk.data_ptr(), pt.struct(), seed, obj, s, ws, wb, self.stream)
+        pk = (keys or self).pk
+        nat.ckks_encrypt(self.h, pk.data_ptr(), pt.struct(), seed, obj, s, ws, wb, self.stream)
         return ct.update(s)
 
-    def decrypt_residues(self, ct):
+    def decrypt_residues(self, ct, keys=None):
         m = self.limbs(ct.level + 1)
         ws, wb = self.ws_for(nat.CKKS_OP_NTT, ct.level + 1)
-        nat.ckks_decrypt(self.h, self.sk.data_ptr(), ct.struct(), m.data_ptr(), ws, wb, self.stream)
+        sk = (keys or self).sk
+        nat.ckks_decrypt(self.h, sk.data_ptr(), ct.struct(), m.data_ptr(), ws, wb, self.stream)
         return m.cpu().numpy().view(np.uint64)
 
-    def decrypt(self, ct, n=None):
-        return self.decode(self.decrypt_residues(ct), ct.level, ct.scale, n)
+    def decrypt(self, ct, n=None, keys=None):
+        return self.decode(self.decrypt_residues(ct, keys), ct.level, ct.scale, n)
 
     # --- evaluation (batched: lists of ciphertexts) ----------------------------------
     @staticmethod
@@ -359,9 +391,8 @@ class Context:
         return self._ptop(nat.ckks_multiply_plain, a, pt)
 
     def const_int(self, c, scale):
-        v = float(c) * scale
-        r = np.sign(v) * np.floor(abs(v) + 0.5)
-        return int(r)
+        """the constant polynomial round_half_away(c * scale), rounded in C"""
+        return int(nat.ckks_encode_scalars(self.h, [c], scale)[0])
 
     def multiply_scalar(self, a, c, c_scale=None):
         c_scale = c_scale or self.default_scale
@@ -380,13 +411,23 @@ class Context:
         nat.ckks_add_scalar(self.h, self._structs([a]), [v], so, ws, wb, self.stream)
         return out.update(so[0])
 
-    def relinearize(self, a):
+    def _key_ptrs(self, keys, n, default):
+        """per-item device key pointers: None = the context's key for all"""
+        if keys is None:
+            return default.data_ptr()
+        keys = list(keys)
+        if len(keys) != n:
+            raise ValueError("need one key per item")
+        return [k.data_ptr() for k in keys]
+
+    def relinearize(self, a, rk=None):
+        """rk: None (this context's key) or one relinearisation key per item"""
         single = isinstance(a, Ciphertext)
         A = [a] if single else list(a)
         outs = [self.new_ct(2, x.level, x.scale) for x in A]
         so = self._structs(outs)
         ws, wb = self.ws_for(nat.CKKS_OP_KEYSWITCH, len(A), [x.level for x in A])
-        nat.ckks_relinearize(self.h, self.rk.data_ptr(), self._structs(A), so, ws, wb, self.stream)
+        nat.ckks_relinearize(self.h, self._key_ptrs(rk, len(A), self.rk), self._structs(A), so, ws, wb, self.stream)
         self._outs(so, outs)
         return outs[0] if single else outs
 
@@ -406,25 +447,36 @@ class Context:
         nat.ckks_mod_switch_to(self.h, s, level)
         return out.update(s)
 
-    def rotate(self, a, step=None, g=None):
-        g = g if g is not None else self.galois_elt(step)
-        if g not in self.gk:
-            raise nat.CkksError(nat.CKKS_ENOKEY, "no Galois key for element %d" % g)
+    def rotate(self, a, step=None, g=None, gk=None):
+        """Left rotation of the slots by step (or Galois element g). With
+        lists: g may be one element per item, and gk one key per item
+        (several clients' keys in one launch); otherwise this context's key."""
         single = isinstance(a, Ciphertext)
         A = [a] if single else list(a)
+        if g is None:
+            g = [self.galois_elt(s) for s in step] if isinstance(step, (list, tuple)) else self.galois_elt(step)
+        elts = list(g) if isinstance(g, (list, tuple)) else [g] * len(A)
+        if gk is None:
+            for e in set(elts):
+                if e not in self.gk:
+                    raise nat.CkksError(nat.CKKS_ENOKEY, "no Galois key for element %d" % e)
+            keys = [self.gk[e].data_ptr() for e in elts]
+        else:
+            keys = [k.data_ptr() for k in gk]
         outs = [self.new_ct(2, x.level, x.scale) for x in A]
         so = self._structs(outs)
         ws, wb = self.ws_for(nat.CKKS_OP_KEYSWITCH, len(A), [x.level for x in A])
-        nat.ckks_rotate(self.h, self.gk[g].data_ptr(), g, self._structs(A), so, ws, wb, self.stream)
+        nat.ckks_rotate(self.h, keys, elts, self._structs(A), so, ws, wb, self.stream)
         self._outs(so, outs)
         return outs[0] if single else outs
 
-    def hmult_relin_rescale(self, A, Bs, outs=None):
+    def hmult_relin_rescale(self, A, Bs, outs=None, rk=None):
+        """rk: None (this context's key) or one relinearisation key per item"""
         outs = outs or [self.new_ct(2, x.level - 1, x.scale) for x in A]
         so = self._structs(outs)
         ws, wb = self.ws_for(nat.CKKS_OP_HMULT, len(A), [x.level for x in A])
-        nat.ckks_hmult_relin_rescale(self.h, self.rk.data_ptr(), self._structs(A), self._structs(Bs), so, ws, wb,
-                                     self.stream)
+        nat.ckks_hmult_relin_rescale(self.h, self._key_ptrs(rk, len(A), self.rk), self._structs(A), self._structs(Bs),
+                                     so, ws, wb, self.stream)
         return self._outs(so, outs)
 
     def linear(self, inputs, W, w_scale=None):
@@ -432,8 +484,8 @@ class Context:
         w_scale = w_scale or self.default_scale
         W = np.asarray(W, dtype=np.float64)
         n_out, n_in = W.shape
-        Wi = np.sign(W * w_scale) * np.floor(np.abs(W * w_scale) + 0.5)
-        Wd = torch.from_numpy(Wi.astype(np.int64)).to(self.device)
+        Wi = nat.ckks_encode_scalars(self.h, W, w_scale).reshape(W.shape)
+        Wd = torch.from_numpy(Wi).to(self.device)
         lvl = inputs[0].level
         outs = [self.new_ct(2, lvl, 1.0) for _ in range(n_out)]
         so = self._structs(outs)

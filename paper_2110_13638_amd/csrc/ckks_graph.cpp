@@ -180,8 +180,10 @@ int rotate_all(ckks_graph *g, const std::vector<ckks_ct> &in, std::vector<ckks_c
         const bool to_out = odd ? (h % 2 == 0) : (h % 2 == 1);
         std::vector<ckks_ct> &dst = to_out ? out : tmp;
         for (u32 b = 0; b < B; b++) dst[b].level = (*src)[b].level;
-        GK(ckks_rotate(g->c, g->gk[seq[h].first], seq[h].first, src->data(), dst.data(), B, scratch(g),
-                       scratch_avail(g), g->stream));
+        const std::vector<const u64 *> keys(B, g->gk[seq[h].first]);
+        const std::vector<u32> elts(B, seq[h].first);
+        GK(ckks_rotate(g->c, keys.data(), elts.data(), src->data(), dst.data(), B, scratch(g), scratch_avail(g),
+                       g->stream));
         src = &dst;
     }
     return CKKS_OK;
@@ -230,7 +232,8 @@ int fire_square(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
     std::vector<u32> lv(B, l);
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_HMULT, B, lv.data()));
     if (g->dry) return CKKS_OK;
-    return ckks_hmult_relin_rescale(g->c, g->rk, in.data(), in.data(), n.out.data(), B, scratch(g),
+    const std::vector<const u64 *> keys(B, g->rk);
+    return ckks_hmult_relin_rescale(g->c, keys.data(), in.data(), in.data(), n.out.data(), B, scratch(g),
                                     scratch_avail(g), g->stream);
 }
 
@@ -272,9 +275,11 @@ int fire_poly(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
         std::vector<ckks_ct> xs = in;
         for (auto &x : xs) x.level = hl;  // switch down: a view
         const double ps = s_x * hs;
-        if (!g->dry)
-            GK(ckks_hmult_relin_rescale(g->c, g->rk, xs.data(), h.data(), t.data(), B, scratch(g), scratch_avail(g),
-                                        g->stream));
+        if (!g->dry) {
+            const std::vector<const u64 *> keys(B, g->rk);
+            GK(ckks_hmult_relin_rescale(g->c, keys.data(), xs.data(), h.data(), t.data(), B, scratch(g),
+                                        scratch_avail(g), g->stream));
+        }
         hs = ps / (double)ckks_ctx_prime(g->c, hl);
         hl -= 1;
         std::swap(h, t);

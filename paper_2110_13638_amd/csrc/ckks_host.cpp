@@ -662,6 +662,39 @@ extern "C" int ckks_encode(const ckks_ctx *c, const double *re, const double *im
     return CKKS_OK;
 }
 
+// a constant c at scale s is the constant polynomial round_half_away(c s)
+static int scalar_int(double c, double scale, int64_t *out) {
+    const double v = c * scale;
+    if (!std::isfinite(v)) return fail(CKKS_EINVAL, "encode_scalar: constant or scale not finite");
+    const double r = v < 0 ? -floor(-v + 0.5) : floor(v + 0.5);
+    if (fabs(r) >= 4611686018427387904.0) return fail(CKKS_EINVAL, "encode_scalar: |c * scale| reaches 2^62");
+    *out = (int64_t)r;
+    return CKKS_OK;
+}
+
+extern "C" int ckks_encode_scalars(const ckks_ctx *c, const double *vals, size_t n, double scale, int64_t *out) {
+    if (!c || (n && (!vals || !out))) return fail(CKKS_EINVAL, "encode_scalars: null argument");
+    for (size_t k = 0; k < n; k++) {
+        const int r = scalar_int(vals[k], scale, out + k);
+        if (r != CKKS_OK) return r;
+    }
+    return CKKS_OK;
+}
+
+extern "C" int ckks_encode_scalar(const ckks_ctx *c, double val, double scale, uint32_t level, uint64_t *per_limb) {
+    if (!c || !per_limb) return fail(CKKS_EINVAL, "encode_scalar: null argument");
+    if (level >= c->n_q) return fail(CKKS_ELEVEL, "encode_scalar: level %u beyond top %u", level, c->n_q - 1);
+    int64_t v;
+    const int r = scalar_int(val, scale, &v);
+    if (r != CKKS_OK) return r;
+    for (u32 i = 0; i <= level; i++) {
+        const u64 q = c->primes[i];
+        const u64 m = (u64)(v < 0 ? -(v + 1) : v) % q;  // |v| - 1 for negative v, no overflow
+        per_limb[i] = v >= 0 ? m : (q - 1 - m);
+    }
+    return CKKS_OK;
+}
+
 extern "C" int ckks_decode(const ckks_ctx *c, const uint64_t *res, uint32_t level, double scale, double *re,
                            double *im, size_t n) {
     if (!c || !res || (!re && n)) return fail(CKKS_EINVAL, "decode: null argument");
@@ -993,32 +1026,40 @@ int relin_op(const ckks_ctx *c, bool rescale) {
 // one ciphertext's share of the key-switch inner product
 struct IpCt {
     u32 level;
+    const u64 *key;  // switching key of this ciphertext (per item: one client's key each)
     const u64 *ext;
     u64 *acc;
     std::vector<const u64 *> own0, own1;  // per data limb t <= level
     std::vector<const u64 *> own2, own3;  // a0, b0 of a product (P d folded into the sums)
 };
-// items of the inner product: ciphertexts of one level are grouped by
-// kIpCts so that each key residue is loaded once per group. Items are
+// items of the inner product: ciphertexts of one level and one switching
+// key are grouped by kIpCts so that each key residue is loaded once per
+// group (requests of different clients, i.e. different keys, share the
+// launch but not an item). Items are
 // emitted prime by prime (every group's item for prime 0, then prime 1, ...)
 // so that the blocks in flight at any time share one prime's key limbs
 // (2 beta limbs), which then stay in L2 instead of every group re-reading
 // all primes' keys.
-void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<IpCt> &cts, const u64 *key) {
+static bool ip_before(const IpCt &x, const IpCt &y) {
+    return x.level != y.level ? x.level < y.level : (uintptr_t)x.key < (uintptr_t)y.key;
+}
+static bool ip_same(const IpCt &x, const IpCt &y) { return x.level == y.level && x.key == y.key; }
+void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<IpCt> &cts) {
     std::vector<size_t> order(cts.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return ip_before(cts[x], cts[y]); });
     struct Grp {
         size_t g, h;
         u32 L, E, beta;
+        const u64 *key;
     };
     std::vector<Grp> groups;
     const size_t group = c->tb.ip_cts == 2 ? 2 : (size_t)kIpCts;  // 16 -> 4 for the deep-digit rest
     for (size_t g = 0; g < order.size();) {
         size_t h = g;
-        while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < group) h++;
+        while (h < order.size() && ip_same(cts[order[h]], cts[order[g]]) && h - g < group) h++;
         const u32 L = cts[order[g]].level + 1;
-        groups.push_back({g, h, L, L + c->n_p, (L + c->alpha - 1) / c->alpha});
+        groups.push_back({g, h, L, L + c->n_p, (L + c->alpha - 1) / c->alpha, cts[order[g]].key});
         g = h;
     }
     for (u32 p = 0; p < c->n_prim; p++) {
@@ -1033,7 +1074,7 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
             it.own_digit = t < G.L ? t / c->alpha : 0xFFFFFFFFu;
             it.E = G.E;
             it.pos = t;
-            it.key = key;
+            it.key = G.key;
             for (size_t k = G.g; k < G.h; k++) {
                 const IpCt &x = cts[order[k]];
                 it.ext[k - G.g] = x.ext;
@@ -1051,7 +1092,7 @@ void add_ip_items(const ckks_ctx *c, std::vector<IpItem> &v, const std::vector<I
 // the inner product of a batch: with IP_CTS = 16 and at most kIpSeqBeta
 // digits, ciphertexts of one level go 16 at a time through k_ip_seq;
 // otherwise groups of 2 or 4 through k_ip
-void add_ip(Plan &P, const std::vector<IpCt> &cts, const u64 *key) {
+void add_ip(Plan &P, const std::vector<IpCt> &cts) {
     const ckks_ctx *c = P.c;
     std::vector<IpItem> ip;
     std::vector<IpSeqItem> seq;
@@ -1059,10 +1100,10 @@ void add_ip(Plan &P, const std::vector<IpCt> &cts, const u64 *key) {
         std::vector<IpCt> rest;
         std::vector<size_t> order(cts.size());
         for (size_t i = 0; i < order.size(); i++) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cts[x].level < cts[y].level; });
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return ip_before(cts[x], cts[y]); });
         for (size_t g = 0; g < order.size();) {
             size_t h = g;
-            while (h < order.size() && cts[order[h]].level == cts[order[g]].level && h - g < (size_t)kIpSeqCts) h++;
+            while (h < order.size() && ip_same(cts[order[h]], cts[order[g]]) && h - g < (size_t)kIpSeqCts) h++;
             const u32 L = cts[order[g]].level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
             if (beta > (u32)kIpSeqBeta) {
                 for (size_t k = g; k < h; k++) rest.push_back(cts[order[k]]);
@@ -1078,7 +1119,7 @@ void add_ip(Plan &P, const std::vector<IpCt> &cts, const u64 *key) {
                 it.own_digit = t < L ? t / c->alpha : 0xFFFFFFFFu;
                 it.E = E;
                 it.pos = t;
-                it.key = key;
+                it.key = cts[order[g]].key;
                 for (size_t k = g; k < h; k++) {
                     const IpCt &x = cts[order[k]];
                     it.ext[k - g] = x.ext;
@@ -1092,9 +1133,9 @@ void add_ip(Plan &P, const std::vector<IpCt> &cts, const u64 *key) {
             }
             g = h;
         }
-        add_ip_items(c, ip, rest, key);
+        add_ip_items(c, ip, rest);
     } else {
-        add_ip_items(c, ip, cts, key);
+        add_ip_items(c, ip, cts);
     }
     P.add(6, 0, seq);
     P.add(3, 0, ip);
@@ -1138,12 +1179,13 @@ int check_ct(const ckks_ctx *c, const ckks_ct &ct, const char *what) {
 // ---------------------------------------------------------------------
 struct KsJob {
     u32 level;
+    const u64 *key;               // switching key (device)
     std::vector<const u64 *> dl;  // limbs of the polynomial to switch (NTT form)
     const u64 *addend[2];         // limb 0 of the poly added to each output, or null
     u64 *out[2];                  // limb 0 of each output poly (limbs contiguous)
 };
 
-void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
+void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs) {
     const ckks_ctx *c = P.c;
     const u32 N = c->N, k = c->n_p, A = c->alpha;
     std::vector<Item> icopy, modup, ipP, mdown;
@@ -1181,6 +1223,7 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
         {
             IpCt x;
             x.level = J.level;
+            x.key = J.key;
             x.ext = ext;
             x.acc = acc;
             x.own0 = J.dl;
@@ -1209,7 +1252,7 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs, const u64 *key) {
     }
     P.add(1, I_SCALE, icopy);
     add_modup(P, modup);
-    add_ip(P, ipc, key);
+    add_ip(P, ipc);
     P.add(1, I_COPY, ipP);
     P.add(0, F_MODDOWN, mdown);
 }
@@ -1425,7 +1468,7 @@ extern "C" int ckks_deserialize(const ckks_ctx *c, int obj_kind, const void *hos
 // ---------------------------------------------------------------------
 // workspace sizing: run the planner on placeholder objects
 // ---------------------------------------------------------------------
-static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B);
+static int plan_hmult(Plan &P, const u64 *const *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B);
 
 extern "C" size_t ckks_workspace_bytes(const ckks_ctx *c, int op, uint32_t B, const uint32_t *levels) {
     if (!c) return 0;
@@ -1450,19 +1493,23 @@ extern "C" size_t ckks_workspace_bytes(const ckks_ctx *c, int op, uint32_t B, co
                 x[b] = ckks_ct{(u64 *)(uintptr_t)0x100000, 2, lev(b), lev(b) + 1, 0, 1.0};
             }
             Plan P(c, nullptr);
+            // every item with its own key: the most inner-product items
+            std::vector<const u64 *> keys(B);
+            for (u32 b = 0; b < B; b++) keys[b] = (const u64 *)(uintptr_t)(0x100000 + 256 * (size_t)b);
             if (op == CKKS_OP_HMULT) {
                 std::vector<ckks_ct> o = x;
-                plan_hmult(P, (const u64 *)(uintptr_t)0x100000, x.data(), x.data(), o.data(), B);
+                plan_hmult(P, keys.data(), x.data(), x.data(), o.data(), B);
             } else {
                 std::vector<KsJob> jobs(B);
                 for (u32 b = 0; b < B; b++) {
                     jobs[b].level = lev(b);
+                    jobs[b].key = keys[b];
                     jobs[b].dl.assign(lev(b) + 1, (const u64 *)(uintptr_t)0x100000);
                     jobs[b].addend[0] = jobs[b].addend[1] = nullptr;
                     jobs[b].out[0] = jobs[b].out[1] = (u64 *)(uintptr_t)0x100000;
                     P.limbs(2 * (lev(b) + 1));  // rotate: automorphism staging
                 }
-                plan_keyswitch(P, jobs, (const u64 *)(uintptr_t)0x100000);
+                plan_keyswitch(P, jobs);
                 std::vector<EwItem> ew(B * 2 * (c->n_q));
                 P.add(2, 0, ew);
             }
@@ -1855,13 +1902,14 @@ extern "C" int ckks_mod_switch_to(const ckks_ctx *c, ckks_ct *ct, uint32_t level
 // ---------------------------------------------------------------------
 // server side: key switching, rescale, rotation, fused HMult
 // ---------------------------------------------------------------------
-extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *rk, const ckks_ct *in3, ckks_ct *out, uint32_t B,
-                                void *ws, size_t ws_bytes, void *stream) {
+extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *const *rk, const ckks_ct *in3, ckks_ct *out,
+                                uint32_t B, void *ws, size_t ws_bytes, void *stream) {
     CK(check_ctx(c));
     if (!rk || !in3 || !out) return fail(CKKS_EINVAL, "relinearize: null argument");
     Plan P(c, ws);
     std::vector<KsJob> jobs(B);
     for (u32 k = 0; k < B; k++) {
+        if (!rk[k]) return fail(CKKS_ENOKEY, "relinearize: null key for item %u", k);
         CK(check_ct(c, in3[k], "relinearize"));
         if (in3[k].n_poly != 3) return fail(CKKS_EINVAL, "relinearize: input must have 3 polys");
         if (!out[k].data) return fail(CKKS_EINVAL, "relinearize: null output");
@@ -1870,13 +1918,14 @@ extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *rk, const ckk
         if (out[k].limb_stride < L) out[k].limb_stride = L;
         KsJob &J = jobs[k];
         J.level = in3[k].level;
+        J.key = rk[k];
         for (u32 i = 0; i < L; i++) J.dl.push_back(limb(c, in3[k], 2, i));
         for (u32 cc = 0; cc < 2; cc++) {
             J.addend[cc] = limb(c, in3[k], cc, 0);
             J.out[cc] = limb(c, out[k], cc, 0);
         }
     }
-    plan_keyswitch(P, jobs, rk);
+    plan_keyswitch(P, jobs);
     CK(P.run(ws_bytes, (hipStream_t)stream));
     for (u32 k = 0; k < B; k++) {
         out[k].n_poly = 2;
@@ -1886,15 +1935,17 @@ extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *rk, const ckk
     return CKKS_OK;
 }
 
-extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *gk, uint32_t g, const ckks_ct *in, ckks_ct *out,
-                           uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *const *gk, const uint32_t *galois_elts,
+                           const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream) {
     CK(check_ctx(c));
-    if (!gk || !in || !out) return fail(CKKS_EINVAL, "rotate: null argument");
-    if (!(g & 1) || g >= 2 * c->N) return fail(CKKS_EINVAL, "rotate: Galois element %u not odd / < 2N", g);
+    if (!gk || !galois_elts || !in || !out) return fail(CKKS_EINVAL, "rotate: null argument");
     Plan P(c, ws);
     std::vector<EwItem> am;
     std::vector<KsJob> jobs(B);
     for (u32 k = 0; k < B; k++) {
+        const u32 g = galois_elts[k];
+        if (!(g & 1) || g >= 2 * c->N) return fail(CKKS_EINVAL, "rotate: Galois element %u not odd / < 2N", g);
+        if (!gk[k]) return fail(CKKS_ENOKEY, "rotate: null Galois key for item %u", k);
         CK(check_ct(c, in[k], "rotate"));
         if (in[k].n_poly != 2) return fail(CKKS_EINVAL, "rotate: input must have 2 polys");
         if (!out[k].data || out[k].data == in[k].data) return fail(CKKS_EINVAL, "rotate: out null or aliasing in");
@@ -1913,6 +1964,7 @@ extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *gk, uint32_t g, co
             }
         KsJob &J = jobs[k];
         J.level = in[k].level;
+        J.key = gk[k];
         for (u32 i = 0; i < L; i++) J.dl.push_back(rot + ((size_t)L + i) * N);
         J.addend[0] = rot;
         J.addend[1] = nullptr;
@@ -1920,7 +1972,7 @@ extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *gk, uint32_t g, co
         J.out[1] = limb(c, out[k], 1, 0);
     }
     P.add(2, 0, am);
-    plan_keyswitch(P, jobs, gk);
+    plan_keyswitch(P, jobs);
     CK(P.run(ws_bytes, (hipStream_t)stream));
     for (u32 k = 0; k < B; k++) {
         out[k].n_poly = 2;
@@ -1989,7 +2041,7 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
 // The corrections run in streaming elementwise kernels so that every NTT of
 // the pipeline stays a plain register-resident transform.
 // By linearity this equals relinearise (ModDown) followed by rescale.
-static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B) {
+static int plan_hmult(Plan &P, const u64 *const *rk, const ckks_ct *a, const ckks_ct *b, ckks_ct *out, u32 B) {
     const ckks_ctx *c = P.c;
     const u32 N = c->N, k = c->n_p, A = c->alpha;
     const bool fuse = c->tb.fuse_tail != 0;
@@ -2052,6 +2104,7 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
         {
             IpCt y;
             y.level = l;
+            y.key = rk[x];
             y.ext = ext;
             y.acc = acc;
             for (u32 t = 0; t < L; t++) {
@@ -2116,7 +2169,7 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
     }
     P.add(1, I_MUL, mul);
     add_modup(P, modup);
-    add_ip(P, ipc, rk);
+    add_ip(P, ipc);
     P.add(1, I_SCALE, scale);
     P.add(2, 0, tt);
     P.add(0, relin_op(c, fuse), fin);
@@ -2124,11 +2177,13 @@ static int plan_hmult(Plan &P, const u64 *rk, const ckks_ct *a, const ckks_ct *b
     return CKKS_OK;
 }
 
-extern "C" int ckks_hmult_relin_rescale(const ckks_ctx *c, const uint64_t *rk, const ckks_ct *a, const ckks_ct *b,
-                                        ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+extern "C" int ckks_hmult_relin_rescale(const ckks_ctx *c, const uint64_t *const *rk, const ckks_ct *a,
+                                        const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws, size_t ws_bytes,
+                                        void *stream) {
     CK(check_ctx(c));
     if (!rk || !a || !b || !out) return fail(CKKS_EINVAL, "hmult: null argument");
     for (u32 x = 0; x < B; x++) {
+        if (!rk[x]) return fail(CKKS_ENOKEY, "hmult: null relinearisation key for item %u", x);
         CK(check_ct(c, a[x], "hmult a"));
         CK(check_ct(c, b[x], "hmult b"));
         if (a[x].n_poly != 2 || b[x].n_poly != 2) return fail(CKKS_EINVAL, "hmult: inputs must have 2 polys");

@@ -76,15 +76,15 @@ class VisionModel:
     def _csr(self, rows, bias):
         ws = self.w_scale
         row_ptr = np.zeros(len(rows) + 1, dtype=np.int64)
-        cols, w = [], []
+        cols, vals = [], []
         for j, r in enumerate(rows):
             for c, x in r:
                 cols.append(c)
-                v = x * ws
-                w.append(int(np.sign(v) * np.floor(abs(v) + 0.5)))
+                vals.append(x)
             row_ptr[j + 1] = len(cols)
         n_in = max(cols) + 1
-        return dict(row_ptr=row_ptr, col=np.array(cols, dtype=np.int64), w=np.array(w, dtype=np.int64),
+        w = nat.ckks_encode_scalars(self.ctx.h, vals, ws)  # integer weights round(x * scale), in C
+        return dict(row_ptr=row_ptr, col=np.array(cols, dtype=np.int64), w=w,
                     n_in=n_in, n_out=len(rows), bias=np.asarray(bias, dtype=np.float64))
 
     def block(self, layer, R):

@@ -225,3 +225,29 @@ def test_serialize_host_checks():
     finally:
         nat.ckks_ctx_destroy(h)
         nat.ckks_ctx_destroy(other)
+
+
+def test_scalar_encoding_in_c_matches_oracle_rounding():
+    # constants round half away from zero (c * scale), reduced per limb;
+    # the expected integers come from the oracle's rounding
+    from paper_2110_13638_amd import _native as nat
+    import oracle as O
+    from oracle import nets as ON
+    primes = O.find_primes(12, [60, 40, 40, 60])
+    h = nat.ckks_ctx_create(12, primes[:3], primes[3:], 3)
+    try:
+        scale = 2.0 ** 40
+        vals = [0.0, -0.3, 0.7, 1.5 / scale, -1.5 / scale, -2.5 / scale, 2.5 / scale, 1234.5678, -4.0e6]
+        got = nat.ckks_encode_scalars(h, vals, scale)
+        want = [ON.round_half_away(v * scale) for v in vals]
+        assert [int(x) for x in got] == want
+        for v, w in zip(vals, want):
+            res = nat.ckks_encode_scalar(h, v, scale, 2)
+            assert [int(x) for x in res] == [w % q for q in primes[:3]]
+        with pytest.raises(nat.CkksError):
+            nat.ckks_encode_scalars(h, [2.0 ** 23], scale)  # 2^63 >= 2^62
+        with pytest.raises(nat.CkksError) as e:
+            nat.ckks_encode_scalar(h, 1.0, scale, 3)  # beyond the chain
+        assert e.value.code == nat.CKKS_ELEVEL
+    finally:
+        nat.ckks_ctx_destroy(h)

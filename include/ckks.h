@@ -326,6 +326,25 @@ int ckks_rotate(const ckks_ctx *ctx, const uint64_t *const *gk, const uint32_t *
 int ckks_hmult_relin_rescale(const ckks_ctx *ctx, const uint64_t *const *rk, const ckks_ct *a,
                              const ckks_ct *b, ckks_ct *out, uint32_t B, void *ws,
                              size_t ws_bytes, void *stream);
+/* The same call without a caller workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * hosts that forbid hipMalloc). Scratch limbs and work-item tables go to a
+ * fixed device array of CKKS_NOALLOC_SCRATCH_BYTES inside the library (one
+ * per GPU, held until the process ends; its address is looked up on the
+ * first call on each device). The call allocates nothing: no device or
+ * pinned memory, no events (launch profiling is skipped); work-item tables
+ * are copied from pageable host memory. Inputs, outputs and keys are
+ * caller-owned device buffers as in ckks_hmult_relin_rescale, whose kernels
+ * it runs, with bit-identical results. CKKS_ENOMEM (nothing launched) when
+ * the batch's scratch (ckks_workspace_bytes(ctx, CKKS_OP_HMULT, B, levels))
+ * exceeds the array (80 MiB: two pairs at N = 2^15 with 16 + 2 primes at
+ * the top level, about 39 MiB each). Every call on one GPU shares the array
+ * and overwrites what the previous call left there; calls that overlap on
+ * one GPU (concurrent streams or host threads) race and must be
+ * serialised by the caller. */
+#define CKKS_NOALLOC_SCRATCH_BYTES (80u << 20)
+int ckks_hmult_relin_rescale_noalloc(const ckks_ctx *ctx, const uint64_t *const *rk, const ckks_ct *a,
+                                     const ckks_ct *b, ckks_ct *out, uint32_t B, void *stream);
 /* Encrypted linear layer with integer weights (conv and dense of the
  * paper's Sections 4.2.2-4.2.3, weights encoded as constant polynomials):
  * out[j] = sum_i W[j * n_in + i] * in[i]  for j < n_out, W device int64.

@@ -25,6 +25,7 @@ CKKS_OBJ_CT, CKKS_OBJ_PT, CKKS_OBJ_KEY = 0, 1, 2
 CKKS_TUNE_NTT_WIDE, CKKS_TUNE_EW_LOG, CKKS_TUNE_XCD_REMAP, CKKS_TUNE_FUSE_TAIL, CKKS_TUNE_IP_CTS = 0, 1, 2, 3, 4
 CKKS_TUNE_LIN_MFMA = 5
 CKKS_TUNE_NTT_FP = 6
+CKKS_NOALLOC_SCRATCH_BYTES = 80 << 20
 
 
 class CkksError(RuntimeError):
@@ -122,6 +123,8 @@ _SIGS = {
     "ckks_rotate": (ctypes.c_int, [_vp, _P(_vp), _P(_u32), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_hmult_relin_rescale": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp,
                                                 _sz, _vp]),
+    "ckks_hmult_relin_rescale_noalloc": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32,
+                                                        _vp]),
     "ckks_encode_scalars": (ctypes.c_int, [_vp, _P(_dbl), _sz, _dbl, _P(ctypes.c_int64)]),
     "ckks_encode_scalar": (ctypes.c_int, [_vp, _dbl, _dbl, _u32, _P(_u64)]),
     "ckks_linear": (ctypes.c_int, [_vp, _P(ckks_ct), _u32, _vp, _dbl, _P(ckks_ct), _u32, _vp, _sz, _vp]),
@@ -369,6 +372,11 @@ def ckks_hmult_relin_rescale(h, rk, a, b, out, ws, ws_bytes, stream=None):
     """rk: one relinearisation key pointer for every item, or one per item"""
     _call("ckks_hmult_relin_rescale", h, _arr(_vp, _per_item(rk, len(out))), a, b, out, len(out), ws, ws_bytes,
           stream)
+
+
+def ckks_hmult_relin_rescale_noalloc(h, rk, a, b, out, stream=None):
+    """The same call with the library's fixed scratch array instead of a workspace"""
+    _call("ckks_hmult_relin_rescale_noalloc", h, _arr(_vp, _per_item(rk, len(out))), a, b, out, len(out), stream)
 
 
 def ckks_encode_scalars(h, values, scale):

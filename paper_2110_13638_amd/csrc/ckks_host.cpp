@@ -809,6 +809,17 @@ static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Host-to-device copy of launch data (descriptors, pointer tables, weight
 // images). While recording, the bytes go to the recording arena, where they
 // stay for replays, and *where receives that address instead of dst.
+// Calls that must not allocate (ckks_hmult_relin_rescale_noalloc) set this
+// flag for their duration on the calling thread: uploads then skip the
+// pinned staging ring (created on first use) and its events and copy
+// straight from the host descriptor buffer, and no profiling events are made.
+static thread_local bool g_no_alloc = false;
+}  // namespace
+namespace ckks {
+void set_no_alloc(bool on) { g_no_alloc = on; }
+}  // namespace ckks
+namespace {
+
 int upload(const ckks_ctx *c, uint8_t *dst, const void *src, size_t bytes, hipStream_t s, uint8_t **where) {
     if (c->rec) {
         Recorder &r = *c->rec;
@@ -819,6 +830,11 @@ int upload(const ckks_ctx *c, uint8_t *dst, const void *src, size_t bytes, hipSt
     }
     *where = dst;
     if (!bytes) return CKKS_OK;
+    if (g_no_alloc) {
+        // pageable copy (synchronous with respect to the host)
+        HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+        return CKKS_OK;
+    }
     ckks_ctx *cm = const_cast<ckks_ctx *>(c);
     if (!cm->stage) {
         Staging *st = new Staging();
@@ -975,7 +991,8 @@ struct Plan {
             const uint8_t *p = dbase + L.off;
             hipError_t e = hipSuccess;
             ProfRec rec;
-            if (g_prof_on) {
+            const bool prof = g_prof_on && !g_no_alloc;
+            if (prof) {
                 rec.name = launch_name(L.kind, L.op, c->log_n);
                 rec.items = (u32)L.n;
                 HIP_TRY(hipEventCreate(&rec.e0));
@@ -996,7 +1013,7 @@ struct Plan {
                 return hipErrorInvalidValue;
             });
             if (e != hipSuccess) return fail(CKKS_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
-            if (g_prof_on) {
+            if (prof) {
                 HIP_TRY(hipEventRecord(rec.e1, s));
                 g_prof.push_back(rec);
             }

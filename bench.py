@@ -152,30 +152,53 @@ def kernel_model(name, items, ctx, level):
     return items * 2 * lb, 0.0
 
 
+# 128-bit security bound on log2(Q P) for ternary secrets (HE standard, classical)
+SEC128_BITS = {10: 27, 11: 54, 12: 109, 13: 218, 14: 438, 15: 881, 16: 1772}
+
+
+def security_label(log_n, primes):
+    bits = sum(int(x).bit_length() for x in primes)
+    ok = bits <= SEC128_BITS.get(log_n, 0)
+    return {"modulus_bits": bits, "bound_128": SEC128_BITS.get(log_n), "secure_128": ok,
+            "label": "128-bit secure" if ok else "below 128-bit security (throughput configuration only)"}
+
+
+N_CLIENTS = 8
+
+
 def serve_leg(args, dev, log, tuning=None):
-    """Serving mix: half HMult pairs (rings 2^13..2^15, levels 3..15), half
-    vision inferences (rings 2^13..2^14, levels 5..7), keys resident,
-    admission by HBM bytes. (1) saturation: a burst of requests served by
-    continuous batching and by the plain one-op-per-launch path, same
-    requests, results compared; (2) load sweep: Poisson arrivals at several
-    rates, latency percentiles from arrival to result."""
+    """Serving mix: half HMult pairs (rings 2^13..2^15, 16 x 50-bit + 2 x
+    60-bit primes, levels 3..15), half vision inferences (rings 2^13..2^15,
+    [60, 40 x 7 | 60], levels 5..7), requests from 8 clients whose key sets
+    stay resident in HBM and count against admission. (1) saturation: a
+    burst served by continuous batching and by the plain one-op-per-launch
+    path, same requests, results compared; (2) load sweep: Poisson arrivals
+    at fractions of the burst's throughput, a warm-up of requests excluded
+    from the statistics, latency percentiles from arrival to observed
+    completion."""
     import numpy as np
     import synthetic as S
     from paper_2110_13638_amd import _native as nat
     from paper_2110_13638_amd import ckks, serve
 
-    ctxs, vision = {}, {}
+    ctxs, vision, keys, security = {}, {}, {}, {}
+    _, P = S.vision_inputs(n_images=1)
     for log_n in (13, 14, 15):
         pr = nat.ckks_find_primes(log_n, Q_BITS + P_BITS)
-        ctxs[("hmult", log_n)] = ckks.Context(log_n, pr[:16], pr[16:], DNUM, device=dev).keygen(7)
-        ctxs[("hmult", log_n)].set_tuning(**(tuning or {}))
-    _, P = S.vision_inputs(n_images=1)
-    for log_n in (13, 14):
+        c = ckks.Context(log_n, pr[:16], pr[16:], DNUM, device=dev).keygen(7)
+        c.set_tuning(**(tuning or {}))
+        ctxs[("hmult", log_n)] = c
+        security["hmult/N=2^%d" % log_n] = security_label(log_n, pr)
         pr = nat.ckks_find_primes(log_n, [60] + [40] * 7 + [60])
         c = ckks.Context(log_n, pr[:8], pr[8:], 8, device=dev).keygen(8)
         c.set_tuning(**(tuning or {}))
         ctxs[("vision", log_n)] = c
         vision[log_n] = serve.VisionModel(c, P)
+        security["vision/N=2^%d" % log_n] = security_label(log_n, pr)
+    for (kind, log_n), c in ctxs.items():
+        for client in range(N_CLIENTS):
+            keys[(kind, log_n, client)] = c.client_keys(1000 + 97 * client + 7 * log_n + (kind == "vision"))
+    torch_sync()
 
     def make(seed, n, rate, lazy=False):
         reqs = []
@@ -183,10 +206,11 @@ def serve_leg(args, dev, log, tuning=None):
         r2 = np.random.default_rng(seed)
         for rid in range(n):
             t += r2.exponential(1.0 / rate)
+            client = int(r2.integers(N_CLIENTS))
             if r2.random() < 0.5:
                 kind, log_n, level, n_ct = "hmult", int(r2.choice([13, 14, 15])), int(r2.integers(3, 16)), 2
             else:
-                kind, log_n, level, n_ct = "vision", int(r2.choice([13, 14])), int(r2.integers(5, 8)), 784
+                kind, log_n, level, n_ct = "vision", int(r2.choice([13, 14, 15])), int(r2.integers(5, 8)), 784
             ctx = ctxs[(kind, log_n)]
 
             def inputs(ctx=ctx, rid=rid, level=level, n_ct=n_ct):
@@ -196,26 +220,28 @@ def serve_leg(args, dev, log, tuning=None):
 
             # long runs create each request's input at admission (HBM holds
             # only what is in flight)
-            reqs.append(serve.Request(rid, kind, log_n, t, inputs if lazy else inputs(), level=level))
+            reqs.append(serve.Request(rid, kind, log_n, t, inputs if lazy else inputs(), level=level,
+                                      client=client))
         return reqs
 
     def engine():
-        return serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30)
+        return serve.Engine(ctxs, vision, hbm_cap=args.serve_cap << 30, client_keys=keys)
 
-    def summary(done):
+    def summary(done, skip=0):
+        done = sorted(done, key=lambda r: r.rid)[skip:]
         span = max(r.finish for r in done) - min(r.arrival for r in done)
         st = serve.latency_stats(done)
         n_vis = sum(r.kind == "vision" for r in done)
         return {"requests": len(done), "vision_requests": n_vis, "requests_per_s": len(done) / span,
                 "encrypted_infer_per_s": n_vis / span, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}
 
-    engine().run(make(99, 8, 1e4))  # warm-up of every kind and ring
+    engine().run(make(99, 12, 1e4))  # warm-up of every kind and ring
     torch_sync()
     # (1) saturation, batched vs plain on the same requests
     n = args.serve_requests
     done = engine().run(make(3, n, 1e4))
     sat = {"batched": summary(done)}
-    plain = serve.run_plain(ctxs, vision, make(3, n, 1e4))
+    plain = serve.run_plain(ctxs, vision, make(3, n, 1e4), client_keys=keys)
     sat["plain"] = summary(plain)
     sat["batched_over_plain"] = sat["batched"]["requests_per_s"] / sat["plain"]["requests_per_s"]
     sat["results_equal_plain"] = all(
@@ -224,15 +250,26 @@ def serve_leg(args, dev, log, tuning=None):
     log("serving burst of %d: batched %.1f req/s (%.2f infer/s), plain %.1f req/s: %.1fx; identical results: %s" %
         (n, sat["batched"]["requests_per_s"], sat["batched"]["encrypted_infer_per_s"],
          sat["plain"]["requests_per_s"], sat["batched_over_plain"], sat["results_equal_plain"]))
-    # (2) load sweep, batched
+    del done, plain
+    # (2) load sweep, batched: rates as fractions of the burst throughput;
+    # each rate serves warm-up + measured requests, the measured count cut to
+    # what arrives within --serve-seconds
+    mu = sat["batched"]["requests_per_s"]
     load = []
-    for rate in args.serve_rates:
-        r = summary(engine().run(make(10 + int(rate), args.serve_sweep_requests, rate, lazy=True)))
-        r["arrival_rate_per_s"] = rate
+    for frac in args.serve_load:
+        rate = frac * mu
+        n_meas = int(min(args.serve_sweep_requests, rate * args.serve_seconds))
+        n_warm = args.serve_warmup
+        r = summary(engine().run(make(10 + int(100 * frac), n_warm + n_meas, rate, lazy=True)), skip=n_warm)
+        r.update({"arrival_rate_per_s": rate, "fraction_of_burst_throughput": frac, "warmup_requests": n_warm,
+                  "request_cap": "%d requests (limit %d, or what arrives in %g s)" %
+                                 (n_meas, args.serve_sweep_requests, args.serve_seconds)})
         load.append(r)
-        log("  Poisson %5.0f req/s: served %.1f req/s, p50 %.1f ms, p99 %.1f ms" %
-            (rate, r["requests_per_s"], r["p50_ms"], r["p99_ms"]))
-    return {"hbm_cap_GiB": args.serve_cap, "saturation": sat, "load": load}
+        log("  Poisson %5.1f req/s (%.2f of burst): %d measured, served %.1f req/s, p50 %.1f ms, p99 %.1f ms" %
+            (rate, frac, n_meas, r["requests_per_s"], r["p50_ms"], r["p99_ms"]))
+    return {"hbm_cap_GiB": args.serve_cap, "clients": N_CLIENTS,
+            "resident_key_GiB": engine().key_bytes / 2 ** 30, "rings": security,
+            "saturation": sat, "load": load}
 
 
 def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
@@ -364,6 +401,7 @@ def nets_leg(args, dev, log, tuning=None):
     for name, items, ms in nat.ckks_profile_collect():
         fam[name] = fam.get(name, 0.0) + ms
     out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
+                     "security": security_label(14, pr)["label"],
                      "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
                      "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])}}
     log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
@@ -396,8 +434,11 @@ def nets_leg(args, dev, log, tuning=None):
     from paper_2110_13638_amd.graph import Graph
     rows, _ = nets.conv_rows(P["conv_w"], 28)
     per = len(rows) // P["conv_w"].shape[0]
+    # rows grouped by shared column list (the 5 filters of one position), as
+    # the vision network lowers its conv
+    rows, order = nets.reorder_conv_rows(rows, P["conv_w"].shape[0])
     g1 = Graph(ctx)
-    g1.chain(g1.input(784, 7, scale), g1.linear(rows, scale, [P["conv_b"][j // per] for j in range(len(rows))]),
+    g1.chain(g1.input(784, 7, scale), g1.linear(rows, scale, [P["conv_b"][j // per] for j in order]),
              g1.square(), g1.output())
     g1.plan()
     g1.run(cts)
@@ -471,9 +512,137 @@ def nets_leg(args, dev, log, tuning=None):
     dt = (time.perf_counter() - t0) / args.net_runs
     out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys, "
                               "hoisted rotations" % (len(cts), len(ctx.gk)),
+                    "security": security_label(14, pr)["label"],
                     "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
     log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
     return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads():
+    """Threads the CPU legs use: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when the host sets it (the share of a shared GPU host)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def _timed_pool(fn, args_list, threads, seconds):
+    """Run fn over args_list on ``threads`` threads, repeating the list until
+    ``seconds`` have passed (at least once); returns (calls, elapsed s)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    done = 0
+    with ThreadPoolExecutor(threads) as ex:
+        while time.perf_counter() - t0 < seconds or done == 0:
+            list(ex.map(fn, args_list))
+            done += len(args_list)
+    return done, time.perf_counter() - t0
+
+
+def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
+    """The oracle (plain C) timed on the host cores: the headline workload on
+    every available thread and on one, the batched NTT microbench, the
+    vision network's encrypted inference (per-op sample) and the FP64
+    plaintext networks (the paper's plaintext-versus-ciphertext comparison).
+    The oracle is compiled -O3 -march=native for this host (same source,
+    same arithmetic) when gcc is available."""
+    import tempfile
+    import numpy as np
+    import oracle as O
+    import synthetic as S
+    from oracle import build as OB
+    from oracle import nets as ON
+    from oracle import plainnet as PN
+
+    try:
+        O.use_library(OB.build_timing_copy(tempfile.mkdtemp(prefix="oracle_timing_")))
+        flags = "gcc -O3 -march=native"
+    except Exception as e:  # no compiler: the prebuilt -O2 copy
+        flags = "gcc -O2 (prebuilt; -march=native build failed: %s)" % type(e).__name__
+    threads = host_threads()
+    secs = args.cpu_seconds
+    orc = O.Oracle(LOG_N, q, p, DNUM)
+    _, sn = orc.keygen_secret(1)
+    rk_o = orc.keygen_relin(sn, 3)
+    host = [(A[i].residues().copy(), Bc[i].residues().copy()) for i in range(threads)]
+
+    def hm(ab):
+        return orc.mul_relin_rescale(ab[0], ab[1], rk_o)
+
+    n_all, el_all = _timed_pool(hm, host, threads, secs)
+    n_one, el_one = _timed_pool(hm, host[:1], 1, secs / 3)
+    want = hm(host[0])
+    cpu = {"value": n_all / el_all, "unit": "HMult+relin+rescale/s", "cores": threads, "kind": "oracle",
+           "sample": "%d HMult+relin+rescale at N=2^15, 16 limbs, dnum=4 on %d threads (%.1f s)"
+                     % (n_all, threads, el_all),
+           "single_thread": n_one / el_one, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "compiler": flags, "gpu_matches_oracle": bool(np.array_equal(outs[0].residues(), want))}
+    log("oracle: %.3f HMult/s on %d threads (%.3f on one), %s; GPU ciphertext == oracle: %s" %
+        (cpu["value"], threads, cpu["single_thread"], cpu["cpu_model"], cpu["gpu_matches_oracle"]))
+    extra = {}
+    # batched NTT (d1): forward transforms of the microbench's limbs
+    n_limbs = ntt["limbs"] if ntt else 5084
+    lim = [(A[k % len(A)].residues()[0, j].copy(), j) for k in range(threads) for j in range(4)]
+    n_t, el_t = _timed_pool(lambda x: orc.ntt(x[0], x[1]), lim, threads, secs / 4)
+    n_t1, el_t1 = _timed_pool(lambda x: orc.ntt(x[0], x[1]), lim[:4], 1, secs / 8)
+    extra["ntt"] = {"limb_ntt_per_s": n_t / el_t, "limb_ntt_per_s_single_thread": n_t1 / el_t1,
+                    "fwd_ms_for_microbench": 1e3 * n_limbs / (n_t / el_t),
+                    "sample": "%d forward transforms of 2^15-residue limbs on %d threads" % (n_t, threads)}
+    # vision network at N = 2^14, [60, 40 x 7 | 60]: every op kind of one
+    # inference timed on a sample of its rows / ciphertexts, scaled by the
+    # op counts of the whole inference (8192 images)
+    vq = O.find_primes(14, [60] + [40] * 7 + [60])
+    vo = O.Oracle(14, vq[:8], vq[8:], 8)
+    vkeys = ON.Keys(vo, 21)
+    _, P = S.vision_inputs(n_images=1)
+    conv_rows, _ = PN.vision_conv_rows(P["conv_w"])
+    scale = 2.0 ** 40
+    layers = [("conv", 7, conv_rows, 784), ("dense1", 5, [[(i, w) for i, w in enumerate(r)] for r in P["w1"]], 845),
+              ("dense2", 3, [[(i, w) for i, w in enumerate(r)] for r in P["w2"]], 100)]
+    est, total = {}, 0.0
+    for name, level, rows, n_in in layers:
+        cts = [S.residues(50 + i, vq[: level + 1], vo.N, 2) for i in range(min(n_in, 32))]
+        pool_rows = [[(i % len(cts), w) for i, w in r] for r in rows[:threads]]
+        n_r, el_r = _timed_pool(lambda r: ON.linear(vo, cts, scale, [r], scale, [0.1]), pool_rows, threads, 0.0)
+        est[name] = {"rows": len(rows), "thread_s_per_row": el_r * threads / n_r}
+        total += est[name]["thread_s_per_row"] * len(rows)
+    for name, level, n_sq in (("square1", 6, 845), ("square2", 4, 100)):
+        xs = [S.residues(70 + i, vq[: level + 1], vo.N, 2) for i in range(threads)]
+        n_s, el_s = _timed_pool(lambda x: ON.square(vo, vkeys, x, scale), xs, threads, 0.0)
+        est[name] = {"ciphertexts": n_sq, "thread_s_per_ct": el_s * threads / n_s}
+        total += est[name]["thread_s_per_ct"] * n_sq
+    extra["vision"] = {"s_per_inference": total / threads, "encrypted_infer_per_s": threads / total,
+                       "sample": "every op kind of one 8192-image inference timed on a sample (one row or "
+                                 "ciphertext per thread), scaled by its count", "ops": est}
+    # FP64 plaintext networks as written (the paper's comparison)
+    xv, Pv = S.vision_inputs()
+    t0 = time.perf_counter()
+    PN.vision_math(xv, Pv)
+    t_v = time.perf_counter() - t0
+    xy, wsy, bsy = S.yield_inputs()
+    t0 = time.perf_counter()
+    PN.yield_math(xy, wsy, bsy)
+    t_y = time.perf_counter() - t0
+    extra["plaintext_fp64"] = {"vision_8192_images_ms": 1e3 * t_v, "yield_4096_windows_ms": 1e3 * t_y,
+                               "note": "numpy FP64, unencrypted, same networks and batch sizes"}
+    log("oracle NTT %.0f limb-NTT/s (%d threads); vision inference ~%.0f s on %d threads; "
+        "FP64 plaintext vision %.1f ms, yield %.1f ms" %
+        (extra["ntt"]["limb_ntt_per_s"], threads, total / threads, threads, 1e3 * t_v, 1e3 * t_y))
+    cpu["extra"] = extra
+    return cpu
 
 
 def torch_sync():
@@ -488,13 +657,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain-pairs", type=int, default=32)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32, help="requests in the saturation burst")
-    ap.add_argument("--serve-rates", type=float, nargs="*", default=[25.0, 50.0, 100.0, 200.0],
-                    help="Poisson arrival rates (requests/s) of the load sweep")
-    ap.add_argument("--serve-sweep-requests", type=int, default=64)
-    ap.add_argument("--serve-cap", type=int, default=96, help="HBM admission cap in GiB")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests in the saturation burst")
+    ap.add_argument("--serve-load", type=float, nargs="*", default=[0.3, 0.6, 0.9],
+                    help="Poisson arrival rates of the load sweep, as fractions of the burst's throughput")
+    ap.add_argument("--serve-sweep-requests", type=int, default=2000, help="measured requests per rate (at most)")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up requests per rate (not measured)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="cap on the measured requests of a rate: those that arrive within this time")
+    ap.add_argument("--serve-cap", type=int, default=160, help="HBM admission cap in GiB")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-nets", action="store_true", help="skip the full-size network inferences")
     ap.add_argument("--net-runs", type=int, default=3)
@@ -561,19 +733,27 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # headline: K steps with nothing between the launches
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+    log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
+    # the same K steps again with every launch bracketed by HIP events on its
+    # launch stream: per-kernel durations for the breakdown and the roofline
     nat.ckks_profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    prof_ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
     nat.ckks_profile_enable(False)
     recs = nat.ckks_profile_collect()
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = B * args.steps / elapsed
-    log("batched: %.2f ms/step, %.1f HMult+relin+rescale/s" % (ms_per_step, value))
 
     # per-kernel-family breakdown. A family's NTT work items are split by
     # prime class into one launch per arithmetic engine (FP64 for primes
@@ -602,7 +782,9 @@ def main():
                 "unit": prim["unit"], "frac": prim["frac"], "traffic": traffic,
                 "other": dict(other, bound="hbm" if bound == "alu" else "alu"),
                 "alg_bytes_per_step": alg_bytes, "alg_ops_per_step": alg_ops, "ms_per_step": d["ms_per_step"],
-                "launches_per_step": d["launches_per_step"]}
+                "launches_per_step": d["launches_per_step"],
+                "timed_region": "%d steps with per-launch HIP events (%.3f ms per step; the headline steps run "
+                                "without events)" % (args.steps, prof_ms_per_step)}
     log("dominant kernel family %s: %.3f ms/step in %g launches, %s %.1f %s (%.1f%% of peak); %s %.1f%%" %
         (dom, d["ms_per_step"], d["launches_per_step"], bound, prim["achieved"], prim["unit"], 100 * prim["frac"],
          other["unit"], 100 * other["frac"]))
@@ -612,30 +794,7 @@ def main():
         ragged_rate, plain_rate, same, ntt = extra_legs(args, ctx, res, A, Bc, outs, B, top, value)
 
     # ---- oracle on the host cores, bounded sample of the same workload
-    cpu = None
-    if not args.no_cpu:
-        import oracle as O
-        from concurrent.futures import ThreadPoolExecutor
-        orc = O.Oracle(LOG_N, q, p, DNUM)
-        _, sn = orc.keygen_secret(1)
-        rk_o = orc.keygen_relin(sn, 3)
-        cores = min(16, os.cpu_count() or 1)
-        host = [(A[i].residues().copy(), Bc[i].residues().copy()) for i in range(cores)]
-        t0 = time.perf_counter()
-        done = 0
-        with ThreadPoolExecutor(cores) as ex:
-            while time.perf_counter() - t0 < args.cpu_seconds or done == 0:
-                list(ex.map(lambda ab: orc.mul_relin_rescale(ab[0], ab[1], rk_o), host))
-                done += len(host)
-        cpu_el = time.perf_counter() - t0
-        want = orc.mul_relin_rescale(host[0][0], host[0][1], rk_o)
-        got = outs[0].residues()
-        cpu = {"value": done / cpu_el, "unit": "HMult+relin+rescale/s", "cores": cores, "kind": "oracle",
-               "sample": "%d HMult+relin+rescale at N=2^15, 16 limbs, dnum=4 on %d threads (%.1f s)"
-                         % (done, cores, cpu_el),
-               "gpu_matches_oracle": bool(np.array_equal(got, want))}
-        log("oracle: %.3f HMult/s on %d threads; GPU ciphertext == oracle: %s" %
-            (cpu["value"], cores, cpu["gpu_matches_oracle"]))
+    cpu = None if args.no_cpu else cpu_leg(args, q, p, A, Bc, outs, ntt, log)
 
     # the other rings take the launch shapes picked for the headline ring
     # (the 32-residue NTT variant does not exist at N = 2^15)
@@ -650,7 +809,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "batched HMult+relin+rescale, N=2^15, 16 x 50-bit data primes + 2 x 60-bit "
                                "special primes, dnum=4, %d ciphertext pairs at 16 limbs per launch" % B,
-                   "log_n": LOG_N, "limbs": 16, "special_primes": 2, "dnum": DNUM, "batch": B},
+                   "log_n": LOG_N, "limbs": 16, "special_primes": 2, "dnum": DNUM, "batch": B,
+                   "security": security_label(LOG_N, primes)["label"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": {"ragged_4_16_hmult_per_s": ragged_rate and round(ragged_rate, 2),

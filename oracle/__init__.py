@@ -30,12 +30,21 @@ _U32P = ctypes.POINTER(ctypes.c_uint32)
 _lib = None
 
 
-def lib():
+def use_library(path):
+    """Bind the oracle to another build of ckks_oracle.c (the benchmark's
+    -O3 -march=native timing copy); call before creating any Oracle."""
+    global _lib
+    _lib = None
+    return lib(path)
+
+
+def lib(path=None):
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
-            _build.build()
+        if path is None:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
         L = ctypes.CDLL(path)
         u64, u32, i64, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_void_p
         sig = {

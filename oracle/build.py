@@ -23,5 +23,17 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+def build_timing_copy(out_dir: str) -> str:
+    """The same source compiled with -O3 -march=native for the host it runs
+    on (the CPU-baseline timing of the benchmark); the arithmetic is the
+    same code. Returns the path of the shared object in ``out_dir``."""
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "liboracle_native%d.so" % os.getpid())
+    cmd = ["gcc", "-O3", "-march=native", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-Wno-unused-function", SRC, "-o", path]
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+    return path
+
+
 if __name__ == "__main__":
     print(build(force="--if-stale" not in sys.argv))

@@ -11,6 +11,12 @@ a queue). Each request's result is computed ciphertext by ciphertext by the
 same kernels whatever batch it lands in, so it is bit-identical alone and in
 the mix.
 
+Each request belongs to a client, whose evaluation keys (made from that
+client's own secret, the threat model of Section 2.3) stay resident in HBM
+for the whole run and are counted against the admission cap; requests of
+different clients share launches through the per-item key arrays of the
+batched key-switching calls.
+
 Programs:
   * ``hmult``: one fused HMult + relinearise + rescale of a ciphertext pair;
   * ``vision``: the slot-batched vision network (conv -> x^2 -> dense ->
@@ -18,10 +24,19 @@ Programs:
     requests in a group run as one block-diagonal sparse layer, squares as
     one fused HMult batch.
 
+Failure handling: a request can be cancelled (``Engine.cancel``) or carry
+a timeout (seconds after arrival); either ends it at the next tick, waiting
+or in flight, and releases its HBM share. A launch that fails for a group is
+retried request by request, so only the request that fails is dropped (with
+its error) and the others continue unchanged. ``CKKS_FAULT_INJECT`` (a comma
+separated list of request ids) makes every launch that carries one of those
+requests fail, to exercise that path.
+
 The plain path (``run_plain``) serves the same requests first-in first-out,
 one operation per launch (B = 1, unfused multiply / relinearize / rescale),
 on the same kernels.
 """
+import os
 import time
 from dataclasses import dataclass, field
 
@@ -41,6 +56,8 @@ class Request:
     inputs: object       # device Ciphertexts (owned by the request), or a callable
                          # that creates them when the request is admitted
     level: int = -1      # input level (needed before a lazy request is admitted)
+    client: int = 0      # whose keys relinearise this request's products
+    timeout: float = None  # seconds after arrival by which it must finish, or None
     stage: int = 0
     state: list = field(default_factory=list)
     footprint: int = 0
@@ -48,6 +65,8 @@ class Request:
     done_event: object = None
     finish: float = -1.0
     result: list = None
+    status: str = "pending"  # done | cancelled | timeout | error
+    error: str = None
 
 
 class VisionModel:
@@ -97,14 +116,42 @@ class VisionModel:
         return row_ptr, col, w, np.tile(L["bias"], R)
 
 
+def key_set_bytes(keys):
+    """device bytes of one client's server-resident keys (public,
+    relinearisation, Galois; the secret stays with the client)"""
+    t = [keys.pk, keys.rk] + list(keys.gk.values())
+    return sum(x.numel() * x.element_size() for x in t if x is not None)
+
+
+def fault_inject_ids(spec=None):
+    """request ids named by CKKS_FAULT_INJECT (or ``spec``): "3,17" -> {3, 17}"""
+    spec = os.environ.get("CKKS_FAULT_INJECT", "") if spec is None else spec
+    return {int(x) for x in str(spec).replace(" ", "").split(",") if x}
+
+
 class Engine:
-    def __init__(self, contexts, vision=None, hbm_cap=64 << 30, square_chunk=1024):
-        self.ctx = contexts          # (kind, log_n) -> Context with resident keys
+    def __init__(self, contexts, vision=None, hbm_cap=64 << 30, square_chunk=1024, client_keys=None,
+                 event_factory=None, sync=None, fault_inject=None):
+        self.ctx = contexts          # (kind, log_n) -> Context
         self.vision = vision or {}   # log_n -> VisionModel
+        # (kind, log_n, client) -> KeySet resident on the device; without it
+        # every request uses its context's own key set
+        self.keys = client_keys or {}
         self.cap = hbm_cap
         self.square_chunk = square_chunk
-        self.used = 0
+        # resident keys occupy HBM for the whole run: admission counts them
+        self.key_bytes = sum(key_set_bytes(k) for k in self.keys.values())
+        self.used = self.key_bytes
         self.waiting, self.active, self.done = [], [], []
+        self.failed = []             # cancelled, timed out or failed requests
+        self._cancel = set()
+        self._event = event_factory or torch.cuda.Event
+        self._sync = sync or torch.cuda.synchronize
+        self.fault = fault_inject_ids(fault_inject)
+
+    def _rk(self, r):
+        k = self.keys.get((r.kind, r.log_n, r.client))
+        return k.rk if k is not None else self.ctx[(r.kind, r.log_n)].rk
 
     # --- memory accounting ---------------------------------------------------
     def footprint(self, req):
@@ -123,9 +170,49 @@ class Engine:
     # --- lifecycle -------------------------------------------------------------
     def submit(self, req):
         req.footprint = self.footprint(req)
-        if req.footprint > self.cap:
-            raise nat.CkksError(nat.CKKS_ENOMEM, "request %d needs %d bytes over the cap" % (req.rid, req.footprint))
+        if req.footprint > self.cap - self.key_bytes:
+            raise nat.CkksError(nat.CKKS_ENOMEM, "request %d needs %d bytes; the cap leaves %d beside the "
+                                "resident keys" % (req.rid, req.footprint, self.cap - self.key_bytes))
         self.waiting.append(req)
+
+    def cancel(self, rid):
+        """end request ``rid`` at the next tick (waiting or in flight)"""
+        self._cancel.add(rid)
+
+    def _drop(self, r, status, stamp, msg=None, active=False):
+        r.status, r.error = status, msg
+        r.finish = stamp()
+        if active:
+            self.used -= r.footprint
+        # its buffers are released; kernels already queued on the stream still
+        # run before the allocator hands the memory to later work
+        r.inputs = r.state = r.result = None
+        self.failed.append(r)
+
+    def _expire(self, now, stamp):
+        def why(r):
+            if r.rid in self._cancel:
+                return "cancelled"
+            if r.timeout is not None and now > r.arrival + r.timeout:
+                return "timeout"
+            return None
+
+        keep = []
+        for r in self.waiting:
+            w = why(r) if r.arrival <= now or r.rid in self._cancel else None
+            if w:
+                self._drop(r, w, stamp)
+            else:
+                keep.append(r)
+        self.waiting = keep
+        keep = []
+        for r in self.active:
+            w = why(r) if r.done_event is None else None  # the last stage is queued: let it finish
+            if w:
+                self._drop(r, w, stamp, active=True)
+            else:
+                keep.append(r)
+        self.active = keep
 
     def _admit(self, now):
         keep = []
@@ -141,11 +228,12 @@ class Engine:
                 keep.append(r)
         self.waiting = keep
 
-    def _retire(self, now):
+    def _retire(self, stamp):
         keep = []
         for r in self.active:
             if r.done_event is not None and r.done_event.query():
-                r.finish = now
+                r.finish = stamp()  # when the completion is observed, not when the tick began
+                r.status = "done"
                 self.used -= r.footprint
                 r.inputs = r.state = None  # the result stays; inputs and intermediates are released
                 self.done.append(r)
@@ -156,7 +244,9 @@ class Engine:
     def _n_stages(self, r):
         return 1 if r.kind == "hmult" else len(self.vision[r.log_n].layers)
 
-    def tick(self, now):
+    def tick(self, now, stamp=None):
+        stamp = stamp or (lambda: now)
+        self._expire(now, stamp)
         self._admit(now)
         groups = {}
         for r in self.active:
@@ -166,21 +256,47 @@ class Engine:
                 lvl = r.state[0].level if r.kind == "vision" else -1
                 groups.setdefault((r.log_n, r.kind, r.stage, lvl), []).append(r)
         for (log_n, kind, stage, _), rs in groups.items():
-            self._launch(log_n, kind, stage, rs)
-            for r in rs:
+            for r in self._launch_isolated(log_n, kind, stage, rs, stamp):
                 r.stage += 1
                 if r.stage == self._n_stages(r):
                     r.result = r.state
-                    ev = torch.cuda.Event()
+                    ev = self._event()
                     ev.record()
                     r.done_event = ev
-        self._retire(now)
+        self._retire(stamp)
         return bool(groups)
 
+    def _launch_isolated(self, log_n, kind, stage, rs, stamp):
+        """Launch a group; if it fails, launch its requests one by one and
+        drop the ones that still fail. Returns the requests that advanced."""
+        try:
+            self._launch(log_n, kind, stage, rs)
+            return rs
+        except nat.CkksError as e:
+            if len(rs) == 1:
+                self._fail(rs[0], e, stamp)
+                return []
+        ok = []
+        for r in rs:
+            try:
+                self._launch(log_n, kind, stage, [r])
+                ok.append(r)
+            except nat.CkksError as e:
+                self._fail(r, e, stamp)
+        return ok
+
+    def _fail(self, r, err, stamp):
+        self.active.remove(r)
+        self._drop(r, "error", stamp, str(err), active=True)
+
     def _launch(self, log_n, kind, stage, rs):
+        bad = sorted(r.rid for r in rs if r.rid in self.fault)
+        if bad:
+            raise nat.CkksError(nat.CKKS_EDEVICE, "injected fault for request(s) %s (CKKS_FAULT_INJECT)" % bad)
         ctx = self.ctx[(kind, log_n)]
         if kind == "hmult":
-            outs = ctx.hmult_relin_rescale([r.state[0] for r in rs], [r.state[1] for r in rs])
+            outs = ctx.hmult_relin_rescale([r.state[0] for r in rs], [r.state[1] for r in rs],
+                                           rk=[self._rk(r) for r in rs])
             for r, o in zip(rs, outs):
                 r.state = [o]
             return
@@ -188,10 +304,11 @@ class Engine:
         layer = m.layers[stage]
         if layer == "square":
             flat = [c for r in rs for c in r.state]
+            keys = [self._rk(r) for r in rs for _ in r.state]
             outs = []
             for k in range(0, len(flat), self.square_chunk):
                 part = flat[k:k + self.square_chunk]
-                outs += ctx.hmult_relin_rescale(part, part)
+                outs += ctx.hmult_relin_rescale(part, part, rk=keys[k:k + self.square_chunk])
             k = 0
             for r in rs:
                 n = len(r.state)
@@ -213,9 +330,13 @@ class Engine:
         for r in sorted(requests, key=lambda r: r.arrival):
             self.submit(r)
         t0 = clock()
+
+        def stamp():
+            return clock() - t0
+
         while self.waiting or self.active:
-            now = clock() - t0
-            busy = self.tick(now)
+            now = stamp()
+            busy = self.tick(now, stamp)
             if not busy:
                 # nothing to launch: sleep until the next arrival or completion
                 nxt = min([r.arrival for r in self.waiting], default=now)
@@ -223,20 +344,21 @@ class Engine:
                     self.active[0].done_event.synchronize()
                 elif nxt > now:
                     time.sleep(min(nxt - now, 0.002))
-        torch.cuda.synchronize()
+        self._sync()
         return self.done
 
 
 # ---------------------------------------------------------------------------
 # plain path: FIFO, one operation per launch
 # ---------------------------------------------------------------------------
-def _plain_square(ctx, c):
+def _plain_square(ctx, c, rk):
     t = ctx.multiply(c, c)
-    r = ctx.relinearize(t)
+    r = ctx.relinearize(t, rk=rk)
     return ctx.rescale(r)
 
 
-def run_plain(contexts, vision, requests, clock=time.perf_counter):
+def run_plain(contexts, vision, requests, clock=time.perf_counter, client_keys=None):
+    keys = client_keys or {}
     t0 = clock()
     for req in sorted(requests, key=lambda r: r.arrival):
         while clock() - t0 < req.arrival:
@@ -244,16 +366,18 @@ def run_plain(contexts, vision, requests, clock=time.perf_counter):
         if callable(req.inputs):
             req.inputs = req.inputs()
         ctx = contexts[(req.kind, req.log_n)]
+        k = keys.get((req.kind, req.log_n, req.client))
+        rk = [k.rk if k is not None else ctx.rk]
         if req.kind == "hmult":
             a, b = req.inputs
             t = ctx.multiply(a, b)
-            req.result = [ctx.rescale(ctx.relinearize(t))]
+            req.result = [ctx.rescale(ctx.relinearize(t, rk=rk))]
         else:
             m = vision[req.log_n]
             state = list(req.inputs)
             for stage, layer in enumerate(m.layers):
                 if layer == "square":
-                    state = [_plain_square(ctx, c) for c in state]
+                    state = [_plain_square(ctx, c, rk) for c in state]
                     continue
                 out = []
                 rp, col, w = layer["row_ptr"], layer["col"], layer["w"]

@@ -85,8 +85,8 @@ def test_admission_by_footprint(env):
     peak = [0]
     orig = eng.tick
 
-    def tick(now):
-        busy = orig(now)
+    def tick(now, *rest):
+        busy = orig(now, *rest)
         peak[0] = max(peak[0], len(eng.active))
         return busy
 
@@ -97,3 +97,44 @@ def test_admission_by_footprint(env):
     small = _engine(serve, ctxs, vision, cap=one // 2)
     with pytest.raises(nat.CkksError):
         small.submit(_requests(serve, ctxs, [("vision", 10, 7, 0.0)])[0])
+
+
+def test_clients_share_launches(env):
+    """Requests of two clients (each with its own resident key set) in one
+    mix: each result equals the request served alone and on the plain path
+    with that client's keys, and an HMult result equals the fused call with
+    the client's relinearisation key."""
+    serve, ctxs, vision = env
+    keys = {}
+    for (kind, log_n), ctx in ctxs.items():
+        for client in (0, 1):
+            keys[(kind, log_n, client)] = ctx.client_keys(40 + 10 * client + log_n)
+    spec = [("hmult", 12, 15, 0.000), ("hmult", 12, 11, 0.000), ("vision", 10, 7, 0.001),
+            ("vision", 10, 7, 0.001), ("hmult", 11, 9, 0.002)]
+    clients = [0, 1, 1, 0, 1]
+
+    def reqs(sp, cl, rids=None):
+        rs = _requests(serve, ctxs, sp, rids)
+        for r, c in zip(rs, cl):
+            r.client = c
+        return rs
+
+    eng = serve.Engine(ctxs, vision, hbm_cap=64 << 30, client_keys=keys)
+    assert eng.used == eng.key_bytes > 0
+    mix = {r.rid: r for r in eng.run(reqs(spec, clients))}
+    assert eng.used == eng.key_bytes
+    for rid, (sp, c) in enumerate(zip(spec, clients)):
+        alone = serve.Engine(ctxs, vision, client_keys=keys).run(reqs([sp[:3] + (0.0,)], [c], rids=[rid]))[0]
+        assert all(np.array_equal(x, y) for x, y in zip(_res(alone), _res(mix[rid]))), rid
+    plain = serve.run_plain(ctxs, vision, reqs(spec, clients), client_keys=keys)
+    for r in plain:
+        assert all(np.array_equal(x, y) for x, y in zip(_res(r), _res(mix[r.rid]))), r.rid
+    # the HMult requests really used their client's key
+    for rid in (0, 1, 4):
+        kind, log_n, level, _ = spec[rid]
+        a, b = _requests(serve, ctxs, [spec[rid]], rids=[rid])[0].inputs
+        ctx = ctxs[(kind, log_n)]
+        want = ctx.hmult_relin_rescale([a], [b], rk=[keys[(kind, log_n, clients[rid])].rk])[0]
+        assert np.array_equal(want.residues(), _res(mix[rid])[0])
+        other = ctx.hmult_relin_rescale([a], [b], rk=[keys[(kind, log_n, 1 - clients[rid])].rk])[0]
+        assert not np.array_equal(other.residues(), _res(mix[rid])[0])

@@ -473,7 +473,8 @@ int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_inputs, ckks
                    uint32_t n_galois, void *ws, size_t ws_bytes, void *stream);
 
 /* Algorithms 6-7 (automatic FHE parameterisation): node cost = depth it
- * consumes (1 for LINEAR, DIAG_DENSE, SQUARE; 0 for INPUT, OUTPUT); every
+ * consumes (1 for LINEAR, DIAG_DENSE, SQUARE; the degree d for POLY; 0 for
+ * INPUT, OUTPUT); every
  * node is labelled with the longest cost from each source that reaches
  * it, OUTPUT nodes are concern nodes where the labelling restarts, and
  * sources meeting at a node are merged into one parameter group whose

@@ -660,6 +660,8 @@ extern "C" int ckks_graph_run(ckks_graph *g, const ckks_ct *inputs, uint32_t n_i
 // largest label any of its sources reached.
 namespace {
 u32 node_cost(const Node &n) {
+    // a polynomial activation of degree d consumes d levels (Horner's rule)
+    if (n.kind == CKKS_NODE_POLY) return n.coeffs.empty() ? 0u : (u32)(n.coeffs.size() - 1);
     return (n.kind == CKKS_NODE_LINEAR || n.kind == CKKS_NODE_DIAG_DENSE || n.kind == CKKS_NODE_SQUARE) ? 1u : 0u;
 }
 

@@ -2447,9 +2447,13 @@ extern "C" size_t ckks_linear_csr_workspace_bytes(const ckks_ctx *c, uint32_t n_
     if (!c) return 0;
     const size_t L = level + 1;
     const size_t grouped = al256(n_out * sizeof(LinGroup)) + al256(nnz * 4) + al256(L * nnz * 8) + al256(L * nnz * 16);
-    // matrix-core path: weights as int64 and their digit planes
-    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = ((size_t)n_in + 63) / 64 * 64;
-    const size_t mfma = al256((size_t)n_in * 4) + al256(nnz * 8) + al256((size_t)kWDig * rows_pad * k_pad);
+    // matrix-core path (every row has the same column list, of nnz / n_out
+    // entries, which may repeat an input): column list, weights as int64,
+    // pointer table and the weights' digit planes
+    const size_t ncols = std::max((size_t)n_in, n_out ? (nnz + n_out - 1) / n_out : 0);
+    const size_t rows_pad = ((size_t)n_out + 31) / 32 * 32, k_pad = (ncols + 63) / 64 * 64;
+    const size_t mfma = al256(ncols * 4) + al256(nnz * 8) + al256((size_t)(n_in + n_out) * 8) +
+                        al256((size_t)kWDig * rows_pad * k_pad);
     return std::max(grouped, mfma) + al256((size_t)(n_in + n_out) * 8) + 1024;
 }
 
@@ -2472,7 +2476,9 @@ int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const
     memcpy(img.data() + o_ptr, ptrs.data(), ptrs.size() * 8);
     uint8_t *w8 = nullptr;
     CK(upload(c, (uint8_t *)ws, img.data(), img.size(), s, &w8));
-    // the digit planes live in the workspace (or right after the recorded image)
+    // the digit planes live in the workspace, at o_wd, in every case: while
+    // recording the image above goes to the arena, but the planes are still
+    // written into the workspace by the recorded kernel on every replay
     int8_t *wd = (int8_t *)((uint8_t *)ws + o_wd);
     const u32 rp = (u32)rows_pad, kp = (u32)k_pad;
     ProfRec rec;
@@ -2522,6 +2528,7 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
         if (row_ptr[j + 1] < row_ptr[j]) return fail(CKKS_EINVAL, "linear_csr: row_ptr not monotone");
     for (size_t e = 0; e < nnz; e++)
         if (col[e] >= n_in) return fail(CKKS_EINVAL, "linear_csr: column %u out of range", col[e]);
+    if (!ws || (((uintptr_t)ws) & 255)) return fail(CKKS_EINVAL, "linear_csr: null or unaligned workspace");
     if (c->tb.lin_mfma) {
         // one column list for every row and small weights: the matrix cores
         const u32 nc = row_ptr[1] - row_ptr[0];
@@ -2583,7 +2590,6 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
                  o_wf = o_wt + al256(wt.size() * 8), o_ptr = o_wf + al256(wf.size() * 8),
                  need = o_ptr + al256((size_t)(n_in + n_out) * 8);
     if (need > ws_bytes) return fail(CKKS_ENOMEM, "linear_csr: workspace too small: need %zu", need);
-    if (!ws || (((uintptr_t)ws) & 255)) return fail(CKKS_EINVAL, "linear_csr: null or unaligned workspace");
     std::vector<uint8_t> img(need, 0);
     memcpy(img.data() + o_groups, groups.data(), groups.size() * sizeof(LinGroup));
     memcpy(img.data() + o_cols, cols.data(), cols.size() * 4);

@@ -28,6 +28,7 @@ least significant digit first.
 """
 import numpy as np
 
+from . import encoding as E
 from . import plainnet as PN
 
 
@@ -179,3 +180,34 @@ def conv_slots(orc, keys, ct, scale, mask_coeffs, steps, bias_pts, pt_scale):
         y, s_out = square(orc, keys, y, s)
         outs.append(y)
     return outs, s_out
+
+
+def conv_commuted(orc, keys, ct, scale, mask_coeffs, bias_pts, pt_scale):
+    """The paper's conv layer with the sum over the kernel commuted past a
+    key rotation (Section 4.2.2): per filter f and tap t the masked product
+    of the unrotated ciphertext, rescaled, plus the commuted bias terms.
+    mask_coeffs[f][t]: integer plaintext at pt_scale; bias_pts[f][t]:
+    NTT-form plaintext at the level and scale after the rescale. Returns
+    ([F * k*k] ciphertexts, filter-major, scale)."""
+    outs, s_out = [], None
+    for f in range(len(mask_coeffs)):
+        for t in range(len(mask_coeffs[f])):
+            y, s_out = diag_dense(orc, keys, ct, scale, [orc.reduce_int(mask_coeffs[f][t], ct.shape[1] - 1)],
+                                  pt_scale, [0], [], bias_pts[f][t])
+            outs.append(y)
+    return outs, s_out
+
+
+def key_rotation(orc, keys, cts, scales, reform, level, scale, seed, obj0=0):
+    """The client's key rotation (Sections 4.2.2 and 6): every ciphertext is
+    sent back, decrypted and decoded; the client's plaintext function
+    ``reform`` maps the list of decoded slot vectors to new slot vectors
+    (here the sum over the kernel and a change of layout), which are
+    encoded at ``scale`` and encrypted afresh at ``level`` (seed, object
+    ids obj0, obj0 + 1, ...). Returns (ciphertexts, their integer
+    plaintexts)."""
+    vals = [E.decode_residues(orc.decrypt(keys.sn, ct), orc.q, s, orc.N).real for ct, s in zip(cts, scales)]
+    new = reform(vals)
+    pts = [E.encode(v, scale, orc.N) for v in new]
+    outs = [orc.encrypt(keys.pk, orc.reduce_int(m, level), level, seed, obj0 + k) for k, m in enumerate(pts)]
+    return outs, pts

@@ -299,6 +299,89 @@ def conv_slots_anchor_values(out, n, side=28, block=1024, out_side=13):
     return res
 
 
+def conv_commuted_layout(conv_w, conv_b, slots, side=28, block=1024, stride=2):
+    """Kernel masquerading with the sum over the kernel left for after a
+    key rotation (Section 4.2.2): per filter f and tap t = (dy, dx) one
+    masked product of the unrotated image-in-slots vector, whose mask holds
+    w_f[dy, dx] at the tap pixel q = p + side dy + dx of every output anchor
+    p = stride y side + stride x with that pixel inside the image. The bias
+    is commuted into the terms: b_f / n(p) at the same positions, n(p) the
+    anchor's taps inside the image, so that the terms of an anchor sum to
+    its biased cross-correlation. Every tap keeps its own ciphertext (a
+    ciphertext cannot be folded onto itself without rotations).
+    Returns (offsets [k*k], masks [F][k*k][slots], bias [F][k*k][slots])."""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    n_blk = slots // block
+    taps = [(dy, dx) for dy in range(k) for dx in range(k)]
+    offsets = [dy * side + dx for dy, dx in taps]
+    masks = np.zeros((F, k * k, slots))
+    bias = np.zeros((F, k * k, slots))
+    for y in range(out_side):
+        for xx in range(out_side):
+            p = stride * y * side + stride * xx
+            valid = [t for t, (dy, dx) in enumerate(taps) if stride * y + dy < side and stride * xx + dx < side]
+            for t in valid:
+                dy, dx = taps[t]
+                for b in range(n_blk):
+                    q = b * block + p + offsets[t]
+                    masks[:, t, q] = conv_w[:, dy, dx]
+                    bias[:, t, q] = conv_b / len(valid)
+    return offsets, masks, bias
+
+
+def conv_commuted_sum(vals, n_img, side=28, block=1024, k=5, stride=2):
+    """The client's side of the key rotation: decoded term vectors
+    vals [n_ct][F][k*k][slots] -> conv outputs [n_img][F][13][13], each the
+    sum over taps t of the term at the anchor's tap pixel."""
+    n_ct, F, kk, slots = vals.shape
+    per = slots // block
+    out_side = (side + 1 - k) // stride + 1
+    offsets = [dy * side + dx for dy in range(k) for dx in range(k)]
+    out = np.zeros((n_img, F, out_side, out_side))
+    for i in range(n_img):
+        c, b = i // per, i % per
+        for y in range(out_side):
+            for xx in range(out_side):
+                p = b * block + stride * y * side + stride * xx
+                for t in range(kk):
+                    if stride * y + t // k < side and stride * xx + t % k < side:
+                        out[i, :, y, xx] += vals[c, :, t, p + offsets[t]]
+    return out
+
+
+def conv_commuted_packed(x, P, slots, block=1024):
+    """the terms of the commuted conv on the packed images (FP64):
+    [n_ct][F][k*k][slots] = mask (.) v + bias"""
+    offsets, masks, bias = conv_commuted_layout(P["conv_w"], P["conv_b"], slots, block=block)
+    v = conv_slots_pack(x, slots, block)
+    return np.stack([masks * v[c][None, None, :] + bias for c in range(v.shape[0])])
+
+
+def vision_conv_math(x, P):
+    """the biased cross-correlation of vision_math: [n][F][13][13]"""
+    n, side, _ = x.shape
+    F, k, _ = P["conv_w"].shape
+    pad = np.zeros((n, side + 1, side + 1))
+    pad[:, :side, :side] = x
+    out_side = (side + 1 - k) // 2 + 1
+    conv = np.zeros((n, F, out_side, out_side))
+    for o in range(F):
+        for y in range(out_side):
+            for xx in range(out_side):
+                patch = pad[:, 2 * y:2 * y + k, 2 * xx:2 * xx + k]
+                conv[:, o, y, xx] = np.tensordot(patch, P["conv_w"][o], axes=([1, 2], [0, 1])) + P["conv_b"][o]
+    return conv
+
+
+def vision_tail_math(conv, P):
+    """the rest of vision_math after the conv: x^2 -> dense -> x^2 -> dense"""
+    n = conv.shape[0]
+    h = (conv ** 2).reshape(n, -1)
+    h = (h @ P["w1"].T + P["b1"]) ** 2
+    return h @ P["w2"].T + P["b2"]
+
+
 def vision_conv_square_math(x, P):
     """the first two layers of vision_math: (conv + bias)^2 [n][F][13][13]"""
     n, side, _ = x.shape

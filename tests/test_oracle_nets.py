@@ -192,3 +192,61 @@ def test_conv_slots_layer_small_ring():
     want = PN.vision_conv_square_math(x, P)
     err = np.max(np.abs(vals - want) / np.maximum(1.0, np.abs(want)))
     assert err <= TOL, err
+
+
+def test_conv_commuted_layout_fp64():
+    # the commuted terms summed by the client equal the biased
+    # cross-correlation, with the bias spread over each anchor's taps
+    x, P = S.vision_inputs(n_images=3)
+    slots = 2048
+    terms = PN.conv_commuted_packed(x, P, slots)
+    got = PN.conv_commuted_sum(terms, 3)
+    want = PN.vision_conv_math(x, P)
+    assert np.max(np.abs(got - want)) < 1e-12
+    assert np.allclose(PN.vision_tail_math(want, P), PN.vision_math(x, P), rtol=0, atol=1e-9)
+    # a dropped or misplaced tap shows: every anchor needs all of its taps
+    offsets, masks, bias = PN.conv_commuted_layout(P["conv_w"], P["conv_b"], slots)
+    assert len(offsets) == 25 and masks.shape == (5, 25, slots)
+    broken = terms.copy()
+    broken[:, :, 7] = 0
+    assert np.max(np.abs(PN.conv_commuted_sum(broken, 3) - want)) > 1e-3
+
+
+def test_conv_commuted_key_rotation_small_ring():
+    # the oracle's commuted conv (masked products, no rotation) at N = 2^11
+    # (one image per ciphertext), then the client's key rotation: decrypt,
+    # sum over the kernel, re-encrypt one ciphertext per conv output
+    # (slot-batched); decoded within tolerance of the FP64 conv
+    logn = 11
+    primes = O.find_primes(logn, [60, 40, 40, 40, 40, 60])
+    orc = O.Oracle(logn, primes[:5], primes[5:], 5)
+    scale = 2.0 ** 40
+    x, P = S.vision_inputs(n_images=2)
+    slots = orc.N // 2
+    offsets, masks, bias = PN.conv_commuted_layout(P["conv_w"], P["conv_b"], slots)
+    keys = ON.Keys(orc, 9)
+    v = PN.conv_slots_pack(x, slots)
+    cts = [_encrypt(orc, keys, v[c], 1, scale, 5, c) for c in range(v.shape[0])]
+    mcs = [[E.encode(masks[f, t], scale, orc.N) for t in range(25)] for f in range(5)]
+    out_scale = scale * scale / orc.q[1]
+    bps = [[orc.reduce_int(E.encode(bias[f, t], out_scale, orc.N), 0) for t in range(25)] for f in range(5)]
+    terms, scales = [], []
+    for ct in cts:
+        ys, s = ON.conv_commuted(orc, keys, ct, scale, mcs, bps, scale)
+        assert s == out_scale and len(ys) == 125
+        terms += ys
+        scales += [s] * len(ys)
+
+    def reform(vals):
+        arr = np.array(vals).reshape(len(cts), 5, 25, slots)
+        conv = PN.conv_commuted_sum(arr, 2).reshape(2, -1)  # [image][845]
+        out = np.zeros((conv.shape[1], slots))
+        out[:, :2] = conv.T  # slot-batched: image i at slot i
+        return list(out)
+
+    fresh, pts = ON.key_rotation(orc, keys, terms, scales, reform, 4, scale, 11)
+    assert len(fresh) == 845 and fresh[0].shape == (2, 5, orc.N)
+    want = PN.vision_conv_math(x, P).reshape(2, -1)
+    for j in (0, 100, 423, 844):
+        got = _decrypt(orc, keys, fresh[j], scale, 2)
+        assert np.max(np.abs(got - want[:, j]) / np.maximum(1.0, np.abs(want[:, j]))) <= TOL, j

@@ -470,7 +470,9 @@ def nets_leg(args, dev, log, tuning=None):
                            "images_per_s": n_slot_img / dt_is, "rotations_per_ciphertext": 5 * (len(steps) - 1)}}
     log("conv+square: slot-batched %.0f images/s, image-in-slots (hoisted taps) %.0f images/s" %
         (n_img / dt_sb, n_slot_img / dt_is))
-    del g, g2, cts, scts, ctx
+    del g2, scts
+    out["conv_layouts"]["image_in_slots_key_rotation"] = key_rotation_leg(ctx, x, P, scale, args.kr_images, log)
+    del g, cts, ctx
     torch.cuda.empty_cache()
     # yield
     pr = nat.ckks_find_primes(14, [60] + [40] * 5 + [60])
@@ -645,6 +647,53 @@ def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
     return cpu
 
 
+def key_rotation_leg(ctx, x, P, scale, n_img, log):
+    """The whole vision network by the paper's own route: image-in-slots
+    ciphertexts (8 images each at N = 2^14, level 1), kernel-masquerading
+    terms with the commuted bias on the server (no rotations), the client's
+    key rotation (decrypt, sum over the kernel, re-encrypt slot-batched at
+    level 4), and the slot-batched rest of the network on the server."""
+    import numpy as np
+    import torch
+    from paper_2110_13638_amd import nets
+    slots = ctx.N // 2
+    xs = x[:n_img]
+    v = nets.conv_slots_pack(xs, slots)
+    cts = [ctx.encrypt(ctx.encode(v[c], level=1), seed=41, obj=c) for c in range(v.shape[0])]
+    g = nets.build_conv_commuted(ctx, P, len(cts), 1, scale)
+    tail = nets.build_vision_tail(ctx, P, 4, scale)
+    n_ct = len(cts)
+
+    def reform(vals):
+        arr = np.array(vals).reshape(5, 25, n_ct, slots).transpose(2, 0, 1, 3)  # node-major -> [c][f][t]
+        conv = nets.conv_commuted_sum(arr, n_img)
+        out = np.zeros((conv.shape[1], slots))
+        out[:, :n_img] = conv.T
+        return list(out)
+
+    g.run(cts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    terms = g.run(cts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fresh = nets.key_rotation(ctx, terms, reform, 4, scale, 42)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    logits = tail.run(fresh)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    r = {"images": n_img, "input_ciphertexts": n_ct, "term_ciphertexts": len(terms),
+         "server_conv_ms": 1e3 * (t1 - t0), "client_key_rotation_ms": 1e3 * (t2 - t1),
+         "server_tail_ms": 1e3 * (t3 - t2), "images_per_s": n_img / (t3 - t0),
+         "note": "one ciphertext per term (5 filters x 25 taps per input ciphertext); the client decrypts, "
+                 "decodes and sums on the host, then re-encrypts one slot-batched ciphertext per conv output"}
+    log("image-in-slots + key rotation (%d images): server conv %.1f ms, client %.0f ms, server tail %.1f ms, "
+        "%.0f images/s" % (n_img, r["server_conv_ms"], r["client_key_rotation_ms"], r["server_tail_ms"],
+                           r["images_per_s"]))
+    return r
+
+
 def torch_sync():
     import torch
     torch.cuda.synchronize()
@@ -670,6 +719,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-nets", action="store_true", help="skip the full-size network inferences")
     ap.add_argument("--net-runs", type=int, default=3)
+    ap.add_argument("--kr-images", type=int, default=64,
+                    help="images through the image-in-slots network with the client key rotation")
     ap.add_argument("--no-extra", action="store_true",
                     help="time only the batched HMult step (ragged, plain, NTT and serving legs skipped)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")

@@ -298,3 +298,103 @@ def build_conv_slots(ctx, P, n_ct, in_level, scale, mask_coeffs=None, bias_coeff
 
 def conv_slots_steps(side=28, k=5):
     return [dy * side + dx for dy in range(k) for dx in range(k)]
+
+
+# ---------------------------------------------------------------------------
+# the paper's own route through its conv (Section 4.2.2): kernel masquerading
+# without rotations, the sum over the kernel commuted past a client key
+# rotation, then the rest of the network in the slot-batched layout
+# ---------------------------------------------------------------------------
+def conv_commuted_layout(conv_w, conv_b, slots, side=28, block=1024, stride=2):
+    """(offsets [k*k], masks [F][k*k][slots], bias [F][k*k][slots]): the term
+    of tap t = (dy, dx) of anchor p = 2y * side + 2x sits at the tap's pixel
+    p + side dy + dx of the unrotated image block, weighted by w_f[dy, dx],
+    with b_f / n(p) added there (n(p): the anchor's taps inside the image;
+    the bias commuted into the sum). Taps outside the image have no term."""
+    F, k, _ = conv_w.shape
+    out_side = (side + 1 - k) // stride + 1
+    ys, xs = np.meshgrid(np.arange(out_side), np.arange(out_side), indexing="ij")
+    ys, xs = ys.ravel(), xs.ravel()
+    anchor = stride * ys * side + stride * xs
+    # taps inside the image per anchor
+    inside = np.array([[(stride * y + dy < side) and (stride * x + dx < side) for dy in range(k) for dx in range(k)]
+                       for y, x in zip(ys, xs)])  # [anchors][k*k]
+    n_valid = inside.sum(axis=1)
+    offsets = [dy * side + dx for dy in range(k) for dx in range(k)]
+    masks = np.zeros((F, k * k, slots))
+    bias = np.zeros((F, k * k, slots))
+    for t, off in enumerate(offsets):
+        dy, dx = divmod(t, k)
+        a = np.nonzero(inside[:, t])[0]
+        for base in range(0, slots - block + 1, block):
+            pos = base + anchor[a] + off
+            masks[:, t, pos] = conv_w[:, dy, dx][:, None]
+            bias[:, t, pos] = conv_b[:, None] / n_valid[a][None, :]
+    return offsets, masks, bias
+
+
+def build_conv_commuted(ctx, P, n_ct, in_level, scale, mask_coeffs=None, bias_coeffs=None, block=1024):
+    """input (image-in-slots ciphertexts) -> one DIAG_DENSE node per filter f
+    and tap t (a single diagonal at step 0: masked product, rescale, commuted
+    bias terms) -> one output node each; run() returns the F * k*k outputs
+    node-major: outs[(f * k*k + t) * n_ct + c]. No Galois keys."""
+    slots = ctx.N // 2
+    offsets, masks, bias = conv_commuted_layout(P["conv_w"], P["conv_b"], slots, block=block)
+    g = Graph(ctx)
+    x = g.input(n_ct, in_level, scale)
+    F, KK = masks.shape[0], masks.shape[1]
+    for f in range(F):
+        for t in range(KK):
+            dc = (mask_coeffs[f][t] if mask_coeffs is not None else ctx.encode_coeffs(masks[f, t], scale))[None]
+            if bias_coeffs is None:
+                node = g.diag_dense(dc, [0], scale, (), bias_slots=bias[f, t])
+            else:
+                node = g.diag_dense(dc, [0], scale, (), bias_coeffs=bias_coeffs[f][t])
+            g.edge(x, node)
+            g.edge(node, g.output())
+    g.plan()
+    return g
+
+
+def conv_commuted_sum(terms, n_img, side=28, block=1024, k=5, stride=2):
+    """Client side of the key rotation: decoded terms [n_ct][F][k*k][slots]
+    -> conv outputs [n_img][F * out_side^2] (filter, row, column order):
+    each output sums its taps' terms at the taps' pixels."""
+    n_ct, F, KK, slots = terms.shape
+    out_side = (side + 1 - k) // stride + 1
+    per = slots // block
+    out = np.zeros((n_img, F, out_side, out_side))
+    for t in range(KK):
+        dy, dx = divmod(t, k)
+        ny = sum(1 for y in range(out_side) if stride * y + dy < side)
+        nx = sum(1 for x in range(out_side) if stride * x + dx < side)
+        pos = (stride * np.arange(ny)[:, None] + dy) * side + (stride * np.arange(nx)[None, :] + dx)
+        for i in range(n_img):
+            c, b = divmod(i, per)
+            out[i, :, :ny, :nx] += terms[c][:, t][:, b * block + pos]
+    return out.reshape(n_img, -1)
+
+
+def key_rotation(ctx, cts, reform, level, scale, seed, obj0=0, keys=None):
+    """The client's key rotation (Sections 4.2.2 and 6): the ciphertexts go
+    back to the key holder, who decrypts and decodes them (ckks_decrypt,
+    ckks_decode), applies its plaintext function ``reform`` (list of slot
+    vectors -> list of slot vectors) and encrypts the result afresh at
+    ``level`` and ``scale`` (ckks_encode, ckks_encrypt; object ids obj0,
+    obj0 + 1, ...). Returns the new ciphertexts."""
+    vals = [ctx.decrypt(c, keys=keys).real for c in cts]
+    return [ctx.encrypt(ctx.encode(v, level=level, scale=scale), seed=seed, obj=obj0 + k, keys=keys)
+            for k, v in enumerate(reform(vals))]
+
+
+def build_vision_tail(ctx, P, in_level, scale, w_scale=None):
+    """The vision network after its conv, on slot-batched conv outputs
+    (filter, row, column order; image s in slot s): x^2 -> dense -> x^2 ->
+    dense."""
+    w_scale = w_scale or scale
+    g = Graph(ctx)
+    x = g.input(P["w1"].shape[1], in_level, scale)
+    g.chain(x, g.square(), g.dense(P["w1"], w_scale, P["b1"]), g.square(), g.dense(P["w2"], w_scale, P["b2"]),
+            g.output())
+    g.plan()
+    return g

@@ -232,3 +232,69 @@ def test_conv_slots_layer(mods):
     err = _rel_err(vals, PN.vision_conv_square_math(x, P))
     print("conv in slots: max relative error 2^%.1f" % np.log2(err))
     assert err <= TOL
+
+
+def test_conv_commuted_key_rotation_network(mods):
+    # the paper's own route through the vision network at N = 2^12 (two
+    # images per ciphertext): kernel-masquerading terms with the commuted
+    # bias (no rotations) bit-exact vs the oracle; the client's key
+    # rotation (decrypt, sum over the kernel, re-encrypt slot-batched)
+    # gives the oracle's plaintext integers up to the encoder rule (+-1,
+    # >= 99.9 % equal); the slot-batched rest of the network on the
+    # re-encrypted ciphertexts decodes within tolerance of the FP64 network
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 12, [60, 40, 40, 40, 40], [60], 5, 7)
+    keys = ON.Keys(orc, 7)
+    slots = ctx.N // 2
+    x, P = S.vision_inputs(n_images=4)
+    offsets, masks, bias = PN.conv_commuted_layout(P["conv_w"], P["conv_b"], slots)
+    o2, m2, b2 = nets.conv_commuted_layout(P["conv_w"], P["conv_b"], slots)
+    assert o2 == offsets and np.array_equal(m2, masks) and np.allclose(b2, bias, rtol=1e-15, atol=0)
+    v = PN.conv_slots_pack(x, slots)
+    n_ct = v.shape[0]
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, v[c], 1, 5, c) for c in range(n_ct)])
+    mcs = [[E.encode(masks[f, t], SCALE, ctx.N) for t in range(25)] for f in range(5)]
+    out_scale = SCALE * SCALE / orc.q[1]
+    bcs = [[E.encode(bias[f, t], out_scale, ctx.N) for t in range(25)] for f in range(5)]
+    g = nets.build_conv_commuted(ctx, P, n_ct, 1, SCALE, mask_coeffs=mcs, bias_coeffs=bcs)
+    outs = g.run(list(cts))  # node-major: outs[(f * 25 + t) * n_ct + c]
+    assert len(outs) == 125 * n_ct
+    terms_g, terms_o = [], []
+    for c in range(n_ct):
+        ys, s = ON.conv_commuted(orc, keys, ctos[c], SCALE, mcs, [[orc.reduce_int(b, 0) for b in bf] for bf in bcs],
+                                 SCALE)
+        for k in range(125):
+            o = outs[k * n_ct + c]
+            assert o.scale == s and np.array_equal(o.residues(), ys[k]), (c, k)
+            terms_g.append(o)
+        terms_o += ys
+
+    def reform(pn):
+        def f(vals):
+            arr = np.array(vals).reshape(n_ct, 5, 25, slots)
+            conv = pn(arr, 4).reshape(4, -1)
+            out = np.zeros((conv.shape[1], slots))
+            out[:, :4] = conv.T
+            return list(out)
+        return f
+
+    # key rotation: GPU client path vs the oracle's
+    fresh_o, pts_o = ON.key_rotation(orc, keys, terms_o, [out_scale] * len(terms_o), reform(PN.conv_commuted_sum),
+                                     4, SCALE, 11)
+    vals_g = [ctx.decrypt(t).real for t in terms_g]
+    ints_g = [ctx.encode_coeffs(v_, SCALE) for v_ in reform(nets.conv_commuted_sum)(vals_g)]
+    diff = np.stack(ints_g).astype(np.int64) - np.stack(pts_o).astype(np.int64)
+    assert np.max(np.abs(diff)) <= 1 and np.mean(diff == 0) >= 0.999
+    fresh = nets.key_rotation(ctx, terms_g, reform(nets.conv_commuted_sum), 4, SCALE, 11)
+    same = [np.array_equal(a.residues(), b) for a, b in zip(fresh, fresh_o)]
+    print("re-encrypted ciphertexts identical to the oracle's: %d of %d" % (sum(same), len(same)))
+    for k, (a, m) in enumerate(zip(fresh, ints_g)):
+        if k % 97 == 0:  # from the same integers, encryption is bit-exact
+            assert np.array_equal(a.residues(), orc.encrypt(keys.pk, orc.reduce_int(m, 4), 4, 11, k))
+    # the rest of the network on the GPU, decoded vs FP64
+    tail = nets.build_vision_tail(ctx, P, 4, SCALE)
+    logits = tail.run(fresh)
+    got = np.stack([ctx.decrypt(o, 4).real for o in logits], axis=1)
+    err = _rel_err(got, PN.vision_math(x, P))
+    print("commuted conv + key rotation + slot-batched tail: max relative error 2^%.1f" % np.log2(err))
+    assert err <= TOL

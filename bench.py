@@ -359,7 +359,53 @@ def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
     log("NTT: %d limbs fwd %.3f ms (%.0f GB/s, %.1f%% HBM) inv %.3f ms" %
         (len(limbs), fwd_ms, ntt["fwd_hbm_GBs"], 100 * ntt["fwd_hbm_frac"], inv_ms))
 
+    ntt["by_ring"] = ntt_rings(dev, len(limbs) * N, ctx.tuning())
     return ragged_rate, plain_rate, same, ntt
+
+
+def ntt_rings(dev, total_residues, tuning):
+    """Batched NTT / INTT at N = 2^13 .. 2^16 on the same number of residues
+    as the 2^15 microbench (16 x 50-bit + 2 x 60-bit primes of each ring,
+    limbs spread over the primes as in the ragged batch)."""
+    import torch
+    import synthetic as S
+    from paper_2110_13638_amd import _native as nat
+    from paper_2110_13638_amd import ckks
+    out = {}
+    for log_n in (13, 14, 15, 16):
+        pr = nat.ckks_find_primes(log_n, Q_BITS + P_BITS)
+        c = ckks.Context(log_n, pr[:16], pr[16:], DNUM, device=dev)
+        c.set_tuning(**{k: v for k, v in tuning.items() if k in ("xcd_remap", "ntt_fp")})
+        if log_n <= 14:
+            c.set_tuning(ntt_wide=1)  # 32 residues per thread: two workgroups per CU
+        N = 1 << log_n
+        n = total_residues // N
+        data = S.residues_device(5, pr[:16], N, -(-n // 16), dev).view(-1, N)[:n]
+        ptrs = [data[i].data_ptr() for i in range(n)]
+        pidx = [i % 16 for i in range(n)]  # row i of the view holds residues of prime i mod 16
+        ws, wb = c.ws_for(nat.CKKS_OP_NTT, n)
+        nat.ckks_ntt(c.h, ptrs, pidx, ws, wb, c.stream)
+        nat.ckks_intt(c.h, ptrs, pidx, ws, wb, c.stream)
+        torch.cuda.synchronize()
+        nat.ckks_profile_enable(True)
+        for _ in range(3):
+            nat.ckks_ntt(c.h, ptrs, pidx, ws, wb, c.stream)
+            nat.ckks_intt(c.h, ptrs, pidx, ws, wb, c.stream)
+        torch.cuda.synchronize()
+        nat.ckks_profile_enable(False)
+        rec = nat.ckks_profile_collect()
+        f = sum(r[2] for r in rec if r[0].startswith("ntt_fwd/")) / 3
+        i = sum(r[2] for r in rec if r[0].startswith("ntt_inv/")) / 3
+        nbytes = n * N * 16
+        out["N=2^%d" % log_n] = {"limbs": n, "fwd_ms": f, "inv_ms": i,
+                                 "fwd_hbm_frac": nbytes / (f * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "inv_hbm_frac": nbytes / (i * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "passes": 2 if log_n == 16 else 1}
+        log("NTT N=2^%d: %d limbs fwd %.3f ms (%.1f%% HBM) inv %.3f ms (%.1f%% HBM)" %
+            (log_n, n, f, 100 * out["N=2^%d" % log_n]["fwd_hbm_frac"], i, 100 * out["N=2^%d" % log_n]["inv_hbm_frac"]))
+        del data, c
+        torch.cuda.empty_cache()
+    return out
 
 
 def nets_leg(args, dev, log, tuning=None):

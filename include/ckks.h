@@ -77,7 +77,10 @@ const char *ckks_last_error(void);
  * entry of Algorithm 8's chain). dnum = number of key-switching digits at
  * the top level; each digit is alpha = ceil(n_q / dnum) consecutive data
  * primes (hybrid key switching). Every prime must be 1 mod 2N, distinct,
- * and below 2^61. log_n in [10, 15]. */
+ * and below 2^61. log_n in [10, 16]; at log_n = 16 only the plain
+ * transforms (ckks_ntt, ckks_intt) and element-wise operations run (a 2^16
+ * limb takes two workgroups of the 2^15 engine after a streaming first
+ * stage); every other device call returns CKKS_EPARAMS. */
 typedef struct {
     uint32_t log_n;
     uint32_t n_q;

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libckks_hip.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["ckks_ntt15.hip", "ckks_ntt15_fixed.hip", "ckks_ntt15_inv.hip", "ckks_ntt14.hip", "ckks_ntt13.hip", "ckks_ntt_small.hip", "ckks_kernels.hip", "ckks_noalloc.hip",
+SOURCES = ["ckks_ntt16.hip", "ckks_ntt15.hip", "ckks_ntt15_fixed.hip", "ckks_ntt15_inv.hip", "ckks_ntt14.hip", "ckks_ntt13.hip", "ckks_ntt_small.hip", "ckks_kernels.hip", "ckks_noalloc.hip",
            "ckks_host.cpp", "ckks_graph.cpp"]
 ARCH = os.environ.get("CKKS_OFFLOAD_ARCH", "gfx950")
 # packed-fp32 instructions are disabled for every HIP translation unit

@@ -284,9 +284,13 @@ struct Ntt {
 
     // Forward stage s = P * LOGE + D of phase P: Cooley-Tukey butterflies
     // (X, Y) -> (X + W Y, X - W Y), W = tw[2^s + group], Harvey lazy ranges.
+    // tm: twiddle-table multiplier. A full transform reads stage s's
+    // twiddles at tw[2^s + group] (tm = 1); half h of a transform of twice
+    // the size, after its first stage, is a transform of this size whose
+    // stage s reads tw[(2 + h) 2^s + group] of the larger table (tm = 2 + h).
     template <int P, int D>
     static __device__ __forceinline__ void fwd_stage(u64 (&r)[E], u32 tid, const ulonglong2 *__restrict__ tw,
-                                                     u64 q) {
+                                                     u64 q, u32 tm) {
         constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
         const u64 two_q = q << 1;
 #pragma unroll
@@ -296,7 +300,7 @@ struct Ntt {
             const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
             const u32 hi = group_hi(P, tid, g);
             const int x = g * (1 << w) + c, y = x + half;
-            const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
+            const u32 ti = (tm << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
             const ulonglong2 W = tw[ti];
             u64 X = r[x];
             X = X >= two_q ? X - two_q : X;
@@ -305,22 +309,22 @@ struct Ntt {
             r[y] = X - Tm + two_q;
             if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (D + 1 < w) fwd_stage<P, D + 1>(r, tid, tw, q);
+        if constexpr (D + 1 < w) fwd_stage<P, D + 1>(r, tid, tw, q, tm);
     }
     template <int P>
     static __device__ __forceinline__ void fwd_phase(u64 (&r)[E], u32 *lds, u32 tid,
-                                                     const ulonglong2 *__restrict__ tw, u64 q) {
+                                                     const ulonglong2 *__restrict__ tw, u64 q, u32 tm) {
         if constexpr (P > 0) exchange<P - 1, P>(r, lds, tid);
-        fwd_stage<P, 0>(r, tid, tw, q);
-        if constexpr (P + 1 < NPH) fwd_phase<P + 1>(r, lds, tid, tw, q);
+        fwd_stage<P, 0>(r, tid, tw, q, tm);
+        if constexpr (P + 1 < NPH) fwd_phase<P + 1>(r, lds, tid, tw, q, tm);
     }
 
     // forward: natural order in, "slot k = a(psi^(2brv(k)+1))" out, stage s
     // (2^s groups, half-size N >> (s+1)) multiplies by tw[2^s + group].
     // Inputs in [0, q) in the coalesced layout; outputs fully reduced.
     static __device__ __forceinline__ void forward(u64 (&r)[E], u32 *lds, u32 tid, const ulonglong2 *__restrict__ tw,
-                                                   u64 q) {
-        fwd_phase<0>(r, lds, tid, tw, q);
+                                                   u64 q, u32 tm = 1) {
+        fwd_phase<0>(r, lds, tid, tw, q, tm);
         exchange<NPH - 1, 0>(r, lds, tid);
         const u64 two_q = q << 1;
 #pragma unroll
@@ -399,7 +403,7 @@ struct Ntt {
     // < 2^52 (the multiplier's input range) and every sum is exact.
     template <int P, int D>
     static __device__ __forceinline__ void fwd_stage_f(double (&r)[E], u32 tid, const double2 *__restrict__ tw,
-                                                       double q, double qinv) {
+                                                       double q, double qinv, u32 tm) {
 #pragma clang fp contract(off)
         constexpr int w = width(P), s0 = P * LOGE, half = 1 << (w - 1 - D);
         constexpr bool recentre = ((s0 + D) % 3) == 2;
@@ -410,7 +414,7 @@ struct Ntt {
             const int c = ((bl >> (w - 1 - D)) << (w - D)) | (bl & (half - 1));
             const u32 hi = group_hi(P, tid, g);
             const int x = g * (1 << w) + c, y = x + half;
-            const u32 ti = (1u << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
+            const u32 ti = (tm << (s0 + D)) + (hi << D) + (u32)(c >> (w - D));
             const double2 W = tw[ti];
             double X = r[x];
             if constexpr (recentre) X = fp_center(X, q, qinv);
@@ -419,27 +423,29 @@ struct Ntt {
             r[y] = X - Tm;
             if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (D + 1 < w) fwd_stage_f<P, D + 1>(r, tid, tw, q, qinv);
+        if constexpr (D + 1 < w) fwd_stage_f<P, D + 1>(r, tid, tw, q, qinv, tm);
     }
     template <int P>
     static __device__ __forceinline__ void fwd_phase_f(double (&r)[E], u32 *lds, u32 tid,
-                                                       const double2 *__restrict__ tw, double q, double qinv) {
+                                                       const double2 *__restrict__ tw, double q, double qinv, u32 tm) {
         if constexpr (P > 0) exchange_f<P - 1, P>(r, lds, tid);
-        fwd_stage_f<P, 0>(r, tid, tw, q, qinv);
-        if constexpr (P + 1 < NPH) fwd_phase_f<P + 1>(r, lds, tid, tw, q, qinv);
+        fwd_stage_f<P, 0>(r, tid, tw, q, qinv, tm);
+        if constexpr (P + 1 < NPH) fwd_phase_f<P + 1>(r, lds, tid, tw, q, qinv, tm);
     }
     // forward() for q < 2^50: inputs in [0, q), outputs fully reduced
     static __device__ __forceinline__ void forward_fp(u64 (&r)[E], u32 *lds, u32 tid,
-                                                      const double2 *__restrict__ tw, const PrimeConst &pc) {
+                                                      const double2 *__restrict__ tw, const PrimeConst &pc,
+                                                      u32 tm = 1) {
         double d[E];
 #pragma unroll
         for (int k = 0; k < E; k++) d[k] = fp_from_u64(r[k]);
-        forward_fpd(d, r, lds, tid, tw, pc);
+        forward_fpd(d, r, lds, tid, tw, pc, tm);
     }
     // the same from integer-valued doubles with |d| < 2q; residues to r
     static __device__ __forceinline__ void forward_fpd(double (&d)[E], u64 (&r)[E], u32 *lds, u32 tid,
-                                                       const double2 *__restrict__ tw, const PrimeConst &pc) {
-        fwd_phase_f<0>(d, lds, tid, tw, pc.qf, pc.qinvf);
+                                                       const double2 *__restrict__ tw, const PrimeConst &pc,
+                                                       u32 tm = 1) {
+        fwd_phase_f<0>(d, lds, tid, tw, pc.qf, pc.qinvf, tm);
         exchange_f<NPH - 1, 0>(d, lds, tid);
 #pragma unroll
         for (int k = 0; k < E; k++) r[k] = fp_to_residue(fp_center(d[k], pc.qf, pc.qinvf), pc.qmf, pc.q);
@@ -945,6 +951,114 @@ k_inv(DevTables tb, const Item *__restrict__ items, int nitems) {
 }
 
 // ---------------------------------------------------------------------
+// Transforms of N = 2^LOGN residues that one workgroup cannot hold in
+// registers (N = 2^16), in two in-place passes over the limb:
+//   forward: (A) the first stage, which pairs j with j + N/2 under the one
+//            twiddle tw[1], as a streaming pass; (B) each half is then a
+//            transform of N/2 whose stage s reads tw[(2 + h) 2^s + group]
+//            (one workgroup per half h);
+//   inverse: (A) the first inverse stage, which pairs 2i with 2i + 1 under
+//            itw[N/2 + i], as a streaming pass; (B) each parity class is
+//            then an inverse transform of N/2 with the same table indices
+//            and the N^-1 merge of the full transform (one workgroup per
+//            class, every other word of the limb).
+// Only the copy prologue / epilogue (plain NTT / INTT of limbs).
+// ---------------------------------------------------------------------
+constexpr int kPairsPerThread = 4, kPairThreads = 256;
+template <bool FP, bool INV>
+__global__ void __launch_bounds__(kPairThreads) k_first_stage(DevTables tb, const Item *__restrict__ items, int nitems) {
+    const u32 N = 1u << tb.log_n, H = N >> 1;
+    const u32 per = H / (kPairThreads * kPairsPerThread);  // blocks per limb
+    const u32 b = blockIdx.x, item = b / per;
+    if ((int)item >= nitems) return;
+    const Item it = items[item];
+    const PrimeConst pc = tb.pc[it.prime];
+    u64 *a = it.out;
+    const u32 base = (b % per) * (kPairThreads * kPairsPerThread) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kPairsPerThread; k++) {
+        const u32 j = base + k * kPairThreads;
+        // forward: (j, j + N/2); inverse: (2j, 2j + 1)
+        const u32 ix = INV ? 2 * j : j, iy = INV ? 2 * j + 1 : j + H;
+        const u64 X = a[ix], Y = a[iy];
+        u64 x2, y2;
+        if constexpr (FP) {
+#pragma clang fp contract(off)
+            const double xd = fp_from_u64(X), yd = fp_from_u64(Y);
+            if constexpr (INV) {
+                const double2 W = tb.itwf[(size_t)it.prime * N + H + j];
+                x2 = fp_to_residue(fp_center(xd + yd, pc.qf, pc.qinvf), pc.qmf, pc.q);
+                y2 = fp_to_residue(fp_mulmod(xd - yd, W.x, W.y, pc.qf), pc.qmf, pc.q);
+            } else {
+                const double2 W = tb.twf[(size_t)it.prime * N + 1];
+                const double t = fp_mulmod(yd, W.x, W.y, pc.qf);
+                x2 = fp_to_residue(fp_center(xd + t, pc.qf, pc.qinvf), pc.qmf, pc.q);
+                y2 = fp_to_residue(fp_center(xd - t, pc.qf, pc.qinvf), pc.qmf, pc.q);
+            }
+        } else {
+            if constexpr (INV) {
+                const ulonglong2 W = tb.itw[(size_t)it.prime * N + H + j];
+                x2 = addm(X, Y, pc.q);
+                y2 = shoup(subm(X, Y, pc.q), W.x, W.y, pc.q);
+            } else {
+                const ulonglong2 W = tb.tw[(size_t)it.prime * N + 1];
+                const u64 t = shoup(Y, W.x, W.y, pc.q);
+                x2 = addm(X, t, pc.q);
+                y2 = subm(X, t, pc.q);
+            }
+        }
+        a[ix] = x2;
+        a[iy] = y2;
+    }
+}
+
+template <int LOGN, int LOGE, bool FP>
+__global__ void __launch_bounds__(1 << (LOGN - 1 - LOGE))
+k_fwd_halves(DevTables tb, const Item *__restrict__ items, int nitems) {
+    using NT = Ntt<LOGN - 1, LOGE>;
+    constexpr int N = 1 << LOGN, H = N / 2, E = NT::E, T = NT::T;
+    __shared__ u32 lds[NT::LDS_WORDS];
+    const int wid = xcd_item(2 * nitems, tb.xcd_remap);
+    if (wid < 0) return;
+    const Item it = items[wid >> 1];
+    const u32 h = (u32)(wid & 1), tid = threadIdx.x, vo = tid * 8;
+    const PrimeConst pc = tb.pc[it.prime];
+    const Buf buf(it.out + (size_t)h * H);
+    u64 r[E];
+#pragma unroll
+    for (int c = 0; c < E; c++) r[c] = buf.ld(vo, c * T * 8);
+    if constexpr (FP)
+        NT::forward_fp(r, lds, tid, tb.twf + (size_t)it.prime * N, pc, 2 + h);
+    else
+        NT::forward(r, lds, tid, tb.tw + (size_t)it.prime * N, pc.q, 2 + h);
+#pragma unroll
+    for (int c = 0; c < E; c++) buf.st(vo, c * T * 8, r[c]);
+}
+
+template <int LOGN, int LOGE, bool FP>
+__global__ void __launch_bounds__(1 << (LOGN - 1 - LOGE))
+k_inv_classes(DevTables tb, const Item *__restrict__ items, int nitems) {
+    using NT = Ntt<LOGN - 1, LOGE>;
+    constexpr int N = 1 << LOGN, E = NT::E, T = NT::T;
+    __shared__ u32 lds[NT::LDS_WORDS];
+    const int wid = xcd_item(2 * nitems, tb.xcd_remap);
+    if (wid < 0) return;
+    const Item it = items[wid >> 1];
+    const u32 p = (u32)(wid & 1), tid = threadIdx.x, vo = tid * 16 + p * 8;  // class element i at word 2i + p
+    const PrimeConst pc = tb.pc[it.prime];
+    const Buf buf(it.out);
+    u64 r[E];
+#pragma unroll
+    for (int c = 0; c < E; c++) r[c] = buf.ld(vo, c * T * 16);
+    if constexpr (FP)
+        NT::inverse_fp(r, lds, tid, tb.itwf + (size_t)it.prime * N, pc);
+    else
+        NT::inverse(r, lds, tid, tb.itw + (size_t)it.prime * N, pc);
+#pragma unroll
+    for (int c = 0; c < E; c++) buf.st(vo, c * T * 16, r[c]);
+}
+
+// ---------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------
 // tb.ntt_fp set: the launch's items all have primes below 2^50 (FP64 engine)
@@ -1019,4 +1133,6 @@ hipError_t launch_fwd_13(const DevTables &tb, int op, const Item *items, int n, 
 hipError_t launch_inv_13(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
 hipError_t launch_fwd_small(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s);
 hipError_t launch_inv_small(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
+hipError_t launch_fwd_16(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s);
+hipError_t launch_inv_16(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
 }  // namespace ckks

@@ -983,6 +983,11 @@ struct Plan {
             return fail(CKKS_ENOMEM, "workspace too small: need %zu bytes, got %zu", total(), ws_bytes);
         if (!ws && total()) return fail(CKKS_EINVAL, "null workspace");
         if (((uintptr_t)ws) & 255) return fail(CKKS_EINVAL, "workspace not 256-byte aligned");
+        if (c->log_n > kMaxFusedLogN)
+            for (const Launch &L : launches)
+                if (!((L.kind == 0 && L.op == F_COPY) || (L.kind == 1 && L.op == I_COPY) || L.kind == 2))
+                    return fail(CKKS_EPARAMS, "N = 2^%u supports plain transforms (ckks_ntt, ckks_intt) and "
+                                "element-wise operations only", c->log_n);
         const size_t doff = (scratch + 255) & ~(size_t)255;
         uint8_t *dbase = ws + doff;
         const int urc = upload(c, ws + doff, desc.data(), desc.size(), s, &dbase);

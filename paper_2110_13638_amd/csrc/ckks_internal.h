@@ -13,7 +13,10 @@ typedef int64_t i64;
 
 constexpr int kMaxPrimes = 64;
 constexpr int kMinLogN = 10;
-constexpr int kMaxLogN = 15;
+constexpr int kMaxLogN = 16;
+// at N = 2^16 a limb does not fit one workgroup: plain transforms (two
+// passes) and element-wise operations only
+constexpr int kMaxFusedLogN = 15;
 
 // Per-prime constants (one entry per prime index: data primes, then the
 // special primes).

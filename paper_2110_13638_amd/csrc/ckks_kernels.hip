@@ -722,6 +722,7 @@ __global__ void k_reduce_weights(DevTables tb, const i64 *__restrict__ W, u64 *_
 hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     switch (tb.log_n) {
+        case 16: return launch_fwd_16(tb, op, items, n, seed, s);
         case 15: return launch_fwd_15(tb, op, items, n, seed, s);
         case 14: return launch_fwd_14(tb, op, items, n, seed, s);
         case 13: return launch_fwd_13(tb, op, items, n, seed, s);
@@ -734,6 +735,7 @@ hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     switch (tb.log_n) {
+        case 16: return launch_inv_16(tb, op, items, n, s);
         case 15: return launch_inv_15(tb, op, items, n, s);
         case 14: return launch_inv_14(tb, op, items, n, s);
         case 13: return launch_inv_13(tb, op, items, n, s);

@@ -136,6 +136,7 @@ int main() {
     chain(12, {60, 40, 40, 40, 60}, 1, 4);
     chain(11, {50, 50, 50, 50, 50, 60, 60}, 2, 2);
     chain(10, {60, 40, 60}, 1, 2);
+    chain(16, {50, 50, 60}, 1, 2);
     printf("host driver ok\n");
     return 0;
 }

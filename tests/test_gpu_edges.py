@@ -134,3 +134,41 @@ def test_fp64_engine_prime_boundary(ck, log_n):
         for o, w in zip(outs, outs_want):
             assert np.array_equal(o.residues(), w), fp
     ctx.set_tuning(ntt_fp=1)
+
+
+def test_ring_2_16_transforms_and_scope(ck):
+    # N = 2^16: a batch of limbs of every prime class (FP64 and 64-bit
+    # engines), forward and inverse each against the oracle from random
+    # residues; operations beyond plain transforms and element-wise ones
+    # are refused with CKKS_EPARAMS
+    from paper_2110_13638_amd import _native as nat
+    log_n = 16
+    primes = O.find_primes(log_n, [60, 50, 49, 60])
+    orc = O.Oracle(log_n, primes[:3], primes[3:], 3)
+    ctx = ck.Context(log_n, primes[:3], primes[3:], 3)
+    pidx = [0, 1, 2, 3, 1, 2, 0]
+    x = np.stack([S.residues(70 + k, [primes[i]], 1 << log_n)[0, 0] for k, i in enumerate(pidx)])
+    for fp in (1, 0):
+        ctx.set_tuning(ntt_fp=fp)
+        print("N=2^16 transforms ntt_fp=%d" % fp, flush=True)
+        dev = torch.from_numpy(x.view(np.int64).copy()).cuda()
+        ptrs = [dev[k].data_ptr() for k in range(len(pidx))]
+        ws, wb = ctx.ws_for(nat.CKKS_OP_NTT, len(pidx))
+        nat.ckks_ntt(ctx.h, ptrs, pidx, ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy().view(np.uint64)
+        for k, i in enumerate(pidx):
+            assert np.array_equal(got[k], orc.ntt(x[k], i)), (fp, k)
+        dev = torch.from_numpy(x.view(np.int64).copy()).cuda()
+        ptrs = [dev[k].data_ptr() for k in range(len(pidx))]
+        nat.ckks_intt(ctx.h, ptrs, pidx, ws, wb, ctx.stream)
+        torch.cuda.synchronize()
+        got = dev.cpu().numpy().view(np.uint64)
+        for k, i in enumerate(pidx):
+            assert np.array_equal(got[k], orc.intt(x[k], i)), (fp, k)
+    a = ctx.ct_from_residues(S.residues(5, primes[:3], 1 << log_n, 2), 2.0 ** 40)
+    b = ctx.add(a, a)  # element-wise: runs
+    assert np.array_equal(b.residues(), orc.add(a.residues(), a.residues()))
+    with pytest.raises(nat.CkksError) as e:
+        ctx.rescale(a)
+    assert e.value.code == nat.CKKS_EPARAMS

@@ -31,7 +31,7 @@ SETTINGS = [dict(ntt_wide=w, ew_log=e, xcd_remap=x, fuse_tail=f, ip_cts=i, ntt_f
             for w, e, x, f, i, p in itertools.product((0, 1), (1, 2, 3), (0, 1), (0, 1), (2, 4, 16), (0, 1))]
 
 
-@pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15])
+@pytest.mark.parametrize("log_n", [11, 12, 13, 14, 15, 16])
 def test_ntt_variants_bit_exact(ck, log_n):
     from paper_2110_13638_amd import _native as nat
     primes = O.find_primes(log_n, [60, 50, 40, 36])

@@ -444,12 +444,15 @@ def nets_leg(args, dev, log, tuning=None):
     torch.cuda.synchronize()
     nat.ckks_profile_enable(False)
     fam = {}
-    for name, items, ms in nat.ckks_profile_collect():
+    recs = nat.ckks_profile_collect()
+    for name, items, ms in recs:
         fam[name] = fam.get(name, 0.0) + ms
+    linear_roofline = vision_linear_roofline(recs, P, ctx)
     out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
                      "security": security_label(14, pr)["label"],
                      "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
-                     "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])}}
+                     "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])},
+                     "linear_layers": linear_roofline}
     log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
     # the same inference recorded once and replayed as a HIP graph: new
     # images are written into the recorded input ciphertexts, no host work
@@ -691,6 +694,50 @@ def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
         (extra["ntt"]["limb_ntt_per_s"], threads, total / threads, threads, 1e3 * t_v, 1e3 * t_y))
     cpu["extra"] = extra
     return cpu
+
+
+# int8 operations of one modular multiply-add on the matrix cores: 6 signed
+# weight digits x 9 residue digits, each product a multiply and an add
+MFMA_OPS_PER_MAC = 2 * 6 * 9
+INT8_PEAK_TOPS = 5000.0  # dense int8 MFMA, MI355X
+
+
+def vision_linear_roofline(recs, P, ctx):
+    """Per linear layer of the slot-batched vision network (conv on the
+    VALU, dense layers on the matrix cores): algorithmic work and bytes of
+    the layer over its profiled launch time. Layers in launch order: the
+    conv (845 rows over 784 pixel ciphertexts, 8 limbs), dense 845 -> 100
+    (6 limbs), dense 100 -> 10 (4 limbs)."""
+    from paper_2110_13638_amd import nets
+    N = ctx.N
+    lb = 8 * N
+    rows, _ = nets.conv_rows(P["conv_w"], 28)
+    nnz = sum(len(r) for r in rows)
+    grouped = [r for r in recs if r[0].startswith("linear_grouped/")]
+    mfma = [r for r in recs if r[0].startswith("linear_mfma/")]
+    out = {}
+    if grouped:
+        L = 8
+        ms = grouped[0][2]
+        fp_limbs = sum(1 for q in ctx.q[:L] if q < FP_PRIME_BOUND)
+        slots = nnz * 2 * N * (fp_limbs * OPS["MAC_FP"] + (L - fp_limbs) * OPS["MAC"])
+        nbytes = (784 + len(rows)) * 2 * L * lb
+        out["conv"] = {"kernel": "k_linear_grouped (VALU)", "ms": ms, "modular_macs": nnz * 2 * L * N,
+                       "alu": {"achieved": slots / (ms * 1e-3) / 1e12, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                               "frac": slots / (ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
+                       "hbm": {"achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    for name, (n_out, n_in, L), rec in zip(("dense1", "dense2"), ((100, 845, 6), (10, 100, 4)), mfma):
+        ms = rec[2]
+        macs = n_out * n_in * 2 * L * N
+        ops = MFMA_OPS_PER_MAC * macs
+        nbytes = (n_in + n_out) * 2 * L * lb
+        out[name] = {"kernel": "k_linear_mfma (int8 matrix cores)", "ms": ms, "modular_macs": macs,
+                     "mfma": {"achieved": ops / (ms * 1e-3) / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOPS int8",
+                              "frac": ops / (ms * 1e-3) / 1e12 / INT8_PEAK_TOPS},
+                     "hbm": {"achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    return out
 
 
 def key_rotation_leg(ctx, x, P, scale, n_img, log):

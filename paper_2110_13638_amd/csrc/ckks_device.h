@@ -145,6 +145,13 @@ __device__ __forceinline__ u64 fp_to_residue(double v, double qm, u64 q) {
     return csub(u, q);
 }
 
+// a wave-uniform 64-bit value held in scalar registers (frees vector
+// registers for the register-resident limb)
+__device__ __forceinline__ u64 uniform64(u64 x) {
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)x), hi = __builtin_amdgcn_readfirstlane((u32)(x >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, class F>
 __device__ __forceinline__ void static_for(F &&f) {
@@ -883,6 +890,23 @@ __device__ __forceinline__ void inv_item(const DevTables &tb, const Item &it, u3
     // |k - x y / q| <= 0.75 for x, y < q < 2^50, so |d| <= 0.75 q, exactly
     constexpr bool kFpMul = FP && OP == I_MUL;
     double d[kFpMul ? E : 1];
+    // the epilogue's constant multiplier (same for the whole item), read
+    // before the transform into scalar registers
+    u64 inv = 0, inv_sh = 0;
+    if constexpr (OP == I_SCALE) {
+        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q;
+        // b == 2: hat_i^-1 of ModUp digit block c, position a (a ModUp source)
+        const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
+        inv = uniform64(it.b == 1 ? pc.pinv : it.b == 2 ? blk[2 * it.a] : tb.moddown[2 * it.a]);
+        inv_sh = uniform64(it.b == 1 ? pc.pinv_sh : it.b == 2 ? blk[2 * it.a + 1] : tb.moddown[2 * it.a + 1]);
+    } else if constexpr (OP == I_MUL) {
+        // it.v == 1: the ModUp source factor hat_i^-1 (digit block it.c, position it.a)
+        if (it.v == 1) {
+            const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
+            inv = uniform64(blk[2 * it.a]);
+            inv_sh = uniform64(blk[2 * it.a + 1]);
+        }
+    }
     if constexpr (OP == I_COPY || OP == I_SCALE) {
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
@@ -923,17 +947,10 @@ __device__ __forceinline__ void inv_item(const DevTables &tb, const Item &it, u3
     if constexpr (OP == I_MUL) {
         // it.v == 1: store [x * hat_i^-1]_{q_i}, the ModUp input (digit block it.c, position it.a)
         if (it.v == 1) {
-            const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
-            const u64 inv = blk[2 * it.a], inv_sh = blk[2 * it.a + 1];
 #pragma unroll
             for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
         }
     } else if constexpr (OP == I_SCALE) {
-        // b == 0: hat_m^-1 mod p_m for special prime m = a; b == 1: P^-1 mod q;
-        // b == 2: hat_i^-1 of ModUp digit block c, position a (a ModUp source)
-        const u64 *blk = tb.modup + (size_t)it.c * modup_block_words(tb.alpha, tb.n_prim);
-        const u64 inv = it.b == 1 ? pc.pinv : it.b == 2 ? blk[2 * it.a] : tb.moddown[2 * it.a];
-        const u64 inv_sh = it.b == 1 ? pc.pinv_sh : it.b == 2 ? blk[2 * it.a + 1] : tb.moddown[2 * it.a + 1];
 #pragma unroll
         for (int c = 0; c < E; c++) r[c] = shoup(r[c], inv, inv_sh, q);
     }

@@ -18,6 +18,7 @@
 #include <type_traits>
 #include <string>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ckks.h"
@@ -235,6 +236,7 @@ struct ckks_ctx {
     u32 log_n, N, n_q, n_p, n_prim, dnum, alpha, digits_top;
     Recorder *rec = nullptr;  // non-null while recording
     Staging *stage = nullptr;  // created on the first upload
+    std::mutex stage_mu;       // host threads sharing the context take turns on the ring
     ~ckks_ctx() { delete stage; }
     std::vector<u64> primes;
     std::vector<u64> image;  // device table image (u64 words)
@@ -759,6 +761,8 @@ std::string launch_name(int kind, int op, u32 log_n) {
         case 3:
         case 6: snprintf(b, sizeof b, "keyswitch_inner_product/N=2^%u", log_n); break;
         case 5: snprintf(b, sizeof b, "hoisted_rotations/N=2^%u", log_n); break;
+        case 7: snprintf(b, sizeof b, "linear_mfma/N=2^%u", log_n); break;
+        case 8: snprintf(b, sizeof b, "linear_grouped/N=2^%u", log_n); break;
         default: snprintf(b, sizeof b, "linear/N=2^%u", log_n); break;
     }
     return b;
@@ -835,7 +839,11 @@ int upload(const ckks_ctx *c, uint8_t *dst, const void *src, size_t bytes, hipSt
         HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
         return CKKS_OK;
     }
+    // The staging ring is mutable state of a context that is otherwise
+    // read-only after upload: calls from several host threads on one
+    // context serialise here (the copies stay asynchronous).
     ckks_ctx *cm = const_cast<ckks_ctx *>(c);
+    std::lock_guard<std::mutex> lock(cm->stage_mu);
     if (!cm->stage) {
         Staging *st = new Staging();
         if (hipHostMalloc((void **)&st->buf, kStagingBytes, hipHostMallocDefault) != hipSuccess) {
@@ -1161,6 +1169,14 @@ void add_ip(Plan &P, const std::vector<IpCt> &cts) {
     }
     P.add(6, 0, seq);
     P.add(3, 0, ip);
+}
+
+// Transform items whose inputs are their own limbs only: launched prime by
+// prime, so that the workgroups in flight on one XCD (consecutive items)
+// read one prime's twiddle tables from that XCD's L2 (stable: within a
+// prime the caller's order is kept).
+void order_by_prime(std::vector<Item> &v) {
+    std::stable_sort(v.begin(), v.end(), [](const Item &x, const Item &y) { return x.prime < y.prime; });
 }
 
 inline u64 *limb(const ckks_ctx *c, const ckks_ct &ct, u32 poly, u32 i) {
@@ -1573,6 +1589,7 @@ static int ntt_common(const ckks_ctx *c, uint64_t *const *limbs, const uint32_t 
         it.prime = pidx[i];
         v.push_back(it);
     }
+    order_by_prime(v);
     if (inverse)
         P.add(1, I_COPY, v);
     else
@@ -2189,6 +2206,7 @@ static int plan_hmult(Plan &P, const u64 *const *rk, const ckks_ct *a, const ckk
                 tail.push_back(w);
             }
     }
+    order_by_prime(mul);
     P.add(1, I_MUL, mul);
     add_modup(P, modup);
     add_ip(P, ipc);
@@ -2488,7 +2506,7 @@ int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const
     const u32 rp = (u32)rows_pad, kp = (u32)k_pad;
     ProfRec rec;
     if (g_prof_on) {
-        rec.name = launch_name(4, 0, c->log_n);
+        rec.name = launch_name(7, 0, c->log_n);
         rec.items = n_out;
         HIP_TRY(hipEventCreate(&rec.e0));
         HIP_TRY(hipEventCreate(&rec.e1));
@@ -2609,7 +2627,7 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
     CK(upload(c, (uint8_t *)ws, img.data(), need, s, &w8));
     ProfRec rec;
     if (g_prof_on) {
-        rec.name = launch_name(4, 0, c->log_n);
+        rec.name = launch_name(8, 0, c->log_n);
         rec.items = (u32)groups.size();
         HIP_TRY(hipEventCreate(&rec.e0));
         HIP_TRY(hipEventCreate(&rec.e1));

@@ -211,3 +211,25 @@ def key_rotation(orc, keys, cts, scales, reform, level, scale, seed, obj0=0):
     pts = [E.encode(v, scale, orc.N) for v in new]
     outs = [orc.encrypt(keys.pk, orc.reduce_int(m, level), level, seed, obj0 + k) for k, m in enumerate(pts)]
     return outs, pts
+
+
+def slots_dense(orc, keys, conv_cts, scale, mask_pts, pt_scale, bias_pts, steps):
+    """Dense layer after the image-in-slots conv, summed on the server
+    (Section 4.2.2 read with Galois rotations): for neuron j the filter
+    outputs conv_cts[f] times the masks mask_pts[j][f] (NTT-form
+    plaintexts at pt_scale, the layer's weights at the anchors), added, rescaled,
+    rotate-and-summed over the image block (steps) and given the bias
+    plaintext bias_pts[j] (at the level and scale after the rescale).
+    Returns ([n] ciphertexts, scale)."""
+    level = conv_cts[0].shape[1] - 1
+    outs, s_out = [], None
+    for j in range(len(mask_pts)):
+        acc = None
+        for f, ct in enumerate(conv_cts):
+            t = orc.mul_plain(ct, mask_pts[j][f])
+            acc = t if acc is None else orc.add(acc, t)
+        acc = orc.rescale(acc)
+        for st in steps:
+            acc = orc.add(acc, rotate(orc, keys, acc, st))
+        outs.append(orc.add_plain(acc, bias_pts[j]))
+    return outs, scale * pt_scale / orc.q[level]

@@ -299,6 +299,53 @@ def conv_slots_anchor_values(out, n, side=28, block=1024, out_side=13):
     return res
 
 
+def slots_dense_masks(W1, slots, block=1024, side=28, out_side=13, stride=2):
+    """Dense 845 -> n after the image-in-slots conv, summed on the server
+    by rotations: for neuron j and filter f a mask holding W1[j, f 169 +
+    13 y + x] at the anchor 2y side + 2x of every image block; the masked
+    filter outputs are added, and a rotate-and-sum over the block (steps 1,
+    2, ..., block / 2) leaves the neuron's value at the block's first slot.
+    Returns masks [n][F][slots]."""
+    n, n_in = W1.shape
+    F = n_in // (out_side * out_side)
+    masks = np.zeros((n, F, slots))
+    for b in range(slots // block):
+        for f in range(F):
+            for y in range(out_side):
+                for xx in range(out_side):
+                    masks[:, f, b * block + stride * y * side + stride * xx] = W1[:, f * out_side * out_side +
+                                                                                   y * out_side + xx]
+    return masks
+
+
+def block_sum_steps(block=1024):
+    """rotate-and-sum steps that sum a block of slots into its first slot"""
+    return [1 << k for k in range(int(np.log2(block)))]
+
+
+def slots_network_packed(x, P, slots, block=1024):
+    """The whole vision network in the image-in-slots layout (FP64, np.roll):
+    conv by masked taps, x^2, dense 1 by masks + rotate-and-sum per neuron,
+    x^2, dense 2 by scalar weights; logits [n_img][classes] read at each
+    block's first slot."""
+    conv = conv_slots_packed(x, P, slots, block)  # [n_ct][F][slots], squared
+    masks = slots_dense_masks(P["w1"], slots, block)
+    n_ct = conv.shape[0]
+    per = slots // block
+    out = []
+    for c in range(n_ct):
+        h = []
+        for j in range(masks.shape[0]):
+            acc = (masks[j] * conv[c]).sum(axis=0)
+            for st in block_sum_steps(block):
+                acc = acc + np.roll(acc, -st)
+            h.append((acc + P["b1"][j]) ** 2)
+        h = np.stack(h)
+        logits = P["w2"] @ h + P["b2"][:, None]  # [classes][slots]
+        out.append(logits[:, ::block][:, :per].T)
+    return np.concatenate(out)[: x.shape[0]]
+
+
 def conv_commuted_layout(conv_w, conv_b, slots, side=28, block=1024, stride=2):
     """Kernel masquerading with the sum over the kernel left for after a
     key rotation (Section 4.2.2): per filter f and tap t = (dy, dx) one

@@ -250,3 +250,52 @@ def test_conv_commuted_key_rotation_small_ring():
     for j in (0, 100, 423, 844):
         got = _decrypt(orc, keys, fresh[j], scale, 2)
         assert np.max(np.abs(got - want[:, j]) / np.maximum(1.0, np.abs(want[:, j]))) <= TOL, j
+
+
+def test_slots_network_fp64_layout():
+    # the whole vision network in the image-in-slots layout (masked taps,
+    # masks + rotate-and-sum per dense neuron) equals the plain network
+    x, P = S.vision_inputs(n_images=3)
+    got = PN.slots_network_packed(x, P, 2048)
+    assert np.max(np.abs(got - PN.vision_math(x, P))) < 1e-12
+    # a rotate-and-sum missing one step sums half the block
+    masks = PN.slots_dense_masks(P["w1"], 2048)
+    assert masks.shape == (100, 5, 2048) and np.count_nonzero(masks[0, 0]) == 2 * 169
+    assert PN.block_sum_steps() == [1 << k for k in range(10)]
+
+
+def test_slots_network_encrypted_small_ring():
+    # the oracle's lowering of the image-in-slots network with server-side
+    # rotate-and-sum dense layers at N = 2^11 (one image per ciphertext),
+    # decoded within tolerance of the FP64 network
+    logn = 11
+    primes = O.find_primes(logn, [60] + [40] * 5 + [60])
+    orc = O.Oracle(logn, primes[:6], primes[6:], 6)
+    scale = 2.0 ** 40
+    x, P = S.vision_inputs(n_images=1)
+    slots = orc.N // 2
+    steps, masks, bias = PN.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    rs = PN.block_sum_steps()
+    keys = ON.Keys(orc, 7, sorted({orc.galois_elt(s) for s in steps if s} | {orc.galois_elt(s) for s in rs}))
+    ct = _encrypt(orc, keys, PN.conv_slots_pack(x, slots)[0], 5, scale, 5, 0)
+    mcs = [np.stack([E.encode(masks[f, t], scale, orc.N) for t in range(25)]) for f in range(5)]
+    s1 = scale * scale / orc.q[5]
+    bps = [orc.reduce_int(E.encode(bias[f], s1, orc.N), 4) for f in range(5)]
+    conv, s = ON.conv_slots(orc, keys, ct, scale, mcs, steps, bps, scale)  # level 3
+    dm = PN.slots_dense_masks(P["w1"], slots)
+    mpts = [[orc.reduce_int(E.encode(dm[j, f], scale, orc.N), 3) for f in range(5)] for j in range(100)]
+    s2 = s * scale / orc.q[3]
+    bvec = np.zeros((100, slots))
+    bvec[:, ::1024] = P["b1"][:, None]
+    bpts = [orc.reduce_int(E.encode(bvec[j], s2, orc.N), 2) for j in range(100)]
+    h, s3 = ON.slots_dense(orc, keys, conv, s, mpts, scale, bpts, rs)
+    assert s3 == s2 and h[0].shape[1] == 3
+    sq = []
+    for y in h:
+        z, s4 = ON.square(orc, keys, y, s3)
+        sq.append(z)
+    rows = [[(j, P["w2"][k, j]) for j in range(100)] for k in range(10)]
+    logits, s5 = ON.linear(orc, sq, s4, rows, scale, P["b2"])
+    got = np.array([_decrypt(orc, keys, o, s5, 1)[0] for o in logits])
+    want = PN.vision_math(x, P)[0]
+    assert np.max(np.abs(got - want) / np.maximum(1.0, np.abs(want))) <= TOL

@@ -521,6 +521,8 @@ def nets_leg(args, dev, log, tuning=None):
         (n_img / dt_sb, n_slot_img / dt_is))
     del g2, scts
     out["conv_layouts"]["image_in_slots_key_rotation"] = key_rotation_leg(ctx, x, P, scale, args.kr_images, log)
+    out["conv_layouts"]["image_in_slots_rotate_and_sum"] = rotate_and_sum_leg(ctx, x, P, scale, args.kr_images,
+                                                                               log)
     del g, cts, ctx
     torch.cuda.empty_cache()
     # yield
@@ -784,6 +786,43 @@ def key_rotation_leg(ctx, x, P, scale, n_img, log):
     log("image-in-slots + key rotation (%d images): server conv %.1f ms, client %.0f ms, server tail %.1f ms, "
         "%.0f images/s" % (n_img, r["server_conv_ms"], r["client_key_rotation_ms"], r["server_tail_ms"],
                            r["images_per_s"]))
+    return r
+
+
+def rotate_and_sum_leg(ctx, x, P, scale, n_img, log):
+    """The whole vision network in the image-in-slots layout on the server
+    alone: conv by masked taps summed with hoisted rotations, x^2, dense 1 by
+    masks + rotate-and-sum per neuron (10 rotations of every neuron's
+    ciphertext), x^2, dense 2 (8 images per ciphertext, N = 2^14, level 5)."""
+    import torch
+    from paper_2110_13638_amd import nets
+    slots = ctx.N // 2
+    for ge in nets.galois_for_steps(ctx, nets.block_sum_steps(), direct=True):
+        if ge not in ctx.gk:
+            ctx.add_galois_key(ge, nets.galois_key_seed(24, ge))
+    v = nets.conv_slots_pack(x[:n_img], slots)
+    cts = [ctx.encrypt(ctx.encode(v[c], level=5), seed=51, obj=c) for c in range(v.shape[0])]
+    n_ct = len(cts)
+    g = nets.build_conv_slots(ctx, P, n_ct, 5, scale)
+    masks = nets.slots_dense_masks(P["w1"], slots)
+    mcs = [[ctx.encode_coeffs(masks[j, f], scale) for f in range(5)] for j in range(masks.shape[0])]
+
+    def run():
+        outs = g.run(cts)
+        conv = [[outs[f * n_ct + c] for c in range(n_ct)] for f in range(5)]
+        h = nets.slots_dense(ctx, conv, scale, P["w1"], P["b1"], mask_coeffs=mcs)
+        head = nets.build_slots_head(ctx, P, len(h), h[0][0].level, h[0][0].scale)
+        return [head.run([h[j][c] for j in range(len(h))]) for c in range(n_ct)]
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r = {"images": n_img, "input_ciphertexts": n_ct, "ms": 1e3 * dt, "images_per_s": n_img / dt,
+         "rotations_per_input_ciphertext": 5 * 24 + 100 * len(nets.block_sum_steps())}
+    log("image-in-slots, dense by rotate-and-sum (%d images): %.1f ms, %.0f images/s" % (n_img, 1e3 * dt, n_img / dt))
     return r
 
 

@@ -390,11 +390,81 @@ def key_rotation(ctx, cts, reform, level, scale, seed, obj0=0, keys=None):
 def build_vision_tail(ctx, P, in_level, scale, w_scale=None):
     """The vision network after its conv, on slot-batched conv outputs
     (filter, row, column order; image s in slot s): x^2 -> dense -> x^2 ->
-    dense."""
-    w_scale = w_scale or scale
+    dense; weights at w_scale (default the context's scale)."""
+    w_scale = w_scale or ctx.default_scale
     g = Graph(ctx)
     x = g.input(P["w1"].shape[1], in_level, scale)
     g.chain(x, g.square(), g.dense(P["w1"], w_scale, P["b1"]), g.square(), g.dense(P["w2"], w_scale, P["b2"]),
             g.output())
+    g.plan()
+    return g
+
+
+# ---------------------------------------------------------------------------
+# the vision network's dense layers directly on the image-in-slots conv
+# outputs, summed on the server by rotations (no key rotation)
+# ---------------------------------------------------------------------------
+def slots_dense_masks(W1, slots, block=1024, side=28, out_side=13, stride=2):
+    """masks [n][F][slots]: neuron j's weight for filter f's output (y, x) at
+    that output's anchor 2y * side + 2x in every image block"""
+    n, n_in = W1.shape
+    per_f = out_side * out_side
+    F = n_in // per_f
+    ys, xs = np.divmod(np.arange(per_f), out_side)
+    anchors = stride * ys * side + stride * xs
+    masks = np.zeros((n, F, slots))
+    for base in range(0, slots - block + 1, block):
+        for f in range(F):
+            masks[:, f, base + anchors] = W1[:, f * per_f:(f + 1) * per_f]
+    return masks
+
+
+def block_sum_steps(block=1024):
+    """steps 1, 2, ..., block / 2: rotate-and-sum of a block into its first slot"""
+    return [1 << k for k in range(block.bit_length() - 1)]
+
+
+def slots_dense(ctx, conv_outs, scale, W1, b1, mask_coeffs=None, bias_coeffs=None, block=1024):
+    """Dense layer over the image-in-slots conv outputs conv_outs[f][c]
+    (filter f, ciphertext c): for every neuron j and ciphertext c,
+    sum_f conv_outs[f][c] (x) mask_{j,f}, rescale, rotate-and-sum over the
+    image block (a Galois key per step 1, 2, ..., block/2), + b1[j] at
+    each block's first slot. Batched: one call per operation over all
+    neurons and ciphertexts. Returns outs[j][c] (neuron j's value at each
+    block's first slot)."""
+    F, n_ct = len(conv_outs), len(conv_outs[0])
+    n = W1.shape[0]
+    slots = ctx.N // 2
+    c0 = conv_outs[0][0]
+    level, s_in = c0.level, c0.scale
+    if mask_coeffs is None:
+        masks = slots_dense_masks(W1, slots, block)
+        mask_coeffs = [[ctx.encode_coeffs(masks[j, f], scale) for f in range(F)] for j in range(n)]
+    pts = [[ctx.pt_from_coeffs(mask_coeffs[j][f], level, scale) for f in range(F)] for j in range(n)]
+    acc = None
+    for f in range(F):
+        t = ctx.multiply_plain([conv_outs[f][c] for j in range(n) for c in range(n_ct)],
+                               [pts[j][f] for j in range(n) for c in range(n_ct)])
+        acc = t if acc is None else ctx.add(acc, t)
+    acc = ctx.rescale(acc)
+    for st in block_sum_steps(block):
+        acc = ctx.add(acc, ctx.rotate(acc, step=st))
+    out_scale = acc[0].scale
+    if bias_coeffs is None:
+        bias = np.zeros((n, slots))
+        bias[:, ::block] = np.asarray(b1)[:, None]
+        bias_coeffs = [ctx.encode_coeffs(bias[j], out_scale) for j in range(n)]
+    bpts = [ctx.pt_from_coeffs(bias_coeffs[j], level - 1, out_scale) for j in range(n)]
+    acc = ctx.add_plain(acc, [bpts[j] for j in range(n) for c in range(n_ct)])
+    return [acc[j * n_ct:(j + 1) * n_ct] for j in range(n)]
+
+
+def build_slots_head(ctx, P, n, in_level, scale, w_scale=None):
+    """x^2 -> dense (scalar weights at w_scale, default the context's scale)
+    on the n neuron ciphertexts of slots_dense at (in_level, scale)"""
+    w_scale = w_scale or ctx.default_scale
+    g = Graph(ctx)
+    x = g.input(n, in_level, scale)
+    g.chain(x, g.square(), g.dense(P["w2"], w_scale, P["b2"]), g.output())
     g.plan()
     return g

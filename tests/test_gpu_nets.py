@@ -298,3 +298,65 @@ def test_conv_commuted_key_rotation_network(mods):
     err = _rel_err(got, PN.vision_math(x, P))
     print("commuted conv + key rotation + slot-batched tail: max relative error 2^%.1f" % np.log2(err))
     assert err <= TOL
+
+
+def test_slots_network_rotate_and_sum(mods):
+    # the vision network in the image-in-slots layout with its dense layers
+    # summed on the server (masks + rotate-and-sum per neuron) at N = 2^12,
+    # two images per ciphertext: conv, dense 1 and the head bit-exact vs
+    # the oracle's lowering; logits within tolerance of the FP64 network
+    ckks, nets = mods
+    ctx, orc = _setup(ckks, 12, [60] + [40] * 5, [60], 6, 7)
+    slots = ctx.N // 2
+    x, P = S.vision_inputs(n_images=4)
+    steps, masks, bias = PN.conv_slots_layout(P["conv_w"], P["conv_b"], slots)
+    rs = PN.block_sum_steps()
+    assert nets.block_sum_steps() == rs
+    assert np.array_equal(nets.slots_dense_masks(P["w1"], slots), PN.slots_dense_masks(P["w1"], slots))
+    elts = sorted(set(nets.galois_for_steps(ctx, steps, direct=True)) | set(nets.galois_for_steps(ctx, rs, direct=True)))
+    keys = ON.Keys(orc, 7, elts)
+    for g in elts:
+        ctx.add_galois_key(g, nets.galois_key_seed(7 + 3, g))
+    v = PN.conv_slots_pack(x, slots)
+    n_ct = v.shape[0]
+    cts, ctos = zip(*[_enc_both(ctx, orc, keys, v[c], 5, 5, c) for c in range(n_ct)])
+    mcs = [np.stack([E.encode(masks[f, t], SCALE, ctx.N) for t in range(25)]) for f in range(5)]
+    s1 = SCALE * SCALE / orc.q[5]
+    bcs = [E.encode(bias[f], s1, ctx.N) for f in range(5)]
+    g = nets.build_conv_slots(ctx, P, n_ct, 5, SCALE, mask_coeffs=mcs, bias_coeffs=bcs)
+    outs = g.run(list(cts))
+    conv = [[outs[f * n_ct + c] for c in range(n_ct)] for f in range(5)]
+    conv_o = [ON.conv_slots(orc, keys, ctos[c], SCALE, mcs, steps, [orc.reduce_int(b, 4) for b in bcs], SCALE)
+              for c in range(n_ct)]
+    s = conv_o[0][1]
+    for c in range(n_ct):
+        for f in range(5):
+            assert np.array_equal(conv[f][c].residues(), conv_o[c][0][f])
+    dm = PN.slots_dense_masks(P["w1"], slots)
+    mc = [[E.encode(dm[j, f], SCALE, ctx.N) for f in range(5)] for j in range(100)]
+    s2 = s * SCALE / orc.q[3]
+    bvec = np.zeros((100, slots))
+    bvec[:, ::1024] = P["b1"][:, None]
+    bc = [E.encode(bvec[j], s2, ctx.N) for j in range(100)]
+    h = nets.slots_dense(ctx, conv, SCALE, P["w1"], P["b1"], mask_coeffs=mc, bias_coeffs=bc)
+    want = PN.vision_math(x, P)
+    for c in range(n_ct):
+        print("rotate-and-sum dense, ciphertext %d" % c, flush=True)
+        ho, s3 = ON.slots_dense(orc, keys, [conv_o[c][0][f] for f in range(5)], s, 
+                                [[orc.reduce_int(m, 3) for m in mj] for mj in mc], SCALE,
+                                [orc.reduce_int(b, 2) for b in bc], rs)
+        for j in range(100):
+            assert h[j][c].scale == s3 and np.array_equal(h[j][c].residues(), ho[j]), (c, j)
+        head = nets.build_slots_head(ctx, P, 100, 2, s3)
+        logits = head.run([h[j][c] for j in range(100)])
+        sq = [ON.square(orc, keys, y, s3)[0] for y in ho]
+        s4 = s3 * s3 / orc.q[2]
+        lo, s5 = ON.linear(orc, sq, s4, [[(j, P["w2"][k, j]) for j in range(100)] for k in range(10)], SCALE,
+                           P["b2"])
+        got = np.zeros((2, 10))
+        for k in range(10):
+            assert logits[k].scale == s5 and np.array_equal(logits[k].residues(), lo[k]), (c, k)
+            got[:, k] = ctx.decrypt(logits[k]).real[::1024][:2]
+        err = _rel_err(got, want[2 * c:2 * c + 2])
+        print("image-in-slots network, rotate-and-sum: max relative error 2^%.1f" % np.log2(err))
+        assert err <= TOL

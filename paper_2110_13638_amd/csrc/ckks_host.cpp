@@ -37,8 +37,8 @@ hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u
 hipError_t launch_reduce_weights(const DevTables &tb, const i64 *W, u64 *wt, u32 count, u32 limbs,
                                  hipStream_t s);
 hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pad, u32 k_pad, const u32 *cols,
-                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 limbs,
-                              u32 in_stride, u32 out_stride, hipStream_t s);
+                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 t_lo,
+                              u32 t_cnt, bool small, u32 in_stride, u32 out_stride, hipStream_t s);
 hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,
                                 hipStream_t s);
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
@@ -2515,12 +2515,21 @@ int linear_mfma(const ckks_ctx *c, const ckks_ct *in, u32 n_in, u32 n_out, const
     HIP_TRY(issue(c, s, [w8, o_w, n_out, ncols, rp, kp, wd](hipStream_t st) {
         return launch_weight_digits((const i64 *)(w8 + o_w), n_out, ncols, rp, kp, wd, st);
     }));
-    HIP_TRY(issue(c, s, [tb = c->tb, wd, rp, kp, w8, o_cols, o_ptr, ncols, n_in, n_out, L, stride,
-                         ostride](hipStream_t st) {
-        return launch_linear_mfma(tb, wd, rp, kp, (const u32 *)(w8 + o_cols), ncols, n_out,
-                                  (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L,
-                                  stride, ostride, st);
-    }));
+    // one launch per run of consecutive limbs of one digit count: primes
+    // below 2^42 take six residue digits, larger ones nine
+    for (u32 t0 = 0; t0 < L;) {
+        const bool small = c->primes[t0] < (1ull << 42);
+        u32 t1 = t0 + 1;
+        while (t1 < L && (c->primes[t1] < (1ull << 42)) == small) t1++;
+        const u32 tc = t1 - t0;
+        HIP_TRY(issue(c, s, [tb = c->tb, wd, rp, kp, w8, o_cols, o_ptr, ncols, n_in, n_out, t0, tc, small, stride,
+                             ostride](hipStream_t st) {
+            return launch_linear_mfma(tb, wd, rp, kp, (const u32 *)(w8 + o_cols), ncols, n_out,
+                                      (const u64 *const *)(w8 + o_ptr), (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8),
+                                      t0, tc, small, stride, ostride, st);
+        }));
+        t0 = t1;
+    }
     if (g_prof_on) {
         HIP_TRY(hipEventRecord(rec.e1, s));
         g_prof.push_back(rec);

@@ -587,38 +587,53 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 // tile of 16 consecutive residues (poly p, limb t, slots k0..k0+15); wave w
 // owns output rows 32 (4 blockIdx.y + w) .. +31 (two 16-row MFMA tiles).
 // The four waves share the tile's inputs: per chunk of 64 inputs each
-// thread loads four residues (input 16 v + tid / 16, slot tid % 16), splits
-// them into kXDig 7-bit digits and stores them as int8 B fragments in LDS
-// (double-buffered: the next chunk's residues are loaded while the matrix
-// cores work on the current one). Each wave multiplies the B fragments with
+// thread loads four residues (input 16 v + tid / 16, slot tid % 16; the
+// inputs' pointers staged in LDS two chunks ahead), splits them into XD
+// 7-bit digits (9, or 6 where every prime of the launch is below 2^42) and
+// stores them as int8 B fragments in LDS (double-buffered: the next
+// chunk's residues are loaded while the matrix cores work on the current
+// one). Each wave multiplies the B fragments with
 // its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad], row-major, 16
 // bytes per lane) by v_mfma_i32_16x16x64_i8, accumulating digit products of
 // weight 128^(a + b) together. Lane layout of that instruction (checked on
 // the device): A[l % 16][16 (l / 16) + e], B[16 (l / 16) + e][l % 16]
 // D[4 (l / 16) + r][l % 16].
 typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr int kMfmaS = kWDig + kXDig - 1;  // digit weights 128^0 .. 128^(s-1)
+// XD residue digits: 9 cover primes below 2^63, 6 primes below 2^42 (the
+// 40-bit primes of the network chains: a third fewer digit products)
+template <int XD>
 __global__ void __launch_bounds__(256, 2)
 k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
               u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
-              u32 limbs, u32 in_stride, u32 out_stride) {
+              u32 t_lo, u32 t_cnt, u32 in_stride, u32 out_stride) {
+    constexpr int S = kWDig + XD - 1;  // digit weights 128^0 .. 128^(S-1)
     // B fragments of two chunks: [buffer][digit][slot][lane group], 16 int8 each
-    __shared__ v4i bfrag[2][kXDig][16][4];
+    __shared__ v4i bfrag[2][XD][16][4];
+    // limb-0 pointers of the inputs of two chunks (staged two chunks ahead,
+    // so the residue loads of the next chunk need no dependent global loads)
+    __shared__ const u64 *cptr[2][64];
     const u32 N = 1u << tb.log_n;
     const u32 tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const u32 tile = blockIdx.x;  // 16 residues of one (p, t)
     const u32 pt = (tile * 16) >> tb.log_n, k0 = (tile * 16) & (N - 1);
-    const u32 p = pt / limbs, t = pt - p * limbs;
+    const u32 p = pt / t_cnt, t = t_lo + (pt - p * t_cnt);
     const u32 row0 = (blockIdx.y * 4 + wave) * 32;
     const bool rows = row0 < rows_pad;  // every wave still stages inputs and meets the barriers
     const u32 col = lane & 15, grp = lane >> 4;
     const u32 scol = tid & 15, srow = tid >> 4;  // staging: slot, input within a quarter chunk
     const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + scol;
+    auto stage_ptrs = [&](u32 kc) {
+        if (tid < 64) {
+            const u32 i = kc + tid;
+            cptr[(kc >> 6) & 1][tid] = i < n_in ? in_ptrs[cols[i]] : nullptr;
+        }
+    };
     auto load = [&](u32 kc, u64 (&x)[4]) {
+        const u32 pb = (kc >> 6) & 1;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const u32 i = kc + 16 * v + srow;
-            x[v] = i < n_in ? in_ptrs[cols[i]][in_off] : 0;
+            const u64 *src = cptr[pb][16 * v + srow];
+            x[v] = src ? src[in_off] : 0;
         }
     };
     auto stage = [&](int buf, const u64 (&x)[4]) {
@@ -628,16 +643,19 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
             const u32 ip = 16 * v + srow;  // position in the chunk
             const u32 g = ip >> 4, e = ip & 15;
 #pragma unroll
-            for (int b = 0; b < kXDig; b++)
+            for (int b = 0; b < XD; b++)
                 b8[((b * 16 + scol) * 4 + g) * 16 + e] = (int8_t)((x[v] >> (7 * b)) & 127);
         }
     };
-    v4i acc[2][kMfmaS];
+    v4i acc[2][S];
 #pragma unroll
     for (int h = 0; h < 2; h++)
 #pragma unroll
-        for (int s = 0; s < kMfmaS; s++) acc[h][s] = v4i{0, 0, 0, 0};
+        for (int s = 0; s < S; s++) acc[h][s] = v4i{0, 0, 0, 0};
     const size_t plane = (size_t)rows_pad * k_pad;
+    stage_ptrs(0);
+    if (64 < k_pad) stage_ptrs(64);
+    __syncthreads();
     {
         u64 x[4];
         load(0, x);
@@ -649,10 +667,13 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
         const bool more = kc + 64 < k_pad;
         u64 xn[4] = {0, 0, 0, 0};
         if (more) load(kc + 64, xn);
+        // chunk kc's pointer slot is free: its residues were loaded in the
+        // previous iteration, which ended at a barrier
+        if (kc + 128 < k_pad) stage_ptrs(kc + 128);
         if (rows) {
-            v4i bd[kXDig];
+            v4i bd[XD];
 #pragma unroll
-            for (int b = 0; b < kXDig; b++) bd[b] = bfrag[buf][b][col][grp];
+            for (int b = 0; b < XD; b++) bd[b] = bfrag[buf][b][col][grp];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 16 * grp;
@@ -660,7 +681,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
                 for (int a = 0; a < kWDig; a++) {
                     const v4i ad = *reinterpret_cast<const v4i *>(wd + a * plane + aoff);
 #pragma unroll
-                    for (int b = 0; b < kXDig; b++)
+                    for (int b = 0; b < XD; b++)
                         acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
                 }
             }
@@ -676,10 +697,10 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const u32 j = row0 + 16 * h + 4 * grp + r;
-            // v = sum_s acc_s 2^(7 s), signed, |v| < 2^120
+            // v = sum_s acc_s 2^(7 s), signed, |v| < 2^(7 S + 32)
             __int128 v = 0;
 #pragma unroll
-            for (int s = kMfmaS - 1; s >= 0; s--) v = v * 128 + (__int128)acc[h][s][r];
+            for (int s = S - 1; s >= 0; s--) v = v * 128 + (__int128)acc[h][s][r];
             const bool neg = v < 0;
             const unsigned __int128 m = neg ? (unsigned __int128)(-v) : (unsigned __int128)v;
             const u64 red = barrett128((u64)m, (u64)(m >> 64), pc);
@@ -823,14 +844,20 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
                        wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
     return hipGetLastError();
 }
+// limbs t_lo .. t_lo + t_cnt - 1 of both polys; `small`: all their primes
+// are below 2^42 (six residue digits)
 hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pad, u32 k_pad, const u32 *cols,
-                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 limbs,
-                              u32 in_stride, u32 out_stride, hipStream_t s) {
+                              u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 t_lo,
+                              u32 t_cnt, bool small, u32 in_stride, u32 out_stride, hipStream_t s) {
     const u32 N = 1u << tb.log_n;
-    const u32 tiles = (u32)(((size_t)2 * limbs * N) / 16);
+    const u32 tiles = (u32)(((size_t)2 * t_cnt * N) / 16);
     const u32 row_blocks = (rows_pad + 127) / 128;
-    hipLaunchKernelGGL(k_linear_mfma, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad, cols, n_in,
-                       n_out, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
+    if (small)
+        hipLaunchKernelGGL(k_linear_mfma<6>, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad, cols,
+                           n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
+    else
+        hipLaunchKernelGGL(k_linear_mfma<kXDig>, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad,
+                           cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
     return hipGetLastError();
 }
 hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,

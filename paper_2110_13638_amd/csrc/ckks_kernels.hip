@@ -513,73 +513,118 @@ k_linear(DevTables tb, const u64 *const *__restrict__ in_ptrs, const u64 *__rest
     }
 }
 
-// Grouped sparse linear layer. One thread owns one residue position
-// (poly p, limb t, slot k) of one row group: it loads each of the group's
-// input residues once and accumulates all of the group's rows in 128-bit
-// accumulators. Weights (reduced mod q_t, layout [t][w]) and the group
-// descriptor are wave-uniform and read through the scalar cache.
+// Grouped sparse linear layer. One thread owns kLinRes consecutive residue
+// positions (poly p, limb t, slots k .. k + kLinRes - 1) of one row group:
+// it loads each of the group's input residues once (two 16-byte loads per
+// column) and accumulates all of the group's rows. Weights (reduced mod
+// q_t, layout [t][w]) and the group descriptor are wave-uniform and read
+// through the scalar cache; the next column's input pointer is fetched
+// while the current column is multiplied.
+constexpr int kLinRes = 4;
 __global__ void __launch_bounds__(256)
 k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups, const u32 *__restrict__ cols,
                  const u64 *__restrict__ wt, const double2 *__restrict__ wf, u32 wt_stride,
                  const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs, u32 limbs, u32 in_stride,
                  u32 out_stride) {
-    const u32 N = 1u << tb.log_n;
-    const size_t per_group = (size_t)2 * limbs * N;
+    const u32 N = 1u << tb.log_n, NQ = N / kLinRes;
+    const size_t per_group = (size_t)2 * limbs * NQ;
     const size_t total = per_group * n_groups;
     for (size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
          g += (size_t)gridDim.x * blockDim.x) {
-        // N >= 64 and k fastest: (group, p, t) is uniform across a wave
+        // NQ >= 256 and k fastest: (group, p, t) is uniform across a wave
         const u32 gi = __builtin_amdgcn_readfirstlane((u32)(g / per_group));
         const u32 rem = (u32)(g - (size_t)gi * per_group);
-        const u32 pt = __builtin_amdgcn_readfirstlane(rem >> tb.log_n);
-        const u32 k = rem & (N - 1);
+        const u32 pt = __builtin_amdgcn_readfirstlane(rem / NQ);
+        const u32 k = (rem - pt * NQ) * kLinRes;
         const u32 p = pt / limbs, t = pt - p * limbs;
         const LinGroup G = groups[gi];
         const PrimeConst pc = tb.pc[t];
         const size_t in_off = ((size_t)p * in_stride + t) * N + k;
         const size_t out_off = ((size_t)p * out_stride + t) * N + k;
+        const u32 *gc = cols + G.col_off;
+        auto load4 = [&](const u64 *src, u64 (&x)[kLinRes]) {
+            const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(src + in_off);
+            const ulonglong2 b = *reinterpret_cast<const ulonglong2 *>(src + in_off + 2);
+            x[0] = a.x, x[1] = a.y, x[2] = b.x, x[3] = b.y;
+        };
+        auto store4 = [&](u32 row, const u64 (&y)[kLinRes]) {
+            u64 *dst = out_ptrs[row] + out_off;
+            *reinterpret_cast<ulonglong2 *>(dst) = ulonglong2{y[0], y[1]};
+            *reinterpret_cast<ulonglong2 *>(dst + 2) = ulonglong2{y[2], y[3]};
+        };
         if (tb.ntt_fp && pc.q < kFpPrimeBound) {
             // FP64: products by (w, w/q) from the table, |term| < q, sums
             // re-centred every four columns (wave-uniform branch on the limb)
 #pragma clang fp contract(off)
             const double2 *wv = wf + (size_t)t * wt_stride + G.w_off;
             const double q = pc.qf, qinv = pc.qinvf;
-            double acc[kLinRows];
+            double acc[kLinRows][kLinRes];
 #pragma unroll
-            for (int r = 0; r < kLinRows; r++) acc[r] = 0.0;
+            for (int r = 0; r < kLinRows; r++)
+#pragma unroll
+                for (int e = 0; e < kLinRes; e++) acc[r][e] = 0.0;
+            const u64 *next = in_ptrs[gc[0]];
             for (u32 c = 0; c < G.ncols; c++) {
-                const double x = fp_from_u64(in_ptrs[cols[G.col_off + c]][in_off]);
+                u64 xi[kLinRes];
+                load4(next, xi);
+                if (c + 1 < G.ncols) next = in_ptrs[gc[c + 1]];
+                double x[kLinRes];
+#pragma unroll
+                for (int e = 0; e < kLinRes; e++) x[e] = fp_from_u64(xi[e]);
 #pragma unroll
                 for (int r = 0; r < kLinRows; r++)
                     if ((u32)r < G.nrows) {
                         const double2 w2 = wv[(size_t)r * G.ncols + c];
-                        acc[r] = acc[r] + fp_mulmod(x, w2.x, w2.y, q);
+#pragma unroll
+                        for (int e = 0; e < kLinRes; e++) acc[r][e] = acc[r][e] + fp_mulmod(x[e], w2.x, w2.y, q);
                     }
                 if ((c & 3) == 3) {
 #pragma unroll
-                    for (int r = 0; r < kLinRows; r++) acc[r] = fp_center(acc[r], q, qinv);
+                    for (int r = 0; r < kLinRows; r++)
+#pragma unroll
+                        for (int e = 0; e < kLinRes; e++) acc[r][e] = fp_center(acc[r][e], q, qinv);
                 }
             }
 #pragma unroll
             for (int r = 0; r < kLinRows; r++)
-                if ((u32)r < G.nrows) out_ptrs[G.row0 + r][out_off] = fp_to_residue(fp_center(acc[r], q, qinv), pc.qmf, pc.q);
+                if ((u32)r < G.nrows) {
+                    u64 y[kLinRes];
+#pragma unroll
+                    for (int e = 0; e < kLinRes; e++)
+                        y[e] = fp_to_residue(fp_center(acc[r][e], q, qinv), pc.qmf, pc.q);
+                    store4(G.row0 + r, y);
+                }
             continue;
         }
+        // 64-bit integer engine: 128-bit sums folded every kLinFold columns,
+        // two residues at a time (the sums of all rows stay in registers)
         const u64 *w = wt + (size_t)t * wt_stride + G.w_off;
-        Acc128 acc[kLinRows];
-        for (u32 c = 0; c < G.ncols; c++) {
-            const u64 x = in_ptrs[cols[G.col_off + c]][in_off];
+        for (int h = 0; h < kLinRes; h += 2) {
+            Acc128 acc[kLinRows][2];
+            for (u32 c = 0; c < G.ncols; c++) {
+                const u64 *src = in_ptrs[gc[c]] + in_off + h;
+                const ulonglong2 x = *reinterpret_cast<const ulonglong2 *>(src);
+#pragma unroll
+                for (int r = 0; r < kLinRows; r++)
+                    if ((u32)r < G.nrows) {
+                        const u64 wr = w[(size_t)r * G.ncols + c];
+                        acc[r][0].mac(x.x, wr);
+                        acc[r][1].mac(x.y, wr);
+                    }
+                if ((c & (kLinFold - 1)) == kLinFold - 1) {
+#pragma unroll
+                    for (int r = 0; r < kLinRows; r++) {
+                        acc[r][0] = Acc128{acc[r][0].reduce(pc), 0};
+                        acc[r][1] = Acc128{acc[r][1].reduce(pc), 0};
+                    }
+                }
+            }
 #pragma unroll
             for (int r = 0; r < kLinRows; r++)
-                if ((u32)r < G.nrows) acc[r].mac(x, w[(size_t)r * G.ncols + c]);
-            if ((c & (kLinFold - 1)) == kLinFold - 1) {
-#pragma unroll
-                for (int r = 0; r < kLinRows; r++) acc[r] = Acc128{acc[r].reduce(pc), 0};
-            }
+                if ((u32)r < G.nrows)
+                    *reinterpret_cast<ulonglong2 *>(out_ptrs[G.row0 + r] + out_off + h) =
+                        ulonglong2{acc[r][0].reduce(pc), acc[r][1].reduce(pc)};
         }
-#pragma unroll
-        for (int r = 0; r < kLinRows; r++)
-            if ((u32)r < G.nrows) out_ptrs[G.row0 + r][out_off] = acc[r].reduce(pc);
     }
 }
 
@@ -839,7 +884,7 @@ hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
                                  const u64 *wt, const double2 *wf, u32 wt_stride, const u64 *const *in_ptrs,
                                  u64 *const *out_ptrs, u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s) {
-    const size_t work = ((size_t)2 * limbs << tb.log_n) * n_groups;
+    const size_t work = (((size_t)2 * limbs << tb.log_n) / kLinRes) * n_groups;
     hipLaunchKernelGGL(k_linear_grouped, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt, wf,
                        wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
     return hipGetLastError();

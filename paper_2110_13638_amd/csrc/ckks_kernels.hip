@@ -134,62 +134,107 @@ __device__ __forceinline__ double fp_mulv(double x, double y, double t, double t
 // digit term is an FP64 product (<= 0.75 t), sums are re-centred every four
 // digits, the P d fold multiplies by P mod t (ratio P/t from 1/t, error
 // <= 2^-52), and the final re-centred sum (|.| <= t/2 + 1) becomes a residue.
+// Each thread takes kEwPer residues as pairs (16-byte loads and stores);
+// the digit loop is unrolled for BETA digits (0: a runtime loop).
+template <int kEwPer, int NCT, int BETA>
+__device__ __forceinline__ void ip_fp_item(const DevTables &tb, const IpItem &it, u32 chunk) {
+#pragma clang fp contract(off)
+    const u32 N = 1u << tb.log_n;
+    const PrimeConst pc = tb.pc[it.prime];
+    const double t = pc.qf, tinv = pc.qinvf;
+    const double pm = fp_from_u64(pc.pmod), pmq = pm * tinv;
+    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
+    const u32 beta = BETA ? (u32)BETA : it.beta;
+    auto ld2 = [](const u64 *p, u32 x, double (&v)[2]) {
+        const ulonglong2 a = *reinterpret_cast<const ulonglong2 *>(p + x);
+        v[0] = fp_from_u64(a.x);
+        v[1] = fp_from_u64(a.y);
+    };
+#pragma unroll
+    for (int e = 0; e < kEwPer / 2; e++) {
+        const u32 x = 2 * ((chunk * (kEwPer / 2) + e) * 256 + threadIdx.x);
+        if (x >= N) break;
+        double s0[NCT][2], s1[NCT][2];
+#pragma unroll
+        for (int c = 0; c < NCT; c++) s0[c][0] = s0[c][1] = s1[c][0] = s1[c][1] = 0.0;
+        auto digit = [&](u32 j) {
+            const u64 *kb = it.key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
+            double k0[2], k1[2];
+            ld2(kb, x, k0);
+            ld2(kb + kstride, x, k1);
+#pragma unroll
+            for (int c = 0; c < NCT; c++) {
+                if ((u32)c >= it.n_ct) break;
+                double v[2];
+                if (j == it.own_digit) {
+                    ld2(it.own0[c], x, v);
+                    if (it.own1[c]) {
+                        double w[2];
+                        ld2(it.own1[c], x, w);
+                        v[0] = fp_mulv(v[0], w[0], t, tinv);
+                        v[1] = fp_mulv(v[1], w[1], t, tinv);
+                    }
+                } else {
+                    ld2(it.ext[c] + ((size_t)j * it.E + it.pos) * N, x, v);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    s0[c][h] = s0[c][h] + fp_mulv(v[h], k0[h], t, tinv);
+                    s1[c][h] = s1[c][h] + fp_mulv(v[h], k1[h], t, tinv);
+                    if ((j & 3) == 3) {
+                        s0[c][h] = fp_center(s0[c][h], t, tinv);
+                        s1[c][h] = fp_center(s1[c][h], t, tinv);
+                    }
+                }
+            }
+        };
+        if constexpr (BETA > 0) {
+#pragma unroll
+            for (int j = 0; j < BETA; j++) digit((u32)j);
+        } else {
+            for (u32 j = 0; j < beta; j++) digit(j);
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; c++) {
+            if ((u32)c >= it.n_ct) break;
+            double r0[2], r1[2];
+#pragma unroll
+            for (int h = 0; h < 2; h++) r0[h] = fp_center(s0[c][h], t, tinv), r1[h] = fp_center(s1[c][h], t, tinv);
+            if (it.own2[c]) {
+                double a0[2], b0[2], a1[2], b1[2];
+                ld2(it.own2[c], x, a0);
+                ld2(it.own3[c], x, b0);
+                ld2(it.own0[c], x, a1);
+                ld2(it.own1[c], x, b1);
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const double d0 = fp_mulv(a0[h], b0[h], t, tinv);
+                    const double d1 = fp_mulv(a0[h], b1[h], t, tinv) + fp_mulv(a1[h], b0[h], t, tinv);
+                    r0[h] = fp_center(r0[h] + fp_mulmod(d0, pm, pmq, t), t, tinv);
+                    r1[h] = fp_center(r1[h] + fp_mulmod(d1, pm, pmq, t), t, tinv);
+                }
+            }
+            *reinterpret_cast<ulonglong2 *>(it.acc[c] + (size_t)it.pos * N + x) =
+                ulonglong2{fp_to_residue(r0[0], pc.qmf, pc.q), fp_to_residue(r0[1], pc.qmf, pc.q)};
+            *reinterpret_cast<ulonglong2 *>(it.acc[c] + ((size_t)it.E + it.pos) * N + x) =
+                ulonglong2{fp_to_residue(r1[0], pc.qmf, pc.q), fp_to_residue(r1[1], pc.qmf, pc.q)};
+        }
+    }
+}
 template <int kEwPer, int NCT>
 __global__ void __launch_bounds__(256) k_ip_fp(DevTables tb, const IpItem *__restrict__ items, int nitems) {
-#pragma clang fp contract(off)
     const u32 N = 1u << tb.log_n;
     const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
     const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
     const u32 chunk = blockIdx.x - iid * per_item;
     if ((int)iid >= nitems) return;
     const IpItem it = items[iid];
-    const PrimeConst pc = tb.pc[it.prime];
-    const double t = pc.qf, tinv = pc.qinvf;
-    const double pm = fp_from_u64(pc.pmod), pmq = pm * tinv;
-    const size_t kstride = (size_t)tb.n_prim * N;  // one key component
-#pragma unroll
-    for (int e = 0; e < kEwPer; e++) {
-        const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
-        if (x >= N) break;
-        double s0[NCT], s1[NCT];
-#pragma unroll
-        for (int c = 0; c < NCT; c++) s0[c] = s1[c] = 0.0;
-        for (u32 j = 0; j < it.beta; j++) {
-            const u64 *kb = it.key + (size_t)(2 * j) * kstride + (size_t)it.prime * N;
-            const double k0 = fp_from_u64(kb[x]), k1 = fp_from_u64(kb[kstride + x]);
-#pragma unroll
-            for (int c = 0; c < NCT; c++) {
-                if ((u32)c >= it.n_ct) break;
-                double v;
-                if (j == it.own_digit) {
-                    const double o = fp_from_u64(it.own0[c][x]);
-                    v = it.own1[c] ? fp_mulv(o, fp_from_u64(it.own1[c][x]), t, tinv) : o;
-                } else {
-                    v = fp_from_u64(it.ext[c][((size_t)j * it.E + it.pos) * N + x]);
-                }
-                s0[c] = s0[c] + fp_mulv(v, k0, t, tinv);
-                s1[c] = s1[c] + fp_mulv(v, k1, t, tinv);
-                if ((j & 3) == 3) {
-                    s0[c] = fp_center(s0[c], t, tinv);
-                    s1[c] = fp_center(s1[c], t, tinv);
-                }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NCT; c++) {
-            if ((u32)c >= it.n_ct) break;
-            double r0 = fp_center(s0[c], t, tinv), r1 = fp_center(s1[c], t, tinv);
-            if (it.own2[c]) {
-                const double a0 = fp_from_u64(it.own2[c][x]), b0 = fp_from_u64(it.own3[c][x]);
-                const double a1 = fp_from_u64(it.own0[c][x]), b1 = fp_from_u64(it.own1[c][x]);
-                const double d0 = fp_mulv(a0, b0, t, tinv);
-                const double d1 = fp_mulv(a0, b1, t, tinv) + fp_mulv(a1, b0, t, tinv);
-                r0 = fp_center(r0 + fp_mulmod(d0, pm, pmq, t), t, tinv);
-                r1 = fp_center(r1 + fp_mulmod(d1, pm, pmq, t), t, tinv);
-            }
-            it.acc[c][(size_t)it.pos * N + x] = fp_to_residue(r0, pc.qmf, pc.q);
-            it.acc[c][((size_t)it.E + it.pos) * N + x] = fp_to_residue(r1, pc.qmf, pc.q);
-        }
+    switch (it.beta) {
+        case 1: ip_fp_item<kEwPer, NCT, 1>(tb, it, chunk); break;
+        case 2: ip_fp_item<kEwPer, NCT, 2>(tb, it, chunk); break;
+        case 3: ip_fp_item<kEwPer, NCT, 3>(tb, it, chunk); break;
+        case 4: ip_fp_item<kEwPer, NCT, 4>(tb, it, chunk); break;
+        default: ip_fp_item<kEwPer, NCT, 0>(tb, it, chunk); break;
     }
 }
 

@@ -272,6 +272,50 @@ def serve_leg(args, dev, log, tuning=None):
             "saturation": sat, "load": load}
 
 
+def stream_chunks_leg(args, ctx, A, Bc, outs, top, log, ks=(1, 2, 4, 8)):
+    """The headline batch split into K chunks issued on K streams (each
+    chunk its own workspace and six launches), so that different chunks'
+    stages run on the GPU at the same time: the overlap a persistent fused
+    kernel would have to win. ms per 256 pairs for each K."""
+    import ctypes
+    import torch
+    from paper_2110_13638_amd import _native as nat
+    dev, rk, B = ctx.device, ctx.rk.data_ptr(), len(A)
+    main = torch.cuda.current_stream(dev)
+    out = {}
+    for K in ks:
+        if B % K:
+            continue
+        c = B // K
+        chunks = []
+        for k in range(K):
+            sl = slice(k * c, (k + 1) * c)
+            nb = nat.ckks_workspace_bytes(ctx.h, nat.CKKS_OP_HMULT, c, [top] * c)
+            buf = torch.empty(nb + 512, dtype=torch.uint8, device=dev)
+            st = torch.cuda.Stream(device=dev) if K > 1 else main
+            chunks.append((ctx._structs(A[sl]), ctx._structs(Bc[sl]), ctx._structs(outs[sl]), buf,
+                           ctypes.c_void_p((buf.data_ptr() + 255) & ~255), nb, st))
+
+        def run():
+            for sa, sb, so, _, ws, nb, st in chunks:
+                st.wait_stream(main)
+                nat.ckks_hmult_relin_rescale(ctx.h, rk, sa, sb, so, ws, nb, ctypes.c_void_p(st.cuda_stream))
+            for ch in chunks:
+                main.wait_stream(ch[6])
+
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            run()
+        torch.cuda.synchronize()
+        out["K=%d" % K] = round(1e3 * (time.perf_counter() - t0) / args.steps, 3)
+        del chunks
+    torch.cuda.empty_cache()
+    log("batch in K chunks on K streams, ms per step: %s" % out)
+    return out
+
+
 def extra_legs(args, ctx, res, A, Bc, outs, B, top, value):
     """Ragged batch, plain one-op-per-launch path and NTT microbench."""
     import numpy as np
@@ -699,8 +743,12 @@ def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
 
 
 # int8 operations of one modular multiply-add on the matrix cores: 6 signed
-# weight digits x 9 residue digits, each product a multiply and an add
-MFMA_OPS_PER_MAC = 2 * 6 * 9
+# weight digits x XD residue digits, each product a multiply and an add;
+# XD = 6 for limbs of primes below 2^42, else 9
+def mfma_ops_per_mac(q):
+    return 2 * 6 * (6 if q < (1 << 42) else 9)
+
+
 INT8_PEAK_TOPS = 5000.0  # dense int8 MFMA, MI355X
 
 
@@ -732,7 +780,7 @@ def vision_linear_roofline(recs, P, ctx):
     for name, (n_out, n_in, L), rec in zip(("dense1", "dense2"), ((100, 845, 6), (10, 100, 4)), mfma):
         ms = rec[2]
         macs = n_out * n_in * 2 * L * N
-        ops = MFMA_OPS_PER_MAC * macs
+        ops = sum(mfma_ops_per_mac(q) for q in ctx.q[:L]) * n_out * n_in * 2 * N
         nbytes = (n_in + n_out) * 2 * L * lb
         out[name] = {"kernel": "k_linear_mfma (int8 matrix cores)", "ms": ms, "modular_macs": macs,
                      "mfma": {"achieved": ops / (ms * 1e-3) / 1e12, "peak": INT8_PEAK_TOPS, "unit": "TOPS int8",
@@ -972,9 +1020,10 @@ def main():
         (dom, d["ms_per_step"], d["launches_per_step"], bound, prim["achieved"], prim["unit"], 100 * prim["frac"],
          other["unit"], 100 * other["frac"]))
 
-    ragged_rate = plain_rate = same = ntt = None
+    ragged_rate = plain_rate = same = ntt = chunks = None
     if not args.no_extra:
         ragged_rate, plain_rate, same, ntt = extra_legs(args, ctx, res, A, Bc, outs, B, top, value)
+        chunks = stream_chunks_leg(args, ctx, A, Bc, outs, top, log)
 
     # ---- oracle on the host cores, bounded sample of the same workload
     cpu = None if args.no_cpu else cpu_leg(args, q, p, A, Bc, outs, ntt, log)
@@ -1000,7 +1049,8 @@ def main():
                   "plain_one_op_per_launch_hmult_per_s": plain_rate and round(plain_rate, 2),
                   "batched_over_plain": plain_rate and round(value / plain_rate, 2),
                   "plain_equals_fused": same, "tuning": tuning,
-                  "ntt": ntt, "kernels": breakdown, "networks": networks, "serving": serving},
+                  "ntt": ntt, "kernels": breakdown, "stream_chunks_ms_per_step": chunks,
+                  "networks": networks, "serving": serving},
     }
     print(json.dumps(line))
 

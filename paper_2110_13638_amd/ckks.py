@@ -164,7 +164,10 @@ class Context:
                 torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            nat.ckks_ctx_destroy(h)
+            # at interpreter exit the binding module may already be torn down
+            destroy = getattr(nat, "ckks_ctx_destroy", None)
+            if destroy is not None:
+                destroy(h)
             self.h = None
 
     # --- plumbing -----------------------------------------------------------

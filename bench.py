@@ -452,6 +452,18 @@ def ntt_rings(dev, total_residues, tuning):
     return out
 
 
+def net_tune(ctx, fn, workload, base):
+    """Launch shapes for a network inference: the headline ring's setting
+    with the knobs that depend on the ring and the workload (residues per
+    NTT thread, inner-product group, streaming granularity) searched on the
+    inference itself."""
+    from paper_2110_13638_amd import tune
+    space = {k: (v,) for k, v in (base or {}).items()}
+    space.update({"ntt_wide": (0, 1), "ip_cts": (2, 4), "ew_log": (1, 2, 3)})
+    best, times = tune.autotune(ctx, fn, workload, space=space, reps=1)
+    return {"setting": best, "candidates_ms": {k: round(v, 3) for k, v in times.items()}}
+
+
 def nets_leg(args, dev, log, tuning=None):
     """Encrypted inference at full size: the vision network on 8192 images
     (N = 2^14, [60, 40 x 7 | 60], one ciphertext per pixel, slot-batched) and
@@ -478,6 +490,8 @@ def nets_leg(args, dev, log, tuning=None):
     g = nets.build_vision(ctx, P, 28, 7, scale)
     g.run(cts)
     torch.cuda.synchronize()
+    vis_tuning = net_tune(ctx, lambda: g.run(cts), "vision-8192", tuning)
+    log("vision launch shapes: %s" % vis_tuning["setting"])
     t0 = time.perf_counter()
     for _ in range(args.net_runs):
         g.run(cts)
@@ -496,7 +510,7 @@ def nets_leg(args, dev, log, tuning=None):
                      "security": security_label(14, pr)["label"],
                      "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
                      "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])},
-                     "linear_layers": linear_roofline}
+                     "linear_layers": linear_roofline, "tuning": vis_tuning}
     log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
     # the same inference recorded once and replayed as a HIP graph: new
     # images are written into the recorded input ciphertexts, no host work
@@ -602,6 +616,8 @@ def nets_leg(args, dev, log, tuning=None):
     g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
     g.run(cts)
     torch.cuda.synchronize()
+    yield_tuning = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted", tuning)
+    log("yield launch shapes: %s" % yield_tuning["setting"])
     t0 = time.perf_counter()
     for _ in range(args.net_runs):
         g.run(cts)
@@ -610,7 +626,8 @@ def nets_leg(args, dev, log, tuning=None):
     out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys, "
                               "hoisted rotations" % (len(cts), len(ctx.gk)),
                     "security": security_label(14, pr)["label"],
-                    "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
+                    "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt,
+                    "tuning": yield_tuning}
     log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
     return out
 

@@ -128,7 +128,9 @@ uint64_t ckks_ctx_prime(const ckks_ctx *ctx, uint32_t index);
  * limb_stride >= level + 1 is the number of limbs allocated per poly, so
  * that switching down the modulus chain (the level matching of Section 4.1)
  * is a change of 'level' only. n_poly is 2, or 3 straight after a
- * tensor product. */
+ * tensor product. data (and every plaintext and key buffer) must be
+ * 16-byte aligned, as any device allocation is: kernels move residues in
+ * pairs. Calls return CKKS_EINVAL for a null or misaligned buffer. */
 typedef struct {
     uint64_t *data;
     uint32_t n_poly;

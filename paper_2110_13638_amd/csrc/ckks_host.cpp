@@ -1198,8 +1198,11 @@ int check_ctx(const ckks_ctx *c) {
     if (!c->uploaded) return fail(CKKS_EINVAL, "context tables not uploaded (ckks_ctx_upload)");
     return CKKS_OK;
 }
+// device buffers of ciphertexts and plaintexts: the kernels move residues
+// in 16-byte pairs
+inline bool bad_ptr(const void *p) { return !p || (((uintptr_t)p) & 15); }
 int check_ct(const ckks_ctx *c, const ckks_ct &ct, const char *what) {
-    if (!ct.data) return fail(CKKS_EINVAL, "%s: null data", what);
+    if (bad_ptr(ct.data)) return fail(CKKS_EINVAL, "%s: null or not 16-byte aligned data", what);
     if (ct.level >= c->n_q) return fail(CKKS_ELEVEL, "%s: level %u beyond top %u", what, ct.level, c->n_q - 1);
     if (ct.limb_stride < ct.level + 1) return fail(CKKS_EINVAL, "%s: limb_stride < level + 1", what);
     if (ct.n_poly < 2 || ct.n_poly > 3) return fail(CKKS_EINVAL, "%s: n_poly must be 2 or 3", what);
@@ -1817,7 +1820,7 @@ static int ew_binary(const ckks_ctx *c, u32 op, const ckks_ct *a, const ckks_ct 
     std::vector<EwItem> items;
     for (u32 k = 0; k < B; k++) {
         CK(check_ct(c, a[k], name));
-        if (!out[k].data) return fail(CKKS_EINVAL, "%s: null output", name);
+        if (bad_ptr(out[k].data)) return fail(CKKS_EINVAL, "%s: null or unaligned output", name);
         const u32 L = a[k].level + 1;
         u32 n_poly_out = a[k].n_poly;
         double scale = a[k].scale;
@@ -1837,7 +1840,7 @@ static int ew_binary(const ckks_ctx *c, u32 op, const ckks_ct *a, const ckks_ct 
             }
         }
         if (p) {
-            if (!p[k].data) return fail(CKKS_EINVAL, "%s: null plaintext", name);
+            if (bad_ptr(p[k].data)) return fail(CKKS_EINVAL, "%s: null or unaligned plaintext", name);
             if (p[k].level < a[k].level) return fail(CKKS_ELEVEL, "%s: plaintext level below ciphertext", name);
             if (op == EW_ADD && a[k].scale != p[k].scale)
                 return fail(CKKS_ESCALE, "%s: scales %.17g vs %.17g differ", name, a[k].scale, p[k].scale);
@@ -1949,9 +1952,10 @@ extern "C" int ckks_relinearize(const ckks_ctx *c, const uint64_t *const *rk, co
     std::vector<KsJob> jobs(B);
     for (u32 k = 0; k < B; k++) {
         if (!rk[k]) return fail(CKKS_ENOKEY, "relinearize: null key for item %u", k);
+        if (bad_ptr(rk[k])) return fail(CKKS_EINVAL, "relinearize: key of item %u not 16-byte aligned", k);
         CK(check_ct(c, in3[k], "relinearize"));
         if (in3[k].n_poly != 3) return fail(CKKS_EINVAL, "relinearize: input must have 3 polys");
-        if (!out[k].data) return fail(CKKS_EINVAL, "relinearize: null output");
+        if (bad_ptr(out[k].data)) return fail(CKKS_EINVAL, "relinearize: null or unaligned output");
         if (out[k].data == in3[k].data) return fail(CKKS_EINVAL, "relinearize: out must not alias in");
         const u32 L = in3[k].level + 1;
         if (out[k].limb_stride < L) out[k].limb_stride = L;
@@ -1985,9 +1989,11 @@ extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *const *gk, const u
         const u32 g = galois_elts[k];
         if (!(g & 1) || g >= 2 * c->N) return fail(CKKS_EINVAL, "rotate: Galois element %u not odd / < 2N", g);
         if (!gk[k]) return fail(CKKS_ENOKEY, "rotate: null Galois key for item %u", k);
+        if (bad_ptr(gk[k])) return fail(CKKS_EINVAL, "rotate: key of item %u not 16-byte aligned", k);
         CK(check_ct(c, in[k], "rotate"));
         if (in[k].n_poly != 2) return fail(CKKS_EINVAL, "rotate: input must have 2 polys");
-        if (!out[k].data || out[k].data == in[k].data) return fail(CKKS_EINVAL, "rotate: out null or aliasing in");
+        if (bad_ptr(out[k].data) || out[k].data == in[k].data)
+            return fail(CKKS_EINVAL, "rotate: out null, unaligned or aliasing in");
         const u32 L = in[k].level + 1, N = c->N;
         if (out[k].limb_stride < L) out[k].limb_stride = L;
         u64 *rot = P.limbs(2 * L);
@@ -2030,7 +2036,7 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
     for (u32 k = 0; k < B; k++) {
         CK(check_ct(c, in[k], "rescale"));
         if (in[k].level == 0) return fail(CKKS_EDEPTH, "rescale: no prime left (level 0)");
-        if (!out[k].data) return fail(CKKS_EINVAL, "rescale: null output");
+        if (bad_ptr(out[k].data)) return fail(CKKS_EINVAL, "rescale: null or unaligned output");
         const u32 l = in[k].level;
         ckks_ct o = out[k];
         if (o.data == in[k].data) o.limb_stride = in[k].limb_stride;
@@ -2224,12 +2230,13 @@ extern "C" int ckks_hmult_relin_rescale(const ckks_ctx *c, const uint64_t *const
     if (!rk || !a || !b || !out) return fail(CKKS_EINVAL, "hmult: null argument");
     for (u32 x = 0; x < B; x++) {
         if (!rk[x]) return fail(CKKS_ENOKEY, "hmult: null relinearisation key for item %u", x);
+        if (bad_ptr(rk[x])) return fail(CKKS_EINVAL, "hmult: key of item %u not 16-byte aligned", x);
         CK(check_ct(c, a[x], "hmult a"));
         CK(check_ct(c, b[x], "hmult b"));
         if (a[x].n_poly != 2 || b[x].n_poly != 2) return fail(CKKS_EINVAL, "hmult: inputs must have 2 polys");
         if (a[x].level != b[x].level) return fail(CKKS_ELEVEL, "hmult: levels %u vs %u", a[x].level, b[x].level);
         if (a[x].level == 0) return fail(CKKS_EDEPTH, "hmult: no prime left to rescale");
-        if (!out[x].data) return fail(CKKS_EINVAL, "hmult: null output");
+        if (bad_ptr(out[x].data)) return fail(CKKS_EINVAL, "hmult: null or unaligned output");
         if (out[x].data == a[x].data || out[x].data == b[x].data)
             return fail(CKKS_EINVAL, "hmult: out must not alias an input");
         if (out[x].limb_stride < a[x].level) out[x].limb_stride = a[x].level;
@@ -2270,7 +2277,7 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
         CK(check_ct(c, in[x], "hoisted"));
         if (in[x].n_poly != 2) return fail(CKKS_EINVAL, "hoisted: inputs must have 2 polys");
         if (in[x].level != l) return fail(CKKS_ELEVEL, "hoisted: input levels differ");
-        if (!out[x].data) return fail(CKKS_EINVAL, "hoisted: null output");
+        if (bad_ptr(out[x].data)) return fail(CKKS_EINVAL, "hoisted: null or unaligned output");
         if (out[x].data == in[x].data) return fail(CKKS_EINVAL, "hoisted: out must not alias the input");
         if (out[x].limb_stride < L) out[x].limb_stride = L;
     }
@@ -2278,6 +2285,7 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
         const u32 g = galois_elts[i];
         if (!(g & 1) || g >= 2 * N) return fail(CKKS_EINVAL, "hoisted: bad Galois element %u", g);
         if (g != 1 && (!galois_keys || !galois_keys[i])) return fail(CKKS_ENOKEY, "hoisted: no key for element %u", g);
+        if (g != 1 && bad_ptr(galois_keys[i])) return fail(CKKS_EINVAL, "hoisted: key for element %u not 16-byte aligned", g);
     }
     if ((size_t)n_rot * 12 > (size_t)N * 8) return fail(CKKS_EINVAL, "hoisted: too many rotations");
     const size_t need = ckks_hoisted_linear_workspace_bytes(c, B, l, n_rot);

@@ -62,6 +62,19 @@ def test_error_paths(small):
         nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr(), ctx._structs([a] * 64), ctx._structs([a] * 64),
                                      ctx._structs([ctx.new_ct(2, 1) for _ in range(64)]), ws, 4096, ctx.stream)
     assert e.value.code == nat.CKKS_ENOMEM
+    # ciphertext and key buffers must be 16-byte aligned (residues move in pairs);
+    # rejected on the host before anything is launched
+    wsb, wbb = ctx.ws_for(nat.CKKS_OP_HMULT, 1, [a.level])
+    sa = ctx._structs([a])
+    sa[0].data += 8
+    with pytest.raises(nat.CkksError) as e:
+        nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr(), sa, ctx._structs([a]),
+                                     ctx._structs([ctx.new_ct(2, a.level - 1)]), wsb, wbb, ctx.stream)
+    assert e.value.code == nat.CKKS_EINVAL and "aligned" in str(e.value)
+    with pytest.raises(nat.CkksError) as e:
+        nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr() + 8, ctx._structs([a]), ctx._structs([a]),
+                                     ctx._structs([ctx.new_ct(2, a.level - 1)]), wsb, wbb, ctx.stream)
+    assert e.value.code == nat.CKKS_EINVAL and "aligned" in str(e.value)
 
 
 def test_bench_configuration_sampled(ck):

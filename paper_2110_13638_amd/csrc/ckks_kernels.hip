@@ -673,44 +673,49 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
     }
 }
 
-// Dense linear layer on the matrix cores. One workgroup = 4 waves on one
-// tile of 16 consecutive residues (poly p, limb t, slots k0..k0+15); wave w
-// owns output rows 32 (4 blockIdx.y + w) .. +31 (two 16-row MFMA tiles).
-// The four waves share the tile's inputs: per chunk of 64 inputs each
-// thread loads four residues (input 16 v + tid / 16, slot tid % 16; the
-// inputs' pointers staged in LDS two chunks ahead), splits them into XD
-// 7-bit digits (9, or 6 where every prime of the launch is below 2^42) and
-// stores them as int8 B fragments in LDS (double-buffered: the next
-// chunk's residues are loaded while the matrix cores work on the current
-// one). Each wave multiplies the B fragments with
-// its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad], row-major, 16
-// bytes per lane) by v_mfma_i32_16x16x64_i8, accumulating digit products of
-// weight 128^(a + b) together. Lane layout of that instruction (checked on
-// the device): A[l % 16][16 (l / 16) + e], B[16 (l / 16) + e][l % 16]
+// Dense linear layer on the matrix cores. One workgroup = 8 waves on one
+// tile of 32 consecutive residues (poly p, limb t, slots k0..k0+31), two
+// sub-tiles of 16; wave w owns output rows 16 (8 blockIdx.y + w) .. +15
+// (one 16-row MFMA tile) for both sub-tiles, so each weight fragment it
+// loads serves 32 residues. The waves share the tile's inputs: per chunk of
+// 64 inputs each thread loads four residues (inputs 4 srow .. 4 srow + 3 of
+// slot tid % 32; the inputs' pointers staged in LDS two chunks ahead),
+// splits them into XD 7-bit digits (9, or 6 where every prime of the launch
+// is below 2^42) and stores digit b of its four inputs as one word of the
+// int8 B fragments in LDS (double-buffered: the next chunk's residues are
+// loaded while the matrix cores work on the current one). Each wave
+// multiplies its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad],
+// row-major, 16 bytes per lane) with the B fragments of each sub-tile by
+// v_mfma_i32_16x16x64_i8, accumulating digit products of weight
+// 128^(a + b) together. Lane layout of that instruction (checked on the
+// device): A[l % 16][16 (l / 16) + e], B[16 (l / 16) + e][l % 16]
 // D[4 (l / 16) + r][l % 16].
 typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr int kMfmaWaves = 8, kMfmaTile = 32;
 // XD residue digits: 9 cover primes below 2^63, 6 primes below 2^42 (the
 // 40-bit primes of the network chains: a third fewer digit products)
 template <int XD>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(64 * kMfmaWaves)
 k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
               u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
               u32 t_lo, u32 t_cnt, u32 in_stride, u32 out_stride) {
     constexpr int S = kWDig + XD - 1;  // digit weights 128^0 .. 128^(S-1)
-    // B fragments of two chunks: [buffer][digit][slot][lane group], 16 int8 each
-    __shared__ v4i bfrag[2][XD][16][4];
+    // B fragments of two chunks: [buffer][digit][slot][lane group], 16 int8
+    // each, one pad fragment per slot: a slot's row is 20 words, so the 16
+    // slots of a sub-tile's fragment read fall in distinct banks
+    __shared__ v4i bfrag[2][XD][kMfmaTile][5];
     // limb-0 pointers of the inputs of two chunks (staged two chunks ahead,
     // so the residue loads of the next chunk need no dependent global loads)
     __shared__ const u64 *cptr[2][64];
     const u32 N = 1u << tb.log_n;
     const u32 tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const u32 tile = blockIdx.x;  // 16 residues of one (p, t)
-    const u32 pt = (tile * 16) >> tb.log_n, k0 = (tile * 16) & (N - 1);
+    const u32 tile = blockIdx.x;  // 32 residues of one (p, t)
+    const u32 pt = (tile * kMfmaTile) >> tb.log_n, k0 = (tile * kMfmaTile) & (N - 1);
     const u32 p = pt / t_cnt, t = t_lo + (pt - p * t_cnt);
-    const u32 row0 = (blockIdx.y * 4 + wave) * 32;
+    const u32 row0 = (blockIdx.y * kMfmaWaves + wave) * 16;
     const bool rows = row0 < rows_pad;  // every wave still stages inputs and meets the barriers
     const u32 col = lane & 15, grp = lane >> 4;
-    const u32 scol = tid & 15, srow = tid >> 4;  // staging: slot, input within a quarter chunk
+    const u32 scol = tid & (kMfmaTile - 1), srow = tid / kMfmaTile;  // staging: slot, inputs 4 srow .. +3
     const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + scol;
     auto stage_ptrs = [&](u32 kc) {
         if (tid < 64) {
@@ -722,27 +727,30 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
         const u32 pb = (kc >> 6) & 1;
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            const u64 *src = cptr[pb][16 * v + srow];
+            const u64 *src = cptr[pb][4 * srow + v];
             x[v] = src ? src[in_off] : 0;
         }
     };
+    // digit b of the four consecutive inputs 4 srow + v (v = 0..3) is one
+    // word: bytes e = 4 (srow & 3) + v of lane group g = srow / 4
     auto stage = [&](int buf, const u64 (&x)[4]) {
-        int8_t *b8 = reinterpret_cast<int8_t *>(&bfrag[buf][0][0][0]);
+        u32 *w32 = reinterpret_cast<u32 *>(&bfrag[buf][0][0][0]);
+        const u32 g = srow >> 2, e4 = srow & 3;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const u32 ip = 16 * v + srow;  // position in the chunk
-            const u32 g = ip >> 4, e = ip & 15;
+        for (int b = 0; b < XD; b++) {
+            u32 w = 0;
 #pragma unroll
-            for (int b = 0; b < XD; b++)
-                b8[((b * 16 + scol) * 4 + g) * 16 + e] = (int8_t)((x[v] >> (7 * b)) & 127);
+            for (int v = 0; v < 4; v++) w |= (u32)((x[v] >> (7 * b)) & 127) << (8 * v);
+            w32[(b * kMfmaTile + scol) * 20 + g * 4 + e4] = w;
         }
     };
     v4i acc[2][S];
 #pragma unroll
-    for (int h = 0; h < 2; h++)
+    for (int u = 0; u < 2; u++)
 #pragma unroll
-        for (int s = 0; s < S; s++) acc[h][s] = v4i{0, 0, 0, 0};
+        for (int s = 0; s < S; s++) acc[u][s] = v4i{0, 0, 0, 0};
     const size_t plane = (size_t)rows_pad * k_pad;
+    const size_t arow = (size_t)(row0 + col) * k_pad + 16 * grp;
     stage_ptrs(0);
     if (64 < k_pad) stage_ptrs(64);
     __syncthreads();
@@ -761,19 +769,19 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
         // previous iteration, which ended at a barrier
         if (kc + 128 < k_pad) stage_ptrs(kc + 128);
         if (rows) {
-            v4i bd[XD];
+            v4i ad[kWDig];
 #pragma unroll
-            for (int b = 0; b < XD; b++) bd[b] = bfrag[buf][b][col][grp];
+            for (int a = 0; a < kWDig; a++) ad[a] = *reinterpret_cast<const v4i *>(wd + a * plane + arow + kc);
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const size_t aoff = (size_t)(row0 + 16 * h + col) * k_pad + kc + 16 * grp;
+            for (int u = 0; u < 2; u++) {
+                v4i bd[XD];
 #pragma unroll
-                for (int a = 0; a < kWDig; a++) {
-                    const v4i ad = *reinterpret_cast<const v4i *>(wd + a * plane + aoff);
+                for (int b = 0; b < XD; b++) bd[b] = bfrag[buf][b][16 * u + col][grp];
+#pragma unroll
+                for (int a = 0; a < kWDig; a++)
 #pragma unroll
                     for (int b = 0; b < XD; b++)
-                        acc[h][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ad, bd[b], acc[h][a + b], 0, 0, 0);
-                }
+                        acc[u][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ad[a], bd[b], acc[u][a + b], 0, 0, 0);
             }
         }
         if (more) stage(buf ^ 1, xn);
@@ -783,18 +791,18 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     const PrimeConst pc = tb.pc[t];
     const size_t out_off = ((size_t)p * out_stride + t) * N + k0 + col;
 #pragma unroll
-    for (int h = 0; h < 2; h++)
+    for (int u = 0; u < 2; u++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const u32 j = row0 + 16 * h + 4 * grp + r;
+            const u32 j = row0 + 4 * grp + r;
             // v = sum_s acc_s 2^(7 s), signed, |v| < 2^(7 S + 32)
             __int128 v = 0;
 #pragma unroll
-            for (int s = S - 1; s >= 0; s--) v = v * 128 + (__int128)acc[h][s][r];
+            for (int s = S - 1; s >= 0; s--) v = v * 128 + (__int128)acc[u][s][r];
             const bool neg = v < 0;
             const unsigned __int128 m = neg ? (unsigned __int128)(-v) : (unsigned __int128)v;
             const u64 red = barrett128((u64)m, (u64)(m >> 64), pc);
-            if (j < n_out) out_ptrs[j][out_off] = neg && red ? pc.q - red : red;
+            if (j < n_out) out_ptrs[j][out_off + 16 * u] = neg && red ? pc.q - red : red;
         }
 }
 
@@ -940,14 +948,14 @@ hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pa
                               u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 t_lo,
                               u32 t_cnt, bool small, u32 in_stride, u32 out_stride, hipStream_t s) {
     const u32 N = 1u << tb.log_n;
-    const u32 tiles = (u32)(((size_t)2 * t_cnt * N) / 16);
-    const u32 row_blocks = (rows_pad + 127) / 128;
+    const u32 tiles = (u32)(((size_t)2 * t_cnt * N) / kMfmaTile);
+    const u32 row_blocks = (rows_pad + 16 * kMfmaWaves - 1) / (16 * kMfmaWaves);
     if (small)
-        hipLaunchKernelGGL(k_linear_mfma<6>, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad, cols,
-                           n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
+        hipLaunchKernelGGL(k_linear_mfma<6>, dim3(tiles, row_blocks), dim3(64 * kMfmaWaves), 0, s, tb, wd, rows_pad,
+                           k_pad, cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
     else
-        hipLaunchKernelGGL(k_linear_mfma<kXDig>, dim3(tiles, row_blocks), dim3(256), 0, s, tb, wd, rows_pad, k_pad,
-                           cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
+        hipLaunchKernelGGL(k_linear_mfma<kXDig>, dim3(tiles, row_blocks), dim3(64 * kMfmaWaves), 0, s, tb, wd,
+                           rows_pad, k_pad, cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
     return hipGetLastError();
 }
 hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,

@@ -674,16 +674,17 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 }
 
 // Dense linear layer on the matrix cores. One workgroup = 8 waves on one
-// tile of 32 consecutive residues (poly p, limb t, slots k0..k0+31), two
-// sub-tiles of 16; wave w owns output rows 16 (8 blockIdx.y + w) .. +15
-// (one 16-row MFMA tile) for both sub-tiles, so each weight fragment it
-// loads serves 32 residues. The waves share the tile's inputs: per chunk of
-// 64 inputs each thread loads four residues (inputs 4 srow .. 4 srow + 3 of
-// slot tid % 32; the inputs' pointers staged in LDS two chunks ahead),
-// splits them into XD 7-bit digits (9, or 6 where every prime of the launch
-// is below 2^42) and stores digit b of its four inputs as one word of the
-// int8 B fragments in LDS (double-buffered: the next chunk's residues are
-// loaded while the matrix cores work on the current one). Each wave
+// tile of 16 U consecutive residues (poly p, limb t, slots k0..k0+16U-1),
+// U sub-tiles of 16; wave w owns output rows 16 (8 blockIdx.y + w) .. +15
+// (one 16-row MFMA tile) for every sub-tile, so each weight fragment it
+// loads serves 16 U residues. The waves share the tile's inputs: per chunk
+// of 64 inputs each thread loads 2 U residues (inputs 2U srow .. 2U srow +
+// 2U - 1 of slot tid % 16U; the inputs' pointers staged in LDS two chunks
+// ahead), splits them into XD 7-bit digits (9, or 6 where every prime of
+// the launch is below 2^42) and stores digit b of each four consecutive
+// inputs as one word of the int8 B fragments in LDS (double-buffered: the
+// next chunk's residues are loaded while the matrix cores work on the
+// current one). Each wave
 // multiplies its weight-digit A fragments (Wd [kWDig][rows_pad][k_pad],
 // row-major, 16 bytes per lane) with the B fragments of each sub-tile by
 // v_mfma_i32_16x16x64_i8, accumulating digit products of weight
@@ -691,15 +692,17 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 // device): A[l % 16][16 (l / 16) + e], B[16 (l / 16) + e][l % 16]
 // D[4 (l / 16) + r][l % 16].
 typedef int v4i __attribute__((ext_vector_type(4)));
-constexpr int kMfmaWaves = 8, kMfmaTile = 32;
+constexpr int kMfmaWaves = 8;
 // XD residue digits: 9 cover primes below 2^63, 6 primes below 2^42 (the
-// 40-bit primes of the network chains: a third fewer digit products)
-template <int XD>
+// 40-bit primes of the network chains: a third fewer digit products).
+// U: sub-tiles per wave (accumulators: U x (kWDig + XD - 1) fragments)
+template <int XD, int U>
 __global__ void __launch_bounds__(64 * kMfmaWaves)
 k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_pad, const u32 *__restrict__ cols,
               u32 n_in, u32 n_out, const u64 *const *__restrict__ in_ptrs, u64 *const *__restrict__ out_ptrs,
               u32 t_lo, u32 t_cnt, u32 in_stride, u32 out_stride) {
     constexpr int S = kWDig + XD - 1;  // digit weights 128^0 .. 128^(S-1)
+    constexpr int kMfmaTile = 16 * U, IPT = 2 * U;  // residues per tile, inputs per staging thread
     // B fragments of two chunks: [buffer][digit][slot][lane group], 16 int8
     // each, one pad fragment per slot: a slot's row is 20 words, so the 16
     // slots of a sub-tile's fragment read fall in distinct banks
@@ -715,7 +718,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     const u32 row0 = (blockIdx.y * kMfmaWaves + wave) * 16;
     const bool rows = row0 < rows_pad;  // every wave still stages inputs and meets the barriers
     const u32 col = lane & 15, grp = lane >> 4;
-    const u32 scol = tid & (kMfmaTile - 1), srow = tid / kMfmaTile;  // staging: slot, inputs 4 srow .. +3
+    const u32 scol = tid & (kMfmaTile - 1), srow = tid / kMfmaTile;  // staging: slot, inputs IPT srow .. +IPT-1
     const size_t in_off = ((size_t)p * in_stride + t) * N + k0 + scol;
     auto stage_ptrs = [&](u32 kc) {
         if (tid < 64) {
@@ -723,30 +726,34 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
             cptr[(kc >> 6) & 1][tid] = i < n_in ? in_ptrs[cols[i]] : nullptr;
         }
     };
-    auto load = [&](u32 kc, u64 (&x)[4]) {
+    auto load = [&](u32 kc, u64 (&x)[IPT]) {
         const u32 pb = (kc >> 6) & 1;
 #pragma unroll
-        for (int v = 0; v < 4; v++) {
-            const u64 *src = cptr[pb][4 * srow + v];
+        for (int v = 0; v < IPT; v++) {
+            const u64 *src = cptr[pb][IPT * srow + v];
             x[v] = src ? src[in_off] : 0;
         }
     };
-    // digit b of the four consecutive inputs 4 srow + v (v = 0..3) is one
-    // word: bytes e = 4 (srow & 3) + v of lane group g = srow / 4
-    auto stage = [&](int buf, const u64 (&x)[4]) {
+    // digit b of the four consecutive inputs i0 + 4 h + v (i0 = IPT srow,
+    // v = 0..3) is one word: bytes e = (i0 + 4 h) % 16 + v of lane group
+    // g = (i0 + 4 h) / 16
+    auto stage = [&](int buf, const u64 (&x)[IPT]) {
         u32 *w32 = reinterpret_cast<u32 *>(&bfrag[buf][0][0][0]);
-        const u32 g = srow >> 2, e4 = srow & 3;
 #pragma unroll
-        for (int b = 0; b < XD; b++) {
-            u32 w = 0;
+        for (int h = 0; h < IPT / 4; h++) {
+            const u32 i4 = IPT * srow + 4 * h, g = i4 >> 4, e4 = (i4 & 15) >> 2;
 #pragma unroll
-            for (int v = 0; v < 4; v++) w |= (u32)((x[v] >> (7 * b)) & 127) << (8 * v);
-            w32[(b * kMfmaTile + scol) * 20 + g * 4 + e4] = w;
+            for (int b = 0; b < XD; b++) {
+                u32 w = 0;
+#pragma unroll
+                for (int v = 0; v < 4; v++) w |= (u32)((x[4 * h + v] >> (7 * b)) & 127) << (8 * v);
+                w32[(b * kMfmaTile + scol) * 20 + g * 4 + e4] = w;
+            }
         }
     };
-    v4i acc[2][S];
+    v4i acc[U][S];
 #pragma unroll
-    for (int u = 0; u < 2; u++)
+    for (int u = 0; u < U; u++)
 #pragma unroll
         for (int s = 0; s < S; s++) acc[u][s] = v4i{0, 0, 0, 0};
     const size_t plane = (size_t)rows_pad * k_pad;
@@ -755,7 +762,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     if (64 < k_pad) stage_ptrs(64);
     __syncthreads();
     {
-        u64 x[4];
+        u64 x[IPT];
         load(0, x);
         stage(0, x);
     }
@@ -763,7 +770,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     int buf = 0;
     for (u32 kc = 0; kc < k_pad; kc += 64, buf ^= 1) {
         const bool more = kc + 64 < k_pad;
-        u64 xn[4] = {0, 0, 0, 0};
+        u64 xn[IPT] = {};
         if (more) load(kc + 64, xn);
         // chunk kc's pointer slot is free: its residues were loaded in the
         // previous iteration, which ended at a barrier
@@ -773,7 +780,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
 #pragma unroll
             for (int a = 0; a < kWDig; a++) ad[a] = *reinterpret_cast<const v4i *>(wd + a * plane + arow + kc);
 #pragma unroll
-            for (int u = 0; u < 2; u++) {
+            for (int u = 0; u < U; u++) {
                 v4i bd[XD];
 #pragma unroll
                 for (int b = 0; b < XD; b++) bd[b] = bfrag[buf][b][16 * u + col][grp];
@@ -791,7 +798,7 @@ k_linear_mfma(DevTables tb, const int8_t *__restrict__ wd, u32 rows_pad, u32 k_p
     const PrimeConst pc = tb.pc[t];
     const size_t out_off = ((size_t)p * out_stride + t) * N + k0 + col;
 #pragma unroll
-    for (int u = 0; u < 2; u++)
+    for (int u = 0; u < U; u++)
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const u32 j = row0 + 4 * grp + r;
@@ -948,14 +955,16 @@ hipError_t launch_linear_mfma(const DevTables &tb, const int8_t *wd, u32 rows_pa
                               u32 n_in, u32 n_out, const u64 *const *in_ptrs, u64 *const *out_ptrs, u32 t_lo,
                               u32 t_cnt, bool small, u32 in_stride, u32 out_stride, hipStream_t s) {
     const u32 N = 1u << tb.log_n;
-    const u32 tiles = (u32)(((size_t)2 * t_cnt * N) / kMfmaTile);
     const u32 row_blocks = (rows_pad + 16 * kMfmaWaves - 1) / (16 * kMfmaWaves);
+    // six residue digits leave room for four sub-tiles' accumulators, nine for two
     if (small)
-        hipLaunchKernelGGL(k_linear_mfma<6>, dim3(tiles, row_blocks), dim3(64 * kMfmaWaves), 0, s, tb, wd, rows_pad,
-                           k_pad, cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
+        hipLaunchKernelGGL((k_linear_mfma<6, 4>), dim3((u32)(((size_t)2 * t_cnt * N) / 64), row_blocks),
+                           dim3(64 * kMfmaWaves), 0, s, tb, wd, rows_pad, k_pad, cols, n_in, n_out, in_ptrs, out_ptrs,
+                           t_lo, t_cnt, in_stride, out_stride);
     else
-        hipLaunchKernelGGL(k_linear_mfma<kXDig>, dim3(tiles, row_blocks), dim3(64 * kMfmaWaves), 0, s, tb, wd,
-                           rows_pad, k_pad, cols, n_in, n_out, in_ptrs, out_ptrs, t_lo, t_cnt, in_stride, out_stride);
+        hipLaunchKernelGGL((k_linear_mfma<kXDig, 2>), dim3((u32)(((size_t)2 * t_cnt * N) / 32), row_blocks),
+                           dim3(64 * kMfmaWaves), 0, s, tb, wd, rows_pad, k_pad, cols, n_in, n_out, in_ptrs, out_ptrs,
+                           t_lo, t_cnt, in_stride, out_stride);
     return hipGetLastError();
 }
 hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad, u32 k_pad, int8_t *wd,

@@ -865,16 +865,16 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 }
 
 // Waves per SIMD the transform kernels are built for. A workgroup of 2^14
-// residues with 32 per thread (8 waves) whose register count would exceed
-// 128 — the inverse transforms and the ModUp / ModDown conversions — is held
-// to 128 VGPRs, so that two of them share a CU and one's memory phases
-// overlap the other's arithmetic (measured: the 8192-image vision network's
-// ModUp 5.3 -> 4.3 ms, product + INTT 1.0 -> 0.8 ms, despite small spills);
-// the other forward kernels fit in 128 already and keep the compiler's
-// schedule, as do all other shapes.
+// or 2^13 residues with 32 per thread (8 or 4 waves) whose register count
+// would exceed 128 — the inverse transforms and the ModUp / ModDown
+// conversions — is held to 128 VGPRs, so that two (four) of them share a CU
+// and one's memory phases overlap another's arithmetic (measured: the
+// 8192-image vision network's ModUp 5.3 -> 4.3 ms, product + INTT 1.0 ->
+// 0.8 ms, despite small spills); the other forward kernels fit in 128
+// already and keep the compiler's schedule, as do all other shapes.
 template <int LOGN, int LOGE, bool INV, int OP>
 constexpr int kWavesPerEu =
-    (LOGN == 14 && LOGE == 5 && (INV || OP == F_MODUP || OP == F_MODDOWN)) ? 4 : 1;
+    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || OP == F_MODUP || OP == F_MODDOWN)) ? 4 : 1;
 
 // FP: every item's prime is below 2^50 and the transforms run in FP64
 // arithmetic (the host splits a launch by prime class); else 64-bit integer

@@ -43,7 +43,7 @@ hipError_t launch_weight_digits(const i64 *W, u32 n_out, u32 n_in, u32 rows_pad,
                                 hipStream_t s);
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
                                  const u64 *wt, const double2 *wf, u32 wt_stride, const u64 *const *in_ptrs, u64 *const *out_ptrs,
-                                 u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s);
+                                 u32 limbs, u32 in_stride, u32 out_stride, u32 max_rows, hipStream_t s);
 
 // kernel op codes (mirrors of the enums in the kernel file)
 enum {
@@ -2651,12 +2651,15 @@ extern "C" int ckks_linear_csr(const ckks_ctx *c, const ckks_ct *in, uint32_t n_
         HIP_TRY(hipEventRecord(rec.e0, s));
     }
     const u32 n_groups = (u32)groups.size();
+    u32 max_rows = 1;
+    for (const LinGroup &g : groups) max_rows = std::max(max_rows, g.nrows);
     HIP_TRY(issue(c, s, [tb = c->tb, w8, n_groups, o_groups, o_cols, o_wt, o_wf, o_ptr, W, n_in, L, stride,
-                         ostride](hipStream_t st) {
+                         ostride, max_rows](hipStream_t st) {
         return launch_linear_grouped(tb, (const LinGroup *)(w8 + o_groups), n_groups, (const u32 *)(w8 + o_cols),
                                      (const u64 *)(w8 + o_wt), (const double2 *)(w8 + o_wf), (u32)W,
                                      (const u64 *const *)(w8 + o_ptr),
-                                     (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L, stride, ostride, st);
+                                     (u64 *const *)(w8 + o_ptr + (size_t)n_in * 8), L, stride, ostride, max_rows,
+                                     st);
     }));
     if (g_prof_on) {
         HIP_TRY(hipEventRecord(rec.e1, s));

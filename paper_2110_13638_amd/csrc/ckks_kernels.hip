@@ -566,6 +566,8 @@ k_linear(DevTables tb, const u64 *const *__restrict__ in_ptrs, const u64 *__rest
 // through the scalar cache; the next column's input pointer is fetched
 // while the current column is multiplied.
 constexpr int kLinRes = 4;
+// NR: rows per group of the launch at most (accumulators per thread)
+template <int NR>
 __global__ void __launch_bounds__(256)
 k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups, const u32 *__restrict__ cols,
                  const u64 *__restrict__ wt, const double2 *__restrict__ wf, u32 wt_stride,
@@ -603,9 +605,9 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 #pragma clang fp contract(off)
             const double2 *wv = wf + (size_t)t * wt_stride + G.w_off;
             const double q = pc.qf, qinv = pc.qinvf;
-            double acc[kLinRows][kLinRes];
+            double acc[NR][kLinRes];
 #pragma unroll
-            for (int r = 0; r < kLinRows; r++)
+            for (int r = 0; r < NR; r++)
 #pragma unroll
                 for (int e = 0; e < kLinRes; e++) acc[r][e] = 0.0;
             const u64 *next = in_ptrs[gc[0]];
@@ -617,7 +619,7 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
 #pragma unroll
                 for (int e = 0; e < kLinRes; e++) x[e] = fp_from_u64(xi[e]);
 #pragma unroll
-                for (int r = 0; r < kLinRows; r++)
+                for (int r = 0; r < NR; r++)
                     if ((u32)r < G.nrows) {
                         const double2 w2 = wv[(size_t)r * G.ncols + c];
 #pragma unroll
@@ -625,13 +627,13 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
                     }
                 if ((c & 3) == 3) {
 #pragma unroll
-                    for (int r = 0; r < kLinRows; r++)
+                    for (int r = 0; r < NR; r++)
 #pragma unroll
                         for (int e = 0; e < kLinRes; e++) acc[r][e] = fp_center(acc[r][e], q, qinv);
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kLinRows; r++)
+            for (int r = 0; r < NR; r++)
                 if ((u32)r < G.nrows) {
                     u64 y[kLinRes];
 #pragma unroll
@@ -645,12 +647,12 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
         // two residues at a time (the sums of all rows stay in registers)
         const u64 *w = wt + (size_t)t * wt_stride + G.w_off;
         for (int h = 0; h < kLinRes; h += 2) {
-            Acc128 acc[kLinRows][2];
+            Acc128 acc[NR][2];
             for (u32 c = 0; c < G.ncols; c++) {
                 const u64 *src = in_ptrs[gc[c]] + in_off + h;
                 const ulonglong2 x = *reinterpret_cast<const ulonglong2 *>(src);
 #pragma unroll
-                for (int r = 0; r < kLinRows; r++)
+                for (int r = 0; r < NR; r++)
                     if ((u32)r < G.nrows) {
                         const u64 wr = w[(size_t)r * G.ncols + c];
                         acc[r][0].mac(x.x, wr);
@@ -658,14 +660,14 @@ k_linear_grouped(DevTables tb, const LinGroup *__restrict__ groups, u32 n_groups
                     }
                 if ((c & (kLinFold - 1)) == kLinFold - 1) {
 #pragma unroll
-                    for (int r = 0; r < kLinRows; r++) {
+                    for (int r = 0; r < NR; r++) {
                         acc[r][0] = Acc128{acc[r][0].reduce(pc), 0};
                         acc[r][1] = Acc128{acc[r][1].reduce(pc), 0};
                     }
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kLinRows; r++)
+            for (int r = 0; r < NR; r++)
                 if ((u32)r < G.nrows)
                     *reinterpret_cast<ulonglong2 *>(out_ptrs[G.row0 + r] + out_off + h) =
                         ulonglong2{acc[r][0].reduce(pc), acc[r][1].reduce(pc)};
@@ -943,10 +945,22 @@ hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u
 }
 hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u32 n_groups, const u32 *cols,
                                  const u64 *wt, const double2 *wf, u32 wt_stride, const u64 *const *in_ptrs,
-                                 u64 *const *out_ptrs, u32 limbs, u32 in_stride, u32 out_stride, hipStream_t s) {
+                                 u64 *const *out_ptrs, u32 limbs, u32 in_stride, u32 out_stride, u32 max_rows,
+                                 hipStream_t s) {
     const size_t work = (((size_t)2 * limbs << tb.log_n) / kLinRes) * n_groups;
-    hipLaunchKernelGGL(k_linear_grouped, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt, wf,
-                       wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride);
+    // accumulators for the largest group only (a conv layer's groups are its filters)
+#define CKKS_LIN_GROUPED(NR)                                                                                    \
+    hipLaunchKernelGGL(k_linear_grouped<NR>, dim3(ew_grid(work)), dim3(256), 0, s, tb, groups, n_groups, cols, wt, \
+                       wf, wt_stride, in_ptrs, out_ptrs, limbs, in_stride, out_stride)
+    if (max_rows <= 2)
+        CKKS_LIN_GROUPED(2);
+    else if (max_rows <= 4)
+        CKKS_LIN_GROUPED(4);
+    else if (max_rows <= 5)
+        CKKS_LIN_GROUPED(5);
+    else
+        CKKS_LIN_GROUPED(kLinRows);
+#undef CKKS_LIN_GROUPED
     return hipGetLastError();
 }
 // limbs t_lo .. t_lo + t_cnt - 1 of both polys; `small`: all their primes

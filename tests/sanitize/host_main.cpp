@@ -29,7 +29,7 @@ hipError_t launch_linear_mfma(const DevTables &, const int8_t *, u32, u32, const
                               u64 *const *, u32, u32, bool, u32, u32, hipStream_t) STUB()
 hipError_t launch_weight_digits(const i64 *, u32, u32, u32, u32, int8_t *, hipStream_t) STUB()
 hipError_t launch_linear_grouped(const DevTables &, const LinGroup *, u32, const u32 *, const u64 *, const double2 *,
-                                 u32, const u64 *const *, u64 *const *, u32, u32, u32, hipStream_t) STUB()
+                                 u32, const u64 *const *, u64 *const *, u32, u32, u32, u32, hipStream_t) STUB()
 }  // namespace ckks
 
 #define CHECK(cond)                                                             \

@@ -314,6 +314,14 @@ int ckks_relinearize(const ckks_ctx *ctx, const uint64_t *const *rk, const ckks_
  * coefficient-wise, scale / q_l, level - 1. out may alias in. */
 int ckks_rescale(const ckks_ctx *ctx, const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws,
                  size_t ws_bytes, void *stream);
+/* rescale, then add the constant v[b] (an integer: a scalar already
+ * multiplied by the output scale and rounded, as ckks_encode_scalars gives)
+ * to every slot of the first polynomial of out[b]: the bias of a conv or
+ * dense layer, which follows its product's rescale (Sections 4.2.2 and
+ * 4.2.3). Bit-identical to ckks_rescale then ckks_add_scalar, in one pass
+ * over the limbs. CKKS_EINVAL for a null v. */
+int ckks_rescale_add_scalar(const ckks_ctx *ctx, const ckks_ct *in, const int64_t *v, ckks_ct *out, uint32_t B,
+                            void *ws, size_t ws_bytes, void *stream);
 /* modulus-chain level match: a view change (no device work) */
 int ckks_mod_switch_to(const ckks_ctx *ctx, ckks_ct *inout, uint32_t level);
 /* slot rotation: X -> X^g on both polys, then key switch of the second

@@ -119,6 +119,8 @@ _SIGS = {
     "ckks_multiply": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_relinearize": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_rescale": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
+    "ckks_rescale_add_scalar": (ctypes.c_int, [_vp, _P(ckks_ct), _P(ctypes.c_int64), _P(ckks_ct), _u32, _vp, _sz,
+                                               _vp]),
     "ckks_mod_switch_to": (ctypes.c_int, [_vp, _P(ckks_ct), _u32]),
     "ckks_rotate": (ctypes.c_int, [_vp, _P(_vp), _P(_u32), _P(ckks_ct), _P(ckks_ct), _u32, _vp, _sz, _vp]),
     "ckks_hmult_relin_rescale": (ctypes.c_int, [_vp, _P(_vp), _P(ckks_ct), _P(ckks_ct), _P(ckks_ct), _u32, _vp,
@@ -355,6 +357,11 @@ def ckks_relinearize(h, rk, in3, out, ws, ws_bytes, stream=None):
 
 def ckks_rescale(h, a, out, ws, ws_bytes, stream=None):
     _call("ckks_rescale", h, a, out, len(out), ws, ws_bytes, stream)
+
+
+def ckks_rescale_add_scalar(h, a, v, out, ws, ws_bytes, stream=None):
+    """rescale, then v[b] (integers at the output scale) added to every slot of out[b]'s first poly"""
+    _call("ckks_rescale_add_scalar", h, a, _arr(ctypes.c_int64, v), out, len(out), ws, ws_bytes, stream)
 
 
 def ckks_mod_switch_to(h, ct, level):

@@ -795,7 +795,10 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
         for (int c = 0; c < E; c++) Buf(it.out).st(vo, c * T * 8, r[c]);
     } else if constexpr (OP == F_RESCALE) {
+        // it.v: a signed constant added to every slot after the division
+        // (a scalar at the output scale on the first polynomial; 0: none)
         const ulonglong2 qi = tb.rescale[(size_t)it.a * tb.n_q + it.prime];
+        const u64 add = it.v ? uniform64(reduce_signed(it.v, pc)) : 0;
         const Buf in1(it.in[1]), dst(it.out);
 #pragma unroll
         for (int c0 = 0; c0 < E; c0 += kEpiChunk) {
@@ -804,7 +807,7 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
             for (int c = 0; c < kEpiChunk; c++) x[c] = in1.ld(vo, (c0 + c) * T * 8);
 #pragma unroll
             for (int c = 0; c < kEpiChunk; c++)
-                dst.st(vo, (c0 + c) * T * 8, shoup(subm(x[c], r[c0 + c], q), qi.x, qi.y, q));
+                dst.st(vo, (c0 + c) * T * 8, addm(shoup(subm(x[c], r[c0 + c], q), qi.x, qi.y, q), add, q));
         }
     } else if constexpr (is_relin_rs(OP) && FP) {
         // y = (acc' P^-1 - z) q_l^-1 in FP64: |acc' P^-1| < q, |. - z| < 2q,
@@ -866,15 +869,16 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 
 // Waves per SIMD the transform kernels are built for. A workgroup of 2^14
 // or 2^13 residues with 32 per thread (8 or 4 waves) whose register count
-// would exceed 128 — the inverse transforms and the ModUp / ModDown
-// conversions — is held to 128 VGPRs, so that two (four) of them share a CU
-// and one's memory phases overlap another's arithmetic (measured: the
-// 8192-image vision network's ModUp 5.3 -> 4.3 ms, product + INTT 1.0 ->
-// 0.8 ms, despite small spills); the other forward kernels fit in 128
-// already and keep the compiler's schedule, as do all other shapes.
+// would exceed 128 — the inverse transforms, the ModUp / ModDown
+// conversions and the rescale — is held to 128 VGPRs, so that two (four) of
+// them share a CU and one's memory phases overlap another's arithmetic
+// (measured: the 8192-image vision network's ModUp 5.3 -> 4.3 ms, product +
+// INTT 1.0 -> 0.8 ms, despite small spills); the other forward kernels fit
+// in 128 already and keep the compiler's schedule, as do all other shapes.
 template <int LOGN, int LOGE, bool INV, int OP>
 constexpr int kWavesPerEu =
-    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || OP == F_MODUP || OP == F_MODDOWN)) ? 4 : 1;
+    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || OP == F_MODUP || OP == F_MODDOWN || OP == F_RESCALE)) ? 4
+                                                                                                             : 1;
 
 // FP: every item's prime is below 2^50 and the transforms run in FP64
 // arithmetic (the host splits a launch by prime class); else 64-bit integer

@@ -211,12 +211,14 @@ int fire_linear(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
     }
     GK(ckks_linear_csr(g->c, in.data(), (u32)in.size(), n.n_out, n.row_ptr.data(), n.col.data(), n.w.data(),
                        n.w_scale, n.out.data(), scratch(g), scratch_avail(g), g->stream));
-    GK(ckks_rescale(g->c, n.out.data(), n.out.data(), n.n_out, scratch(g), scratch_avail(g), g->stream));
-    if (!n.bias.empty()) {
+    if (n.bias.empty()) {
+        GK(ckks_rescale(g->c, n.out.data(), n.out.data(), n.n_out, scratch(g), scratch_avail(g), g->stream));
+    } else {
+        // the bias at the scale after the rescale, added in the rescale's pass
         std::vector<i64> v(n.n_out);
-        for (u32 j = 0; j < n.n_out; j++) v[j] = round_half_away(n.bias[j] * n.out[j].scale);
-        GK(ckks_add_scalar(g->c, n.out.data(), v.data(), n.out.data(), n.n_out, scratch(g), scratch_avail(g),
-                           g->stream));
+        for (u32 j = 0; j < n.n_out; j++) v[j] = round_half_away(n.bias[j] * n.out_scale);
+        GK(ckks_rescale_add_scalar(g->c, n.out.data(), v.data(), n.out.data(), n.n_out, scratch(g),
+                                   scratch_avail(g), g->stream));
     }
     return CKKS_OK;
 }

@@ -2027,8 +2027,10 @@ extern "C" int ckks_rotate(const ckks_ctx *c, const uint64_t *const *gk, const u
     return CKKS_OK;
 }
 
-extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws,
-                            size_t ws_bytes, void *stream) {
+// rescale of a batch; v (or null): per item, a signed constant added to
+// every slot of the first polynomial after the division
+static int rescale_impl(const ckks_ctx *c, const ckks_ct *in, const int64_t *v, ckks_ct *out, uint32_t B, void *ws,
+                        size_t ws_bytes, void *stream) {
     CK(check_ctx(c));
     if (!in || !out) return fail(CKKS_EINVAL, "rescale: null argument");
     Plan P(c, ws);
@@ -2055,6 +2057,7 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
                 r.a = l;
                 r.prime = i;
                 r.out = limb(c, o, t, i);
+                r.v = (v && t == 0) ? v[k] : 0;
                 res.push_back(r);
             }
         }
@@ -2072,6 +2075,15 @@ extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, 
         out[k].scale = scale;
     }
     return CKKS_OK;
+}
+extern "C" int ckks_rescale(const ckks_ctx *c, const ckks_ct *in, ckks_ct *out, uint32_t B, void *ws,
+                            size_t ws_bytes, void *stream) {
+    return rescale_impl(c, in, nullptr, out, B, ws, ws_bytes, stream);
+}
+extern "C" int ckks_rescale_add_scalar(const ckks_ctx *c, const ckks_ct *in, const int64_t *v, ckks_ct *out,
+                                       uint32_t B, void *ws, size_t ws_bytes, void *stream) {
+    if (!v) return fail(CKKS_EINVAL, "rescale_add_scalar: null constants");
+    return rescale_impl(c, in, v, out, B, ws, ws_bytes, stream);
 }
 
 // Fused HMult + relinearise + rescale over a ragged batch:

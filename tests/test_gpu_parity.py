@@ -163,6 +163,19 @@ def test_relin_rescale_rotate_bit_exact(request, which):
     rs = ctx.rescale(r)
     rso = orc.rescale(ro)
     assert np.array_equal(rs.residues(), rso)
+    # rescale with a bias in the same pass: the oracle's rescale, then its
+    # constant addition (a negative and a positive constant, two items)
+    from paper_2110_13638_amd import _native as nat
+    vs = [ON.round_half_away(-0.45 * rs.scale), ON.round_half_away(1.25 * rs.scale)]
+    ins = [r, r]
+    outs = [ctx.new_ct(2, r.level) for _ in ins]
+    so = ctx._structs(outs)
+    ws, wb = ctx.ws_for(nat.CKKS_OP_RESCALE, 2, [r.level, r.level])
+    nat.ckks_rescale_add_scalar(ctx.h, ctx._structs(ins), vs, so, ws, wb, ctx.stream)
+    for o, s_, v in zip(outs, so, vs):
+        o.update(s_)
+        assert o.level == rs.level and o.scale == rs.scale
+        assert np.array_equal(o.residues(), orc.add_const(rso, v))
     # decoding is meaningful only where the special modulus exceeds a
     # digit's modulus (one prime per digit here); the wide chain (four
     # 50-bit primes per digit against two 60-bit special primes) is a

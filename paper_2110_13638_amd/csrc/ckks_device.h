@@ -225,7 +225,9 @@ __device__ __forceinline__ u64 sample_uniform(u32 j, u32 limb, u32 obj, u32 tag,
 // thread)
 constexpr int kTwiddleChunk = 16;
 // the inverse stages keep more constants live: fewer barriers spill less
+// (integer engine); the FP64 inverse stays spill-free with half as many
 constexpr int kTwiddleChunkInv = 16;
+constexpr int kTwiddleChunkInvFp = 8;
 // residues converted per pass over the source limbs of a basis conversion
 constexpr int kConvChunk = 8;
 // residues whose epilogue inputs are loaded together before any is stored
@@ -488,7 +490,7 @@ struct Ntt {
                 r[x] = recentre ? fp_center(U, q, pc.qinvf) : U;
                 r[y] = fp_mulmod(X - Y, W.x, W.y, q);
             }
-            if ((b & (kTwiddleChunkInv - 1)) == kTwiddleChunkInv - 1) __builtin_amdgcn_sched_barrier(0);
+            if ((b & (kTwiddleChunkInvFp - 1)) == kTwiddleChunkInvFp - 1) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (D > 0) inv_stage_f<P, D - 1>(r, tid, itw, pc);
     }

@@ -224,6 +224,7 @@ __device__ __forceinline__ u64 sample_uniform(u32 j, u32 limb, u32 obj, u32 tag,
 // pairs the scheduler keeps in flight (register pressure at 32 residues per
 // thread)
 constexpr int kTwiddleChunk = 16;
+constexpr int kTwiddleChunkFp = 8;
 // the inverse stages keep more constants live: fewer barriers spill less
 // (integer engine); the FP64 inverse stays spill-free with half as many
 constexpr int kTwiddleChunkInv = 16;
@@ -430,7 +431,7 @@ struct Ntt {
             const double Tm = fp_mulmod(r[y], W.x, W.y, q);
             r[x] = X + Tm;
             r[y] = X - Tm;
-            if ((b & (kTwiddleChunk - 1)) == kTwiddleChunk - 1) __builtin_amdgcn_sched_barrier(0);
+            if ((b & (kTwiddleChunkFp - 1)) == kTwiddleChunkFp - 1) __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (D + 1 < w) fwd_stage_f<P, D + 1>(r, tid, tw, q, qinv, tm);
     }

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libckks_hip.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["ckks_ntt16.hip", "ckks_ntt15.hip", "ckks_ntt15_fixed.hip", "ckks_ntt15_inv.hip", "ckks_ntt14.hip", "ckks_ntt13.hip", "ckks_ntt_small.hip", "ckks_kernels.hip", "ckks_noalloc.hip",
-           "ckks_host.cpp", "ckks_graph.cpp"]
+           "ckks_host.cpp", "ckks_eval.cpp", "ckks_linear.cpp", "ckks_graph.cpp"]
 ARCH = os.environ.get("CKKS_OFFLOAD_ARCH", "gfx950")
 # packed-fp32 instructions are disabled for every HIP translation unit
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -42,6 +42,7 @@ def test_host_runtime_under_asan_ubsan(tmp_path):
         pytest.skip("hipcc not available")
     exe = str(tmp_path / "host_asan")
     srcs = [os.path.join(HERE, "sanitize", "host_main.cpp")] + [
-        os.path.join(CSRC, f) for f in ("ckks_host.cpp", "ckks_graph.cpp", "ckks_noalloc.hip")]
+        os.path.join(CSRC, f) for f in ("ckks_host.cpp", "ckks_eval.cpp", "ckks_linear.cpp", "ckks_graph.cpp",
+                                         "ckks_noalloc.hip")]
     _run(shlex.split(HIPCC_SAN) + srcs + ["-o", exe], str(tmp_path))
     assert "host driver ok" in _run([exe], str(tmp_path))

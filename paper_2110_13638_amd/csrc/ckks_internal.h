@@ -1,4 +1,4 @@
-// Internal definitions shared by the host runtime (ckks_host.cpp) and the
+// Internal definitions shared by the host runtime (ckks_runtime.h) and the
 // gfx950 kernels (ckks_kernels.hip). Not part of the public ABI.
 #pragma once
 

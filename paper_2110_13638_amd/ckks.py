@@ -483,17 +483,25 @@ class Context:
         return self._outs(so, outs)
 
     def linear(self, inputs, W, w_scale=None):
-        """out[j] = sum_i round(W[j,i] * w_scale) * inputs[i]"""
+        """out[j] = sum_i round(W[j,i] * w_scale) * inputs[i]: dense rows through
+        ckks_linear_csr (the matrix cores when the context enables them)"""
         w_scale = w_scale or self.default_scale
         W = np.asarray(W, dtype=np.float64)
         n_out, n_in = W.shape
-        Wi = nat.ckks_encode_scalars(self.h, W, w_scale).reshape(W.shape)
-        Wd = torch.from_numpy(Wi).to(self.device)
+        Wi = nat.ckks_encode_scalars(self.h, W, w_scale).reshape(-1)
+        row_ptr = np.arange(n_out + 1, dtype=np.uint32) * n_in
+        col = np.tile(np.arange(n_in, dtype=np.uint32), n_out)
+        return self.linear_csr(inputs, row_ptr, col, Wi, w_scale)
+
+    def linear_device_weights(self, inputs, W_int, w_scale):
+        """the same product with the integer weights [n_out][n_in] already in
+        device memory (ckks_linear, VALU)"""
+        n_out, n_in = W_int.shape
         lvl = inputs[0].level
         outs = [self.new_ct(2, lvl, 1.0) for _ in range(n_out)]
         so = self._structs(outs)
         ws, wb = self.workspace(nat.ckks_workspace_bytes(self.h, nat.CKKS_OP_LINEAR, n_out, [lvl, n_in]))
-        nat.ckks_linear(self.h, self._structs(inputs), Wd.data_ptr(), w_scale, so, ws, wb, self.stream)
+        nat.ckks_linear(self.h, self._structs(inputs), W_int.data_ptr(), w_scale, so, ws, wb, self.stream)
         return self._outs(so, outs)
 
     # --- batched helpers used by the serving engine ---------------------------------

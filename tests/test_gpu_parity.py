@@ -225,13 +225,25 @@ def test_linear_bit_exact(small):
         cts.append(c)
         cos.append(co)
     W = S.gaussian(3, (3, 5), 0.3)
-    outs = ctx.linear(cts, W)
+    wants = []
     for j in range(3):
         want = None
         for i in range(5):
             term = orc.mul_const(cos[i], ON.round_half_away(W[j, i] * ctx.default_scale))
             want = term if want is None else orc.add(want, term)
-        assert np.array_equal(outs[j].residues(), want)
+        wants.append(want)
+    # dense rows (matrix cores, then the VALU path), and ckks_linear with the
+    # weights in device memory
+    Wi = np.array([[ON.round_half_away(w * ctx.default_scale) for w in row] for row in W], dtype=np.int64)
+    for mfma in (1, 0):
+        ctx.set_tuning(lin_mfma=mfma)
+        outs = ctx.linear(cts, W)
+        for j in range(3):
+            assert np.array_equal(outs[j].residues(), wants[j]), (mfma, j)
+    ctx.set_tuning(lin_mfma=1)
+    outs = ctx.linear_device_weights(cts, torch.from_numpy(Wi).to(ctx.device), ctx.default_scale)
+    for j in range(3):
+        assert np.array_equal(outs[j].residues(), wants[j]), j
 
 
 def test_full_size_hmult_sampled(ck):

@@ -629,6 +629,35 @@ def nets_leg(args, dev, log, tuning=None):
                     "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt,
                     "tuning": yield_tuning}
     log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
+    del g, cts, ctx
+    torch.cuda.empty_cache()
+    # the same regressor at N = 2^13 (16 windows per ciphertext, 256
+    # ciphertexts): the configuration's smaller ring, above the 128-bit
+    # security bound for this chain
+    pr = nat.ckks_find_primes(13, [60] + [40] * 5 + [60])
+    ctx = ckks.Context(13, pr[:6], pr[6:], 6, device=dev).keygen(31)
+    ctx.set_tuning(**(tuning or {}))
+    W = nets.yield_windows(ctx.N // 2)
+    steps = nets.yield_steps(ws, W)
+    for ge in nets.galois_for_steps(ctx, steps, direct=True):
+        ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
+    packed = nets.yield_pack(xw, ctx.N // 2)
+    cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
+    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
+    g.run(cts)
+    torch.cuda.synchronize()
+    t13 = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted-n8192", tuning)
+    t0 = time.perf_counter()
+    for _ in range(args.net_runs):
+        g.run(cts)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.net_runs
+    out["yield_n8192"] = {"config": "N=2^13, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois "
+                                    "keys, hoisted rotations" % (len(cts), len(ctx.gk)),
+                          "security": security_label(13, pr)["label"], "encrypted_infer_per_s": 1.0 / dt,
+                          "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt, "tuning": t13}
+    log("yield at N=2^13 (%s): %.1f ms per inference, %.0f windows/s" %
+        (security_label(13, pr)["label"], 1e3 * dt, 4096 / dt))
     return out
 
 
@@ -741,6 +770,39 @@ def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
     extra["vision"] = {"s_per_inference": total / threads, "encrypted_infer_per_s": threads / total,
                        "sample": "every op kind of one 8192-image inference timed on a sample (one row or "
                                  "ciphertext per thread), scaled by its count", "ops": est}
+    # yield regressor at N = 2^14, [60, 40 x 5 | 60], hoisted rotations: the
+    # whole three-layer chain of one ciphertext per thread, scaled to the
+    # 128 ciphertexts (4096 windows) of one inference
+    yq = O.find_primes(14, [60] + [40] * 5 + [60])
+    yo = O.Oracle(14, yq[:6], yq[6:], 6)
+    _, ysw, ysb = S.yield_inputs(n_windows=1)
+    ywn = PN.yield_layout(yo.N // 2)
+    periods = [256, 64, 16]
+    plans = [PN.yield_layer_plan(ysw[l].shape[1], ysw[l].shape[0], periods[l], ywn) for l in range(3)]
+    ysteps = sorted({st for a, b in plans for st in a + b if st})
+    t0 = time.perf_counter()
+    ykeys = ON.Keys(yo, 31, [yo.galois_elt(st) for st in ysteps])
+    t_keys = time.perf_counter() - t0
+    from oracle import encoding as OE
+    ycoef = [np.stack([OE.encode(di, scale, yo.N) for di in PN.yield_diagonals(ysw[l], periods[l], ywn)])
+             for l in range(3)]
+
+    def ychain(seed):
+        y, sy = S.residues(seed, yq[:6], yo.N, 2), scale
+        for l in range(3):
+            y, sy = ON.diag_dense_hoisted(yo, ykeys, y, sy, ycoef[l], scale, plans[l][0], plans[l][1], None)
+            if l < 2:
+                y, sy = ON.square(yo, ykeys, y, sy)
+        return y
+
+    n_y, el_y = _timed_pool(ychain, [90 + i for i in range(threads)], threads, 0.0)
+    n_ct = -(-4096 // ywn)
+    # thread-seconds per ciphertext, times the inference's ciphertexts, over the threads
+    extra["yield"] = {"s_per_inference": (el_y * threads / n_y) * n_ct / threads,
+                      "thread_s_per_ciphertext": el_y * threads / n_y, "ciphertexts_per_inference": n_ct,
+                      "galois_keys": len(ysteps), "keygen_s": t_keys,
+                      "sample": "the three hoisted-rotation layers and two squares of one ciphertext per thread "
+                                "(%d ciphertexts), scaled to one 4096-window inference" % n_y}
     # FP64 plaintext networks as written (the paper's comparison)
     xv, Pv = S.vision_inputs()
     t0 = time.perf_counter()
@@ -752,9 +814,10 @@ def cpu_leg(args, q, p, A, Bc, outs, ntt, log):
     t_y = time.perf_counter() - t0
     extra["plaintext_fp64"] = {"vision_8192_images_ms": 1e3 * t_v, "yield_4096_windows_ms": 1e3 * t_y,
                                "note": "numpy FP64, unencrypted, same networks and batch sizes"}
-    log("oracle NTT %.0f limb-NTT/s (%d threads); vision inference ~%.0f s on %d threads; "
-        "FP64 plaintext vision %.1f ms, yield %.1f ms" %
-        (extra["ntt"]["limb_ntt_per_s"], threads, total / threads, threads, 1e3 * t_v, 1e3 * t_y))
+    log("oracle NTT %.0f limb-NTT/s (%d threads); vision inference ~%.0f s, yield inference ~%.0f s on %d "
+        "threads; FP64 plaintext vision %.1f ms, yield %.1f ms" %
+        (extra["ntt"]["limb_ntt_per_s"], threads, total / threads, extra["yield"]["s_per_inference"], threads,
+         1e3 * t_v, 1e3 * t_y))
     cpu["extra"] = extra
     return cpu
 

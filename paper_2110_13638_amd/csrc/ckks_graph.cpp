@@ -254,23 +254,27 @@ int fire_poly(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_HMULT, B, lv.data()));
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_RESCALE, B, nullptr));
     need(g, ckks_workspace_bytes(g->c, CKKS_OP_ELEMENTWISE, B, nullptr));
-    // h = rescale(x * c_d)
+    // h = rescale(x * c_d) + c_{d-1} (c_0 when d = 1), the constant added in
+    // the rescale's pass at the scale after it
     double hs = s_x * n.w_scale;
+    hs /= (double)ckks_ctx_prime(g->c, l);
+    const u32 k_first = d >= 2 ? d - 1 : 0;
     if (!g->dry) {
         std::vector<i64> v(B, round_half_away(n.coeffs[d] * n.w_scale));
         std::vector<double> vs(B, n.w_scale);
         GK(ckks_multiply_scalar(g->c, in.data(), v.data(), vs.data(), h.data(), B, scratch(g), scratch_avail(g),
                                 g->stream));
-        GK(ckks_rescale(g->c, h.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
+        std::vector<i64> c1(B, round_half_away(n.coeffs[k_first] * hs));
+        GK(ckks_rescale_add_scalar(g->c, h.data(), c1.data(), h.data(), B, scratch(g), scratch_avail(g),
+                                   g->stream));
     }
-    hs /= (double)ckks_ctx_prime(g->c, l);
     u32 hl = l - 1;
     auto set = [&](std::vector<ckks_ct> &v, u32 level, double scale) {
         for (auto &x : v) x.level = level, x.scale = scale;
     };
     set(h, hl, hs);
     for (u32 k = d - 1; k >= 1; k--) {
-        if (!g->dry) {
+        if (!g->dry && k != k_first) {
             std::vector<i64> v(B, round_half_away(n.coeffs[k] * hs));
             GK(ckks_add_scalar(g->c, h.data(), v.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
         }
@@ -288,7 +292,7 @@ int fire_poly(ckks_graph *g, Node &n, std::vector<ckks_ct> in) {
         set(h, hl, hs);
         set(t, hl, hs);
     }
-    if (!g->dry) {
+    if (!g->dry && d >= 2) {
         std::vector<i64> v(B, round_half_away(n.coeffs[0] * hs));
         GK(ckks_add_scalar(g->c, h.data(), v.data(), h.data(), B, scratch(g), scratch_avail(g), g->stream));
     }

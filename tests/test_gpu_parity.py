@@ -275,16 +275,46 @@ def test_wide_linear_no_accumulator_overflow(ck):
     rows = np.zeros((2, n_in))
     rows[0, :] = -1.0 / 2 ** 40
     rows[1, ::2] = 3.0 / 2 ** 40
-    for sparse in (False, True):
-        if sparse:
+    wi = np.stack([np.full(n_in, -1), np.where(np.arange(n_in) % 2 == 0, 3, 0)]).astype(np.int64)
+    for path in ("sparse", "dense", "device"):
+        if path == "sparse":  # grouped VALU kernel (two different column lists)
             outs = ctx.linear_csr(cts, np.array([0, n_in, n_in + n_in // 2]),
                                   np.concatenate([np.arange(n_in), np.arange(0, n_in, 2)]),
                                   np.concatenate([np.full(n_in, -1), np.full(n_in // 2, 3)]).astype(np.int64), 2.0 ** 40)
-        else:
+        elif path == "dense":  # dense rows: the matrix cores
             outs = ctx.linear(cts, rows, w_scale=2.0 ** 40)
+        else:  # weights in device memory: the VALU dense kernel
+            outs = ctx.linear_device_weights(cts, torch.from_numpy(wi).to(ctx.device), 2.0 ** 40)
         for j, w in enumerate(([-1] * n_in, [3 if i % 2 == 0 else 0 for i in range(n_in)])):
             want = orc.lincomb([one] * n_in, w)
-            assert np.array_equal(outs[j].residues(), want), (sparse, j)
+            assert np.array_equal(outs[j].residues(), want), (path, j)
+
+
+def test_grouped_linear_row_groups(ck):
+    # sparse rows whose column lists repeat in runs of 1..11 rows: the
+    # grouped kernel's instantiations for groups of up to 2, 4, 5 and 8 rows
+    # (runs above 8 split), on an FP64-engine prime and a 60-bit prime
+    primes = O.find_primes(10, [60, 40, 60])
+    q = primes[:2]
+    ctx = ck.Context(10, q, primes[2:], 2).set_tuning(lin_mfma=0)
+    orc = O.Oracle(10, q, primes[2:], 2)
+    n_in = 40
+    res = [S.residues(400 + i, q, ctx.N, 2) for i in range(n_in)]
+    cts = [ctx.ct_from_residues(r, 2.0 ** 40) for r in res]
+    rng = np.random.default_rng(5)
+    for runs in ([1, 2, 1, 2], [3, 4, 1], [5, 5, 2], [7, 8, 11, 6]):
+        rows = []
+        for run in runs:
+            cols = np.sort(rng.choice(n_in, size=int(rng.integers(1, 12)), replace=False))
+            for _ in range(run):
+                rows.append((cols, rng.integers(-(1 << 40), 1 << 40, size=len(cols))))
+        row_ptr = np.concatenate([[0], np.cumsum([len(c) for c, _ in rows])])
+        col = np.concatenate([c for c, _ in rows])
+        w = np.concatenate([x for _, x in rows]).astype(np.int64)
+        outs = ctx.linear_csr(cts, row_ptr, col, w, 2.0 ** 40)
+        for j, (c, x) in enumerate(rows):
+            want = orc.lincomb([res[i] for i in c], [int(v) for v in x])
+            assert np.array_equal(outs[j].residues(), want), (runs, j)
 
 
 @pytest.mark.parametrize("shape", [(845, 100), (37, 5), (64, 33)])

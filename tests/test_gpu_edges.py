@@ -75,6 +75,12 @@ def test_error_paths(small):
         nat.ckks_hmult_relin_rescale(ctx.h, ctx.rk.data_ptr() + 8, ctx._structs([a]), ctx._structs([a]),
                                      ctx._structs([ctx.new_ct(2, a.level - 1)]), wsb, wbb, ctx.stream)
     assert e.value.code == nat.CKKS_EINVAL and "aligned" in str(e.value)
+    # the fused rescale + bias needs its constants
+    wsr, wbr = ctx.ws_for(nat.CKKS_OP_RESCALE, 1, [a.level])
+    with pytest.raises(nat.CkksError) as e:
+        nat._call("ckks_rescale_add_scalar", ctx.h, ctx._structs([a]), None, ctx._structs([ctx.new_ct(2, a.level)]),
+                  1, wsr, wbr, ctx.stream)
+    assert e.value.code == nat.CKKS_EINVAL
 
 
 def test_bench_configuration_sampled(ck):

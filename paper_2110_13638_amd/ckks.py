@@ -524,6 +524,15 @@ class Context:
         nat.ckks_rescale(self.h, s, s, ws, wb, self.stream)
         return self._outs(s, cts)
 
+    def rescale_add_scalars_inplace(self, cts, values):
+        """rescale, then cts[k] += values[k] at the scale after the rescale,
+        in one pass (ckks_rescale_add_scalar)"""
+        v = [self.const_int(x, c.scale / float(self.q[c.level])) for x, c in zip(values, cts)]
+        s = self._structs(cts)
+        ws, wb = self.ws_for(nat.CKKS_OP_RESCALE, len(cts), [c.level for c in cts])
+        nat.ckks_rescale_add_scalar(self.h, s, v, s, ws, wb, self.stream)
+        return self._outs(s, cts)
+
     def add_scalars_inplace(self, cts, values):
         """cts[k] += values[k] (floats, encoded at each ciphertext's scale)"""
         v = [self.const_int(x, c.scale) for x, c in zip(values, cts)]

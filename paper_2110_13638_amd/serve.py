@@ -319,8 +319,7 @@ class Engine:
         row_ptr, col, w, bias = m.block(stage, R)
         flat = [c for r in rs for c in r.state]
         outs = ctx.linear_csr(flat, row_ptr, col, w, m.w_scale)
-        ctx.rescale_inplace(outs)
-        ctx.add_scalars_inplace(outs, bias)
+        ctx.rescale_add_scalars_inplace(outs, bias)
         n = layer["n_out"]
         for i, r in enumerate(rs):
             r.state = outs[i * n:(i + 1) * n]

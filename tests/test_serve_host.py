@@ -56,6 +56,9 @@ class FakeCtx:
             c.data = (c.data + int(round(v * 100))) % 1000003
         return cts
 
+    def rescale_add_scalars_inplace(self, cts, values):
+        return self.add_scalars_inplace(self.rescale_inplace(cts), values)
+
 class FakeVision:
     """two tiny linear layers around a square, in the VisionModel shape"""
     n_pix = 3

@@ -26,7 +26,10 @@ class Graph:
     def __del__(self):
         g = getattr(self, "g", None)
         if g:
-            nat.ckks_graph_destroy(g)
+            # at interpreter exit the binding module may already be torn down
+            destroy = getattr(nat, "ckks_graph_destroy", None)
+            if destroy is not None:
+                destroy(g)
             self.g = None
 
     # --- nodes -----------------------------------------------------------------

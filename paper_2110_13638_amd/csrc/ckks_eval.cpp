@@ -542,8 +542,8 @@ extern "C" size_t ckks_hoisted_linear_workspace_bytes(const ckks_ctx *c, uint32_
     const size_t L = level + 1, E = L + c->n_p, beta = (L + c->alpha - 1) / c->alpha;
     const size_t limb = ((size_t)c->N * 8 + 255) & ~(size_t)255;
     const size_t per_ct = (L + beta * E + 2 * E) * limb;
-    const size_t items = B * (L + beta * E + 2 * (c->n_p + L)) * sizeof(Item) +
-                         E * ((B + kHoCts - 1) / kHoCts) * sizeof(HoItem) + (size_t)n_rot * E * sizeof(Item);
+    const size_t items = B * (L + beta * E + 2 * (c->n_p + L)) * sizeof(Item) + E * B * sizeof(HoItem) +
+                         (size_t)n_rot * E * sizeof(Item);
     return B * per_ct + ((size_t)n_rot * E + 1) * limb + items + 16 * 4096;
 }
 
@@ -649,9 +649,17 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
                 mdown.push_back(it);
             }
     }
-    for (u32 g0 = 0; g0 < B; g0 += kHoCts) {
-        const u32 n = std::min<u32>(kHoCts, B - g0);
-        for (u32 t = 0; t < E; t++) {
+    // Staged form (see kHoChunk): every Galois element is 1 mod 2N / kHoChunk,
+    // so each aligned block of kHoChunk slots is mapped onto itself; then up
+    // to kHoStageRows rows (ciphertexts x digits) of a block sit in LDS.
+    u32 per = kHoCts;
+    bool staged = N >= kHoChunk && beta <= kHoStageRows;
+    for (u32 i = 0; i < n_rot && staged; i++) staged = galois_elts[i] % (2 * N / kHoChunk) == 1;
+    if (staged) per = std::min<u32>(kHoCts, kHoStageRows / beta);
+    // items ordered by limb, so the workgroups that read one limb of a key run together
+    for (u32 t = 0; t < E; t++) {
+        for (u32 g0 = 0; g0 < B; g0 += per) {
+            const u32 n = std::min<u32>(per, B - g0);
             HoItem h;
             memset(&h, 0, sizeof h);
             h.n_ct = n;
@@ -677,7 +685,7 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
     P.add(0, F_INT, ptl);
     P.add(1, I_SCALE, isc);
     add_modup(P, modup);
-    P.add(5, 0, ho);
+    P.add(5, staged ? (int)(per * beta) : 0, ho);
     P.add(1, I_COPY, scl);
     P.add(0, F_MODDOWN, mdown);
     CK(P.run(ws_bytes, s));

@@ -152,6 +152,11 @@ struct IpSeqItem {
 // multiplied by that rotation's Galois key; P sigma(c0) joins the b-sum on
 // data limbs; the weighted sums over all rotations go to acc [2][E][N].
 constexpr int kHoCts = 4;
+// Staged form: when every rotation maps each aligned block of kHoChunk NTT
+// slots onto itself, a workgroup keeps its block of the digits in LDS,
+// at most kHoStageRows rows (ciphertexts x digits) of kHoChunk residues.
+constexpr unsigned kHoChunk = 256;
+constexpr unsigned kHoStageRows = 24;
 struct HoItem {
     const u64 *ext[kHoCts];  // ModUp'd digits of c1, [digit][E][N]
     const u64 *c0[kHoCts];   // limb `pos` of c0 (data limbs only)

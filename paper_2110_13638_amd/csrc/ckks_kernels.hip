@@ -347,9 +347,18 @@ __device__ __forceinline__ u32 automorph_src(u32 j, u32 g, u32 log_n) {
 
 // Hoisted rotations with plaintext weights; see HoItem. The 128-bit
 // weighted sums are reduced every kHoFold rotations (each term < q^2).
+//
+// STAGED: every rotation of the launch maps each aligned block of
+// kHoChunk NTT slots onto itself (the host checks that every Galois
+// element is 1 modulo 2N / kHoChunk), so a workgroup owns one such
+// block, copies its part of the digits once into LDS ([ct][digit]
+// [kHoChunk]) and reads the automorphism's sources from there for every
+// rotation instead of re-reading them from memory.
 constexpr int kHoFold = 8;
-template <int kEwPer>
+template <int kEwPer, bool STAGED>
 __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
+    extern __shared__ u64 ho_lds[];
     const u32 N = 1u << tb.log_n;
     const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
     const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
@@ -360,6 +369,19 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
     const size_t kstride = (size_t)tb.n_prim * N;  // one key component
     const bool data = it.pos < it.L;
     const u32 own = data ? it.pos / it.alpha : 0xFFFFFFFFu;
+    const u32 base = chunk * kHoChunk;
+    if constexpr (STAGED) {
+#pragma unroll
+        for (int c = 0; c < kHoCts; c++) {
+            if ((u32)c >= it.n_ct) break;
+            for (u32 j = 0; j < it.beta; j++) {
+                const u32 x = base + threadIdx.x;
+                ho_lds[(c * it.beta + j) * kHoChunk + threadIdx.x] =
+                    (j == own) ? it.c1[c][(size_t)it.pos * N + x] : it.ext[c][((size_t)j * it.E + it.pos) * N + x];
+            }
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int e = 0; e < kEwPer; e++) {
         const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
@@ -384,13 +406,18 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
                 const u32 src = automorph_src(x, g, tb.log_n);
                 const u64 *key = it.keys[i] + (size_t)it.prime * N + x;
                 Acc128 sb[kHoCts], sa[kHoCts];
+                const u32 ls = (src - base) & (kHoChunk - 1);
                 for (u32 j = 0; j < it.beta; j++) {
                     const u64 k0 = key[(size_t)(2 * j) * kstride], k1 = key[(size_t)(2 * j + 1) * kstride];
 #pragma unroll
                     for (int c = 0; c < kHoCts; c++) {
                         if ((u32)c >= it.n_ct) break;
-                        const u64 v = (j == own) ? it.c1[c][(size_t)it.pos * N + src]
-                                                 : it.ext[c][((size_t)j * it.E + it.pos) * N + src];
+                        u64 v;
+                        if constexpr (STAGED)
+                            v = ho_lds[(c * it.beta + j) * kHoChunk + ls];
+                        else
+                            v = (j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                           : it.ext[c][((size_t)j * it.E + it.pos) * N + src];
                         sb[c].mac(v, k0);
                         sa[c].mac(v, k1);
                     }
@@ -425,9 +452,13 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
 // product is an FP64 product of two residues (<= 0.75 t), the digit sums
 // and the per-rotation sums are re-centred every four terms, P (c0, c1)
 // uses an FP64 product by P mod t (ratio from 1/t, error <= 2^-52).
-template <int kEwPer>
+// STAGED as in k_hoist; the staged digits are held as FP64 values.
+template <int kEwPer, bool STAGED>
 __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__restrict__ items, int nitems) {
 #pragma clang fp contract(off)
+    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
+    extern __shared__ u64 ho_lds[];
+    double *const sv = reinterpret_cast<double *>(ho_lds);
     const u32 N = 1u << tb.log_n;
     const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
     const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
@@ -440,6 +471,19 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
     const size_t kstride = (size_t)tb.n_prim * N;  // one key component
     const bool data = it.pos < it.L;
     const u32 own = data ? it.pos / it.alpha : 0xFFFFFFFFu;
+    const u32 base = chunk * kHoChunk;
+    if constexpr (STAGED) {
+#pragma unroll
+        for (int c = 0; c < kHoCts; c++) {
+            if ((u32)c >= it.n_ct) break;
+            for (u32 j = 0; j < it.beta; j++) {
+                const u32 x = base + threadIdx.x;
+                sv[(c * it.beta + j) * kHoChunk + threadIdx.x] = fp_from_u64(
+                    (j == own) ? it.c1[c][(size_t)it.pos * N + x] : it.ext[c][((size_t)j * it.E + it.pos) * N + x]);
+            }
+        }
+        __syncthreads();
+    }
 #pragma unroll
     for (int e = 0; e < kEwPer; e++) {
         const u32 x = (chunk * kEwPer + e) * 256 + threadIdx.x;
@@ -468,14 +512,19 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
                 double sb[kHoCts], sa[kHoCts];
 #pragma unroll
                 for (int c = 0; c < kHoCts; c++) sb[c] = sa[c] = 0.0;
+                const u32 ls = (src - base) & (kHoChunk - 1);
                 for (u32 j = 0; j < it.beta; j++) {
                     const double k0 = fp_from_u64(key[(size_t)(2 * j) * kstride]);
                     const double k1 = fp_from_u64(key[(size_t)(2 * j + 1) * kstride]);
 #pragma unroll
                     for (int c = 0; c < kHoCts; c++) {
                         if ((u32)c >= it.n_ct) break;
-                        const double v = fp_from_u64((j == own) ? it.c1[c][(size_t)it.pos * N + src]
-                                                                : it.ext[c][((size_t)j * it.E + it.pos) * N + src]);
+                        double v;
+                        if constexpr (STAGED)
+                            v = sv[(c * it.beta + j) * kHoChunk + ls];
+                        else
+                            v = fp_from_u64((j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                                       : it.ext[c][((size_t)j * it.E + it.pos) * N + src]);
                         sb[c] = sb[c] + fp_mulv(v, k0, t, tinv);
                         sa[c] = sa[c] + fp_mulv(v, k1, t, tinv);
                         if ((j & 3) == 3) {
@@ -893,12 +942,21 @@ hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, 
     }
     return hipGetLastError();
 }
-hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s) {
+hipError_t launch_hoist(const DevTables &tb, int staged_rows, const HoItem *items, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (staged_rows > 0) {  // one workgroup per kHoChunk slots, rows x kHoChunk staged residues
+        if (staged_rows > (int)kHoStageRows || (1u << tb.log_n) < kHoChunk) return hipErrorInvalidValue;
+        const size_t lds = (size_t)staged_rows * kHoChunk * sizeof(u64);
+        if (tb.ntt_fp)
+            hipLaunchKernelGGL((k_hoist_fp<1, true>), dim3(ew_blocks(tb, n, 1)), dim3(256), lds, s, tb, items, n);
+        else
+            hipLaunchKernelGGL((k_hoist<1, true>), dim3(ew_blocks(tb, n, 1)), dim3(256), lds, s, tb, items, n);
+        return hipGetLastError();
+    }
     if (tb.ntt_fp)  // every item's prime is below 2^50
-        hipLaunchKernelGGL(k_hoist_fp<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
+        hipLaunchKernelGGL((k_hoist_fp<2, false>), dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
     else
-        hipLaunchKernelGGL(k_hoist<2>, dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
+        hipLaunchKernelGGL((k_hoist<2, false>), dim3(ew_blocks(tb, n, 2)), dim3(256), 0, s, tb, items, n);
     return hipGetLastError();
 }
 template <int NCT>

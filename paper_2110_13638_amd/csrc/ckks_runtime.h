@@ -25,7 +25,7 @@ hipError_t launch_fwd(const DevTables &tb, int op, const Item *items, int n, u64
 hipError_t launch_inv(const DevTables &tb, int op, const Item *items, int n, hipStream_t s);
 hipError_t launch_ew(const DevTables &tb, const EwItem *items, int n, u64 seed, hipStream_t s);
 hipError_t launch_ip(const DevTables &tb, const IpItem *items, int n, hipStream_t s);
-hipError_t launch_hoist(const DevTables &tb, const HoItem *items, int n, hipStream_t s);
+hipError_t launch_hoist(const DevTables &tb, int staged_rows, const HoItem *items, int n, hipStream_t s);
 hipError_t launch_ip_seq(const DevTables &tb, const IpSeqItem *items, int n, hipStream_t s);
 hipError_t launch_linear(const DevTables &tb, const u64 *const *in_ptrs, const u64 *wt,
                          u64 *const *out_ptrs, u32 n_in, u32 n_out, u32 limbs, u32 in_stride,
@@ -406,7 +406,7 @@ struct Plan {
                     case 1: return launch_inv(tb, L.op, (const Item *)p, L.n, st);
                     case 2: return launch_ew(tb, (const EwItem *)p, L.n, L.seed, st);
                     case 3: return launch_ip(tb, (const IpItem *)p, L.n, st);
-                    case 5: return launch_hoist(tb, (const HoItem *)p, L.n, st);
+                    case 5: return launch_hoist(tb, L.op, (const HoItem *)p, L.n, st);
                     case 6: return launch_ip_seq(tb, (const IpSeqItem *)p, L.n, st);
                 }
                 return hipErrorInvalidValue;

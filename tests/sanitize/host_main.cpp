@@ -20,7 +20,7 @@ hipError_t launch_fwd(const DevTables &, int, const Item *, int, u64, hipStream_
 hipError_t launch_inv(const DevTables &, int, const Item *, int, hipStream_t) STUB()
 hipError_t launch_ew(const DevTables &, const EwItem *, int, u64, hipStream_t) STUB()
 hipError_t launch_ip(const DevTables &, const IpItem *, int, hipStream_t) STUB()
-hipError_t launch_hoist(const DevTables &, const HoItem *, int, hipStream_t) STUB()
+hipError_t launch_hoist(const DevTables &, int, const HoItem *, int, hipStream_t) STUB()
 hipError_t launch_ip_seq(const DevTables &, const IpSeqItem *, int, hipStream_t) STUB()
 hipError_t launch_linear(const DevTables &, const u64 *const *, const u64 *, u64 *const *, u32, u32, u32, u32, u32,
                          hipStream_t) STUB()

@@ -25,19 +25,30 @@ def mods():
     return ckks, nets
 
 
-@pytest.mark.parametrize("chain", ["one_prime_digits", "four_prime_digits"])
-def test_hoisted_linear_bit_exact(mods, chain):
+# rotation sets: arbitrary steps, and steps that are multiples of 8 slots at
+# N = 2^12 (every Galois element is then 1 mod 2N / 256, so each aligned block
+# of 256 NTT slots maps onto itself and the kernel keeps the digits in LDS)
+STEPS = {"any_steps": [0, 1, 5, 100, 2047, 3], "block_steps": [0, 8, 64, 1000, 2040, 24]}
+
+
+@pytest.mark.parametrize("ntt_fp", [1, 0])
+@pytest.mark.parametrize("steps_kind", ["any_steps", "block_steps"])
+@pytest.mark.parametrize("chain", ["one_prime_digits", "four_prime_digits", "eight_one_prime_digits"])
+def test_hoisted_linear_bit_exact(mods, chain, steps_kind, ntt_fp):
     ckks, nets = mods
     from paper_2110_13638_amd import _native as nat
     if chain == "one_prime_digits":
         q_bits, p_bits, dnum, level = [60, 40, 40], [60], 3, 2
-    else:
+    elif chain == "four_prime_digits":
         q_bits, p_bits, dnum, level = [50] * 8, [60, 60], 2, 6
+    else:  # 8 digits: 3 ciphertexts per staged work item
+        q_bits, p_bits, dnum, level = [50] * 8, [60], 8, 7
     primes = O.find_primes(12, q_bits + p_bits)
     q, p = primes[: len(q_bits)], primes[len(q_bits):]
     ctx = ckks.Context(12, q, p, dnum).keygen(5)
+    ctx.set_tuning(ntt_fp=ntt_fp)
     orc = O.Oracle(12, q, p, dnum)
-    steps = [0, 1, 5, 100, 2047, 3]
+    steps = STEPS[steps_kind]
     elts = [1 if s == 0 else orc.galois_elt(s) for s in steps]
     keys = ON.Keys(orc, 5, [g for g in elts if g != 1])
     for g in elts:
@@ -53,7 +64,7 @@ def test_hoisted_linear_bit_exact(mods, chain):
     dev = torch.from_numpy(coeffs).to(ctx.device)
     wb = nat.ckks_hoisted_linear_workspace_bytes(ctx.h, B, level, len(steps))
     ws, wbytes = ctx.workspace(wb)
-    print("hoisted case", chain, "B", B, "rotations", len(steps), flush=True)
+    print("hoisted case", chain, steps_kind, "ntt_fp", ntt_fp, "B", B, "rotations", len(steps), flush=True)
     nat.ckks_hoisted_linear(ctx.h, ctx._structs(cts), so, elts, [ctx.gk[g].data_ptr() if g != 1 else None
                                                                  for g in elts], dev.data_ptr(), SCALE, ws, wbytes,
                             ctx.stream)

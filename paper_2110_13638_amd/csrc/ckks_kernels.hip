@@ -355,6 +355,7 @@ __device__ __forceinline__ u32 automorph_src(u32 j, u32 g, u32 log_n) {
 // [kHoChunk]) and reads the automorphism's sources from there for every
 // rotation instead of re-reading them from memory.
 constexpr int kHoFold = 8;
+constexpr u32 kHoKeyBatch = 8;  // digits whose key residues are in flight together
 template <int kEwPer, bool STAGED>
 __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__restrict__ items, int nitems) {
     static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
@@ -407,19 +408,31 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
                 const u64 *key = it.keys[i] + (size_t)it.prime * N + x;
                 Acc128 sb[kHoCts], sa[kHoCts];
                 const u32 ls = (src - base) & (kHoChunk - 1);
-                for (u32 j = 0; j < it.beta; j++) {
-                    const u64 k0 = key[(size_t)(2 * j) * kstride], k1 = key[(size_t)(2 * j + 1) * kstride];
+                for (u32 j0 = 0; j0 < it.beta; j0 += kHoKeyBatch) {
+                    // the batch's key residues are loaded together, then used
+                    u64 kk[2 * kHoKeyBatch];
 #pragma unroll
-                    for (int c = 0; c < kHoCts; c++) {
-                        if ((u32)c >= it.n_ct) break;
-                        u64 v;
-                        if constexpr (STAGED)
-                            v = ho_lds[(c * it.beta + j) * kHoChunk + ls];
-                        else
-                            v = (j == own) ? it.c1[c][(size_t)it.pos * N + src]
-                                           : it.ext[c][((size_t)j * it.E + it.pos) * N + src];
-                        sb[c].mac(v, k0);
-                        sa[c].mac(v, k1);
+                    for (u32 jj = 0; jj < kHoKeyBatch; jj++)
+                        if (j0 + jj < it.beta) {
+                            kk[2 * jj] = key[(size_t)(2 * (j0 + jj)) * kstride];
+                            kk[2 * jj + 1] = key[(size_t)(2 * (j0 + jj) + 1) * kstride];
+                        }
+#pragma unroll
+                    for (u32 jj = 0; jj < kHoKeyBatch; jj++) {
+                        const u32 j = j0 + jj;
+                        if (j >= it.beta) break;
+#pragma unroll
+                        for (int c = 0; c < kHoCts; c++) {
+                            if ((u32)c >= it.n_ct) break;
+                            u64 v;
+                            if constexpr (STAGED)
+                                v = ho_lds[(c * it.beta + j) * kHoChunk + ls];
+                            else
+                                v = (j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                               : it.ext[c][((size_t)j * it.E + it.pos) * N + src];
+                            sb[c].mac(v, kk[2 * jj]);
+                            sa[c].mac(v, kk[2 * jj + 1]);
+                        }
                     }
                 }
 #pragma unroll
@@ -513,23 +526,35 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
 #pragma unroll
                 for (int c = 0; c < kHoCts; c++) sb[c] = sa[c] = 0.0;
                 const u32 ls = (src - base) & (kHoChunk - 1);
-                for (u32 j = 0; j < it.beta; j++) {
-                    const double k0 = fp_from_u64(key[(size_t)(2 * j) * kstride]);
-                    const double k1 = fp_from_u64(key[(size_t)(2 * j + 1) * kstride]);
+                for (u32 j0 = 0; j0 < it.beta; j0 += kHoKeyBatch) {
+                    // the batch's key residues are loaded together, then used
+                    u64 kk[2 * kHoKeyBatch];
 #pragma unroll
-                    for (int c = 0; c < kHoCts; c++) {
-                        if ((u32)c >= it.n_ct) break;
-                        double v;
-                        if constexpr (STAGED)
-                            v = sv[(c * it.beta + j) * kHoChunk + ls];
-                        else
-                            v = fp_from_u64((j == own) ? it.c1[c][(size_t)it.pos * N + src]
-                                                       : it.ext[c][((size_t)j * it.E + it.pos) * N + src]);
-                        sb[c] = sb[c] + fp_mulv(v, k0, t, tinv);
-                        sa[c] = sa[c] + fp_mulv(v, k1, t, tinv);
-                        if ((j & 3) == 3) {
-                            sb[c] = fp_center(sb[c], t, tinv);
-                            sa[c] = fp_center(sa[c], t, tinv);
+                    for (u32 jj = 0; jj < kHoKeyBatch; jj++)
+                        if (j0 + jj < it.beta) {
+                            kk[2 * jj] = key[(size_t)(2 * (j0 + jj)) * kstride];
+                            kk[2 * jj + 1] = key[(size_t)(2 * (j0 + jj) + 1) * kstride];
+                        }
+#pragma unroll
+                    for (u32 jj = 0; jj < kHoKeyBatch; jj++) {
+                        const u32 j = j0 + jj;
+                        if (j >= it.beta) break;
+                        const double k0 = fp_from_u64(kk[2 * jj]), k1 = fp_from_u64(kk[2 * jj + 1]);
+#pragma unroll
+                        for (int c = 0; c < kHoCts; c++) {
+                            if ((u32)c >= it.n_ct) break;
+                            double v;
+                            if constexpr (STAGED)
+                                v = sv[(c * it.beta + j) * kHoChunk + ls];
+                            else
+                                v = fp_from_u64((j == own) ? it.c1[c][(size_t)it.pos * N + src]
+                                                           : it.ext[c][((size_t)j * it.E + it.pos) * N + src]);
+                            sb[c] = sb[c] + fp_mulv(v, k0, t, tinv);
+                            sa[c] = sa[c] + fp_mulv(v, k1, t, tinv);
+                            if ((j & 3) == 3) {
+                                sb[c] = fp_center(sb[c], t, tinv);
+                                sa[c] = fp_center(sa[c], t, tinv);
+                            }
                         }
                     }
                 }

@@ -356,16 +356,10 @@ __device__ __forceinline__ u32 automorph_src(u32 j, u32 g, u32 log_n) {
 // rotation instead of re-reading them from memory.
 constexpr int kHoFold = 8;
 constexpr u32 kHoKeyBatch = 8;  // digits whose key residues are in flight together
-template <int kEwPer, bool STAGED>
-__global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__restrict__ items, int nitems) {
-    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
+template <int kEwPer, bool STAGED, int NCT>
+__device__ __forceinline__ void hoist_item(const DevTables &tb, const HoItem &it, u32 chunk) {
     extern __shared__ u64 ho_lds[];
     const u32 N = 1u << tb.log_n;
-    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
-    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
-    const u32 chunk = blockIdx.x - iid * per_item;
-    if ((int)iid >= nitems) return;
-    const HoItem it = items[iid];
     const PrimeConst pc = tb.pc[it.prime];
     const size_t kstride = (size_t)tb.n_prim * N;  // one key component
     const bool data = it.pos < it.L;
@@ -373,8 +367,7 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
     const u32 base = chunk * kHoChunk;
     if constexpr (STAGED) {
 #pragma unroll
-        for (int c = 0; c < kHoCts; c++) {
-            if ((u32)c >= it.n_ct) break;
+        for (int c = 0; c < NCT; c++) {
             for (u32 j = 0; j < it.beta; j++) {
                 const u32 x = base + threadIdx.x;
                 ho_lds[(c * it.beta + j) * kHoChunk + threadIdx.x] =
@@ -395,8 +388,7 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
                 // identity: P (c0, c1) on data limbs, nothing on special limbs
                 if (data) {
 #pragma unroll
-                    for (int c = 0; c < kHoCts; c++) {
-                        if ((u32)c >= it.n_ct) break;
+                    for (int c = 0; c < NCT; c++) {
                         const u64 p0 = shoup(it.c0[c][x], pc.pmod, pc.pmod_sh, pc.q);
                         const u64 p1 = shoup(it.c1[c][(size_t)it.pos * N + x], pc.pmod, pc.pmod_sh, pc.q);
                         tb_[c].mac(p0, w);
@@ -422,8 +414,7 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
                         const u32 j = j0 + jj;
                         if (j >= it.beta) break;
 #pragma unroll
-                        for (int c = 0; c < kHoCts; c++) {
-                            if ((u32)c >= it.n_ct) break;
+                        for (int c = 0; c < NCT; c++) {
                             u64 v;
                             if constexpr (STAGED)
                                 v = ho_lds[(c * it.beta + j) * kHoChunk + ls];
@@ -436,8 +427,7 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < kHoCts; c++) {
-                    if ((u32)c >= it.n_ct) break;
+                for (int c = 0; c < NCT; c++) {
                     u64 rb = sb[c].reduce(pc);
                     if (data) rb = addm(rb, shoup(it.c0[c][src], pc.pmod, pc.pmod_sh, pc.q), pc.q);
                     tb_[c].mac(rb, w);
@@ -446,18 +436,33 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
             }
             if ((i & (kHoFold - 1)) == kHoFold - 1) {
 #pragma unroll
-                for (int c = 0; c < kHoCts; c++) {
+                for (int c = 0; c < NCT; c++) {
                     tb_[c] = Acc128{tb_[c].reduce(pc), 0};
                     ta_[c] = Acc128{ta_[c].reduce(pc), 0};
                 }
             }
         }
 #pragma unroll
-        for (int c = 0; c < kHoCts; c++) {
-            if ((u32)c >= it.n_ct) break;
+        for (int c = 0; c < NCT; c++) {
             it.acc[c][(size_t)it.pos * N + x] = tb_[c].reduce(pc);
             it.acc[c][((size_t)it.E + it.pos) * N + x] = ta_[c].reduce(pc);
         }
+    }
+}
+template <int kEwPer, bool STAGED>
+__global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const HoItem it = items[iid];
+    switch (it.n_ct) {  // ciphertexts per item, unrolled
+        case 1: hoist_item<kEwPer, STAGED, 1>(tb, it, chunk); break;
+        case 2: hoist_item<kEwPer, STAGED, 2>(tb, it, chunk); break;
+        case 3: hoist_item<kEwPer, STAGED, 3>(tb, it, chunk); break;
+        default: hoist_item<kEwPer, STAGED, kHoCts>(tb, it, chunk);
     }
 }
 
@@ -466,18 +471,12 @@ __global__ void __launch_bounds__(256) k_hoist(DevTables tb, const HoItem *__res
 // and the per-rotation sums are re-centred every four terms, P (c0, c1)
 // uses an FP64 product by P mod t (ratio from 1/t, error <= 2^-52).
 // STAGED as in k_hoist; the staged digits are held as FP64 values.
-template <int kEwPer, bool STAGED>
-__global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+template <int kEwPer, bool STAGED, int NCT>
+__device__ __forceinline__ void hoist_fp_item(const DevTables &tb, const HoItem &it, u32 chunk) {
 #pragma clang fp contract(off)
-    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
     extern __shared__ u64 ho_lds[];
     double *const sv = reinterpret_cast<double *>(ho_lds);
     const u32 N = 1u << tb.log_n;
-    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
-    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
-    const u32 chunk = blockIdx.x - iid * per_item;
-    if ((int)iid >= nitems) return;
-    const HoItem it = items[iid];
     const PrimeConst pc = tb.pc[it.prime];
     const double t = pc.qf, tinv = pc.qinvf;
     const double pm = fp_from_u64(pc.pmod), pmq = pm * tinv;
@@ -487,8 +486,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
     const u32 base = chunk * kHoChunk;
     if constexpr (STAGED) {
 #pragma unroll
-        for (int c = 0; c < kHoCts; c++) {
-            if ((u32)c >= it.n_ct) break;
+        for (int c = 0; c < NCT; c++) {
             for (u32 j = 0; j < it.beta; j++) {
                 const u32 x = base + threadIdx.x;
                 sv[(c * it.beta + j) * kHoChunk + threadIdx.x] = fp_from_u64(
@@ -503,7 +501,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
         if (x >= N) break;
         double tb_[kHoCts], ta_[kHoCts];
 #pragma unroll
-        for (int c = 0; c < kHoCts; c++) tb_[c] = ta_[c] = 0.0;
+        for (int c = 0; c < NCT; c++) tb_[c] = ta_[c] = 0.0;
         for (u32 i = 0; i < it.n_rot; i++) {
             const u32 g = it.galois[i];
             const double w = fp_from_u64(it.pts[((size_t)i * it.E + it.pos) * N + x]);
@@ -511,8 +509,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
                 // identity: P (c0, c1) on data limbs, nothing on special limbs
                 if (data) {
 #pragma unroll
-                    for (int c = 0; c < kHoCts; c++) {
-                        if ((u32)c >= it.n_ct) break;
+                    for (int c = 0; c < NCT; c++) {
                         const double p0 = fp_mulmod(fp_from_u64(it.c0[c][x]), pm, pmq, t);
                         const double p1 = fp_mulmod(fp_from_u64(it.c1[c][(size_t)it.pos * N + x]), pm, pmq, t);
                         tb_[c] = tb_[c] + fp_mulv(p0, w, t, tinv);
@@ -524,7 +521,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
                 const u64 *key = it.keys[i] + (size_t)it.prime * N + x;
                 double sb[kHoCts], sa[kHoCts];
 #pragma unroll
-                for (int c = 0; c < kHoCts; c++) sb[c] = sa[c] = 0.0;
+                for (int c = 0; c < NCT; c++) sb[c] = sa[c] = 0.0;
                 const u32 ls = (src - base) & (kHoChunk - 1);
                 for (u32 j0 = 0; j0 < it.beta; j0 += kHoKeyBatch) {
                     // the batch's key residues are loaded together, then used
@@ -541,8 +538,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
                         if (j >= it.beta) break;
                         const double k0 = fp_from_u64(kk[2 * jj]), k1 = fp_from_u64(kk[2 * jj + 1]);
 #pragma unroll
-                        for (int c = 0; c < kHoCts; c++) {
-                            if ((u32)c >= it.n_ct) break;
+                        for (int c = 0; c < NCT; c++) {
                             double v;
                             if constexpr (STAGED)
                                 v = sv[(c * it.beta + j) * kHoChunk + ls];
@@ -559,8 +555,7 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < kHoCts; c++) {
-                    if ((u32)c >= it.n_ct) break;
+                for (int c = 0; c < NCT; c++) {
                     double rb = fp_center(sb[c], t, tinv);
                     if (data) rb = fp_center(rb + fp_mulmod(fp_from_u64(it.c0[c][src]), pm, pmq, t), t, tinv);
                     tb_[c] = tb_[c] + fp_mulv(rb, w, t, tinv);
@@ -569,18 +564,34 @@ __global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__
             }
             if ((i & 3) == 3) {
 #pragma unroll
-                for (int c = 0; c < kHoCts; c++) {
+                for (int c = 0; c < NCT; c++) {
                     tb_[c] = fp_center(tb_[c], t, tinv);
                     ta_[c] = fp_center(ta_[c], t, tinv);
                 }
             }
         }
 #pragma unroll
-        for (int c = 0; c < kHoCts; c++) {
-            if ((u32)c >= it.n_ct) break;
+        for (int c = 0; c < NCT; c++) {
             it.acc[c][(size_t)it.pos * N + x] = fp_to_residue(fp_center(tb_[c], t, tinv), pc.qmf, pc.q);
             it.acc[c][((size_t)it.E + it.pos) * N + x] = fp_to_residue(fp_center(ta_[c], t, tinv), pc.qmf, pc.q);
         }
+    }
+}
+template <int kEwPer, bool STAGED>
+__global__ void __launch_bounds__(256) k_hoist_fp(DevTables tb, const HoItem *__restrict__ items, int nitems) {
+#pragma clang fp contract(off)
+    static_assert(!STAGED || kEwPer == 1, "a staged workgroup owns one block of kHoChunk slots");
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const HoItem it = items[iid];
+    switch (it.n_ct) {  // ciphertexts per item, unrolled
+        case 1: hoist_fp_item<kEwPer, STAGED, 1>(tb, it, chunk); break;
+        case 2: hoist_fp_item<kEwPer, STAGED, 2>(tb, it, chunk); break;
+        case 3: hoist_fp_item<kEwPer, STAGED, 3>(tb, it, chunk); break;
+        default: hoist_fp_item<kEwPer, STAGED, kHoCts>(tb, it, chunk);
     }
 }
 

@@ -33,7 +33,8 @@ STEPS = {"any_steps": [0, 1, 5, 100, 2047, 3], "block_steps": [0, 8, 64, 1000, 2
 
 @pytest.mark.parametrize("ntt_fp", [1, 0])
 @pytest.mark.parametrize("steps_kind", ["any_steps", "block_steps"])
-@pytest.mark.parametrize("chain", ["one_prime_digits", "four_prime_digits", "eight_one_prime_digits"])
+@pytest.mark.parametrize("chain", ["one_prime_digits", "four_prime_digits", "eight_one_prime_digits",
+                                   "ten_one_prime_digits"])
 def test_hoisted_linear_bit_exact(mods, chain, steps_kind, ntt_fp):
     ckks, nets = mods
     from paper_2110_13638_amd import _native as nat
@@ -41,8 +42,10 @@ def test_hoisted_linear_bit_exact(mods, chain, steps_kind, ntt_fp):
         q_bits, p_bits, dnum, level = [60, 40, 40], [60], 3, 2
     elif chain == "four_prime_digits":
         q_bits, p_bits, dnum, level = [50] * 8, [60, 60], 2, 6
-    else:  # 8 digits: 3 ciphertexts per staged work item
+    elif chain == "eight_one_prime_digits":  # 3 ciphertexts per staged work item
         q_bits, p_bits, dnum, level = [50] * 8, [60], 8, 7
+    else:  # 10 digits: two batches of key loads, 2 ciphertexts per staged work item
+        q_bits, p_bits, dnum, level = [50] * 10, [60], 10, 9
     primes = O.find_primes(12, q_bits + p_bits)
     q, p = primes[: len(q_bits)], primes[len(q_bits):]
     ctx = ckks.Context(12, q, p, dnum).keygen(5)

@@ -135,8 +135,10 @@ __device__ __forceinline__ double fp_mulv(double x, double y, double t, double t
 // digits, the P d fold multiplies by P mod t (ratio P/t from 1/t, error
 // <= 2^-52), and the final re-centred sum (|.| <= t/2 + 1) becomes a residue.
 // Each thread takes kEwPer residues as pairs (16-byte loads and stores);
-// the digit loop is unrolled for BETA digits (0: a runtime loop).
-template <int kEwPer, int NCT, int BETA>
+// the digit loop is unrolled for BETA digits (0: a runtime loop); FULL:
+// the item holds NCT ciphertexts, so no per-ciphertext test separates the
+// loads of one digit.
+template <int kEwPer, int NCT, int BETA, bool FULL>
 __device__ __forceinline__ void ip_fp_item(const DevTables &tb, const IpItem &it, u32 chunk) {
 #pragma clang fp contract(off)
     const u32 N = 1u << tb.log_n;
@@ -164,18 +166,16 @@ __device__ __forceinline__ void ip_fp_item(const DevTables &tb, const IpItem &it
             ld2(kb + kstride, x, k1);
 #pragma unroll
             for (int c = 0; c < NCT; c++) {
-                if ((u32)c >= it.n_ct) break;
+                if (!FULL && (u32)c >= it.n_ct) break;
                 double v[2];
-                if (j == it.own_digit) {
-                    ld2(it.own0[c], x, v);
-                    if (it.own1[c]) {
-                        double w[2];
-                        ld2(it.own1[c], x, w);
-                        v[0] = fp_mulv(v[0], w[0], t, tinv);
-                        v[1] = fp_mulv(v[1], w[1], t, tinv);
-                    }
-                } else {
-                    ld2(it.ext[c] + ((size_t)j * it.E + it.pos) * N, x, v);
+                // the own digit's limb, else digit j's ModUp output (a select, not a branch)
+                const bool own = j == it.own_digit;
+                ld2(own ? it.own0[c] : it.ext[c] + ((size_t)j * it.E + it.pos) * N, x, v);
+                if (own && it.own1[c]) {
+                    double w[2];
+                    ld2(it.own1[c], x, w);
+                    v[0] = fp_mulv(v[0], w[0], t, tinv);
+                    v[1] = fp_mulv(v[1], w[1], t, tinv);
                 }
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
@@ -196,7 +196,7 @@ __device__ __forceinline__ void ip_fp_item(const DevTables &tb, const IpItem &it
         }
 #pragma unroll
         for (int c = 0; c < NCT; c++) {
-            if ((u32)c >= it.n_ct) break;
+            if (!FULL && (u32)c >= it.n_ct) break;
             double r0[2], r1[2];
 #pragma unroll
             for (int h = 0; h < 2; h++) r0[h] = fp_center(s0[c][h], t, tinv), r1[h] = fp_center(s1[c][h], t, tinv);
@@ -229,12 +229,22 @@ __global__ void __launch_bounds__(256) k_ip_fp(DevTables tb, const IpItem *__res
     const u32 chunk = blockIdx.x - iid * per_item;
     if ((int)iid >= nitems) return;
     const IpItem it = items[iid];
+    if (it.n_ct == NCT) {
+        switch (it.beta) {
+            case 1: ip_fp_item<kEwPer, NCT, 1, true>(tb, it, chunk); break;
+            case 2: ip_fp_item<kEwPer, NCT, 2, true>(tb, it, chunk); break;
+            case 3: ip_fp_item<kEwPer, NCT, 3, true>(tb, it, chunk); break;
+            case 4: ip_fp_item<kEwPer, NCT, 4, true>(tb, it, chunk); break;
+            default: ip_fp_item<kEwPer, NCT, 0, true>(tb, it, chunk); break;
+        }
+        return;
+    }
     switch (it.beta) {
-        case 1: ip_fp_item<kEwPer, NCT, 1>(tb, it, chunk); break;
-        case 2: ip_fp_item<kEwPer, NCT, 2>(tb, it, chunk); break;
-        case 3: ip_fp_item<kEwPer, NCT, 3>(tb, it, chunk); break;
-        case 4: ip_fp_item<kEwPer, NCT, 4>(tb, it, chunk); break;
-        default: ip_fp_item<kEwPer, NCT, 0>(tb, it, chunk); break;
+        case 1: ip_fp_item<kEwPer, NCT, 1, false>(tb, it, chunk); break;
+        case 2: ip_fp_item<kEwPer, NCT, 2, false>(tb, it, chunk); break;
+        case 3: ip_fp_item<kEwPer, NCT, 3, false>(tb, it, chunk); break;
+        case 4: ip_fp_item<kEwPer, NCT, 4, false>(tb, it, chunk); break;
+        default: ip_fp_item<kEwPer, NCT, 0, false>(tb, it, chunk); break;
     }
 }
 

@@ -248,14 +248,10 @@ __global__ void __launch_bounds__(256) k_ip_fp(DevTables tb, const IpItem *__res
     }
 }
 
-template <int kEwPer, int NCT>
-__global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restrict__ items, int nitems) {
+// FULL as in ip_fp_item.
+template <int kEwPer, int NCT, bool FULL>
+__device__ __forceinline__ void ip_int_item(const DevTables &tb, const IpItem &it, u32 chunk) {
     const u32 N = 1u << tb.log_n;
-    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
-    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
-    const u32 chunk = blockIdx.x - iid * per_item;
-    if ((int)iid >= nitems) return;
-    const IpItem it = items[iid];
     const PrimeConst pc = tb.pc[it.prime];
     const size_t kstride = (size_t)tb.n_prim * N;  // one key component
 #pragma unroll
@@ -268,20 +264,18 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
             const u64 k0 = kb[x], k1 = kb[kstride + x];
 #pragma unroll
             for (int c = 0; c < NCT; c++) {
-                if ((u32)c >= it.n_ct) break;
-                u64 v;
-                if (j == it.own_digit) {
-                    v = it.own1[c] ? mulm(it.own0[c][x], it.own1[c][x], pc) : it.own0[c][x];
-                } else {
-                    v = it.ext[c][((size_t)j * it.E + it.pos) * N + x];
-                }
+                if (!FULL && (u32)c >= it.n_ct) break;
+                // the own digit's limb, else digit j's ModUp output (a select, not a branch)
+                const bool own = j == it.own_digit;
+                u64 v = (own ? it.own0[c] : it.ext[c] + ((size_t)j * it.E + it.pos) * N)[x];
+                if (own && it.own1[c]) v = mulm(v, it.own1[c][x], pc);
                 s0[c].mac(v, k0);
                 s1[c].mac(v, k1);
             }
         }
 #pragma unroll
         for (int c = 0; c < NCT; c++) {
-            if ((u32)c >= it.n_ct) break;
+            if (!FULL && (u32)c >= it.n_ct) break;
             if (it.own2[c]) {
                 const u64 a0 = it.own2[c][x], b0 = it.own3[c][x], a1 = it.own0[c][x], b1 = it.own1[c][x];
                 Acc128 t;
@@ -294,6 +288,19 @@ __global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restri
             it.acc[c][((size_t)it.E + it.pos) * N + x] = s1[c].reduce(pc);
         }
     }
+}
+template <int kEwPer, int NCT>
+__global__ void __launch_bounds__(256) k_ip(DevTables tb, const IpItem *__restrict__ items, int nitems) {
+    const u32 N = 1u << tb.log_n;
+    const u32 per_item = (N + 256 * kEwPer - 1) / (256 * kEwPer);
+    const u32 iid = __builtin_amdgcn_readfirstlane(blockIdx.x / per_item);
+    const u32 chunk = blockIdx.x - iid * per_item;
+    if ((int)iid >= nitems) return;
+    const IpItem it = items[iid];
+    if (it.n_ct == NCT)
+        ip_int_item<kEwPer, NCT, true>(tb, it, chunk);
+    else
+        ip_int_item<kEwPer, NCT, false>(tb, it, chunk);
 }
 
 template <int kEwPer>

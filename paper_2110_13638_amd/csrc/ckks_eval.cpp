@@ -410,10 +410,11 @@ int ckks::plan_hmult(Plan &P, const u64 *const *rk, const ckks_ct *a, const ckks
             it.a = i - lo;
             mul.push_back(it);
         }
-        // ModUp of every digit to the primes outside it, then NTT
-        for (u32 j = 0; j < beta; j++) {
-            const u32 lo = j * A, s = std::min(A, L - lo);
-            for (u32 t = 0; t < E; t++) {
+        // ModUp of every digit to the primes outside it, then NTT; limb-major,
+        // so that consecutive items (one XCD's) share a prime's twiddle table
+        for (u32 t = 0; t < E; t++) {
+            for (u32 j = 0; j < beta; j++) {
+                const u32 lo = j * A, s = std::min(A, L - lo);
                 if (t >= lo && t < lo + s) continue;
                 Item it = item0();
                 it.in[0] = dcoef + (size_t)lo * N;

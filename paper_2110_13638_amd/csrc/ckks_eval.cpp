@@ -467,9 +467,10 @@ int ckks::plan_hmult(Plan &P, const u64 *const *rk, const ckks_ct *a, const ckks
             v.y[0] = top + (size_t)cc * N;
             tt.push_back(v);
         }
-        // remaining limbs: ModDown correction, NTT, rescale
-        for (u32 cc = 0; cc < 2; cc++)
-            for (u32 i = 0; i < l; i++) {
+        // remaining limbs: ModDown correction, NTT, rescale; limb-major, so
+        // that the two polynomials' items of one prime share its twiddles
+        for (u32 i = 0; i < l; i++)
+            for (u32 cc = 0; cc < 2; cc++) {
                 Item it = item0();
                 it.in[0] = acc + ((size_t)cc * E + L) * N;
                 it.in[1] = top + (size_t)cc * N;

@@ -479,185 +479,187 @@ def nets_leg(args, dev, log, tuning=None):
 
     out = {}
     scale = 2.0 ** 40
-    # vision
-    pr = nat.ckks_find_primes(14, [60] + [40] * 7 + [60])
-    ctx = ckks.Context(14, pr[:8], pr[8:], 8, device=dev).keygen(21)
-    ctx.set_tuning(**(tuning or {}))
-    n_img = ctx.N // 2
-    x, P = S.vision_inputs(n_images=n_img)
-    pix = x.reshape(n_img, -1).T
-    cts = [ctx.encrypt(ctx.encode(pix[i], level=7), seed=22, obj=i) for i in range(pix.shape[0])]
-    g = nets.build_vision(ctx, P, 28, 7, scale)
-    g.run(cts)
-    torch.cuda.synchronize()
-    vis_tuning = net_tune(ctx, lambda: g.run(cts), "vision-8192", tuning)
-    log("vision launch shapes: %s" % vis_tuning["setting"])
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+    if args.nets_only in (None, "vision"):
+        # vision
+        pr = nat.ckks_find_primes(14, [60] + [40] * 7 + [60])
+        ctx = ckks.Context(14, pr[:8], pr[8:], 8, device=dev).keygen(21)
+        ctx.set_tuning(**(tuning or {}))
+        n_img = ctx.N // 2
+        x, P = S.vision_inputs(n_images=n_img)
+        pix = x.reshape(n_img, -1).T
+        cts = [ctx.encrypt(ctx.encode(pix[i], level=7), seed=22, obj=i) for i in range(pix.shape[0])]
+        g = nets.build_vision(ctx, P, 28, 7, scale)
         g.run(cts)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.net_runs
-    nat.ckks_profile_enable(True)
-    g.run(cts)
-    torch.cuda.synchronize()
-    nat.ckks_profile_enable(False)
-    fam = {}
-    recs = nat.ckks_profile_collect()
-    for name, items, ms in recs:
-        fam[name] = fam.get(name, 0.0) + ms
-    linear_roofline = vision_linear_roofline(recs, P, ctx)
-    out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
-                     "security": security_label(14, pr)["label"],
-                     "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
-                     "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])},
-                     "linear_layers": linear_roofline, "tuning": vis_tuning}
-    log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
-    # the same inference recorded once and replayed as a HIP graph: new
-    # images are written into the recorded input ciphertexts, no host work
-    # per inference; the replayed outputs are checked against an eager run
-    with ctx.record(1 << 30) as rec:
-        routs = g.run(cts)
-    cap = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(cap):
-        rec.plan.launch()
-    cap.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+        torch.cuda.synchronize()
+        vis_tuning = net_tune(ctx, lambda: g.run(cts), "vision-8192", tuning)
+        log("vision launch shapes: %s" % vis_tuning["setting"])
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g.run(cts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.net_runs
+        nat.ckks_profile_enable(True)
+        g.run(cts)
+        torch.cuda.synchronize()
+        nat.ckks_profile_enable(False)
+        fam = {}
+        recs = nat.ckks_profile_collect()
+        for name, items, ms in recs:
+            fam[name] = fam.get(name, 0.0) + ms
+        linear_roofline = vision_linear_roofline(recs, P, ctx)
+        out["vision"] = {"config": "N=2^14, [60,40x7|60], 8192 images per inference, 784 input ciphertexts",
+                         "security": security_label(14, pr)["label"],
+                         "encrypted_infer_per_s": 1.0 / dt, "images_per_s": n_img / dt, "ms_per_inference": 1e3 * dt,
+                         "kernel_ms": {k: round(v, 3) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])},
+                         "linear_layers": linear_roofline, "tuning": vis_tuning}
+        log("vision (8192 images, N=2^14): %.1f ms per inference, %.0f images/s" % (1e3 * dt, n_img / dt))
+        # the same inference recorded once and replayed as a HIP graph: new
+        # images are written into the recorded input ciphertexts, no host work
+        # per inference; the replayed outputs are checked against an eager run
+        with ctx.record(1 << 30) as rec:
+            routs = g.run(cts)
+        cap = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cap):
+            rec.plan.launch()
         cap.replay()
-    torch.cuda.synchronize()
-    dt_g = (time.perf_counter() - t0) / args.net_runs
-    eager = g.run(cts)
-    same = all(np.array_equal(a.residues(), b.residues()) for a, b in zip(routs, eager))
-    out["vision"].update({"graph_replay": {"ms_per_inference": 1e3 * dt_g, "encrypted_infer_per_s": 1.0 / dt_g,
-                                           "images_per_s": n_img / dt_g, "launches": rec.plan.n_launches,
-                                           "same_as_eager": bool(same)}})
-    log("vision, recorded graph replay: %.1f ms per inference, %.0f images/s (%d launches), same as eager: %s" %
-        (1e3 * dt_g, n_img / dt_g, rec.plan.n_launches, same))
-    del cap, rec, routs, eager
-    # conv + bias + x^2 in the two layouts: slot-batched (one ciphertext per
-    # pixel) and the paper's image-in-slots masked kernels (8 images per
-    # ciphertext, taps summed by hoisted rotations)
-    from paper_2110_13638_amd.graph import Graph
-    rows, _ = nets.conv_rows(P["conv_w"], 28)
-    per = len(rows) // P["conv_w"].shape[0]
-    # rows grouped by shared column list (the 5 filters of one position), as
-    # the vision network lowers its conv
-    rows, order = nets.reorder_conv_rows(rows, P["conv_w"].shape[0])
-    g1 = Graph(ctx)
-    g1.chain(g1.input(784, 7, scale), g1.linear(rows, scale, [P["conv_b"][j // per] for j in order]),
-             g1.square(), g1.output())
-    g1.plan()
-    g1.run(cts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            cap.replay()
+        torch.cuda.synchronize()
+        dt_g = (time.perf_counter() - t0) / args.net_runs
+        eager = g.run(cts)
+        same = all(np.array_equal(a.residues(), b.residues()) for a, b in zip(routs, eager))
+        out["vision"].update({"graph_replay": {"ms_per_inference": 1e3 * dt_g, "encrypted_infer_per_s": 1.0 / dt_g,
+                                               "images_per_s": n_img / dt_g, "launches": rec.plan.n_launches,
+                                               "same_as_eager": bool(same)}})
+        log("vision, recorded graph replay: %.1f ms per inference, %.0f images/s (%d launches), same as eager: %s" %
+            (1e3 * dt_g, n_img / dt_g, rec.plan.n_launches, same))
+        del cap, rec, routs, eager
+        # conv + bias + x^2 in the two layouts: slot-batched (one ciphertext per
+        # pixel) and the paper's image-in-slots masked kernels (8 images per
+        # ciphertext, taps summed by hoisted rotations)
+        from paper_2110_13638_amd.graph import Graph
+        rows, _ = nets.conv_rows(P["conv_w"], 28)
+        per = len(rows) // P["conv_w"].shape[0]
+        # rows grouped by shared column list (the 5 filters of one position), as
+        # the vision network lowers its conv
+        rows, order = nets.reorder_conv_rows(rows, P["conv_w"].shape[0])
+        g1 = Graph(ctx)
+        g1.chain(g1.input(784, 7, scale), g1.linear(rows, scale, [P["conv_b"][j // per] for j in order]),
+                 g1.square(), g1.output())
+        g1.plan()
         g1.run(cts)
-    torch.cuda.synchronize()
-    dt_sb = (time.perf_counter() - t0) / args.net_runs
-    del g1
-    steps = nets.conv_slots_steps()
-    for ge in nets.galois_for_steps(ctx, steps, direct=True):
-        ctx.add_galois_key(ge, nets.galois_key_seed(24, ge))
-    n_slot_img = 1024
-    packed = nets.conv_slots_pack(x[:n_slot_img], ctx.N // 2)
-    scts = [ctx.encrypt(ctx.encode(packed[c], level=7), seed=23, obj=c) for c in range(packed.shape[0])]
-    g2 = nets.build_conv_slots(ctx, P, len(scts), 7, scale)
-    g2.run(scts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g1.run(cts)
+        torch.cuda.synchronize()
+        dt_sb = (time.perf_counter() - t0) / args.net_runs
+        del g1
+        steps = nets.conv_slots_steps()
+        for ge in nets.galois_for_steps(ctx, steps, direct=True):
+            ctx.add_galois_key(ge, nets.galois_key_seed(24, ge))
+        n_slot_img = 1024
+        packed = nets.conv_slots_pack(x[:n_slot_img], ctx.N // 2)
+        scts = [ctx.encrypt(ctx.encode(packed[c], level=7), seed=23, obj=c) for c in range(packed.shape[0])]
+        g2 = nets.build_conv_slots(ctx, P, len(scts), 7, scale)
         g2.run(scts)
-    torch.cuda.synchronize()
-    dt_is = (time.perf_counter() - t0) / args.net_runs
-    out["conv_layouts"] = {
-        "workload": "conv 5x5x5 stride 2 + bias + x^2, N=2^14, level 7",
-        "slot_batched": {"images": n_img, "ms": 1e3 * dt_sb, "images_per_s": n_img / dt_sb},
-        "image_in_slots": {"images": n_slot_img, "ciphertexts": len(scts), "ms": 1e3 * dt_is,
-                           "images_per_s": n_slot_img / dt_is, "rotations_per_ciphertext": 5 * (len(steps) - 1)}}
-    log("conv+square: slot-batched %.0f images/s, image-in-slots (hoisted taps) %.0f images/s" %
-        (n_img / dt_sb, n_slot_img / dt_is))
-    del g2, scts
-    out["conv_layouts"]["image_in_slots_key_rotation"] = key_rotation_leg(ctx, x, P, scale, args.kr_images, log)
-    out["conv_layouts"]["image_in_slots_rotate_and_sum"] = rotate_and_sum_leg(ctx, x, P, scale, args.kr_images,
-                                                                               log)
-    del g, cts, ctx
-    torch.cuda.empty_cache()
-    # yield
-    pr = nat.ckks_find_primes(14, [60] + [40] * 5 + [60])
-    ctx = ckks.Context(14, pr[:6], pr[6:], 6, device=dev).keygen(31)
-    ctx.set_tuning(**(tuning or {}))
-    W = nets.yield_windows(ctx.N // 2)
-    xw, ws, bs = S.yield_inputs(n_windows=4096)
-    steps = nets.yield_steps(ws, W)
-    for ge in nets.galois_for_steps(ctx, steps):
-        ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
-    packed = nets.yield_pack(xw, ctx.N // 2)
-    cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
-    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale)
-    g.run(cts)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
-        g.run(cts)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.net_runs
-    out["yield_sequential"] = {
-        "config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d power-of-two Galois keys, "
-                  "rotations composed and key-switched one by one" % (len(cts), len(ctx.gk)),
-        "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
-    log("yield, sequential rotations (4096 windows, N=2^14): %.1f ms per inference, %.0f windows/s" %
-        (1e3 * dt, 4096 / dt))
-    del g
-    # hoisted: one decomposition and one ModDown per layer and ciphertext, a key per step
-    for ge in nets.galois_for_steps(ctx, steps, direct=True):
-        if ge not in ctx.gk:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g2.run(scts)
+        torch.cuda.synchronize()
+        dt_is = (time.perf_counter() - t0) / args.net_runs
+        out["conv_layouts"] = {
+            "workload": "conv 5x5x5 stride 2 + bias + x^2, N=2^14, level 7",
+            "slot_batched": {"images": n_img, "ms": 1e3 * dt_sb, "images_per_s": n_img / dt_sb},
+            "image_in_slots": {"images": n_slot_img, "ciphertexts": len(scts), "ms": 1e3 * dt_is,
+                               "images_per_s": n_slot_img / dt_is, "rotations_per_ciphertext": 5 * (len(steps) - 1)}}
+        log("conv+square: slot-batched %.0f images/s, image-in-slots (hoisted taps) %.0f images/s" %
+            (n_img / dt_sb, n_slot_img / dt_is))
+        del g2, scts
+        out["conv_layouts"]["image_in_slots_key_rotation"] = key_rotation_leg(ctx, x, P, scale, args.kr_images, log)
+        out["conv_layouts"]["image_in_slots_rotate_and_sum"] = rotate_and_sum_leg(ctx, x, P, scale, args.kr_images,
+                                                                                   log)
+        del g, cts, ctx
+        torch.cuda.empty_cache()
+    if args.nets_only in (None, "yield"):
+        # yield
+        pr = nat.ckks_find_primes(14, [60] + [40] * 5 + [60])
+        ctx = ckks.Context(14, pr[:6], pr[6:], 6, device=dev).keygen(31)
+        ctx.set_tuning(**(tuning or {}))
+        W = nets.yield_windows(ctx.N // 2)
+        xw, ws, bs = S.yield_inputs(n_windows=4096)
+        steps = nets.yield_steps(ws, W)
+        for ge in nets.galois_for_steps(ctx, steps):
             ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
-    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
-    g.run(cts)
-    torch.cuda.synchronize()
-    yield_tuning = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted", tuning)
-    log("yield launch shapes: %s" % yield_tuning["setting"])
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+        packed = nets.yield_pack(xw, ctx.N // 2)
+        cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
+        g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale)
         g.run(cts)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.net_runs
-    out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys, "
-                              "hoisted rotations" % (len(cts), len(ctx.gk)),
-                    "security": security_label(14, pr)["label"],
-                    "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt,
-                    "tuning": yield_tuning}
-    log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
-    del g, cts, ctx
-    torch.cuda.empty_cache()
-    # the same regressor at N = 2^13 (16 windows per ciphertext, 256
-    # ciphertexts): the configuration's smaller ring, above the 128-bit
-    # security bound for this chain
-    pr = nat.ckks_find_primes(13, [60] + [40] * 5 + [60])
-    ctx = ckks.Context(13, pr[:6], pr[6:], 6, device=dev).keygen(31)
-    ctx.set_tuning(**(tuning or {}))
-    W = nets.yield_windows(ctx.N // 2)
-    steps = nets.yield_steps(ws, W)
-    for ge in nets.galois_for_steps(ctx, steps, direct=True):
-        ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
-    packed = nets.yield_pack(xw, ctx.N // 2)
-    cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
-    g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
-    g.run(cts)
-    torch.cuda.synchronize()
-    t13 = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted-n8192", tuning)
-    t0 = time.perf_counter()
-    for _ in range(args.net_runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g.run(cts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.net_runs
+        out["yield_sequential"] = {
+            "config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d power-of-two Galois keys, "
+                      "rotations composed and key-switched one by one" % (len(cts), len(ctx.gk)),
+            "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt}
+        log("yield, sequential rotations (4096 windows, N=2^14): %.1f ms per inference, %.0f windows/s" %
+            (1e3 * dt, 4096 / dt))
+        del g
+        # hoisted: one decomposition and one ModDown per layer and ciphertext, a key per step
+        for ge in nets.galois_for_steps(ctx, steps, direct=True):
+            if ge not in ctx.gk:
+                ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
+        g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
         g.run(cts)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.net_runs
-    out["yield_n8192"] = {"config": "N=2^13, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois "
-                                    "keys, hoisted rotations" % (len(cts), len(ctx.gk)),
-                          "security": security_label(13, pr)["label"], "encrypted_infer_per_s": 1.0 / dt,
-                          "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt, "tuning": t13}
-    log("yield at N=2^13 (%s): %.1f ms per inference, %.0f windows/s" %
-        (security_label(13, pr)["label"], 1e3 * dt, 4096 / dt))
+        torch.cuda.synchronize()
+        yield_tuning = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted", tuning)
+        log("yield launch shapes: %s" % yield_tuning["setting"])
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g.run(cts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.net_runs
+        out["yield"] = {"config": "N=2^14, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois keys, "
+                                  "hoisted rotations" % (len(cts), len(ctx.gk)),
+                        "security": security_label(14, pr)["label"],
+                        "encrypted_infer_per_s": 1.0 / dt, "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt,
+                        "tuning": yield_tuning}
+        log("yield, hoisted rotations: %.1f ms per inference, %.0f windows/s" % (1e3 * dt, 4096 / dt))
+        del g, cts, ctx
+        torch.cuda.empty_cache()
+        # the same regressor at N = 2^13 (16 windows per ciphertext, 256
+        # ciphertexts): the configuration's smaller ring, above the 128-bit
+        # security bound for this chain
+        pr = nat.ckks_find_primes(13, [60] + [40] * 5 + [60])
+        ctx = ckks.Context(13, pr[:6], pr[6:], 6, device=dev).keygen(31)
+        ctx.set_tuning(**(tuning or {}))
+        W = nets.yield_windows(ctx.N // 2)
+        steps = nets.yield_steps(ws, W)
+        for ge in nets.galois_for_steps(ctx, steps, direct=True):
+            ctx.add_galois_key(ge, nets.galois_key_seed(34, ge))
+        packed = nets.yield_pack(xw, ctx.N // 2)
+        cts = [ctx.encrypt(ctx.encode(packed[c], level=5), seed=32, obj=c) for c in range(packed.shape[0])]
+        g = nets.build_yield(ctx, ws, bs, len(cts), 5, scale, hoisted=True)
+        g.run(cts)
+        torch.cuda.synchronize()
+        t13 = net_tune(ctx, lambda: g.run(cts), "yield-4096-hoisted-n8192", tuning)
+        t0 = time.perf_counter()
+        for _ in range(args.net_runs):
+            g.run(cts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.net_runs
+        out["yield_n8192"] = {"config": "N=2^13, [60,40x5|60], 4096 windows per inference, %d ciphertexts, %d Galois "
+                                        "keys, hoisted rotations" % (len(cts), len(ctx.gk)),
+                              "security": security_label(13, pr)["label"], "encrypted_infer_per_s": 1.0 / dt,
+                              "windows_per_s": 4096 / dt, "ms_per_inference": 1e3 * dt, "tuning": t13}
+        log("yield at N=2^13 (%s): %.1f ms per inference, %.0f windows/s" %
+            (security_label(13, pr)["label"], 1e3 * dt, 4096 / dt))
     return out
 
 
@@ -978,6 +980,8 @@ def main():
     ap.add_argument("--serve-cap", type=int, default=160, help="HBM admission cap in GiB")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-nets", action="store_true", help="skip the full-size network inferences")
+    ap.add_argument("--nets-only", choices=["vision", "yield"], default=None,
+                    help="run only the vision (with the conv layouts) or the yield part of the network leg")
     ap.add_argument("--net-runs", type=int, default=3)
     ap.add_argument("--kr-images", type=int, default=64,
                     help="images through the image-in-slots network with the client key rotation")

@@ -880,8 +880,8 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 // in 128 already and keep the compiler's schedule, as do all other shapes.
 template <int LOGN, int LOGE, bool INV, int OP>
 constexpr int kWavesPerEu =
-    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || OP == F_MODUP || OP == F_MODDOWN || OP == F_RESCALE)) ? 4
-                                                                                                             : 1;
+    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || is_modup(OP) || OP == F_MODDOWN || OP == F_RESCALE)) ? 4
+                                                                                                              : 1;
 
 // FP: every item's prime is below 2^50 and the transforms run in FP64
 // arithmetic (the host splits a launch by prime class); else 64-bit integer
@@ -1134,8 +1134,8 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
             case F_INT: return launch_fwd_t<LN, LE, F_INT>(tb, items, n, seed, s);         \
         }                                                                            \
         break;
-// fixed-size conversion variants: only where the register budget needs them
-// (N = 2^15, 32 residues per thread); elsewhere the generic kernels take the
+// fixed-size conversion variants: at 32 residues per thread (N = 2^15, and
+// N = 2^14 with the wide shape); elsewhere the generic kernels take the
 // same items
 #define CKKS_FWD_FIXED(LN, LE)                                                        \
     switch (op) {                                                                     \

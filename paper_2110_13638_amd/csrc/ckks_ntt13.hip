@@ -3,6 +3,9 @@
 
 namespace ckks {
 hipError_t launch_fwd_13(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
+    // one-prime digits and 1-2 special primes: conversions of a fixed size
+    if (tb.ntt_wide) CKKS_FWD_FIXED_SMALL(13, 5)
+    else CKKS_FWD_FIXED_SMALL(13, 4)
     if (is_modup(op)) op = F_MODUP;
     if (is_relin(op)) op = is_relin_rs(op) ? F_RELIN_RS : F_RELIN;
     if (tb.ntt_wide) {

@@ -3,8 +3,9 @@
 
 namespace ckks {
 hipError_t launch_fwd_14(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
-    // 32 residues per thread: conversions of a fixed digit size / special-prime count
-    if (tb.ntt_wide) CKKS_FWD_FIXED(14, 5)
+    // one-prime digits and 1-2 special primes: conversions of a fixed size
+    if (tb.ntt_wide) CKKS_FWD_FIXED_SMALL(14, 5)
+    else CKKS_FWD_FIXED_SMALL(14, 4)
     if (is_modup(op)) op = F_MODUP;
     if (is_relin(op)) op = is_relin_rs(op) ? F_RELIN_RS : F_RELIN;
     if (tb.ntt_wide) {

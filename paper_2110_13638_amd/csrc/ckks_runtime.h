@@ -321,7 +321,7 @@ struct Plan {
                 auto fp_ok = [&](const Item &it) {
                     if (c->primes[it.prime] >= kFpPrimeBound) return false;
                     if (relin && c->primes[it.a] >= kFpPrimeBound) return false;
-                    // below 2^15 (the generic ModUp kernel) sources of 2^50 or more
+                    // below 2^15 (every ModUp kernel) sources of 2^50 or more
                     // are converted too; at 2^15 every source must be below 2^50
                     if (modup && c->log_n >= 15) {
                         const u32 sz = op == F_MODUP ? it.b : (u32)(op - F_MODUP_S1 + 1);

@@ -216,6 +216,34 @@ def test_ragged_batched_hmult(wide):
         assert np.array_equal(outs[i].residues(), orc.mul_relin_rescale(AO[i], BO[i], rk)), i
 
 
+# A 60-bit base prime as a ModUp source below N = 2^15: the FP64 engine
+# splits such a source into two products in every ModUp kernel (generic and
+# fixed digit size), for both transform shapes; one- and two-prime digits.
+@pytest.mark.parametrize("ntt_fp", [1, 0])
+@pytest.mark.parametrize("wide", [0, 1])
+@pytest.mark.parametrize("chain", ["one_prime_digits", "two_prime_digits"])
+@pytest.mark.parametrize("log_n", [13, 14])
+def test_hmult_60bit_modup_sources(ck, log_n, chain, wide, ntt_fp):
+    if chain == "one_prime_digits":
+        ctx, orc = _pair(ck, log_n, [60, 40, 40, 40], [60], 4)
+    else:
+        ctx, orc = _pair(ck, log_n, [60, 40, 40, 40], [60, 60], 2)
+    ctx.set_tuning(ntt_wide=wide, ntt_fp=ntt_fp)
+    _, _, _, rk = _keys_oracle(orc, 3)
+    lv = ctx.max_level
+    A, Bs, AO, BO = [], [], [], []
+    for i in range(3):
+        res = S.residues(300 + i, ctx.q[: lv + 1], ctx.N, 4)
+        AO.append(res[:2])
+        BO.append(res[2:])
+        A.append(ctx.ct_from_residues(res[:2]))
+        Bs.append(ctx.ct_from_residues(res[2:]))
+    print("60-bit source case log_n=%d %s wide=%d ntt_fp=%d" % (log_n, chain, wide, ntt_fp), flush=True)
+    outs = ctx.hmult_relin_rescale(A, Bs)
+    for i in range(3):
+        assert np.array_equal(outs[i].residues(), orc.mul_relin_rescale(AO[i], BO[i], rk)), i
+
+
 def test_linear_bit_exact(small):
     ctx, orc = small
     level = ctx.max_level

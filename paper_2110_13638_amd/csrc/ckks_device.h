@@ -542,11 +542,14 @@ enum FwdOp : int {
     // keep the transform register-resident (no spills)
     F_MODUP_S1 = 8, F_MODUP_S2 = 9, F_MODUP_S3 = 10, F_MODUP_S4 = 11,
     F_RELIN_P1 = 12, F_RELIN_P2 = 13, F_RELIN_RS_P1 = 14, F_RELIN_RS_P2 = 15,
+    F_MODDOWN_P1 = 16, F_MODDOWN_P2 = 17,  // F_MODDOWN with 1 or 2 special primes
 };
 __host__ __device__ constexpr bool is_modup(int op) { return op == F_MODUP || (op >= F_MODUP_S1 && op <= F_MODUP_S4); }
 __host__ __device__ constexpr int modup_s(int op) { return op >= F_MODUP_S1 && op <= F_MODUP_S4 ? op - F_MODUP_S1 + 1 : 0; }
 __host__ __device__ constexpr bool is_relin_rs(int op) { return op == F_RELIN_RS || op == F_RELIN_RS_P1 || op == F_RELIN_RS_P2; }
 __host__ __device__ constexpr bool is_relin(int op) { return op == F_RELIN || op == F_RELIN_P1 || op == F_RELIN_P2 || is_relin_rs(op); }
+__host__ __device__ constexpr bool is_moddown(int op) { return op == F_MODDOWN || op == F_MODDOWN_P1 || op == F_MODDOWN_P2; }
+__host__ __device__ constexpr int moddown_np(int op) { return op == F_MODDOWN_P1 ? 1 : op == F_MODDOWN_P2 ? 2 : 0; }
 __host__ __device__ constexpr int relin_np(int op) {
     return op == F_RELIN_P1 || op == F_RELIN_RS_P1 ? 1 : op == F_RELIN_P2 || op == F_RELIN_RS_P2 ? 2 : 0;
 }
@@ -678,9 +681,10 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 #pragma unroll
             for (int c = 0; c < kCC; c++) r[c0 + c] = acc[c].reduce(pc);
         });
-    } else if constexpr (OP == F_MODDOWN) {
+    } else if constexpr (is_moddown(OP)) {
         // sum_m [x_m * hat_m^-1]_{p_m} * (hat_m mod t), one Barrett at the end
-        const u32 lo = it.a, s = it.b;  // first source prime index, count
+        constexpr int NP = moddown_np(OP);  // 0: count from the item
+        const u32 lo = it.a, s = NP ? (u32)NP : it.b;  // first source prime index, count
         const u64 *blk = tb.moddown;
         const u64 *hat = blk + 2 * tb.n_p + it.prime;  // hat[m * n_q + t]
         const Buf src(it.in[0]);
@@ -850,7 +854,7 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
                 dst.st(vo, (c0 + c) * T * 8, shoup(subm(u, r[c0 + c], q), qi.x, qi.y, q));
             }
         }
-    } else if constexpr (OP == F_MODDOWN) {
+    } else if constexpr (is_moddown(OP)) {
         const Buf in1(it.in[1]), in2(it.in[2] ? it.in[2] : it.in[1]), dst(it.out);
         const bool add = it.in[2] != nullptr;
 #pragma unroll
@@ -880,7 +884,7 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
 // in 128 already and keep the compiler's schedule, as do all other shapes.
 template <int LOGN, int LOGE, bool INV, int OP>
 constexpr int kWavesPerEu =
-    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || is_modup(OP) || OP == F_MODDOWN || OP == F_RESCALE)) ? 4
+    ((LOGN == 14 || LOGN == 13) && LOGE == 5 && (INV || is_modup(OP) || is_moddown(OP) || OP == F_RESCALE)) ? 4
                                                                                                               : 1;
 
 // FP: every item's prime is below 2^50 and the transforms run in FP64
@@ -1147,8 +1151,10 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
         case F_RELIN_P2: return launch_fwd_t<LN, LE, F_RELIN_P2>(tb, items, n, seed, s);       \
         case F_RELIN_RS_P1: return launch_fwd_t<LN, LE, F_RELIN_RS_P1>(tb, items, n, seed, s); \
         case F_RELIN_RS_P2: return launch_fwd_t<LN, LE, F_RELIN_RS_P2>(tb, items, n, seed, s); \
+        case F_MODDOWN_P1: return launch_fwd_t<LN, LE, F_MODDOWN_P1>(tb, items, n, seed, s);   \
+        case F_MODDOWN_P2: return launch_fwd_t<LN, LE, F_MODDOWN_P2>(tb, items, n, seed, s);   \
     }
-// below 2^15: the one-prime-digit ModUp and the ModDown variants (the
+// below 2^15: the one-prime-digit ModUp and the ModDown (+ rescale) variants (the
 // multi-prime ModUp variants, which also carry the split of 60-bit sources
 // there, spill; the generic kernel takes those items)
 #define CKKS_FWD_FIXED_SMALL(LN, LE)                                                  \
@@ -1158,6 +1164,8 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
         case F_RELIN_P2: return launch_fwd_t<LN, LE, F_RELIN_P2>(tb, items, n, seed, s);       \
         case F_RELIN_RS_P1: return launch_fwd_t<LN, LE, F_RELIN_RS_P1>(tb, items, n, seed, s); \
         case F_RELIN_RS_P2: return launch_fwd_t<LN, LE, F_RELIN_RS_P2>(tb, items, n, seed, s); \
+        case F_MODDOWN_P1: return launch_fwd_t<LN, LE, F_MODDOWN_P1>(tb, items, n, seed, s);   \
+        case F_MODDOWN_P2: return launch_fwd_t<LN, LE, F_MODDOWN_P2>(tb, items, n, seed, s);   \
     }
 #define CKKS_INV_CASE(LN, LE)                                                        \
     case LN:                                                                         \

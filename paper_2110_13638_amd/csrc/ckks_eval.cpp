@@ -74,7 +74,7 @@ void plan_keyswitch(Plan &P, const std::vector<KsJob> &jobs) {
     add_modup(P, modup);
     add_ip(P, ipc);
     P.add(1, I_COPY, ipP);
-    P.add(0, F_MODDOWN, mdown);
+    P.add(0, moddown_op(c), mdown);
 }
 }  // namespace ckks
 
@@ -689,7 +689,7 @@ extern "C" int ckks_hoisted_linear(const ckks_ctx *c, const ckks_ct *in, ckks_ct
     add_modup(P, modup);
     P.add(5, staged ? (int)(per * beta) : 0, ho);
     P.add(1, I_COPY, scl);
-    P.add(0, F_MODDOWN, mdown);
+    P.add(0, moddown_op(c), mdown);
     CK(P.run(ws_bytes, s));
     for (u32 x = 0; x < B; x++) {
         out[x].n_poly = 2;

@@ -515,7 +515,8 @@ namespace {
 const char *fwd_names[] = {"ntt_fwd", "ntt_fwd_modup", "ntt_fwd_rescale", "ntt_fwd_moddown",
                            "ntt_fwd_moddown_z", "ntt_fwd_sample", "ntt_fwd_int", "ntt_fwd_relin_rescale",
                            "ntt_fwd_modup", "ntt_fwd_modup", "ntt_fwd_modup", "ntt_fwd_modup",
-                           "ntt_fwd_moddown_z", "ntt_fwd_moddown_z", "ntt_fwd_relin_rescale", "ntt_fwd_relin_rescale"};
+                           "ntt_fwd_moddown_z", "ntt_fwd_moddown_z", "ntt_fwd_relin_rescale", "ntt_fwd_relin_rescale",
+                           "ntt_fwd_moddown", "ntt_fwd_moddown"};
 const char *inv_names[] = {"ntt_inv", "ntt_inv_mul", "ntt_inv_scale", "ntt_inv_decrypt"};
 const char *ew_names[] = {"ew_add", "ew_sub", "ew_mul", "ew_mul_const", "ew_add_const", "ew_tensor", "ew_copy",
                           "ew_automorph", "ew_neg", "ew_keygen", "ew_encrypt", "ew_square_s", "ew_hmult_fin",
@@ -672,6 +673,8 @@ int relin_op(const ckks_ctx *c, bool rescale) {
     if (c->n_p <= 2) return base + (int)c->n_p - 1;
     return rescale ? F_RELIN_RS : F_RELIN;
 }
+// ModDown kernel for the context's special-prime count
+int moddown_op(const ckks_ctx *c) { return c->n_p <= 2 ? F_MODDOWN_P1 + (int)c->n_p - 1 : F_MODDOWN; }
 
 // items of the inner product: ciphertexts of one level and one switching
 // key are grouped by kIpCts so that each key residue is loaded once per

@@ -7,6 +7,7 @@ hipError_t launch_fwd_13(const DevTables &tb, int op, const Item *items, int n, 
     if (tb.ntt_wide) CKKS_FWD_FIXED_SMALL(13, 5)
     else CKKS_FWD_FIXED_SMALL(13, 4)
     if (is_modup(op)) op = F_MODUP;
+    if (is_moddown(op)) op = F_MODDOWN;
     if (is_relin(op)) op = is_relin_rs(op) ? F_RELIN_RS : F_RELIN;
     if (tb.ntt_wide) {
         switch (tb.log_n) {

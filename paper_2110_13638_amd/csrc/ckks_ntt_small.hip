@@ -4,6 +4,7 @@
 namespace ckks {
 hipError_t launch_fwd_small(const DevTables &tb, int op, const Item *items, int n, u64 seed, hipStream_t s) {
     if (is_modup(op)) op = F_MODUP;
+    if (is_moddown(op)) op = F_MODDOWN;
     if (is_relin(op)) op = is_relin_rs(op) ? F_RELIN_RS : F_RELIN;
     if (tb.ntt_wide) {
         switch (tb.log_n) {

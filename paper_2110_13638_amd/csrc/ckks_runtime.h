@@ -44,7 +44,7 @@ hipError_t launch_linear_grouped(const DevTables &tb, const LinGroup *groups, u3
 // kernel op codes (mirrors of the enums in the kernel file)
 enum {
     F_COPY = 0, F_MODUP = 1, F_RESCALE = 2, F_MODDOWN = 3, F_RELIN = 4, F_SAMPLE = 5, F_INT = 6, F_RELIN_RS = 7,
-    F_MODUP_S1 = 8, F_RELIN_P1 = 12, F_RELIN_RS_P1 = 14
+    F_MODUP_S1 = 8, F_RELIN_P1 = 12, F_RELIN_RS_P1 = 14, F_MODDOWN_P1 = 16
 };
 enum { I_COPY = 0, I_MUL = 1, I_SCALE = 2, I_DECRYPT = 3 };
 enum {
@@ -425,6 +425,7 @@ struct Plan {
 void add_modup(Plan &P, const std::vector<Item> &v);
 // ModDown + rescale kernel for the context's special-prime count
 int relin_op(const ckks_ctx *c, bool rescale);
+int moddown_op(const ckks_ctx *c);
 // one ciphertext's share of the key-switch inner product
 struct IpCt {
     u32 level;

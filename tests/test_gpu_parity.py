@@ -218,7 +218,8 @@ def test_ragged_batched_hmult(wide):
 
 # A 60-bit base prime as a ModUp source below N = 2^15: the FP64 engine
 # splits such a source into two products in every ModUp kernel (generic and
-# fixed digit size), for both transform shapes; one- and two-prime digits.
+# fixed digit size), for both transform shapes; one- and two-prime digits
+# (one and two special primes), through HMult and a rotation.
 @pytest.mark.parametrize("ntt_fp", [1, 0])
 @pytest.mark.parametrize("wide", [0, 1])
 @pytest.mark.parametrize("chain", ["one_prime_digits", "two_prime_digits"])
@@ -229,7 +230,7 @@ def test_hmult_60bit_modup_sources(ck, log_n, chain, wide, ntt_fp):
     else:
         ctx, orc = _pair(ck, log_n, [60, 40, 40, 40], [60, 60], 2)
     ctx.set_tuning(ntt_wide=wide, ntt_fp=ntt_fp)
-    _, _, _, rk = _keys_oracle(orc, 3)
+    s, sn, _, rk = _keys_oracle(orc, 3)
     lv = ctx.max_level
     A, Bs, AO, BO = [], [], [], []
     for i in range(3):
@@ -242,6 +243,11 @@ def test_hmult_60bit_modup_sources(ck, log_n, chain, wide, ntt_fp):
     outs = ctx.hmult_relin_rescale(A, Bs)
     for i in range(3):
         assert np.array_equal(outs[i].residues(), orc.mul_relin_rescale(AO[i], BO[i], rk)), i
+    # a rotation: key switch with the plain ModDown (one or two special primes)
+    g = ctx.galois_elt(1)
+    ctx.add_galois_key(g, 51)
+    rot = ctx.rotate(A[0], g=g)
+    assert np.array_equal(rot.residues(), orc.apply_galois(AO[0], g, orc.keygen_galois(s, sn, g, 51)))
 
 
 def test_linear_bit_exact(small):

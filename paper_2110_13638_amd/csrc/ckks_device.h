@@ -596,7 +596,8 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
         for (int c = 0; c < E; c++) r[c] = Buf(it.in[0]).ld(vo, c * T * 8);
     } else if constexpr (kFpModup) {
         // sum_i src_i (hat_i mod t) with the target t below 2^50 (and, at
-        // N = 2^15, every source prime): each term is an FP64
+        // N = 2^15 or for a fixed digit size above one, every source
+        // prime): each term is an FP64
         // modular product of magnitude
         // <= 0.75 t (its quotient from hat_i * (1/t), relative error
         // <= 2^-52); partial sums are re-centred every four terms and at the
@@ -614,10 +615,10 @@ __device__ __forceinline__ void fwd_item(const DevTables &tb, const Item &it, u3
             const u64 hh = hat[i * tb.n_prim];
             const double h = fp_from_u64(hh);
             const double hq = h * tinv;
-            // below 2^15 (generic and fixed-size kernels alike): a source
+            // below 2^15, generic and one-prime-digit kernels: a source
             // prime of 2^50 or more (a 60-bit base prime) enters as
             // hi 2^26 + lo, two products (<= 0.5 t each)
-            if constexpr (LOGN <= 14) {
+            if constexpr (LOGN <= 14 && S <= 1) {
                 if (tb.pc[it.c * tb.alpha + i].q >= kFpPrimeBound) {
                     constexpr int kSC = kConvChunk / 2;
                     const double h26 = fp_from_u64(mulm(hh, 1ull << 26, pc)), h26q = h26 * tinv;
@@ -1154,12 +1155,15 @@ static hipError_t launch_inv_t(const DevTables &tb, const Item *items, int n, hi
         case F_MODDOWN_P1: return launch_fwd_t<LN, LE, F_MODDOWN_P1>(tb, items, n, seed, s);   \
         case F_MODDOWN_P2: return launch_fwd_t<LN, LE, F_MODDOWN_P2>(tb, items, n, seed, s);   \
     }
-// below 2^15: the one-prime-digit ModUp and the ModDown (+ rescale) variants (the
-// multi-prime ModUp variants, which also carry the split of 60-bit sources
-// there, spill; the generic kernel takes those items)
+// below 2^15 (N = 2^13, 2^14); the multi-prime ModUp variants take no
+// 60-bit sources in FP64 (the planner sends those items to the integer
+// engine), the one-prime-digit variant splits them like the generic kernel
 #define CKKS_FWD_FIXED_SMALL(LN, LE)                                                  \
     switch (op) {                                                                     \
         case F_MODUP_S1: return launch_fwd_t<LN, LE, F_MODUP_S1>(tb, items, n, seed, s);       \
+        case F_MODUP_S2: return launch_fwd_t<LN, LE, F_MODUP_S2>(tb, items, n, seed, s);       \
+        case F_MODUP_S3: return launch_fwd_t<LN, LE, F_MODUP_S3>(tb, items, n, seed, s);       \
+        case F_MODUP_S4: return launch_fwd_t<LN, LE, F_MODUP_S4>(tb, items, n, seed, s);       \
         case F_RELIN_P1: return launch_fwd_t<LN, LE, F_RELIN_P1>(tb, items, n, seed, s);       \
         case F_RELIN_P2: return launch_fwd_t<LN, LE, F_RELIN_P2>(tb, items, n, seed, s);       \
         case F_RELIN_RS_P1: return launch_fwd_t<LN, LE, F_RELIN_RS_P1>(tb, items, n, seed, s); \

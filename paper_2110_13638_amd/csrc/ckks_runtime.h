@@ -321,9 +321,11 @@ struct Plan {
                 auto fp_ok = [&](const Item &it) {
                     if (c->primes[it.prime] >= kFpPrimeBound) return false;
                     if (relin && c->primes[it.a] >= kFpPrimeBound) return false;
-                    // below 2^15 (every ModUp kernel) sources of 2^50 or more
-                    // are converted too; at 2^15 every source must be below 2^50
-                    if (modup && c->log_n >= 15) {
+                    // sources of 2^50 or more are converted in FP64 below 2^15 by
+                    // the generic and one-prime-digit kernels; the fixed
+                    // multi-prime kernels (2^13 .. 2^15) and every 2^15 kernel
+                    // need every source below 2^50
+                    if (modup && (c->log_n >= 15 || (c->log_n >= 13 && op > F_MODUP_S1 && op < F_MODUP_S1 + 4))) {
                         const u32 sz = op == F_MODUP ? it.b : (u32)(op - F_MODUP_S1 + 1);
                         for (u32 i = 0; i < sz; i++)
                             if (c->primes[it.c * c->alpha + i] >= kFpPrimeBound) return false;
